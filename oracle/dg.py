@@ -1,0 +1,207 @@
+"""The LDG discretisation, eq. (DGformulation), in weak form with GLL quadrature.
+
+Pass 1 (auxiliary gradient):  (q, p) = -(u, div p) + <u_hat, p.n>
+Pass 2 (state):               (du/dt, w) = (F(u, q), grad w) - <F_hat.n, w> + (s(u, q), w)
+
+Numerical trace and flux, eq. (LDG2), at interior faces:
+    u_hat = (u + u^-)/2
+    F_hat.n = (F(u, q) + F(u^-, q^-)).n / 2 + sigma(u_hat) (u - u_hat)
+with sigma = lambda_max I + sigma_d(u_hat) (physics.sigma).
+
+Boundary faces (section 2.3, the details being the stated reading):
+  lower (tag 1): u_b = (varrho, 0, T_bot sqrt(rho)); u_hat = u_b;
+                 F_hat.n = F(u_b, q).n + sigma(u_b) (u - u_b)
+  upper (tag 2): u_hat = u; F_hat.n = F_inviscid(u).n (zero normal stress, adiabatic)
+  bc_mode 1 (test problems): every boundary is a Dirichlet state u_D (a constant
+                 vector, or P["bc_fn"](x)), treated like the lower boundary with u_b = u_D.
+
+All integrals use the collocated GLL rule, so the mass matrix is diag(w_i J_i) and
+R = M^{-1}(...) is the nodal time derivative du/dt.
+"""
+import numpy as np
+
+from . import physics as ph
+
+
+def _arr(lst, like):
+    return np.array([np.broadcast_to(np.asarray(v, dtype=like.dtype), like.shape) for v in lst])
+
+
+def _arr2(lst, like):
+    return np.array([[np.broadcast_to(np.asarray(v, dtype=like.dtype), like.shape) for v in row] for row in lst])
+
+
+def _dot_n(F, Sn, d):
+    # F: [f, d, ...], Sn: [d, ...]
+    return sum(F[:, k] * Sn[k] for k in range(d))
+
+
+def boundary_value(mesh, P, uin, Xf):
+    """state u_b imposed on a boundary face (before the tag decides how it is used)"""
+    if P.get("bc_mode", 0) == 1:
+        if "bc_fn" in P:
+            return np.asarray(P["bc_fn"](Xf), dtype=uin.dtype)
+        ud = np.asarray(P["bc_state"][: P["d"] + 2], dtype=uin.dtype)
+        return np.broadcast_to(ud[:, None, None], uin.shape).copy()
+    return _arr(ph.bottom_state(uin, P, np), uin[0])
+
+
+def traces(mesh, P, u):
+    """u_hat on every face node: list over faces of [f, E, Nf]"""
+    ref = mesh.ref
+    f = P["d"] + 2
+    E, N = mesh.E, ref.N
+    unodes = np.moveaxis(u, 1, 0).reshape(f, E * N)
+    out = []
+    for fi, (a, side, nodes, wf) in enumerate(ref.faces):
+        uin = np.moveaxis(u[:, :, nodes], 1, 0)          # [f, E, Nf]
+        nb = mesh.nbr[:, fi, :]
+        uout = unodes[:, np.where(nb >= 0, nb, 0)]
+        uh = 0.5 * (uin + uout)
+        tag = mesh.tag[:, fi][None, :, None]
+        Xf = np.moveaxis(mesh.X[:, nodes, :], 2, 0)      # [d, E, Nf]
+        ub = boundary_value(mesh, P, uin, Xf)
+        if P.get("bc_mode", 0) == 1:
+            uh = np.where(tag > 0, ub, uh)
+        else:
+            uh = np.where(tag == 1, ub, np.where(tag == 2, uin, uh))
+        out.append(uh)
+    return out
+
+
+def gradient(mesh, P, u):
+    """pass 1: q[e, c, k, j] (weak form with GLL quadrature)"""
+    ref = mesh.ref
+    d = P["d"]
+    W = ref.W
+    uh = traces(mesh, P, u)
+    q = np.zeros(u.shape[:2] + (d, ref.N), dtype=u.dtype)
+    for a in range(d):
+        # T[e, c, k, i] = w_i Ja[e, i, a, k] u[e, c, i]
+        JaT = np.transpose(mesh.Ja[:, :, a, :], (0, 2, 1))          # [E, k, i]
+        T = u[:, :, None, :] * (W[None, None, None, :] * JaT[:, None, :, :])
+        q -= T @ ref.Dr[a]
+    for fi, (a, side, nodes, wf) in enumerate(ref.faces):
+        Sn = side * mesh.Ja[:, nodes, a, :]                          # [E, Nf, k]
+        q[:, :, :, nodes] += np.einsum("cem,emk,m->eckm", uh[fi], Sn, wf)
+    q /= (W[None, :] * mesh.J)[:, None, None, :]
+    return q
+
+
+def residual(mesh, P, u, t=0.0, q=None):
+    """R(u) = du/dt of the semi-discrete system, shape [E, f, N]"""
+    ref = mesh.ref
+    d = P["d"]
+    f = d + 2
+    E, N = mesh.E, ref.N
+    W = ref.W
+    if q is None:
+        q = gradient(mesh, P, u)
+    uh = traces(mesh, P, u)
+    un = np.moveaxis(u, 1, 0)                         # [f, E, N]
+    qn = np.moveaxis(q, 1, 0)                         # [f, E, d, N] -> index as [c][k]
+    qn = np.moveaxis(qn, 2, 1)                        # [f, d, E, N]
+    xn = np.moveaxis(mesh.X, 2, 0)                    # [d, E, N]
+    F = _arr2(ph.flux(un, qn, P, np), un[0])          # [f, d, E, N]
+    S = _arr(ph.source(un, qn, xn, t, P, np), un[0])  # [f, E, N]
+    R = np.zeros((f, E, N), dtype=u.dtype)
+    for a in range(d):
+        # contravariant flux G[c, e, i] = w_i sum_k Ja[e, i, a, k] F[c, k, e, i]
+        G = W[None, None, :] * np.einsum("eik,ckei->cei", mesh.Ja[:, :, a, :], F)
+        R += G @ ref.Dr[a]
+    unodes = un.reshape(f, E * N)
+    qnodes = qn.reshape(f, d, E * N)
+    for fi, (a, side, nodes, wf) in enumerate(ref.faces):
+        Sn = np.moveaxis(side * mesh.Ja[:, nodes, a, :], 2, 0)       # [d, E, Nf]
+        Smag = np.sqrt(sum(Sn[k] ** 2 for k in range(d)))
+        uin = un[:, :, nodes]
+        qin = qn[:, :, :, nodes]
+        Fin = F[:, :, :, nodes]
+        nb = mesh.nbr[:, fi, :]
+        safe = np.where(nb >= 0, nb, 0)
+        uout = unodes[:, safe]
+        qout = qnodes[:, :, safe]
+        Fout = _arr2(ph.flux(uout, qout, P, np), uout[0])
+        uhat = uh[fi]
+        sig = _arr(ph.sigma(uhat, P, np), uhat[0])
+        Fh_int = 0.5 * (_dot_n(Fin, Sn, d) + _dot_n(Fout, Sn, d)) + Smag * sig * (uin - uhat)
+        # boundary versions
+        Xf = np.moveaxis(mesh.X[:, nodes, :], 2, 0)
+        ub = boundary_value(mesh, P, uin, Xf)
+        Fb = _arr2(ph.flux(ub, qin, P, np), ub[0])
+        sigb = _arr(ph.sigma(ub, P, np), ub[0])
+        Fh_dir = _dot_n(Fb, Sn, d) + Smag * sigb * (uin - ub)
+        Fi_top = _arr2(ph.flux_inviscid(uin, P, np), uin[0])
+        Fh_top = _dot_n(Fi_top, Sn, d)
+        tag = mesh.tag[:, fi][None, :, None]
+        if P.get("bc_mode", 0) == 1:
+            Fh = np.where(tag > 0, Fh_dir, Fh_int)
+        else:
+            Fh = np.where(tag == 1, Fh_dir, np.where(tag == 2, Fh_top, Fh_int))
+        R[:, :, nodes] -= Fh * wf[None, None, :]
+    R = R / (W[None, :] * mesh.J)[None] + S
+    return np.moveaxis(R, 0, 1).copy()
+
+
+def residual_parts(mesh, P, u, t=0.0):
+    """(R, term scale): the scale is |volume divergence| + |face lift| + |source| per
+    node, used to express parity tolerances relative to the cancelling terms."""
+    ref = mesh.ref
+    d = P["d"]
+    R = residual(mesh, P, u, t)
+    # volume part alone, face part alone
+    P0 = dict(P)
+    q = gradient(mesh, P, u)
+    un = np.moveaxis(u, 1, 0)
+    qn = np.moveaxis(np.moveaxis(q, 1, 0), 2, 1)
+    xn = np.moveaxis(mesh.X, 2, 0)
+    S = _arr(ph.source(un, qn, xn, t, P0, np), un[0])
+    F = _arr2(ph.flux(un, qn, P0, np), un[0])
+    V = np.zeros_like(S)
+    for a in range(d):
+        G = ref.W[None, None, :] * np.einsum("eik,ckei->cei", mesh.Ja[:, :, a, :], F)
+        V += G @ ref.Dr[a]
+    V = V / (ref.W[None, :] * mesh.J)[None]
+    Fc = np.moveaxis(R, 0, 1) - V - S            # face contribution
+    scale = np.abs(V) + np.abs(Fc) + np.abs(S)
+    return R, np.moveaxis(scale, 0, 1).copy()
+
+
+def conservation_terms(mesh, P, u, t=0.0):
+    """(sum_i w_i J_i R_i, boundary flux + source integral) per field: equal for a
+    conservative scheme since interior face fluxes are single valued."""
+    ref = mesh.ref
+    d = P["d"]
+    q = gradient(mesh, P, u)
+    R = residual(mesh, P, u, t, q=q)
+    WJ = ref.W[None, :] * mesh.J
+    lhs = np.einsum("ecj,ej->c", R, WJ)
+    un = np.moveaxis(u, 1, 0)
+    qn = np.moveaxis(np.moveaxis(q, 1, 0), 2, 1)
+    xn = np.moveaxis(mesh.X, 2, 0)
+    S = _arr(ph.source(un, qn, xn, t, P, np), un[0])
+    rhs = np.einsum("cej,ej->c", S, WJ)
+    mag = np.einsum("cej,ej->c", np.abs(S), WJ) + np.einsum("ecj,ej->c", np.abs(R), WJ)
+    # boundary flux integrals
+    for fi, (a, side, nodes, wf) in enumerate(ref.faces):
+        tag = mesh.tag[:, fi]
+        if not np.any(tag > 0):
+            continue
+        Sn = np.moveaxis(side * mesh.Ja[:, nodes, a, :], 2, 0)
+        Smag = np.sqrt(sum(Sn[k] ** 2 for k in range(d)))
+        uin = un[:, :, nodes]
+        qin = qn[:, :, :, nodes]
+        Xf = np.moveaxis(mesh.X[:, nodes, :], 2, 0)
+        ub = boundary_value(mesh, P, uin, Xf)
+        Fb = _arr2(ph.flux(ub, qin, P, np), ub[0])
+        sigb = _arr(ph.sigma(ub, P, np), ub[0])
+        Fh_dir = _dot_n(Fb, Sn, d) + Smag * sigb * (uin - ub)
+        Fh_top = _dot_n(_arr2(ph.flux_inviscid(uin, P, np), uin[0]), Sn, d)
+        t_ = tag[None, :, None]
+        if P.get("bc_mode", 0) == 1:
+            Fh = np.where(t_ > 0, Fh_dir, 0.0)
+        else:
+            Fh = np.where(t_ == 1, Fh_dir, np.where(t_ == 2, Fh_top, 0.0))
+        rhs -= np.einsum("cem,m->c", Fh, wf)
+        mag += np.einsum("cem,m->c", np.abs(Fh), wf)
+    return lhs, rhs, mag

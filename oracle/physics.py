@@ -1,0 +1,187 @@
+"""Pointwise physics of the nondimensional thermosphere model.
+
+State u = (varrho, U, Theta) with varrho = log(rho/rho0), U = sqrt(rho) v (d components)
+and Theta = sqrt(rho) T (section 2.4). Fluxes and sources follow eq.
+(fluxSWNondimensional); the acceleration follows the nondimensional form given right
+after it (gravity / gamma, centripetal Fr^2/gamma, Coriolis 2 Fr/sqrt(gamma)); the
+transport coefficients are the molecular + eddy laws of section 2.1.2 normalised by
+their lower-boundary values: mu = sqrt(T m) + nu_r rho, kappa = alpha0c T^0.69 +
+alpha_r rho c_p, with c_v = c_p = 1/m for a constant mean molecular mass m (the
+grad(c_v) source term then vanishes).
+
+Every function takes plain component lists and a math namespace `xp` (numpy for
+numbers, including complex numbers for the complex step; sympy for the symbolic
+check of the transformation from eq. (NS1)).
+"""
+import numpy as np
+
+
+def _consts(P, xp):
+    g = P["gamma"]
+    return dict(
+        inv_gm=1.0 / (g * P["m"]),
+        c_visc=1.0 / xp.sqrt(g * P["Gr"]),
+        c_cond=(1.0 / P["Pr"]) * xp.sqrt(g / P["Gr"]),
+        c_diss=(g - 1.0) * xp.sqrt(g / P["Gr"]),
+    )
+
+
+def primitives(u, P, xp):
+    d = P["d"]
+    lr = u[0]
+    U = [u[1 + i] for i in range(d)]
+    Th = u[1 + d]
+    rho = xp.exp(lr)
+    s = xp.exp(-0.5 * lr)          # 1/sqrt(rho)
+    v = [s * Ui for Ui in U]
+    T = s * Th
+    return lr, U, Th, rho, s, v, T
+
+
+def transport(rho, T, P, xp):
+    m = P["m"]
+    mu = xp.sqrt(T * m) + P["nu_r"] * rho
+    kap = P["alpha0c"] * T ** P.get("kappa_exp", 0.69) + P["alpha_r"] * rho * (1.0 / m)
+    return mu, kap
+
+
+def gradients(u, q, P, xp):
+    """velocity gradient gv[i][k] = d v_i / d x_k and temperature gradient gT[k]
+    recovered from the auxiliary variable q = grad u."""
+    d = P["d"]
+    lr, U, Th, rho, s, v, T = primitives(u, P, xp)
+    gl = [q[0][k] for k in range(d)]
+    gv = [[s * (q[1 + i][k] - 0.5 * U[i] * gl[k]) for k in range(d)] for i in range(d)]
+    gT = [s * (q[1 + d][k] - 0.5 * Th * gl[k]) for k in range(d)]
+    return gl, gv, gT
+
+
+def strain(gv, d):
+    div = sum(gv[i][i] for i in range(d))
+    eps = [[gv[i][k] + gv[k][i] - (2.0 / 3.0 if i == k else 0.0) * div for k in range(d)] for i in range(d)]
+    return eps, div
+
+
+def flux_inviscid(u, P, xp):
+    d = P["d"]
+    C = _consts(P, xp)
+    lr, U, Th, rho, s, v, T = primitives(u, P, xp)
+    F = [[lr * v[k] for k in range(d)]]
+    for i in range(d):
+        F.append([U[i] * v[k] + (C["inv_gm"] * Th if i == k else 0.0) for k in range(d)])
+    F.append([Th * v[k] for k in range(d)])
+    return F
+
+
+def flux_viscous(u, q, P, xp):
+    """the diffusive part of F, returned with the sign it has inside F"""
+    d = P["d"]
+    C = _consts(P, xp)
+    lr, U, Th, rho, s, v, T = primitives(u, P, xp)
+    mu, kap = transport(rho, T, P, xp)
+    gl, gv, gT = gradients(u, q, P, xp)
+    eps, div = strain(gv, d)
+    F = [[0.0 * lr for k in range(d)]]
+    for i in range(d):
+        F.append([-C["c_visc"] * mu * s * eps[i][k] for k in range(d)])
+    F.append([-C["c_cond"] * kap * s * P["m"] * gT[k] for k in range(d)])
+    return F
+
+
+def flux(u, q, P, xp):
+    Fi = flux_inviscid(u, P, xp)
+    Fv = flux_viscous(u, q, P, xp)
+    return [[Fi[c][k] + Fv[c][k] for k in range(P["d"])] for c in range(P["d"] + 2)]
+
+
+def heating(x, t, P, xp):
+    """prescribed Chapman-shaped EUV heating rate Q(x, t) (nondimensional, W/m^3 over
+    rho0 c_vO T0 a0/H0): Q = amp qm exp(1 - z - e^{-z}/cos chi) on the day side,
+    z = (|r| - rm)/H, zero where cos chi <= 0; 1D columns take cos chi = 1.
+    The solar zenith angle follows section 2.2: cos chi = r_hat . s_hat(t), the
+    sub-solar point moving in longitude at the nondimensional rotation rate."""
+    d = P["d"]
+    r = xp.sqrt(sum(x[k] * x[k] for k in range(d)))
+    if d == 3:
+        lon = P["sun_lon0"] - P["sun_rate"] * t
+        lat = P["sun_lat"]
+        sh = [xp.cos(lat) * xp.cos(lon), xp.cos(lat) * xp.sin(lon), xp.sin(lat)]
+        cchi = sum(x[k] * sh[k] for k in range(3)) / r
+    else:
+        cchi = 1.0 + 0.0 * r
+    z = (r - P["heat_rm"]) / P["heat_H"]
+    if xp is np:
+        cchi = np.asarray(cchi, dtype=np.float64)
+        day = cchi > 0
+        safe = np.where(day, cchi, 1.0)
+        Q = P["heat_amp"] * P["heat_qm"] * np.exp(1.0 - z - np.exp(-z) / safe)
+        return np.where(day, Q, 0.0)
+    return P["heat_amp"] * P["heat_qm"] * xp.exp(1 - z - xp.exp(-z) / cchi)
+
+
+def acceleration_times_sqrt_rho(u, x, P, xp):
+    """sqrt(rho) a with a = g/gamma - Fr^2/gamma w x (w x r) - 2 Fr/sqrt(gamma) w x v,
+    g = -(r_ref/|r|)^2 r_hat (gravity normalised at the lower boundary)."""
+    d = P["d"]
+    g = P["gamma"]
+    lr, U, Th, rho, s, v, T = primitives(u, P, xp)
+    sq = xp.exp(0.5 * lr)
+    r2 = sum(x[k] * x[k] for k in range(d))
+    r3 = r2 * xp.sqrt(r2)
+    out = [sq * (-(P["r_ref"] ** 2) * x[k] / r3) / g for k in range(d)]
+    if d == 3:
+        w = P["omega"]
+        wr = sum(w[k] * x[k] for k in range(3))
+        ww = sum(w[k] * w[k] for k in range(3))
+        wwr = [w[k] * wr - ww * x[k] for k in range(3)]             # w x (w x r)
+        wU = [w[1] * U[2] - w[2] * U[1], w[2] * U[0] - w[0] * U[2], w[0] * U[1] - w[1] * U[0]]
+        Fr = P["Fr"]
+        for k in range(3):
+            out[k] = out[k] - sq * (Fr ** 2 / g) * wwr[k] - (2.0 * Fr / xp.sqrt(g)) * wU[k]
+    return out
+
+
+def source(u, q, x, t, P, xp):
+    d = P["d"]
+    g = P["gamma"]
+    C = _consts(P, xp)
+    m = P["m"]
+    lr, U, Th, rho, s, v, T = primitives(u, P, xp)
+    mu, kap = transport(rho, T, P, xp)
+    gl, gv, gT = gradients(u, q, P, xp)
+    eps, div = strain(gv, d)
+    S = [(lr - 1.0) * div]
+    acc = acceleration_times_sqrt_rho(u, x, P, xp)
+    for i in range(d):
+        eg = sum(eps[i][k] * gl[k] for k in range(d))
+        S.append(acc[i] + 0.5 * div * U[i] - 0.5 * C["inv_gm"] * Th * gl[i]
+                 + 0.5 * C["c_visc"] * mu * s * eg)
+    Q = heating(x, t, P, xp)
+    Tg = sum(gT[k] * gl[k] for k in range(d))
+    ed = sum(eps[i][k] * gv[i][k] for i in range(d) for k in range(d))
+    S.append(Q * s * m + (1.5 - g) * Th * div + 0.5 * C["c_cond"] * kap * s * m * Tg
+             + C["c_diss"] * mu * s * m * ed)
+    return S
+
+
+def sigma(uhat, P, xp):
+    """stabilisation of eq. (LDG2): sigma_c = lambda_max I plus the diffusive block
+    diag(0, mu/(sqrt(rho) sqrt(gamma Gr)) I_d, kappa/(Pr sqrt(rho) c_v) sqrt(gamma/Gr)),
+    evaluated at the numerical trace."""
+    d = P["d"]
+    C = _consts(P, xp)
+    lr, U, Th, rho, s, v, T = primitives(uhat, P, xp)
+    mu, kap = transport(rho, T, P, xp)
+    lam = P["lam"]
+    sig = [lam + 0.0 * lr]
+    for i in range(d):
+        sig.append(lam + C["c_visc"] * mu * s)
+    sig.append(lam + C["c_cond"] * kap * s * P["m"])
+    return sig
+
+
+def bottom_state(u, P, xp):
+    """lower boundary (section 2.3): no slip, isothermal T = T_bot, log-density from the interior"""
+    d = P["d"]
+    lr = u[0]
+    return [lr] + [0.0 * lr for _ in range(d)] + [P["T_bot"] * xp.exp(0.5 * lr)]

@@ -1,0 +1,117 @@
+"""Implicit time stepping: DIRK stages solved by Newton (eq. NewtonSolve).
+
+DIRK(3,3) and DIRK(2,2) are Alexander's L-stable, stiffly accurate singly-diagonal
+schemes (cited in section 3.1; the tableaux are not printed in the paper and are
+restated here from their defining order conditions):
+  DIRK(2,2): g = 1 - 1/sqrt(2); A = [[g, 0], [1-g, g]]; c = (g, 1)
+  DIRK(3,3): g the root in (1/6, 1/2) of g^3 - 3 g^2 + 3/2 g - 1/6 = 0;
+             c = (g, (1+g)/2, 1); a21 = (1-g)/2;
+             b1 = -(6g^2 - 16g + 1)/4, b2 = (6g^2 - 20g + 5)/4, b3 = g.
+Stage i solves G_i(U) = U - dt a_ii R(U, t + c_i dt) - b_i = 0 with
+b_i = u_n + dt sum_{j<i} a_ij R(U_j, t + c_j dt); u_{n+1} = U_last.
+
+The exact stage solution used for parity is a dense Newton (numpy LU on the
+complex-step Jacobian) iterated to a residual of 1e-13 relative to |G(u_n)|.
+"""
+import numpy as np
+
+from . import dg, jac
+
+
+def dirk_tableau(scheme):
+    if scheme == 22:
+        g = 1.0 - 1.0 / np.sqrt(2.0)
+        A = np.array([[g, 0.0], [1.0 - g, g]])
+        return A, A[-1].copy(), np.array([g, 1.0])
+    if scheme == 33:
+        roots = np.roots([1.0, -3.0, 1.5, -1.0 / 6.0])
+        g = float(np.real([r for r in roots if abs(r.imag) < 1e-12 and 1 / 6 < r.real < 0.5][0]))
+        a21 = 0.5 * (1.0 - g)
+        b1 = -(6 * g * g - 16 * g + 1) / 4.0
+        b2 = (6 * g * g - 20 * g + 5) / 4.0
+        A = np.array([[g, 0, 0], [a21, g, 0], [b1, b2, g]])
+        return A, A[-1].copy(), np.array([g, 0.5 * (1 + g), 1.0])
+    raise ValueError(scheme)
+
+
+def newton_dense(Gfun, Jfun, U0, ref_norm, rtol=1e-13, maxit=30):
+    U = U0.copy()
+    hist = []
+    for it in range(maxit):
+        G = Gfun(U)
+        nG = np.linalg.norm(G)
+        hist.append(nG)
+        if nG <= rtol * ref_norm:
+            return U, it, hist
+        Jm = Jfun(U)
+        U = U - np.linalg.solve(Jm, G.ravel()).reshape(U.shape)
+    raise RuntimeError("dense Newton did not converge: %s" % hist[-5:])
+
+
+def implicit_step_dense(mesh, P, u, t, dt, scheme=33, rtol=1e-13, guesses=None):
+    """one DIRK step with every stage solved by dense Newton. Returns (u_new, stages)."""
+    A, b, c = dirk_tableau(scheme)
+    s = len(c)
+    Rs, Us = [], []
+    for i in range(s):
+        ti = t + c[i] * dt
+        bi = u + dt * sum(A[i, j] * Rs[j] for j in range(i))
+        aii = A[i, i]
+        G = lambda U: U - dt * aii * dg.residual(mesh, P, U, ti) - bi
+        Jf = lambda U: np.eye(U.size) - dt * aii * jac.dense_jacobian(mesh, P, U, ti)
+        ref = np.linalg.norm(G(u))
+        U0 = u if guesses is None else guesses[i]
+        Ui, _, _ = newton_dense(G, Jf, U0, ref, rtol)
+        Us.append(Ui)
+        Rs.append(dg.residual(mesh, P, Ui, ti))
+    return Us[-1], Us
+
+
+def gmres(Aop, rhs, x0=None, m=30, rtol=1e-10, max_restarts=50, M=None):
+    """right-preconditioned restarted GMRES(m) with classical Gram-Schmidt applied
+    twice (CGS2) and Givens rotations. Aop, M: callables on flat vectors."""
+    n = rhs.size
+    x = np.zeros(n) if x0 is None else x0.copy()
+    Mf = (lambda z: z) if M is None else M
+    bnorm = np.linalg.norm(rhs)
+    total = 0
+    for _ in range(max_restarts):
+        r = rhs - Aop(x)
+        beta = np.linalg.norm(r)
+        if beta <= rtol * bnorm:
+            return x, total
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        V[0] = r / beta
+        g = np.zeros(m + 1)
+        g[0] = beta
+        cs, sn = np.zeros(m), np.zeros(m)
+        k_used = 0
+        for j in range(m):
+            w = Aop(Mf(V[j]))
+            h = V[: j + 1] @ w
+            w = w - V[: j + 1].T @ h
+            h2 = V[: j + 1] @ w
+            w = w - V[: j + 1].T @ h2
+            h = h + h2
+            H[: j + 1, j] = h
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t0 = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t0
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            total += 1
+            k_used = j + 1
+            if abs(g[j + 1]) <= rtol * bnorm:
+                break
+        y = np.linalg.solve(np.triu(H[:k_used, :k_used]), g[:k_used])
+        x = x + Mf(V[:k_used].T @ y)
+    return x, total

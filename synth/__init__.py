@@ -1,0 +1,321 @@
+"""Seeded synthetic workloads for the thermosphere DG solver.
+
+This module is shared by the tests, the benchmark and the smoke run. It holds
+the *inputs* only: physical constants and reference scales (paper section 2.5),
+the random draws of each workload, the Bates temperature profile with its
+hydrostatic log-density (the stand-in for the MSIS initial state of section 2.3),
+seeded smooth perturbations and tangent vectors. It performs none of the DG
+arithmetic (no basis, no mesh, no flux, no residual): states are produced as
+callables of node coordinates, and each side evaluates them at its own nodes.
+
+Everything is nondimensional in the scalings of section 2.5: lengths by H0,
+speeds by a0, time by H0/a0, density by rho0, temperature by T0 = T(100 km).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# physical constants (SI)
+KB = 1.380649e-23           # Boltzmann constant
+AMU = 1.66053906660e-27     # atomic mass unit
+M_O = 16.0 * AMU            # atomic oxygen, the reference molecular mass
+R_EARTH = 6.371e6
+GM = 3.986004418e14
+OMEGA0 = 7.2921159e-5       # Earth rotation rate
+GAMMA = 5.0 / 3.0
+Z_BOT = 100e3
+Z_TOP = 600e3
+T_REF = 200.0               # T0: temperature at the lower boundary
+RHO_REF = 5.0e-7            # rho0: order of magnitude at 100 km (assumed)
+MU_REF = 4.03e-5            # mu0: molecular viscosity at T0 (reading of the viscosity law)
+ALPHA_O = 5.6e-4            # conductivity coefficient of atomic oxygen
+Q_COLUMN = 1.223e-3         # W/m^2, column EUV heating (0.25 x 4.89 mW/m^2 at F10.7 = 150)
+
+R0_SI = R_EARTH + Z_BOT
+G0 = GM / R0_SI ** 2
+H0 = KB * T_REF / (M_O * G0)
+A0 = math.sqrt(GAMMA * KB * T_REF / M_O)
+T_UNIT = H0 / A0
+KAPPA_REF = ALPHA_O * T_REF ** 0.69
+CP_O = GAMMA / (GAMMA - 1.0) * KB / M_O
+CV_O = CP_O / GAMMA
+GR = G0 * H0 ** 3 / (MU_REF / RHO_REF) ** 2
+PR = MU_REF * CP_O / KAPPA_REF
+FR = math.sqrt(OMEGA0 ** 2 * H0 / G0)
+Q_UNIT = RHO_REF * CV_O * T_REF * A0 / H0   # W/m^3 per unit nondimensional heating
+
+R_BOT = R0_SI / H0
+R_TOP = (R_EARTH + Z_TOP) / H0
+
+
+def seconds_to_nondim(dt_s: float) -> float:
+    return dt_s / T_UNIT
+
+
+def z_km(r):
+    """altitude in km from nondimensional radius"""
+    return np.asarray(r) * H0 / 1e3 - R_EARTH / 1e3
+
+
+# --------------------------------------------------------------------------
+# physics parameter set: plain numbers consumed by both the oracle and the library
+def base_physics(d: int) -> dict:
+    return dict(
+        d=d, gamma=GAMMA, Gr=GR, Pr=PR, Fr=FR, m=1.0,
+        nu_r=200.0, alpha_r=10.0, alpha0c=1.0,
+        lam=1.0, T_bot=1.0, r_ref=R_BOT,
+        omega=[0.0, 0.0, 1.0] if d == 3 else [0.0, 0.0, 0.0],
+        heat_amp=0.0, heat_qm=0.0, heat_rm=R_BOT, heat_H=1.0,
+        sun_lat=0.0, sun_lon0=0.0, sun_rate=FR / math.sqrt(GAMMA),
+        bc_mode=0, bc_state=[0.0] * 5,
+    )
+
+
+# --------------------------------------------------------------------------
+# Bates temperature profile and its hydrostatic log-density
+def bates_T(r, T_inf):
+    """nondimensional temperature T/T0 of the Bates profile at nondim radius r"""
+    z = z_km(r)
+    T = T_inf - (T_inf - T_REF) * np.exp(-0.02 * (z - Z_BOT / 1e3))
+    return T / T_REF
+
+
+_GL_X, _GL_W = np.polynomial.legendre.leggauss(24)
+
+
+def hydrostatic_logrho(r, T_inf, r_ref=R_BOT):
+    """log(rho/rho0) of the hydrostatic rest state with temperature bates_T and
+    gravity g = -(r_ref/r)^2 (m = 1):  d(rho T)/dr = -rho (r_ref/r)^2, rho(r_ref) = 1.
+    Integrated with composite 24-point Gauss-Legendre between sorted radii."""
+    r = np.asarray(r, dtype=np.float64)
+    flat = r.ravel()
+    uniq, inv = np.unique(flat, return_inverse=True)
+    pts = np.concatenate([[r_ref], uniq])
+    a, b = pts[:-1], pts[1:]
+    # subdivide each gap so that no panel is longer than 0.5 (in H0 units)
+    integ = np.zeros(len(uniq))
+    nsub = np.maximum(1, np.ceil(np.abs(b - a) / 0.5).astype(int))
+    for i in range(len(uniq)):
+        edges = np.linspace(a[i], b[i], nsub[i] + 1)
+        lo, hi = edges[:-1, None], edges[1:, None]
+        x = 0.5 * (hi + lo) + 0.5 * (hi - lo) * _GL_X[None, :]
+        f = (r_ref / x) ** 2 / bates_T(x, T_inf)
+        integ[i] = np.sum(0.5 * (hi - lo)[:, 0] * (f @ _GL_W))
+    cum = np.cumsum(integ)
+    lr = -np.log(bates_T(uniq, T_inf)) - cum
+    return lr[inv].reshape(r.shape)
+
+
+def chapman_params(T_inf, z_peak_km, amp):
+    """heating peak radius, width (local scale height at the peak) and peak rate
+    so that the column integral e*qm*H equals Q_COLUMN (nondimensional)."""
+    r_m = (R_EARTH + z_peak_km * 1e3) / H0
+    g_m = (R_BOT / r_m) ** 2
+    H_q = float(bates_T(r_m, T_inf)) / g_m
+    q_m_si = Q_COLUMN / (math.e * H_q * H0)
+    return dict(heat_amp=float(amp), heat_qm=q_m_si / Q_UNIT, heat_rm=r_m, heat_H=H_q)
+
+
+def sound_speed_max(T_inf):
+    """max over the rest state of |v| + sqrt(T/m): the top of the Bates profile"""
+    return float(math.sqrt(np.max(bates_T(np.array([R_BOT, R_TOP]), T_inf))))
+
+
+# --------------------------------------------------------------------------
+# state generators (callables of node coordinates)
+def column_state(r, T_inf):
+    """(logrho, sqrt(rho) v_r, sqrt(rho) T) of the hydrostatic rest column"""
+    lr = hydrostatic_logrho(r, T_inf)
+    T = bates_T(r, T_inf)
+    return np.stack([lr, np.zeros_like(lr), np.exp(0.5 * lr) * T])
+
+
+def _real_sph_harm(l, m, theta, phi):
+    """real orthonormal spherical harmonic; theta = colatitude"""
+    from scipy.special import lpmv
+    am = abs(m)
+    norm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
+    P = lpmv(am, l, np.cos(theta)) * (-1) ** am   # remove Condon-Shortley phase
+    if m == 0:
+        return norm * P
+    if m > 0:
+        return math.sqrt(2) * norm * P * np.cos(am * phi)
+    return math.sqrt(2) * norm * P * np.sin(am * phi)
+
+
+@dataclass
+class ShellPerturbation:
+    coef: np.ndarray          # [5, 80]
+    amp: float = 1e-3
+    lmax: int = 8
+
+    def __call__(self, xyz):
+        x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+        r = np.sqrt(x * x + y * y + z * z)
+        theta = np.arccos(np.clip(z / r, -1, 1))
+        phi = np.arctan2(y, x)
+        Y = []
+        for l in range(1, self.lmax + 1):
+            for m in range(-l, l + 1):
+                Y.append(_real_sph_harm(l, m, theta, phi))
+        Y = np.stack(Y, axis=-1)                  # [..., 80]
+        radial = np.sin(math.pi * (r - R_BOT) / (R_TOP - R_BOT))
+        return self.amp * np.einsum("...j,kj->k...", Y, self.coef) * radial
+
+
+def shell_state_fn(T_inf, pert: ShellPerturbation | None):
+    """hydrostatic Bates rest state on the shell plus smooth perturbations:
+    logrho += d1, T *= (1 + d2), v += (d3, d4, d5) (so U = sqrt(rho) v)."""
+    def fn(xyz):
+        xyz = np.asarray(xyz, dtype=np.float64)
+        r = np.linalg.norm(xyz, axis=-1)
+        lr = hydrostatic_logrho(r, T_inf)
+        T = bates_T(r, T_inf)
+        v = np.zeros(xyz.shape[:-1] + (3,))
+        if pert is not None:
+            dd = pert(xyz)
+            lr = lr + dd[0]
+            T = T * (1.0 + dd[1])
+            v = np.moveaxis(dd[2:5], 0, -1)
+        sq = np.exp(0.5 * lr)
+        U = sq[..., None] * v
+        return np.stack([lr, U[..., 0], U[..., 1], U[..., 2], sq * T])
+    return fn
+
+
+# --------------------------------------------------------------------------
+# workloads
+@dataclass
+class ColumnWorkload:
+    name: str
+    nelem: np.ndarray          # [n_col] elements per column
+    p: np.ndarray              # [n_col] degree per column
+    T_inf: np.ndarray          # [n_col]
+    phys: dict                 # shared physics
+    col_phys: dict             # per-column arrays: heat_amp, heat_qm, heat_rm, heat_H, lam
+    stretch: float = 1.0
+    r_bot: float = R_BOT
+    r_top: float = R_TOP
+    dt: float = seconds_to_nondim(10.0)
+    n_steps: int = 200
+
+    def state(self, col, r):
+        return column_state(r, self.T_inf[col])
+
+
+@dataclass
+class ShellWorkload:
+    name: str
+    p: int
+    n_ang: int
+    n_rad: int
+    stretch: float
+    T_inf: float
+    phys: dict
+    pert: ShellPerturbation | None
+    r_bot: float = R_BOT
+    r_top: float = R_TOP
+    dt: float = seconds_to_nondim(60.0)
+    n_steps: int = 5
+    extra: dict = field(default_factory=dict)
+
+    def state_fn(self):
+        return shell_state_fn(self.T_inf, self.pert)
+
+    @property
+    def n_elem(self):
+        return 6 * self.n_ang * self.n_ang * self.n_rad
+
+    @property
+    def n_dof(self):
+        return self.n_elem * (self.p + 1) ** 3 * 5
+
+
+def _column_phys(T_inf, z_pk, amp):
+    c = chapman_params(T_inf, z_pk, amp)
+    c["lam"] = sound_speed_max(T_inf)
+    return c
+
+
+def column_workload(seed=0, n_elem=64, p=2, n_col=1, stretch=1.0, name="column") -> ColumnWorkload:
+    """A column (or several identical-shape columns) of the 1D radial model,
+    100-600 km: T_inf ~ U(700, 1300) K, heating peak z_m ~ U(150, 250) km."""
+    rng = np.random.default_rng(seed)
+    T_inf = rng.uniform(700.0, 1300.0, n_col)
+    z_pk = rng.uniform(150.0, 250.0, n_col)
+    amp = np.ones(n_col)
+    return _columns(name, np.full(n_col, n_elem), np.full(n_col, p), T_inf, z_pk, amp, stretch)
+
+
+def column_batch_workload(seed=0, n_col=4096, name="column-batch") -> ColumnWorkload:
+    """The parametric sweep: n_col columns, elements ~ U{32..256}, p ~ U{2,3,4},
+    T_inf ~ U(600, 1500) K, heating multiplier ~ U(0.5, 3), z_m ~ U(150, 250) km."""
+    rng = np.random.default_rng(seed)
+    nelem = rng.integers(32, 257, n_col)
+    p = rng.integers(2, 5, n_col)
+    T_inf = rng.uniform(600.0, 1500.0, n_col)
+    amp = rng.uniform(0.5, 3.0, n_col)
+    z_pk = rng.uniform(150.0, 250.0, n_col)
+    w = _columns(name, nelem, p, T_inf, z_pk, amp, 1.0)
+    w.n_steps = 100
+    return w
+
+
+def _columns(name, nelem, p, T_inf, z_pk, amp, stretch):
+    cp = [_column_phys(T_inf[i], z_pk[i], amp[i]) for i in range(len(nelem))]
+    col_phys = {k: np.array([c[k] for c in cp]) for k in cp[0]}
+    phys = base_physics(1)
+    for k in col_phys:
+        phys[k] = float(col_phys[k][0])
+    return ColumnWorkload(name=name, nelem=np.asarray(nelem, np.int32), p=np.asarray(p, np.int32),
+                          T_inf=np.asarray(T_inf, np.float64), phys=phys, col_phys=col_phys,
+                          stretch=stretch)
+
+
+def shell_workload(seed=0, p=3, n_ang=16, n_rad=16, stretch=1.15, name="shell",
+                   perturb=True, heating=True, rotation=True) -> ShellWorkload:
+    """3D shell 100-600 km: Bates hydrostatic state (T_inf ~ U(700, 1300) K) plus
+    spherical-harmonic perturbations up to l = 8 of amplitude 1e-3, rotation about z,
+    day-side Chapman heating with the sub-solar point at (0, 0) at t = 0."""
+    rng = np.random.default_rng(seed)
+    T_inf = float(rng.uniform(700.0, 1300.0))
+    z_pk = float(rng.uniform(150.0, 250.0))
+    coef = rng.standard_normal((5, 80)) / math.sqrt(80.0)
+    phys = base_physics(3)
+    phys.update(chapman_params(T_inf, z_pk, 1.0 if heating else 0.0))
+    phys["lam"] = sound_speed_max(T_inf) + (0.01 if perturb else 0.0)
+    if not rotation:
+        phys["omega"] = [0.0, 0.0, 0.0]
+    pert = ShellPerturbation(coef) if perturb else None
+    return ShellWorkload(name=name, p=p, n_ang=n_ang, n_rad=n_rad, stretch=stretch,
+                         T_inf=T_inf, phys=phys, pert=pert)
+
+
+def config_column(seed=0):
+    """1D column, 64 uniform elements, p = 2, 200 DIRK(3,3) steps of 10 s"""
+    return column_workload(seed=seed, n_elem=64, p=2, name="column-64e-p2")
+
+
+def config_shell_p3(seed=0):
+    """cubed sphere 6x16x16 x 16 layers, stretch 1.15, p = 3 (7,864,320 DOF)"""
+    return shell_workload(seed=seed, p=3, n_ang=16, n_rad=16, stretch=1.15, name="shell-6x16x16x16-p3")
+
+
+def config_shell_p4(seed=0):
+    """cubed sphere 6x32x32 x 24 layers, stretch 1.15, p = 4 (92,160,000 DOF)"""
+    return shell_workload(seed=seed, p=4, n_ang=32, n_rad=24, stretch=1.15, name="shell-6x32x32x24-p4")
+
+
+def tangent(shape, seed=1):
+    """unit-norm Gaussian tangent vector"""
+    v = np.random.default_rng(seed).standard_normal(shape)
+    return v / np.linalg.norm(v)
+
+
+def uniform_state(d, rho_log=-0.3, U=(0.05, -0.02, 0.03), Theta=1.1):
+    """a constant state (free-stream tests)"""
+    return np.array([rho_log, *U[:d], Theta])

@@ -1,0 +1,309 @@
+"""Pins of the oracle's DG residual against what the method and the mathematics fix:
+free-stream preservation, discrete conservation, mesh geometry, rotation symmetry of
+the cubed sphere, hydrostatic balance, design order of accuracy on a manufactured
+solution, the Chapman column integral, and J(u)v."""
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+from scipy.integrate import quad
+
+import synth
+from oracle import dg, jac
+from oracle import mesh as M
+from oracle import physics as ph
+
+
+def _free_params(d):
+    P = synth.base_physics(d)
+    us = synth.uniform_state(d)
+    P.update(r_ref=0.0, heat_amp=0.0, bc_mode=1, bc_state=list(us), omega=[0.0, 0.0, 0.0])
+    return P, us
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_free_stream_column(p):
+    P, us = _free_params(1)
+    m = M.columns_mesh([5, 3], p, synth.R_BOT, synth.R_TOP, 1.15)
+    u = np.broadcast_to(us[None, :, None], (m.E, 3, m.ref.N)).copy()
+    assert np.max(np.abs(dg.residual(m, P, u))) < 1e-13
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_free_stream_shell(p):
+    """a uniform state (with a uniform velocity) is preserved to round-off on curved
+    cube-sphere elements: the curl-form metric terms satisfy the metric identities"""
+    P, us = _free_params(3)
+    m = M.shell_mesh(p, 2, 2, synth.R_BOT, synth.R_TOP, 1.15)
+    u = np.broadcast_to(us[None, :, None], (m.E, 5, m.ref.N)).copy()
+    R = dg.residual(m, P, u)
+    assert np.max(np.abs(R)) < 1e-13
+    # the discrete metric identities themselves
+    for n in range(3):
+        ident = sum(np.einsum("ij,ej->ei", m.ref.Dr[a], m.Ja[:, :, a, n]) for a in range(3))
+        assert np.max(np.abs(ident)) < 1e-9 * np.max(np.abs(m.Ja))
+
+
+def test_cross_product_metrics_break_free_stream():
+    """control: the pointwise cross-product metric terms do not satisfy the identities
+    on these curved elements, so the curl form above is what makes the test pass"""
+    P, us = _free_params(3)
+    m = M.shell_mesh(3, 2, 1, synth.R_BOT, synth.R_TOP, 1.0)
+    for e in range(m.E):
+        dX = [m.ref.Dr[a] @ m.X[e] for a in range(3)]
+        m.Ja[e, :, 0, :] = np.cross(dX[1], dX[2])
+        m.Ja[e, :, 1, :] = np.cross(dX[2], dX[0])
+        m.Ja[e, :, 2, :] = np.cross(dX[0], dX[1])
+    u = np.broadcast_to(us[None, :, None], (m.E, 5, m.ref.N)).copy()
+    assert np.max(np.abs(dg.residual(m, P, u))) > 1e-10
+
+
+def test_shell_geometry_converges():
+    """GLL-integrated shell volume and lower-sphere area approach the exact
+    4/3 pi (R_top^3 - R_bot^3) and 4 pi R_bot^2 at high order under refinement"""
+    vol_exact = 4 * math.pi / 3 * (synth.R_TOP ** 3 - synth.R_BOT ** 3)
+    area_exact = 4 * math.pi * synth.R_BOT ** 2
+    errs = []
+    for n_ang in (1, 2, 4):
+        m = M.shell_mesh(3, n_ang, 1, synth.R_BOT, synth.R_TOP, 1.0)
+        assert np.all(m.J > 0)
+        vol = np.sum(m.ref.W[None, :] * m.J)
+        a_, side, nodes, wf = m.ref.faces[4]           # xi_3 = -1: the lower sphere
+        assert (a_, side) == (2, -1)
+        area = np.sum(wf[None, :] * np.linalg.norm(m.Ja[:, nodes, 2, :], axis=-1))
+        errs.append((abs(vol / vol_exact - 1), abs(area / area_exact - 1)))
+    errs = np.array(errs)
+    assert np.all(errs[1:] < errs[:-1] / 10.0), errs
+    assert errs[-1, 0] < 1e-6 and errs[-1, 1] < 1e-5
+
+
+def test_element_count_and_dof_convention():
+    """section 3.3 and the convergence table of section 4.1.1: 6 x 36 x 36 x 28 =
+    217,728 hexes and n_dof = n_elem (k+1)^3 x 5 for k = 1, 2, 3"""
+    from oracle.gll import RefElement
+    gold = {}
+    with open(__file__.replace("test_oracle_dg.py", "golden/dof_counts.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                gold[k] = float(v)
+    E = 6 * 36 * 36 * 28
+    assert E == gold["n_elem_default"]
+    assert 6 * 72 * 72 * 28 == gold["n_elem_refined"]
+    for k in (1, 2, 3):
+        # printed in millions with two decimals
+        assert abs(E * RefElement(k, 3).N * 5 / 1e6 - gold["n_dof_k%d_millions" % k]) < 0.005
+
+
+def _conservation(m, P, u):
+    lhs, rhs, mag = dg.conservation_terms(m, P, u)
+    return np.max(np.abs(lhs - rhs) / mag)
+
+
+def test_conservation_column():
+    w = synth.config_column(0)
+    m = M.columns_mesh([12], 3, w.r_bot, w.r_top, 1.1)
+    u = np.moveaxis(w.state(0, m.X[:, :, 0]), 0, 1)
+    u = u + 1e-2 * np.random.default_rng(3).standard_normal(u.shape)
+    assert _conservation(m, w.phys, u) < 1e-13
+
+
+@pytest.mark.parametrize("bc_mode", [0, 1])
+def test_conservation_shell(bc_mode):
+    w = synth.shell_workload(0, p=2, n_ang=2, n_rad=2)
+    m = M.shell_mesh(2, 2, 2, w.r_bot, w.r_top, 1.15)
+    u = np.moveaxis(w.state_fn()(m.X), 0, 1)
+    u = u + 1e-3 * np.random.default_rng(4).standard_normal(u.shape)
+    P = dict(w.phys)
+    P["bc_mode"] = bc_mode
+    P["bc_state"] = list(synth.uniform_state(3))
+    assert _conservation(m, P, u) < 1e-13
+
+
+def _rotation_perm(X):
+    """flat node permutation pi with X[pi[i]] = Rz(90) X[i]: elements are matched by
+    centroid first (face nodes exist once per element), then nodes inside them"""
+    from scipy.spatial import cKDTree
+    E, N, _ = X.shape
+    Rz = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    cent = X.mean(axis=1)
+    dist, emap = cKDTree(cent).query(cent @ Rz.T)
+    assert np.max(dist) < 1e-9 * np.max(np.abs(X))
+    perm = np.zeros(E * N, dtype=np.int64)
+    for e in range(E):
+        d2, loc = cKDTree(X[emap[e]]).query(X[e] @ Rz.T)
+        assert np.max(d2) < 1e-9 * np.max(np.abs(X))
+        perm[e * N:(e + 1) * N] = emap[e] * N + loc
+    assert len(np.unique(perm)) == E * N
+    return perm, Rz
+
+
+def test_rotation_symmetry_shell():
+    """a 90 degree rotation about the rotation axis maps the cube-sphere onto itself:
+    R(rot u) = rot R(u) with the sun rotated along. This pins the face matching and
+    the orientation of the metric terms across panel edges."""
+    w = synth.shell_workload(1, p=2, n_ang=2, n_rad=2)
+    m = M.shell_mesh(2, 2, 2, w.r_bot, w.r_top, 1.15)
+    P = dict(w.phys)
+    P["sun_lat"] = 0.3
+    u = np.moveaxis(w.state_fn()(m.X), 0, 1)
+    u += 1e-3 * np.random.default_rng(5).standard_normal(u.shape)
+    perm, Rz = _rotation_perm(m.X)
+    E, f, N = u.shape
+
+    def rotate(a):
+        flat = np.moveaxis(a, 1, 0).reshape(f, -1).copy()
+        out = np.empty_like(flat)
+        out[:, perm] = flat
+        out[1:4, perm] = Rz @ flat[1:4]
+        return np.moveaxis(out.reshape(f, E, N), 0, 1)
+
+    t = 0.7
+    R1 = dg.residual(m, P, u, t)
+    P2 = dict(P)
+    P2["sun_lon0"] = P["sun_lon0"] + math.pi / 2
+    R2 = dg.residual(m, P2, rotate(u), t)
+    _, scale = dg.residual_parts(m, P, u, t)
+    assert np.max(np.abs(R2 - rotate(R1)) / np.max(rotate(scale))) < 1e-12
+
+
+def _isothermal_column(m, P):
+    """exact hydrostatic rest state for T = 1, m = 1: varrho = r_ref^2 (1/r - 1/r_ref)"""
+    r = m.X[:, :, 0]
+    lr = P["r_ref"] ** 2 * (1.0 / r - 1.0 / P["r_ref"])
+    return np.stack([lr, 0 * lr, np.exp(0.5 * lr)], axis=1)
+
+
+def test_hydrostatic_interpolant_converges():
+    """the interpolated exact hydrostatic state is steady only up to the truncation
+    residual of the operator; with second-derivative (conduction) terms that residual
+    falls like h^(p-1) (the solution error falls like h^(p+1), see the
+    manufactured-solution test)"""
+    P = synth.base_physics(1)
+    P["lam"] = 1.0
+    for p in (2, 3, 4):
+        errs = []
+        for E in (16, 32, 64):
+            m = M.columns_mesh([E], p, synth.R_BOT, synth.R_BOT + 20.0)
+            R = dg.residual(m, P, _isothermal_column(m, P))
+            errs.append(np.sqrt(np.sum((m.ref.W[None, :] * m.J)[:, None, :] * R ** 2)))
+        rate = np.log2(errs[-2] / errs[-1])
+        assert rate > p - 1 - 0.3, (p, errs)
+        assert np.all(np.diff(errs) < 0)
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_rest_state_with_physical_boundaries(d):
+    """without sources (no gravity, heating or rotation) an isothermal gas at rest
+    with T = T_bot is steady under the physical boundary conditions (no-slip
+    isothermal bottom, adiabatic stress-free top): R = 0 to round-off"""
+    P = synth.base_physics(d)
+    P.update(r_ref=0.0, heat_amp=0.0, omega=[0.0, 0.0, 0.0], bc_mode=0, T_bot=1.3)
+    lr = -0.7
+    us = np.array([lr] + [0.0] * d + [1.3 * np.exp(0.5 * lr)])
+    if d == 1:
+        m = M.columns_mesh([6], 3, synth.R_BOT, synth.R_TOP, 1.2)
+    else:
+        m = M.shell_mesh(2, 2, 2, synth.R_BOT, synth.R_TOP, 1.15)
+    u = np.broadcast_to(us[None, :, None], (m.E, d + 2, m.ref.N)).copy()
+    assert np.max(np.abs(dg.residual(m, P, u))) < 1e-13
+    # a non-isothermal profile is not steady: the test above is not vacuous
+    u2 = u.copy()
+    u2[:, d + 1] *= 1.0 + 0.01 * np.sin(np.linalg.norm(m.X, axis=-1))
+    assert np.max(np.abs(dg.residual(m, P, u2))) > 1e-6
+
+
+def _mms_params():
+    return dict(d=1, gamma=5 / 3, Gr=1e5, Pr=0.9, Fr=0.0, m=1.0, nu_r=1.0, alpha_r=0.5, alpha0c=1.0,
+                lam=2.5, T_bot=1.0, r_ref=1.0, omega=[0, 0, 0], heat_amp=1.0, heat_qm=0.1, heat_rm=1.5,
+                heat_H=0.2, sun_lat=0, sun_lon0=0, sun_rate=0, bc_mode=1, bc_state=[0] * 5)
+
+
+@pytest.mark.slow
+def test_manufactured_solution_order():
+    """steady manufactured solution with every term active (gravity, heating,
+    viscosity, conduction) and Dirichlet states: L2 error decreases like h^(p+1)"""
+    P = _mms_params()
+    x = sp.Symbol("x")
+    lr = 0.3 * sp.sin(2 * x) - 0.5
+    uex = [lr, 0.3 * sp.cos(3 * x) + 0.2, sp.exp(lr / 2) * (1 + 0.2 * sp.sin(x))]
+    q = [[sp.diff(c, x)] for c in uex]
+    F = ph.flux(uex, q, P, sp)
+    S = ph.source(uex, q, [x], 0.0, P, sp)
+    forcing = sp.lambdify(x, [sp.diff(F[c][0], x) - S[c] for c in range(3)], "numpy")
+    fu = sp.lambdify(x, uex, "numpy")
+    U = lambda xx: np.array([np.broadcast_to(v, np.shape(xx)) for v in fu(xx)])
+    P["bc_fn"] = lambda Xf: U(Xf[0])
+    for p in (2, 3, 4):
+        errs = []
+        for E in (8, 16, 32):
+            m = M.columns_mesh([E], p, 1.0, 2.0)
+            X = m.X[:, :, 0]
+            fh = np.moveaxis(np.array([np.broadcast_to(v, X.shape) for v in forcing(X)]), 0, 1)
+            ue = np.moveaxis(U(X), 0, 1)
+            u = ue.copy()
+            for _ in range(20):
+                G = dg.residual(m, P, u) + fh
+                if np.max(np.abs(G)) < 1e-11:
+                    break
+                u = u - np.linalg.solve(jac.dense_jacobian(m, P, u), G.ravel()).reshape(u.shape)
+            errs.append(np.sqrt(np.sum((m.ref.W[None, :] * m.J)[:, None, :] * (u - ue) ** 2)))
+        rate = math.log2(errs[-2] / errs[-1])
+        assert rate > p + 1 - 0.3, (p, errs)
+
+
+def test_chapman_column_integral():
+    """int Q dr over the column equals e qm H (section 2.2 profile, overhead sun)"""
+    P = synth.base_physics(1)
+    P.update(heat_amp=1.7, heat_qm=0.3, heat_rm=600.0, heat_H=4.0)
+    f = lambda r: float(ph.heating([np.array([r])], 0.0, P, np)[0])
+    val, _ = quad(f, 600.0 - 40 * 4.0, 600.0 + 200 * 4.0, limit=400, epsabs=0, epsrel=1e-13)
+    assert abs(val / (math.e * 1.7 * 0.3 * 4.0) - 1) < 1e-10
+    # night side is dark
+    P3 = synth.base_physics(3)
+    P3.update(heat_amp=1.0, heat_qm=1.0, heat_rm=600.0, heat_H=4.0, sun_lon0=0.0)
+    Q = ph.heating([np.array([-600.0]), np.array([0.0]), np.array([0.0])], 0.0, P3, np)
+    assert Q[0] == 0.0
+
+
+# ----------------------------------------------------------------- J(u) v
+def _small_column():
+    w = synth.config_column(0)
+    m = M.columns_mesh([4], 2, w.r_bot, w.r_top)
+    u = np.moveaxis(w.state(0, m.X[:, :, 0]), 0, 1)
+    u = u + 1e-3 * np.random.default_rng(7).standard_normal(u.shape)
+    return m, w.phys, u
+
+
+def test_jvp_complex_step_vs_finite_differences():
+    """Taylor test: the central difference error against the complex step falls like eps^2"""
+    m, P, u = _small_column()
+    v = synth.tangent(u.shape, 2)
+    jv = jac.jvp_complex(m, P, u, v)
+    errs = []
+    for eps in (1e-3, 5e-4, 2.5e-4, 1.25e-4):
+        fd = jac.jvp_fd(m, P, u, v, eps=eps, central=True)
+        errs.append(np.linalg.norm(fd - jv))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8), rates
+    # the paper's one-sided difference is first order
+    e1 = np.linalg.norm(jac.jvp_fd(m, P, u, v, eps=1e-4) - jv)
+    e2 = np.linalg.norm(jac.jvp_fd(m, P, u, v, eps=5e-5) - jv)
+    assert 1.7 < e1 / e2 < 2.3
+
+
+def test_dense_jacobian_brute_force():
+    """complex-step Jacobian vs one built column by column with central differences"""
+    m, P, u = _small_column()
+    Jc = jac.dense_jacobian(m, P, u)
+    n = u.size
+    Jf = np.zeros((n, n))
+    h = 1e-6
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = h
+        Jf[:, j] = (dg.residual(m, P, u + e.reshape(u.shape)) - dg.residual(m, P, u - e.reshape(u.shape))).ravel() / (2 * h)
+    assert np.max(np.abs(Jc - Jf)) < 1e-6 * np.max(np.abs(Jc))
+    v = synth.tangent(u.shape, 3)
+    assert np.allclose(Jc @ v.ravel(), jac.jvp_complex(m, P, u, v).ravel(), rtol=0, atol=1e-12 * np.max(np.abs(Jc)))

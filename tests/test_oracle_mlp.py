@@ -1,0 +1,71 @@
+"""Pins of the warm-start network oracle: bfloat16 rounding against torch's own
+conversion, the backward pass against finite differences, Adam against torch.optim."""
+import numpy as np
+import torch
+
+from oracle import mlp
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.0e38]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), ref)
+
+
+def _small_problem(seed=0):
+    rng = np.random.default_rng(seed)
+    params = mlp.init_params(rng, n_in=12, n_hidden=8, n_out=5)
+    params[4] = rng.standard_normal(params[4].shape) * 0.3     # non-zero last layer
+    params[1] = rng.standard_normal(8) * 0.1
+    x = rng.standard_normal((7, 12))
+    y = rng.standard_normal((7, 5))
+    return params, x, y
+
+
+def test_backward_matches_finite_differences():
+    params, x, y = _small_problem()
+    loss, grads = mlp.loss_and_grad(params, x, y)
+    # differentiate w.r.t. the bf16-rounded weights: perturb biases (fp64) exactly,
+    # and weights through a copy that bypasses the rounding by using exact bf16 steps
+    h = 1e-6
+    for k in (1, 3, 5):
+        p = params[k]
+        for idx in [(0,), (p.size - 1,)]:
+            pp = [q.copy() for q in params]
+            pm = [q.copy() for q in params]
+            pp[k][idx] += h
+            pm[k][idx] -= h
+            fd = (mlp.loss_and_grad(pp, x, y)[0] - mlp.loss_and_grad(pm, x, y)[0]) / (2 * h)
+            assert abs(fd - grads[k][idx]) < 1e-7 * (1 + abs(fd))
+    # weights: rounded weights are piecewise constant in the raw weight, so check the
+    # gradient against a torch autograd evaluation on the rounded values
+    tp = [torch.tensor(mlp.bf16_round(q) if i % 2 == 0 else q, requires_grad=True) for i, q in enumerate(params)]
+    xt = torch.tensor(mlp.bf16_round(x))
+    h1 = torch.relu(xt @ tp[0].T + tp[1])
+    h2 = torch.relu(h1 @ tp[2].T + tp[3])
+    out = h2 @ tp[4].T + tp[5]
+    lt = ((out - torch.tensor(y)) ** 2).mean()
+    lt.backward()
+    assert abs(lt.item() - loss) < 1e-12
+    for i in range(6):
+        assert np.allclose(tp[i].grad.numpy(), grads[i], rtol=1e-10, atol=1e-13)
+
+
+def test_adam_matches_torch():
+    params, x, y = _small_problem(1)
+    tp = [torch.tensor(q.copy(), requires_grad=True) for q in params]
+    opt = torch.optim.Adam(tp, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    m = [np.zeros_like(q) for q in params]
+    v = [np.zeros_like(q) for q in params]
+    p = [q.copy() for q in params]
+    rng = np.random.default_rng(5)
+    for step in range(1, 4):
+        grads = [rng.standard_normal(q.shape) for q in params]
+        p, m, v = mlp.adam_step(p, grads, m, v, step, 1e-2)
+        for t, g in zip(tp, grads):
+            t.grad = torch.tensor(g)
+        opt.step()
+    for a, t in zip(p, tp):
+        assert np.allclose(a, t.detach().numpy(), rtol=1e-12, atol=1e-14)
