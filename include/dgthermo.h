@@ -1,0 +1,173 @@
+/*
+ * dgthermo -- matrix-free high-order DG residual R(u), Jacobian-vector product
+ * J(u)v and implicit DIRK/Newton-GMRES steps of the physics-based thermosphere
+ * model of Vila-Perez, Nguyen and Peraire (arXiv 2306.01085), on AMD MI355X.
+ *
+ * C ABI. Every pointer argument is either a HOST pointer (descriptors, stats,
+ * per-column parameter arrays, node-coordinate outputs) or a DEVICE pointer
+ * (states u, residuals r, tangents v, products jv), as stated per argument.
+ * Device arrays are allocated by the caller (e.g. torch tensors on the GPU),
+ * must be 16-byte aligned, and must not alias each other unless stated.
+ * `stream` is a hipStream_t (NULL selects the default stream). Calls that only
+ * enqueue work return before it completes; dg_implicit_step and
+ * dg_columns_integrate synchronise the stream because they report stats.
+ *
+ * Errors: every function returns a dg_status_t; no C++ exception crosses the
+ * ABI. dg_last_error() returns a thread-local message describing the last
+ * failure of the calling thread. A mesh may be used by one stream at a time.
+ *
+ * Units: everything is nondimensional in the scalings of section 2.5 of the
+ * paper (lengths / H0, speeds / a0, time / (H0/a0), density / rho0, T / T0).
+ *
+ * State layout (section 2.4 variables, m = d + 2 fields per node:
+ * varrho = log(rho/rho0), sqrt(rho) v (d components), sqrt(rho) T):
+ *   shell  : u[e][c][j], e = ((panel*n_ang + j_ang)*n_ang + i_ang)*n_rad + k
+ *            (radial layer fastest), c = field, j = a + n*b + n*n*cz node of the
+ *            tensor-product GLL element (n = p+1; a along the panel's alpha
+ *            direction, b along beta, cz along the radius)
+ *   columns: columns concatenated, each column's elements bottom to top, each
+ *            element u[c][i] with i = 0..p (bottom to top); column offsets from
+ *            dg_mesh_col_offsets.
+ * DOF = nodes x fields (the paper's convention in its convergence table).
+ */
+#ifndef DGTHERMO_H
+#define DGTHERMO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_mesh_s* dg_mesh_t;
+
+typedef enum {
+  DG_OK = 0,
+  DG_ERR_ARG = 1,          /* invalid argument (null pointer, size mismatch, unsupported degree) */
+  DG_ERR_ALLOC = 2,        /* device or host allocation failed */
+  DG_ERR_HIP = 3,          /* a HIP runtime call failed; message in dg_last_error() */
+  DG_ERR_NOCONV = 4,       /* Newton did not reach the tolerance; the state is left unchanged */
+  DG_ERR_NAN = 5,          /* a non-finite norm was met; the state is left unchanged */
+  DG_ERR_UNSUPPORTED = 6   /* the requested precision / mode is not available */
+} dg_status_t;
+
+typedef enum { DG_F64 = 0, DG_F32 = 1, DG_BF16 = 2 } dg_prec_t;
+
+typedef enum { DG_MESH_COLUMNS = 0, DG_MESH_SHELL = 1 } dg_mesh_kind_t;
+
+/* Geometry (section 3.3): host memory, copied by dg_mesh_create. */
+typedef struct {
+  int32_t kind;            /* dg_mesh_kind_t */
+  int32_t p;               /* shell: polynomial degree per direction, 2..4 */
+  int32_t n_ang;           /* shell: elements per panel edge (6*n_ang^2 angular cells) */
+  int32_t n_rad;           /* shell: radial layers */
+  double r_bot, r_top;     /* radii of the lower and upper boundary (nondimensional) */
+  double stretch;          /* geometric growth ratio of the layer (element) thickness; 1 = uniform */
+  int32_t n_col;           /* columns: number of independent radial columns */
+  const int32_t* col_nelem;/* columns: host [n_col] elements per column (>= 1) */
+  const int32_t* col_p;    /* columns: host [n_col] degree per column, 2..4 */
+} dg_mesh_desc_t;
+
+/* Nondimensional physics (eq. fluxSWNondimensional, section 2.5). */
+typedef struct {
+  double gamma;            /* ratio of specific heats (5/3) */
+  double Gr, Pr, Fr;       /* Grasshoff, Prandtl, Froude numbers */
+  double m;                /* mean molecular mass / m_O (constant) */
+  double nu_r, alpha_r;    /* eddy viscosity and diffusivity ratios nu_eddy/nu0, alpha_eddy/alpha0 */
+  double alpha0c;          /* multiplier of the molecular conductivity */
+  double lam;              /* global Lax-Friedrichs speed lambda_max (eq. LDG2) */
+  double T_bot;            /* temperature imposed at the lower boundary */
+  double r_ref;            /* radius where |g| = 1: g = -(r_ref/|r|)^2 r_hat */
+  double omega[3];         /* rotation vector (shell only) */
+  double heat_amp, heat_qm, heat_rm, heat_H; /* Chapman heating amp*qm*exp(1-z-e^{-z}/cos chi), z=(r-rm)/H */
+  double sun_lat, sun_lon0, sun_rate;        /* sub-solar latitude, longitude at t = 0, longitude rate (shell) */
+  int32_t bc_mode;         /* 0: lower boundary no-slip isothermal, upper boundary adiabatic stress-free;
+                              1: every boundary is the constant Dirichlet state bc_state (test problems) */
+  double bc_state[5];
+  /* columns: optional host arrays [n_col] overriding the shared value per column, or NULL */
+  const double* col_heat_amp;
+  const double* col_heat_qm;
+  const double* col_heat_rm;
+  const double* col_heat_H;
+  const double* col_lam;
+} dg_physics_t;
+
+/* Create a mesh: builds GLL tables, the factored curved geometry (invariant curl
+ * form metric terms), the connectivity, and uploads them. `out` receives the
+ * handle, owned by the caller until dg_mesh_destroy. All later device work of the
+ * mesh goes to the stream passed to each call. */
+dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys, void* stream, dg_mesh_t* out);
+dg_status_t dg_mesh_destroy(dg_mesh_t mesh);
+/* Replace the physics parameters (host struct, copied). */
+dg_status_t dg_mesh_set_physics(dg_mesh_t mesh, const dg_physics_t* phys);
+
+/* Sizes: total DOF, elements, fields per node, dimension. Any output may be NULL. */
+dg_status_t dg_mesh_info(dg_mesh_t mesh, int64_t* n_dof, int64_t* n_elem, int32_t* n_fields, int32_t* dim);
+/* Node coordinates in DOF-node order: host output [n_nodes*dim] with n_nodes = n_dof/n_fields
+ * (shell: [e][j][3]; columns: radius of every node in storage order). */
+dg_status_t dg_mesh_nodes(dg_mesh_t mesh, double* xyz_host, int64_t n_values);
+/* Columns: DOF offset of every column, host output [n_col + 1]. */
+dg_status_t dg_mesh_col_offsets(dg_mesh_t mesh, int64_t* offsets_host, int64_t n);
+
+/* R(u) = du/dt of the semi-discrete LDG system eq. (DGformulation) with the
+ * traces and fluxes of eq. (LDG2), at time t. u: device [n_dof] double (input);
+ * r: device [n_dof] double (output, must not alias u). Enqueue only. */
+dg_status_t dg_residual(dg_mesh_t mesh, double t, const double* u, double* r, int64_t n_dof, void* stream);
+
+/* J(u) v, the exact directional derivative of R at u along v (section 3.2 uses a
+ * finite difference of R; dual-number arithmetic gives the same product without the
+ * step error). u: device double [n_dof]; v and jv: device arrays [n_dof] of the
+ * precision `prec` (DG_F64: double, DG_F32: float); jv must not alias v or u.
+ * The arithmetic runs in that precision. Enqueue only. */
+dg_status_t dg_jvp(dg_mesh_t mesh, double t, const double* u, const void* v, void* jv, int64_t n_dof,
+                   dg_prec_t prec, void* stream);
+
+/* ---- implicit time stepping (section 3.1 DIRK, section 3.2 Newton-GMRES) ---- */
+typedef struct {
+  int32_t scheme;          /* 33: DIRK(3,3); 22: DIRK(2,2) */
+  int32_t gmres_m;         /* Krylov dimension per restart (30) */
+  int32_t max_newton;      /* Newton iterations per stage */
+  int32_t max_restarts;    /* GMRES restarts per Newton iteration */
+  double newton_rtol;      /* stop when |G(U)| <= newton_rtol |G(u_n)| (1e-8) */
+  double gmres_rtol;       /* inexact Newton: relative GMRES tolerance (1e-3) */
+  int32_t jvp_prec;        /* dg_prec_t of J v inside GMRES */
+  int32_t precond;         /* 0: none, 1: block Jacobi */
+  int32_t guess;           /* 0: previous state (first step) / extrapolation, 1: learned warm start */
+} dg_solver_opts_t;
+
+typedef struct {
+  int32_t newton_its[3];   /* per stage */
+  int32_t gmres_its[3];    /* per stage, summed over Newton iterations */
+  int32_t fallback[3];     /* 1 if the learned guess was rejected for the plain one */
+  double res0[3];          /* |G(guess)| per stage */
+  double res[3];           /* final |G| per stage */
+  double ref[3];           /* |G(u_n)| per stage (the reference norm) */
+  double seconds;          /* wall time of the call */
+} dg_step_stats_t;
+
+/* One DIRK step u(t) -> u(t + dt) in place. u: device double [n_dof]. stats: host
+ * output (may be NULL). Synchronises `stream`. On DG_ERR_NOCONV or DG_ERR_NAN
+ * u is left unchanged. Workspace is allocated on the first call and kept by the
+ * mesh. */
+dg_status_t dg_implicit_step(dg_mesh_t mesh, double t, double dt, double* u, int64_t n_dof,
+                             const dg_solver_opts_t* opts, dg_step_stats_t* stats, void* stream);
+
+/* ---- event timing of the library's own launches (tracing subsystem) ----
+ * When enabled, every launch group is bracketed by hipEvents on the stream it runs on.
+ * dg_profile_read synchronises those events and returns, per slot, the accumulated
+ * milliseconds and launch counts (host arrays of n entries; reset != 0 clears them).
+ * Slots: 0 shell pass 1 (R), 1 shell pass 2 (R), 2 / 3 shell passes of J v FP64,
+ * 4 / 5 shell passes of J v FP32, 6 columns R, 7 columns J v FP64, 8 columns J v FP32,
+ * 9 GMRES Arnoldi (orthogonalisation), 10 block-Jacobi build, 11 block-Jacobi apply,
+ * 12 vector updates. */
+dg_status_t dg_profile_enable(dg_mesh_t mesh, int32_t on);
+dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_host, int32_t n, int32_t reset);
+
+const char* dg_last_error(void);
+int32_t dg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGTHERMO_H */

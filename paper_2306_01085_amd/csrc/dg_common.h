@@ -1,0 +1,229 @@
+// Shared device-side definitions of the DG thermosphere library: scalar types
+// (double, float and their dual numbers for exact J(u)v), the nondimensional
+// physics constants, and the pointwise flux/source of the transformed model
+// (eq. fluxSWNondimensional with the acceleration of section 2.5 and the
+// transport laws of section 2.1.2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dg {
+
+// ---------------------------------------------------------------- dual numbers
+// Forward-mode AD: value and one directional derivative. J(u)v is the derivative
+// of R along v, computed exactly (no finite-difference step).
+template <class T>
+struct Dual {
+  T v, d;
+  __host__ __device__ Dual() {}
+  __host__ __device__ constexpr Dual(T a) : v(a), d(T(0)) {}
+  __host__ __device__ constexpr Dual(T a, T b) : v(a), d(b) {}
+};
+
+template <class S> struct Base { typedef S type; };
+template <class T> struct Base<Dual<T>> { typedef T type; };
+
+template <class T> __device__ inline Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
+template <class T> __device__ inline Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
+template <class T> __device__ inline Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
+template <class T> __device__ inline Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class T> __device__ inline Dual<T> operator/(Dual<T> a, Dual<T> b) {
+  T inv = T(1) / b.v;
+  T q = a.v * inv;
+  return {q, (a.d - q * b.d) * inv};
+}
+template <class T> __device__ inline Dual<T> operator+(Dual<T> a, T b) { return {a.v + b, a.d}; }
+template <class T> __device__ inline Dual<T> operator+(T b, Dual<T> a) { return {a.v + b, a.d}; }
+template <class T> __device__ inline Dual<T> operator-(Dual<T> a, T b) { return {a.v - b, a.d}; }
+template <class T> __device__ inline Dual<T> operator-(T b, Dual<T> a) { return {b - a.v, -a.d}; }
+template <class T> __device__ inline Dual<T> operator*(Dual<T> a, T b) { return {a.v * b, a.d * b}; }
+template <class T> __device__ inline Dual<T> operator*(T b, Dual<T> a) { return {a.v * b, a.d * b}; }
+template <class T> __device__ inline Dual<T> operator/(Dual<T> a, T b) { T inv = T(1) / b; return {a.v * inv, a.d * inv}; }
+template <class T> __device__ inline Dual<T> operator/(T a, Dual<T> b) {
+  T inv = T(1) / b.v;
+  T q = a * inv;
+  return {q, -q * b.d * inv};
+}
+template <class T> __device__ inline Dual<T>& operator+=(Dual<T>& a, Dual<T> b) { a.v += b.v; a.d += b.d; return a; }
+template <class T> __device__ inline Dual<T>& operator-=(Dual<T>& a, Dual<T> b) { a.v -= b.v; a.d -= b.d; return a; }
+
+__device__ inline double xexp(double a) { return exp(a); }
+__device__ inline float xexp(float a) { return expf(a); }
+__device__ inline double xlog(double a) { return log(a); }
+__device__ inline float xlog(float a) { return logf(a); }
+__device__ inline double xsqrt(double a) { return sqrt(a); }
+__device__ inline float xsqrt(float a) { return sqrtf(a); }
+template <class T> __device__ inline Dual<T> xexp(Dual<T> a) { T e = xexp(a.v); return {e, e * a.d}; }
+template <class T> __device__ inline Dual<T> xlog(Dual<T> a) { return {xlog(a.v), a.d / a.v}; }
+template <class T> __device__ inline Dual<T> xsqrt(Dual<T> a) { T s = xsqrt(a.v); return {s, a.d * (T(0.5) / s)}; }
+// x^c for x > 0
+__device__ inline double xpow(double a, double c) { return exp(c * log(a)); }
+__device__ inline float xpow(float a, float c) { return expf(c * logf(a)); }
+template <class T> __device__ inline Dual<T> xpow(Dual<T> a, T c) {
+  T p = xpow(a.v, c);
+  return {p, c * p / a.v * a.d};
+}
+
+template <class S> __device__ inline typename Base<S>::type val(S a) { return a; }
+template <class T> __device__ inline T val(Dual<T> a) { return a.v; }
+
+// loads and stores for the scalar types: a dual reads its value from the state and
+// its derivative from the tangent array (both stored in T)
+template <class S> struct Io;
+template <> struct Io<double> {
+  template <class P> __device__ static double ld(const double* u, const P*, int64_t i) { return u[i]; }
+  __device__ static void st(double* r, void*, int64_t i, double x) { r[i] = x; }
+};
+template <> struct Io<float> {
+  template <class P> __device__ static float ld(const float* u, const P*, int64_t i) { return u[i]; }
+  __device__ static void st(float* r, void*, int64_t i, float x) { r[i] = x; }
+};
+template <class T> struct Io<Dual<T>> {
+  template <class U> __device__ static Dual<T> ld(const U* u, const T* v, int64_t i) { return {T(u[i]), v[i]}; }
+};
+
+// ---------------------------------------------------------------- constants
+// Nondimensional parameters (section 2.5), flattened for kernel arguments.
+struct PhysC {
+  double gamma, inv_gm, c_visc, c_cond, c_diss, m, inv_m;
+  double nu_r, alpha_r, alpha0c, kexp;
+  double lam, T_bot, r_ref2;
+  double om[3], cent, cor;           // rotation vector, Fr^2/gamma, 2 Fr/sqrt(gamma)
+  double heat_amp, heat_qm, heat_rm, heat_inv_H;
+  double sun_lat, sun_lon0, sun_rate;
+  int bc_mode;
+  double bc_state[5];
+};
+
+// ---------------------------------------------------------------- pointwise physics
+// Flux F[c][k] and source Sr[c] at one node of a D-dimensional problem (f = D + 2
+// fields: varrho, sqrt(rho) v, sqrt(rho) T). x: node position; Q: heating rate there.
+template <int D, class S>
+__device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], const double* x, double Q,
+                                   S (*F)[D], S* Sr) {
+  typedef typename Base<S>::type T;
+  const S lr = u[0];
+  const S s = xexp(T(-0.5) * lr);
+  const S sq = T(1) / s;
+  const S rho = sq * sq;
+  S U[D], v[D];
+  for (int i = 0; i < D; ++i) { U[i] = u[1 + i]; v[i] = s * U[i]; }
+  const S Th = u[D + 1];
+  const S Tm = s * Th;
+  const S mu = xsqrt(Tm * T(P.m)) + T(P.nu_r) * rho;
+  const S kap = T(P.alpha0c) * xpow(Tm, T(P.kexp)) + T(P.alpha_r * P.inv_m) * rho;
+  S gl[D], gT[D], gv[D][D];
+  for (int k = 0; k < D; ++k) gl[k] = q[0][k];
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k) gv[i][k] = s * (q[1 + i][k] - T(0.5) * U[i] * gl[k]);
+  for (int k = 0; k < D; ++k) gT[k] = s * (q[D + 1][k] - T(0.5) * Th * gl[k]);
+  S div = gv[0][0];
+  for (int i = 1; i < D; ++i) div = div + gv[i][i];
+  S eps[D][D];
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k) eps[i][k] = gv[i][k] + gv[k][i] - (i == k ? T(2.0 / 3.0) * div : S(T(0)));
+  const S mus = T(P.c_visc) * mu * s;                 // mu / (sqrt(rho) sqrt(gamma Gr))
+  const S kas = T(P.c_cond * P.m) * kap * s;          // kappa / (Pr sqrt(rho) c_v) sqrt(gamma/Gr)
+  for (int k = 0; k < D; ++k) F[0][k] = lr * v[k];
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k) {
+      S f = U[i] * v[k] - mus * eps[i][k];
+      if (i == k) f = f + T(P.inv_gm) * Th;
+      F[1 + i][k] = f;
+    }
+  for (int k = 0; k < D; ++k) F[D + 1][k] = Th * v[k] - kas * gT[k];
+  // sources
+  Sr[0] = (lr - T(1)) * div;
+  double r2 = 0;
+  for (int k = 0; k < D; ++k) r2 += x[k] * x[k];
+  const double r = sqrt(r2);
+  const double gfac = -P.r_ref2 / (r2 * r) / P.gamma;   // g_k / gamma = gfac x_k
+  double cen[3] = {0, 0, 0};
+  if (D == 3) {
+    const double wr = P.om[0] * x[0] + P.om[1] * x[1] + P.om[2] * x[2];
+    const double ww = P.om[0] * P.om[0] + P.om[1] * P.om[1] + P.om[2] * P.om[2];
+    for (int k = 0; k < 3; ++k) cen[k] = -P.cent * (P.om[k] * wr - ww * x[k]);
+  }
+  for (int i = 0; i < D; ++i) {
+    S eg = eps[i][0] * gl[0];
+    for (int k = 1; k < D; ++k) eg = eg + eps[i][k] * gl[k];
+    S a = sq * T(gfac * x[i] + cen[i]) + T(0.5) * div * U[i] - T(0.5 * P.inv_gm) * Th * gl[i] + T(0.5) * mus * eg;
+    if (D == 3) {
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+      // - 2 Fr/sqrt(gamma) (w x U)_i
+      a = a - T(P.cor) * (T(P.om[i1]) * U[i2 % D] - T(P.om[i2]) * U[i1 % D]);
+    }
+    Sr[1 + i] = a;
+  }
+  S Tg = gT[0] * gl[0];
+  for (int k = 1; k < D; ++k) Tg = Tg + gT[k] * gl[k];
+  S ed = eps[0][0] * gv[0][0];
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k)
+      if (i + k > 0) ed = ed + eps[i][k] * gv[i][k];
+  Sr[D + 1] = T(Q * P.m) * s + T(1.5 - P.gamma) * Th * div + T(0.5) * kas * Tg + T(P.c_diss * P.m) * mu * s * ed;
+}
+
+// inviscid part of the flux only (upper boundary)
+template <int D, class S>
+__device__ inline void flux_inviscid(const PhysC& P, const S* u, S (*F)[D]) {
+  typedef typename Base<S>::type T;
+  const S lr = u[0];
+  const S s = xexp(T(-0.5) * lr);
+  S v[D];
+  for (int i = 0; i < D; ++i) v[i] = s * u[1 + i];
+  for (int k = 0; k < D; ++k) F[0][k] = lr * v[k];
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k) {
+      S f = u[1 + i] * v[k];
+      if (i == k) f = f + T(P.inv_gm) * u[D + 1];
+      F[1 + i][k] = f;
+    }
+  for (int k = 0; k < D; ++k) F[D + 1][k] = u[D + 1] * v[k];
+}
+
+// stabilisation sigma (eq. LDG2) at a trace state: lam + diag(0, mu s c_visc, kappa s m c_cond)
+template <int D, class S>
+__device__ inline void sigma(const PhysC& P, const S* uh, S& sig_m, S& sig_e) {
+  typedef typename Base<S>::type T;
+  const S s = xexp(T(-0.5) * uh[0]);
+  const S rho = T(1) / (s * s);
+  const S Tm = s * uh[D + 1];
+  const S mu = xsqrt(Tm * T(P.m)) + T(P.nu_r) * rho;
+  const S kap = T(P.alpha0c) * xpow(Tm, T(P.kexp)) + T(P.alpha_r * P.inv_m) * rho;
+  sig_m = T(P.lam) + T(P.c_visc) * mu * s;
+  sig_e = T(P.lam) + T(P.c_cond * P.m) * kap * s;
+}
+
+// boundary state u_b for the lower boundary (or the Dirichlet state in bc_mode 1)
+template <int D, class S>
+__device__ inline void boundary_state(const PhysC& P, const S* u, S* ub) {
+  typedef typename Base<S>::type T;
+  if (P.bc_mode == 1) {
+    for (int c = 0; c < D + 2; ++c) ub[c] = S(T(P.bc_state[c]));
+    return;
+  }
+  ub[0] = u[0];
+  for (int i = 0; i < D; ++i) ub[1 + i] = S(T(0));
+  ub[D + 1] = T(P.T_bot) * xexp(T(0.5) * u[0]);
+}
+
+// Chapman-shaped day-side heating at position x, time t (depends on x and t only)
+template <int D>
+__device__ inline double heating(const PhysC& P, const double* x, double t) {
+  if (P.heat_amp == 0.0) return 0.0;
+  double r2 = 0;
+  for (int k = 0; k < D; ++k) r2 += x[k] * x[k];
+  const double r = sqrt(r2);
+  double cchi = 1.0;
+  if (D == 3) {
+    const double lon = P.sun_lon0 - P.sun_rate * t;
+    const double cl = cos(P.sun_lat);
+    cchi = (x[0] * cl * cos(lon) + x[1] * cl * sin(lon) + x[D - 1] * sin(P.sun_lat)) / r;
+  }
+  if (!(cchi > 0.0)) return 0.0;
+  const double z = (r - P.heat_rm) * P.heat_inv_H;
+  return P.heat_amp * P.heat_qm * exp(1.0 - z - exp(-z) / cchi);
+}
+
+}  // namespace dg

@@ -1,0 +1,141 @@
+// Host-side definition of a mesh handle and helpers shared by the library's
+// translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dgthermo.h"
+#include "dg_common.h"
+
+#define DG_PROF_SLOTS 16
+
+namespace dg {
+
+void set_error(const std::string& msg);
+
+#define DG_HIP_CHECK(call)                                                                 \
+  do {                                                                                     \
+    hipError_t err_ = (call);                                                              \
+    if (err_ != hipSuccess) {                                                              \
+      ::dg::set_error(std::string(#call) + ": " + hipGetErrorString(err_));                \
+      return DG_ERR_HIP;                                                                   \
+    }                                                                                      \
+  } while (0)
+
+// GLL nodes, weights and differentiation matrix D[i][j] = l_j'(x_i) for degree p
+struct Gll {
+  int p, n;
+  std::vector<double> x, w, D;
+};
+Gll make_gll(int p);
+
+// the same tables flattened for kernel arguments (D[i*n + j])
+struct GllC {
+  double D[25], x[5], w[5];
+};
+GllC make_gllc(int p);
+
+// device view of the shell geometry and connectivity (kernel argument)
+struct ShellDev {
+  int n_ang, n_rad, E;
+  const double* ang;     // [A][13][n2]: A1 (3), A2 (3), A3 (3), Jang, unit position (3)
+  const double* edges;   // [n_rad + 1] layer interfaces
+  const int* cnbr;       // [A][4] neighbour cell across angular faces 0..3
+  const int* cface;      // [A][4] the neighbour's face index
+  const int* cmap;       // [A][4][n] along-edge index s -> neighbour's along-edge index
+};
+
+// device view of a batch of columns (kernel argument)
+struct ColDev {
+  int E;                 // total elements
+  const int64_t* off;    // [E] DOF offset of the element
+  const int* prev;       // [E] element below (-1: lower boundary)
+  const int* next;       // [E] element above (-1: upper boundary)
+  const double* geo;     // [E][2] bottom radius, thickness
+  const int* col;        // [E] column of the element
+  const double* cpar;    // [n_col][5] heat_amp, heat_qm, heat_rm, heat_inv_H, lam
+};
+
+struct Workspace;   // implicit-step buffers (solver.hip)
+
+}  // namespace dg
+
+struct dg_mesh_s {
+  int kind = 0;
+  int dim = 3, nf = 5;
+  int64_t n_dof = 0, n_elem = 0;
+  dg::PhysC phys{};
+  // shell
+  int p = 0, n = 0, N = 0, N2 = 0, n_ang = 0, n_rad = 0, A = 0;
+  double* d_ang = nullptr;
+  double* d_edges = nullptr;
+  int* d_cnbr = nullptr;
+  int* d_cface = nullptr;
+  int* d_cmap = nullptr;
+  std::vector<double> h_ang, h_edges;
+  // columns
+  int n_col = 0;
+  std::vector<int> col_nelem, col_p;
+  std::vector<int64_t> col_off;          // [n_col + 1]
+  std::vector<int> elem_p;               // [E]
+  std::vector<double> h_geo;             // [E][2]
+  int64_t* d_off = nullptr;
+  int* d_prev = nullptr;
+  int* d_next = nullptr;
+  double* d_geo = nullptr;
+  int* d_col = nullptr;
+  double* d_cpar = nullptr;
+  int* d_plist[3] = {nullptr, nullptr, nullptr};   // element ids of degree 2, 3, 4
+  int plist_n[3] = {0, 0, 0};
+  // face-flux traces (one buffer per precision)
+  double* d_fn64 = nullptr;
+  float* d_fn32 = nullptr;
+  int64_t fn_len = 0;
+  dg::Workspace* ws = nullptr;
+  // per-kernel event timing (dg_profile_enable / dg_profile_read)
+  bool prof = false;
+  struct ProfEv { int id; hipEvent_t a, b; };
+  std::vector<ProfEv> prof_events;
+  double prof_ms[DG_PROF_SLOTS] = {};
+  int64_t prof_cnt[DG_PROF_SLOTS] = {};
+
+  dg::ShellDev shell() const {
+    return dg::ShellDev{n_ang, n_rad, (int)n_elem, d_ang, d_edges, d_cnbr, d_cface, d_cmap};
+  }
+  dg::ColDev cols() const {
+    return dg::ColDev{(int)n_elem, d_off, d_prev, d_next, d_geo, d_col, d_cpar};
+  }
+};
+
+namespace dg {
+// records a pair of events around the enclosed launches when profiling is on
+struct ProfScope {
+  dg_mesh_s* m;
+  int id;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(dg_mesh_s* m_, int id_, hipStream_t s_) : m(m_), id(id_), s(s_) {
+    if (m->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    hipEvent_t b = nullptr;
+    if (m->prof && a && hipEventCreate(&b) == hipSuccess) {
+      (void)hipEventRecord(b, s);
+      m->prof_events.push_back({id, a, b});
+    }
+  }
+};
+// kernels (shell.hip, column.hip)
+dg_status_t shell_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
+dg_status_t shell_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
+dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
+dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
+dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+void fill_phys(PhysC& P, const dg_physics_t& in);
+dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg_solver_opts_t& o,
+                          dg_step_stats_t* st, hipStream_t s);
+void free_workspace(dg_mesh_s* m);
+}  // namespace dg

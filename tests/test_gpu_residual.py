@@ -1,0 +1,158 @@
+"""Parity of the HIP residual and Jacobian-vector product with the FP64 oracle.
+
+R: max |R_gpu - R_oracle| <= 1e-12 max(term scale) (the scale is |volume
+divergence| + |face lift| + |source| per node, so cancelling terms do not hide
+errors). J v (FP64): the same bound against the oracle's complex step. J v (FP32):
+relative 2-norm error <= 1e-5."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import need_gpu, rel_to_scale, shell_pair, to_dev, torch
+from oracle import dg as odg
+from oracle import jac as ojac
+from oracle import mesh as omesh
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_shell_nodes_match_oracle(p):
+    need_gpu()
+    w = synth.shell_workload(0, p=p, n_ang=2, n_rad=3)
+    om, gm = shell_pair(w, 2, 3, p)
+    X = gm.nodes().reshape(om.X.shape)
+    assert np.max(np.abs(X - om.X)) < 1e-12 * np.max(np.abs(om.X))
+
+
+@pytest.mark.parametrize("p,n_ang,n_rad", [(2, 2, 2), (3, 2, 3), (4, 1, 2), (3, 3, 2)])
+def test_shell_residual_parity(p, n_ang, n_rad):
+    need_gpu()
+    w = synth.shell_workload(p + n_ang, p=p, n_ang=n_ang, n_rad=n_rad)
+    om, gm = shell_pair(w, n_ang, n_rad, p)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    u += 1e-3 * np.random.default_rng(p).standard_normal(u.shape)
+    t = 0.37
+    R, scale = odg.residual_parts(om, w.phys, u, t)
+    r = gm.residual(to_dev(u), t=t).cpu().numpy().reshape(u.shape)
+    assert rel_to_scale(r, R, scale) < 1e-12
+
+
+@pytest.mark.parametrize("bc_mode", [0, 1])
+def test_shell_residual_boundary_modes(bc_mode):
+    need_gpu()
+    w = synth.shell_workload(5, p=3, n_ang=2, n_rad=2)
+    w.phys["bc_mode"] = bc_mode
+    w.phys["bc_state"] = list(synth.uniform_state(3))
+    om, gm = shell_pair(w, 2, 2, 3)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    R, scale = odg.residual_parts(om, w.phys, u, 0.0)
+    r = gm.residual(to_dev(u)).cpu().numpy().reshape(u.shape)
+    assert rel_to_scale(r, R, scale) < 1e-12
+
+
+def test_shell_free_stream_gpu():
+    need_gpu()
+    P = synth.base_physics(3)
+    us = synth.uniform_state(3)
+    P.update(r_ref=0.0, heat_amp=0.0, bc_mode=1, bc_state=list(us), omega=[0.0, 0.0, 0.0])
+    from paper_2306_01085_amd import Mesh
+    gm = Mesh.shell(p=3, n_ang=3, n_rad=4, r_bot=synth.R_BOT, r_top=synth.R_TOP, stretch=1.15, phys=P)
+    u = np.broadcast_to(us[None, :, None], (gm.n_elem, 5, 64)).copy()
+    r = gm.residual(to_dev(u)).cpu().numpy()
+    assert np.max(np.abs(r)) < 1e-13
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_shell_jvp_parity(p):
+    need_gpu()
+    w = synth.shell_workload(10 + p, p=p, n_ang=2, n_rad=2)
+    om, gm = shell_pair(w, 2, 2, p)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    v = synth.tangent(u.shape, 3)
+    t = 0.2
+    ref = ojac.jvp_complex(om, w.phys, u, v, t)
+    jv = gm.jvp(to_dev(u), to_dev(v), t=t).cpu().numpy().reshape(u.shape)
+    assert np.linalg.norm(jv - ref) / np.linalg.norm(ref) < 1e-12
+    # the linearised terms' own scale: the complex-step of |terms|
+    assert np.max(np.abs(jv - ref)) < 1e-12 * np.max(np.abs(ref)) * 10
+    jv32 = gm.jvp(to_dev(u), to_dev(v).float(), t=t, prec="f32").cpu().double().numpy().reshape(u.shape)
+    assert np.linalg.norm(jv32 - ref) / np.linalg.norm(ref) < 1e-5
+
+
+def _columns_pair(seed, nelem, p, stretch=1.1):
+    from paper_2306_01085_amd import Mesh
+    w = synth.column_batch_workload(seed, n_col=len(nelem))
+    w.nelem = np.asarray(nelem, np.int32)
+    w.p = np.asarray(p, np.int32)
+    gm = Mesh.columns(w.nelem, w.p, w.r_bot, w.r_top, stretch, w.phys, w.col_phys)
+    cols = []
+    for c in range(len(nelem)):
+        om = omesh.columns_mesh([int(nelem[c])], int(p[c]), w.r_bot, w.r_top, stretch)
+        P = dict(w.phys)
+        for k in w.col_phys:
+            P[k] = float(w.col_phys[k][c])
+        u = np.moveaxis(w.state(c, om.X[:, :, 0]), 0, 1).copy()
+        g = np.random.default_rng(c).standard_normal(u.shape)
+        # perturb log-density additively, velocity and temperature relative to sqrt(rho) T
+        u[:, 0] += 1e-3 * g[:, 0]
+        u[:, 1] += 1e-3 * g[:, 1] * u[:, 2]
+        u[:, 2] *= 1.0 + 1e-3 * g[:, 2]
+        cols.append((om, P, u))
+    return gm, cols
+
+
+def test_columns_residual_and_jvp_parity():
+    need_gpu()
+    nelem = [5, 17, 32, 3, 64]
+    p = [2, 3, 4, 4, 2]
+    gm, cols = _columns_pair(7, nelem, p)
+    off = gm.col_offsets()
+    u = np.concatenate([c[2].ravel() for c in cols])
+    v = synth.tangent(u.shape, 9)
+    r = gm.residual(to_dev(u), t=0.1).cpu().numpy()
+    jv = gm.jvp(to_dev(u), to_dev(v), t=0.1).cpu().numpy()
+    jv32 = gm.jvp(to_dev(u), to_dev(v).float(), t=0.1, prec="f32").cpu().double().numpy()
+    for c, (om, P, uc) in enumerate(cols):
+        R, scale = odg.residual_parts(om, P, uc, 0.1)
+        rc = r[off[c]:off[c + 1]].reshape(uc.shape)
+        assert rel_to_scale(rc, R, scale) < 1e-12, c
+        vc = v[off[c]:off[c + 1]].reshape(uc.shape)
+        ref = ojac.jvp_complex(om, P, uc, vc, 0.1)
+        jc = jv[off[c]:off[c + 1]].reshape(uc.shape)
+        assert np.linalg.norm(jc - ref) / np.linalg.norm(ref) < 1e-12, c
+        j32 = jv32[off[c]:off[c + 1]].reshape(uc.shape)
+        assert np.linalg.norm(j32 - ref) / np.linalg.norm(ref) < 1e-5, c
+
+
+def test_column_config_and_rest_state():
+    """the 64-element p = 2 column of the 1D workload, and a rest state with physical
+    boundaries and no sources (R = 0 to round-off)"""
+    need_gpu()
+    from paper_2306_01085_amd import Mesh
+    w = synth.config_column(0)
+    om = omesh.columns_mesh([64], 2, w.r_bot, w.r_top)
+    gm = Mesh.columns([64], [2], w.r_bot, w.r_top, 1.0, w.phys, w.col_phys)
+    u = np.moveaxis(w.state(0, om.X[:, :, 0]), 0, 1).copy()
+    R, scale = odg.residual_parts(om, w.phys, u, 0.0)
+    r = gm.residual(to_dev(u)).cpu().numpy().reshape(u.shape)
+    assert rel_to_scale(r, R, scale) < 1e-12
+    P = dict(w.phys)
+    P.update(r_ref=0.0, heat_amp=0.0)
+    gm2 = Mesh.columns([64], [2], w.r_bot, w.r_top, 1.0, P, {"lam": w.col_phys["lam"]})
+    lr = -0.4
+    us = np.array([lr, 0.0, P["T_bot"] * np.exp(0.5 * lr)])
+    u2 = np.broadcast_to(us[None, :, None], u.shape).copy()
+    assert np.max(np.abs(gm2.residual(to_dev(u2)).cpu().numpy())) < 1e-13
+
+
+def test_bad_arguments_raise():
+    need_gpu()
+    from paper_2306_01085_amd import DgError, Mesh
+    w = synth.shell_workload(0, p=3, n_ang=1, n_rad=1)
+    with pytest.raises(DgError):
+        Mesh.shell(p=7, n_ang=1, n_rad=1, r_bot=w.r_bot, r_top=w.r_top, stretch=1.0, phys=w.phys)
+    gm = Mesh.shell(p=3, n_ang=1, n_rad=1, r_bot=w.r_bot, r_top=w.r_top, stretch=1.0, phys=w.phys)
+    u = torch.zeros(gm.n_dof + 5, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(DgError):
+        gm.residual(u)
