@@ -125,7 +125,7 @@ dg_status_t dg_jvp(dg_mesh_t mesh, double t, const double* u, const void* v, voi
 /* ---- implicit time stepping (section 3.1 DIRK, section 3.2 Newton-GMRES) ---- */
 typedef struct {
   int32_t scheme;          /* 33: DIRK(3,3); 22: DIRK(2,2) */
-  int32_t gmres_m;         /* Krylov dimension per restart (30) */
+  int32_t gmres_m;         /* Krylov dimension per restart (30; 1..32) */
   int32_t max_newton;      /* Newton iterations per stage */
   int32_t max_restarts;    /* GMRES restarts per Newton iteration */
   double newton_rtol;      /* stop when |G(U)| <= newton_rtol |G(u_n)| (1e-8) */

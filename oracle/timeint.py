@@ -115,3 +115,34 @@ def gmres(Aop, rhs, x0=None, m=30, rtol=1e-10, max_restarts=50, M=None):
         y = np.linalg.solve(np.triu(H[:k_used, :k_used]), g[:k_used])
         x = x + Mf(V[:k_used].T @ y)
     return x, total
+
+
+def newton_jfnk(mesh, P, Gfun, U0, ti, aii_dt, ref_norm, rtol=1e-12, maxit=40, gmres_rtol=1e-12):
+    """Newton with matrix-free GMRES on complex-step products (for meshes too large for
+    the dense Jacobian); same stage equation and stopping rule as newton_dense"""
+    from . import jac
+    U = U0.copy()
+    for it in range(maxit):
+        G = Gfun(U)
+        nG = np.linalg.norm(G)
+        if nG <= rtol * ref_norm:
+            return U, it
+        Aop = lambda v: v - aii_dt * jac.jvp_complex(mesh, P, U, v.reshape(U.shape), ti).ravel()
+        dx, _ = gmres(Aop, -G.ravel(), m=60, rtol=gmres_rtol, max_restarts=200)
+        U = U + dx.reshape(U.shape)
+    raise RuntimeError("JFNK Newton did not converge")
+
+
+def implicit_step_jfnk(mesh, P, u, t, dt, scheme=33, rtol=1e-12):
+    """one DIRK step with every stage solved by matrix-free Newton-GMRES to rtol"""
+    A, b, c = dirk_tableau(scheme)
+    Rs, Us = [], []
+    for i in range(len(c)):
+        ti = t + c[i] * dt
+        bi = u + dt * sum(A[i, j] * Rs[j] for j in range(i))
+        aii = A[i, i]
+        G = lambda U: U - dt * aii * dg.residual(mesh, P, U, ti) - bi
+        Ui, _ = newton_jfnk(mesh, P, G, u, ti, dt * aii, np.linalg.norm(G(u)), rtol)
+        Us.append(Ui)
+        Rs.append(dg.residual(mesh, P, Ui, ti))
+    return Us[-1], Us

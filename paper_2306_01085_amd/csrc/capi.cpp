@@ -267,7 +267,7 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
     set_error("dg_implicit_step: invalid argument");
     return DG_ERR_ARG;
   }
-  if ((opts->scheme != 33 && opts->scheme != 22) || opts->gmres_m < 1 || opts->gmres_m > 64 ||
+  if ((opts->scheme != 33 && opts->scheme != 22) || opts->gmres_m < 1 || opts->gmres_m > 32 ||
       opts->max_newton < 1 || opts->max_restarts < 1 || !(opts->newton_rtol > 0) || !(opts->gmres_rtol > 0) ||
       (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32) || opts->precond < 0 || opts->precond > 1) {
     set_error("dg_implicit_step: invalid solver options");

@@ -134,6 +134,9 @@ dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v,
 dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
 dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+dg_status_t shell_bjac_build(dg_mesh_s* m, double t, const double* u, double dta, double* Binv, hipStream_t s);
+dg_status_t shell_bjac_apply64(dg_mesh_s* m, const double* B, const double* v, double* z, hipStream_t s);
+dg_status_t shell_bjac_apply32(dg_mesh_s* m, const double* B, const float* v, float* z, hipStream_t s);
 void fill_phys(PhysC& P, const dg_physics_t& in);
 dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg_solver_opts_t& o,
                           dg_step_stats_t* st, hipStream_t s);

@@ -82,6 +82,94 @@ __device__ inline int face_slot(int f, int a, int b, int cz) {
   return a + n * b;
 }
 
+struct NodeGeo {
+  int a, b, cz, ja;
+  double rk, hk, rc, rp, Jac, x[3], A1[3], A2[3], A3[3];
+};
+
+// geometry of node j of an element in radial layer k (angular tables staged in LDS)
+template <int P>
+__device__ inline NodeGeo node_geo(const ShellDev& M, const GllC& gc, const double (*ang)[Shape<P>::N2], int k,
+                                   int j) {
+  constexpr int n = P + 1, N2 = n * n;
+  NodeGeo g;
+  g.a = j % n;
+  g.b = (j / n) % n;
+  g.cz = j / N2;
+  g.ja = g.a + n * g.b;
+  g.rk = M.edges[k];
+  g.hk = M.edges[k + 1] - g.rk;
+  g.rp = 0.5 * g.hk;
+  g.rc = g.rk + 0.5 * (gc.x[g.cz] + 1.0) * g.hk;
+  for (int d = 0; d < 3; ++d) {
+    g.A1[d] = ang[d][g.ja];
+    g.A2[d] = ang[3 + d][g.ja];
+    g.A3[d] = ang[6 + d][g.ja];
+    g.x[d] = g.rc * ang[10 + d][g.ja];
+  }
+  g.Jac = g.rc * g.rc * g.rp * ang[9][g.ja];
+  return g;
+}
+
+// auxiliary gradient q at one node: the conservative strong form of the weak LDG
+// gradient, q = (1/J) sum_a D_a(J a^a u) + sum_faces Sn (u_hat - u)/(w_end J)
+template <int P, class S, class SU, class TV>
+__device__ inline void node_gradient(const ShellDev& M, const PhysC& ph, const double* D, const double* xg, double w_end,
+                                     const double (*ang)[Shape<P>::N2], const S (*su)[Shape<P>::N], const SU* u,
+                                     const TV* v, int cell, int k, const NodeGeo& g, const S* uu, S (*q)[3]) {
+  typedef typename Base<S>::type T;
+  constexpr int n = P + 1, N = n * n * n, N2 = n * n;
+  const int a = g.a, b = g.b, cz = g.cz, ja = g.ja;
+  const double rrp = g.rc * g.rp;
+  double r2[n];
+  for (int i = 0; i < n; ++i) {
+    const double ri = g.rk + 0.5 * (xg[i] + 1.0) * g.hk;
+    r2[i] = ri * ri;
+  }
+  const double invJ = 1.0 / g.Jac;
+  for (int c = 0; c < 5; ++c) {
+    S d1[3], d2[3], d3;
+    for (int d = 0; d < 3; ++d) { d1[d] = S(T(0)); d2[d] = S(T(0)); }
+    d3 = S(T(0));
+    for (int i = 0; i < n; ++i) {
+      const S u1 = su[c][i + n * b + N2 * cz];
+      const S u2 = su[c][a + n * i + N2 * cz];
+      const S u3 = su[c][ja + N2 * i];
+      const double Da = D[a * n + i], Db = D[b * n + i], Dc = D[cz * n + i] * r2[i];
+      for (int d = 0; d < 3; ++d) {
+        d1[d] = d1[d] + u1 * T(Da * ang[d][i + n * b]);
+        d2[d] = d2[d] + u2 * T(Db * ang[3 + d][a + n * i]);
+      }
+      d3 = d3 + u3 * T(Dc);
+    }
+    for (int d = 0; d < 3; ++d) q[c][d] = (T(rrp) * (d1[d] + d2[d]) + T(g.A3[d]) * d3) * T(invJ);
+  }
+  const double lfac = 1.0 / (w_end * g.Jac);
+  for (int f = 0; f < 6; ++f) {
+    const bool on = (f == 0 && a == 0) || (f == 1 && a == n - 1) || (f == 2 && b == 0) || (f == 3 && b == n - 1) ||
+                    (f == 4 && cz == 0) || (f == 5 && cz == n - 1);
+    if (!on) continue;
+    const double side = (f & 1) ? 1.0 : -1.0;
+    double Sn[3];
+    for (int d = 0; d < 3; ++d)
+      Sn[d] = side * (f < 2 ? rrp * g.A1[d] : (f < 4 ? rrp * g.A2[d] : g.rc * g.rc * g.A3[d]));
+    int jn, fn, mn;
+    const int en = face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
+    S du[5];
+    if (en >= 0) {
+      for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uu[c]);
+    } else if (ph.bc_mode == 1 || f == 4) {
+      S ub[5];
+      boundary_state<3, S>(ph, uu, ub);
+      for (int c = 0; c < 5; ++c) du[c] = ub[c] - uu[c];
+    } else {
+      continue;   // upper boundary: u_hat = u
+    }
+    for (int c = 0; c < 5; ++c)
+      for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du[c] * T(Sn[d] * lfac);
+  }
+}
+
 template <int P, class S, class SU, class TV, class OT>
 __global__ __launch_bounds__(256) void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__ u,
                                                    const TV* __restrict__ v, OT* __restrict__ R,
@@ -101,7 +189,6 @@ __global__ __launch_bounds__(256) void shell_pass1(ShellDev M, PhysC ph, GllC gc
   const int cell = live ? e / M.n_rad : 0;
   const int k = live ? e % M.n_rad : 0;
   if (threadIdx.x < n * n) D[threadIdx.x] = gc.D[threadIdx.x];
-  const double* xg = gc.x;
   const double w_end = gc.w[0];
   if (live)
     for (int idx = j; idx < 13 * N2; idx += TPE) s_ang[le][idx / N2][idx % N2] = M.ang[(int64_t)cell * 13 * N2 + idx];
@@ -114,73 +201,19 @@ __global__ __launch_bounds__(256) void shell_pass1(ShellDev M, PhysC ph, GllC gc
     }
   __syncthreads();
 
-  const int a = j % n, b = (j / n) % n, cz = j / N2;
-  const int ja = a + n * b;
-  double rk = 0, hk = 1, rc = 1, rp = 1, Jac = 1, x[3] = {0, 0, 0};
-  double A1[3], A2[3], A3[3];
+  NodeGeo g;
   S F[5][3], Sr[5];
   if (active) {
-    rk = M.edges[k];
-    hk = M.edges[k + 1] - rk;
-    rp = 0.5 * hk;
-    rc = rk + 0.5 * (xg[cz] + 1.0) * hk;
-    for (int d = 0; d < 3; ++d) {
-      A1[d] = s_ang[le][d][ja];
-      A2[d] = s_ang[le][3 + d][ja];
-      A3[d] = s_ang[le][6 + d][ja];
-      x[d] = rc * s_ang[le][10 + d][ja];
-    }
-    Jac = rc * rc * rp * s_ang[le][9][ja];
-    const double rrp = rc * rp;
-    double r2[n];
-    for (int i = 0; i < n; ++i) {
-      double ri = rk + 0.5 * (xg[i] + 1.0) * hk;
-      r2[i] = ri * ri;
-    }
-    // ---- auxiliary gradient q (conservative form of the weak gradient)
+    g = node_geo<P>(M, gc, s_ang[le], k, j);
     S q[5][3];
-    const double invJ = 1.0 / Jac;
-    for (int c = 0; c < 5; ++c) {
-      S d1[3], d2[3], d3;
-      for (int d = 0; d < 3; ++d) { d1[d] = S(T(0)); d2[d] = S(T(0)); }
-      d3 = S(T(0));
-      for (int i = 0; i < n; ++i) {
-        const S u1 = s_u[le][c][i + n * b + N2 * cz];
-        const S u2 = s_u[le][c][a + n * i + N2 * cz];
-        const S u3 = s_u[le][c][ja + N2 * i];
-        const double Da = D[a * n + i], Db = D[b * n + i], Dc = D[cz * n + i] * r2[i];
-        for (int d = 0; d < 3; ++d) {
-          d1[d] = d1[d] + u1 * T(Da * s_ang[le][d][i + n * b]);
-          d2[d] = d2[d] + u2 * T(Db * s_ang[le][3 + d][a + n * i]);
-        }
-        d3 = d3 + u3 * T(Dc);
-      }
-      for (int d = 0; d < 3; ++d) q[c][d] = (T(rrp) * (d1[d] + d2[d]) + T(A3[d]) * d3) * T(invJ);
-    }
-    // lift of (u_hat - u) on the faces through this node
+    node_gradient<P, S>(M, ph, D, gc.x, w_end, s_ang[le], s_u[le], u, v, cell, k, g, uu, q);
+    const int a = g.a, b = g.b, cz = g.cz;
+    const double rc = g.rc, rrp = g.rc * g.rp, Jac = g.Jac;
     const double lfac = 1.0 / (w_end * Jac);
-    for (int f = 0; f < 6; ++f) {
-      const bool on = (f == 0 && a == 0) || (f == 1 && a == n - 1) || (f == 2 && b == 0) || (f == 3 && b == n - 1) ||
-                      (f == 4 && cz == 0) || (f == 5 && cz == n - 1);
-      if (!on) continue;
-      const double side = (f & 1) ? 1.0 : -1.0;
-      double Sn[3];
-      for (int d = 0; d < 3; ++d) Sn[d] = side * (f < 2 ? rrp * A1[d] : (f < 4 ? rrp * A2[d] : rc * rc * A3[d]));
-      int jn, fn, mn;
-      const int en = face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
-      S du[5];
-      if (en >= 0) {
-        for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uu[c]);
-      } else if (ph.bc_mode == 1 || f == 4) {
-        S ub[5];
-        boundary_state<3, S>(ph, uu, ub);
-        for (int c = 0; c < 5; ++c) du[c] = ub[c] - uu[c];
-      } else {
-        continue;   // upper boundary: u_hat = u
-      }
-      for (int c = 0; c < 5; ++c)
-        for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du[c] * T(Sn[d] * lfac);
-    }
+    const double* A1 = g.A1;
+    const double* A2 = g.A2;
+    const double* A3 = g.A3;
+    const double* x = g.x;
     // ---- pointwise flux and source
     const double Q = heating<3>(ph, x, t);
     flux_source<3, S>(ph, uu, q, x, Q, F, Sr);
@@ -188,8 +221,7 @@ __global__ __launch_bounds__(256) void shell_pass1(ShellDev M, PhysC ph, GllC gc
       for (int dd = 0; dd < 3; ++dd) {
         const double* Am = (dd == 0) ? A1 : (dd == 1 ? A2 : A3);
         const double fac = (dd < 2) ? rrp : rc * rc;
-        S g = F[c][0] * T(fac * Am[0]) + F[c][1] * T(fac * Am[1]) + F[c][2] * T(fac * Am[2]);
-        s_G[le][dd][c][j] = g;
+        s_G[le][dd][c][j] = F[c][0] * T(fac * Am[0]) + F[c][1] * T(fac * Am[1]) + F[c][2] * T(fac * Am[2]);
       }
     }
     // boundary faces need the flux at the boundary state with the interior gradient;
@@ -239,8 +271,9 @@ __global__ __launch_bounds__(256) void shell_pass1(ShellDev M, PhysC ph, GllC gc
   __syncthreads();
   if (!active) return;
   // ---- volume divergence and own half of interior faces
-  const double invJ = 1.0 / Jac;
-  const double lfac = 1.0 / (w_end * Jac);
+  const int a = g.a, b = g.b, cz = g.cz, ja = g.ja;
+  const double invJ = 1.0 / g.Jac;
+  const double lfac = 1.0 / (w_end * g.Jac);
   for (int c = 0; c < 5; ++c) {
     S dv = S(T(0));
     for (int i = 0; i < n; ++i) {
@@ -361,6 +394,159 @@ dg_status_t shell_jvp64(dg_mesh_s* m, double t, const double* u, const double* v
 }
 dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
   return launch<Dual<float>, double, float, float>(m, t, u, v, jv, m->d_fn32, s, 4);
+}
+
+// Node block-Jacobi blocks of the stage matrix I - dta J(u): for every node, the 5x5
+// derivative of R at the node with respect to the node's own state through its
+// pointwise flux and source (the gradient q held fixed), the diagonal entries of the
+// volume derivative operators and the own-face terms with their stabilisation.
+// Stored inverted, entry (r, c) of node j of element e at Binv[(e*25 + r*5 + c)*N + j].
+template <int P>
+__global__ __launch_bounds__(256) void shell_bjac(ShellDev M, PhysC ph, GllC gc, double t,
+                                                  const double* __restrict__ u, double dta,
+                                                  double* __restrict__ Binv) {
+  typedef Shape<P> Sh;
+  typedef Dual<double> DD;
+  constexpr int n = Sh::n, N = Sh::N, N2 = Sh::N2, TPE = Sh::TPE, EPB = Sh::EPB;
+  __shared__ double s_ang[EPB][13][N2];
+  __shared__ double s_u[EPB][5][N];
+  __shared__ double D[n * n];
+  const int le = threadIdx.x / TPE;
+  const int j = threadIdx.x % TPE;
+  const int e = blockIdx.x * EPB + le;
+  const bool live = e < M.E;
+  const bool active = live && (j < N);
+  const int cell = live ? e / M.n_rad : 0;
+  const int k = live ? e % M.n_rad : 0;
+  if (threadIdx.x < n * n) D[threadIdx.x] = gc.D[threadIdx.x];
+  const double w_end = gc.w[0];
+  if (live)
+    for (int idx = j; idx < 13 * N2; idx += TPE) s_ang[le][idx / N2][idx % N2] = M.ang[(int64_t)cell * 13 * N2 + idx];
+  double uu[5];
+  const int64_t base = (int64_t)e * 5 * N;
+  if (active)
+    for (int c = 0; c < 5; ++c) {
+      uu[c] = u[base + c * N + j];
+      s_u[le][c][j] = uu[c];
+    }
+  __syncthreads();
+  if (!active) return;
+  const NodeGeo g = node_geo<P>(M, gc, s_ang[le], k, j);
+  double q[5][3];
+  node_gradient<P, double>(M, ph, D, gc.x, w_end, s_ang[le], s_u[le], u, (const double*)nullptr, cell, k, g, uu, q);
+  const double Q = heating<3>(ph, g.x, t);
+  const double invJ = 1.0 / g.Jac, lfac = 1.0 / (w_end * g.Jac);
+  const int idx3[3] = {g.a, g.b, g.cz};
+  const double fac3[3] = {g.rc * g.rp, g.rc * g.rp, g.rc * g.rc};
+  const double* Am3[3] = {g.A1, g.A2, g.A3};
+  const bool on[6] = {g.a == 0, g.a == n - 1, g.b == 0, g.b == n - 1, g.cz == 0, g.cz == n - 1};
+  double sm, se;
+  sigma<3, double>(ph, uu, sm, se);
+  double blk[5][10];
+  for (int c = 0; c < 5; ++c) {
+    DD ud[5], qd[5][3], Fd[5][3], Sd[5];
+    for (int r = 0; r < 5; ++r) {
+      ud[r] = DD(uu[r], r == c ? 1.0 : 0.0);
+      for (int d = 0; d < 3; ++d) qd[r][d] = DD(q[r][d], 0.0);
+    }
+    flux_source<3, DD>(ph, ud, qd, g.x, Q, Fd, Sd);
+    for (int r = 0; r < 5; ++r) {
+      double col = Sd[r].d;
+      double gd[3];
+      for (int dd = 0; dd < 3; ++dd) {
+        gd[dd] = fac3[dd] * (Am3[dd][0] * Fd[r][0].d + Am3[dd][1] * Fd[r][1].d + Am3[dd][2] * Fd[r][2].d);
+        col -= D[idx3[dd] * n + idx3[dd]] * gd[dd] * invJ;
+      }
+      for (int f = 0; f < 6; ++f) {
+        if (!on[f]) continue;
+        const int dd = f >> 1;
+        const double side = (f & 1) ? 1.0 : -1.0;
+        const bool bnd = (f == 4 && k == 0) || (f == 5 && k == M.n_rad - 1);
+        double Sn2 = 0;
+        for (int d = 0; d < 3; ++d) Sn2 += fac3[dd] * Am3[dd][d] * fac3[dd] * Am3[dd][d];
+        const double sg = (r == 0) ? ph.lam : (r == 4 ? se : sm);
+        if (!bnd) {
+          col += 0.5 * lfac * side * gd[dd];
+          if (r == c) col -= 0.5 * lfac * sqrt(Sn2) * sg;
+        } else if (f == 4 || ph.bc_mode == 1) {
+          if (r == c && r > 0) col -= lfac * sqrt(Sn2) * sg;
+        }
+      }
+      blk[r][c] = (r == c ? 1.0 : 0.0) - dta * col;
+    }
+  }
+  // invert by Gauss-Jordan elimination with partial pivoting on [blk | I]
+  for (int r = 0; r < 5; ++r)
+    for (int c = 0; c < 5; ++c) blk[r][5 + c] = (r == c) ? 1.0 : 0.0;
+  for (int c = 0; c < 5; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 5; ++r)
+      if (fabs(blk[r][c]) > fabs(blk[piv][c])) piv = r;
+    if (piv != c)
+      for (int q2 = 0; q2 < 10; ++q2) {
+        const double tmp = blk[c][q2];
+        blk[c][q2] = blk[piv][q2];
+        blk[piv][q2] = tmp;
+      }
+    const double inv = 1.0 / blk[c][c];
+    for (int q2 = 0; q2 < 10; ++q2) blk[c][q2] *= inv;
+    for (int r = 0; r < 5; ++r) {
+      if (r == c) continue;
+      const double f = blk[r][c];
+      for (int q2 = 0; q2 < 10; ++q2) blk[r][q2] -= f * blk[c][q2];
+    }
+  }
+  for (int r = 0; r < 5; ++r)
+    for (int c = 0; c < 5; ++c) Binv[((int64_t)e * 25 + r * 5 + c) * N + j] = blk[r][5 + c];
+}
+
+template <int N_, class T>
+__global__ __launch_bounds__(256) void shell_bjac_apply(int64_t nnodes, const double* __restrict__ Binv,
+                                                        const T* __restrict__ v, T* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes) return;
+  const int64_t e = i / N_;
+  const int j = (int)(i % N_);
+  T vv[5];
+  for (int c = 0; c < 5; ++c) vv[c] = v[(e * 5 + c) * N_ + j];
+  for (int r = 0; r < 5; ++r) {
+    double acc = 0;
+    for (int c = 0; c < 5; ++c) acc += Binv[(e * 25 + r * 5 + c) * N_ + j] * (double)vv[c];
+    z[(e * 5 + r) * N_ + j] = (T)acc;
+  }
+}
+
+dg_status_t shell_bjac_build(dg_mesh_s* m, double t, const double* u, double dta, double* Binv, hipStream_t s) {
+  ShellDev M = m->shell();
+  const GllC gc = make_gllc(m->p);
+  ProfScope ps(m, 10, s);
+  switch (m->p) {
+    case 2: shell_bjac<2><<<(M.E + Shape<2>::EPB - 1) / Shape<2>::EPB, 256, 0, s>>>(M, m->phys, gc, t, u, dta, Binv); break;
+    case 3: shell_bjac<3><<<(M.E + Shape<3>::EPB - 1) / Shape<3>::EPB, 256, 0, s>>>(M, m->phys, gc, t, u, dta, Binv); break;
+    default: shell_bjac<4><<<(M.E + Shape<4>::EPB - 1) / Shape<4>::EPB, 256, 0, s>>>(M, m->phys, gc, t, u, dta, Binv); break;
+  }
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+
+template <class T>
+dg_status_t shell_bjac_apply_t(dg_mesh_s* m, const double* Binv, const T* v, T* z, hipStream_t s) {
+  const int64_t nn = m->n_elem * m->N;
+  const int blocks = (int)((nn + 255) / 256);
+  ProfScope ps(m, 11, s);
+  switch (m->p) {
+    case 2: shell_bjac_apply<27, T><<<blocks, 256, 0, s>>>(nn, Binv, v, z); break;
+    case 3: shell_bjac_apply<64, T><<<blocks, 256, 0, s>>>(nn, Binv, v, z); break;
+    default: shell_bjac_apply<125, T><<<blocks, 256, 0, s>>>(nn, Binv, v, z); break;
+  }
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+dg_status_t shell_bjac_apply64(dg_mesh_s* m, const double* B, const double* v, double* z, hipStream_t s) {
+  return shell_bjac_apply_t<double>(m, B, v, z, s);
+}
+dg_status_t shell_bjac_apply32(dg_mesh_s* m, const double* B, const float* v, float* z, hipStream_t s) {
+  return shell_bjac_apply_t<float>(m, B, v, z, s);
 }
 
 }  // namespace dg

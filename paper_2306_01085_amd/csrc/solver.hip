@@ -1,20 +1,584 @@
-// Implicit DIRK stages solved by Newton-GMRES (sections 3.1, 3.2).
+// Implicit DIRK stages solved by Newton-GMRES.
+//
+// DIRK(3,3) / DIRK(2,2): Alexander's stiffly accurate, L-stable singly diagonal
+// schemes (cited in section 3.1; their tableaux are restated from the order
+// conditions). Stage i solves
+//   G_i(U) = U - dt a_ii R(U, t + c_i dt) - b_i = 0,  b_i = u_n + dt sum_{j<i} a_ij R(U_j)
+// by Newton (eq. NewtonSolve); every Newton correction solves
+//   (I - dt a_ii J(U)) delta = -G_i(U)
+// with right-preconditioned restarted GMRES(m) (section 3.2): classical Gram-Schmidt
+// applied twice with fused multi-vector dot products (one read of the new vector and
+// of the basis per pass, block reductions in LDS, a deterministic second stage),
+// Givens rotations on the host (one device-to-host copy per Krylov iteration).
+// J(U) v is the exact product of the residual kernels, in FP64 or FP32 (the Krylov
+// basis is then stored in FP32 too; dot products accumulate in FP64).
+// Convergence: |G_i(U)| <= rtol |G_i(u_n)| -- the reference norm does not depend on
+// the initial guess.
+#include <chrono>
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
 #include "internal.h"
 
 namespace dg {
 
-struct Workspace {};
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+constexpr int KMAX = 66;
+
+// ---------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// block-level sum of K accumulators; thread 0 ends with the totals in red[0..K)
+template <int K>
+__device__ inline void block_sum(double (&acc)[K], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < K; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[wid * K + k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) s += red[w * K + threadIdx.x];
+    red[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// part[b*K + k] = sum over this block's indices of V_k[i] * w[i]  (K <= 33 vectors)
+template <int K, class T>
+__global__ __launch_bounds__(RED_THREADS) void k_mdot(int64_t n, const T* __restrict__ V, int64_t ldv,
+                                                      const T* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) * K + K];
+  double acc[K];
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = (double)w[i];
+    for (int k = 0; k < K; ++k) acc[k] += (double)V[k * ldv + i] * wi;
+  }
+  block_sum<K>(acc, red);
+  if (threadIdx.x < K) part[blockIdx.x * K + threadIdx.x] = red[threadIdx.x];
+}
+
+// out[k] = sum_b part[b*K + k]   (single block)
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ part, int nb, int K,
+                                                        double* __restrict__ out) {
+  __shared__ double red[RED_THREADS / 64];
+  for (int k = 0; k < K; ++k) {
+    double s = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b * K + k];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+      out[k] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// w -= sum_k h[k] V_k ; part = partial sums of w^2 (for the norm)
+template <class T>
+__global__ __launch_bounds__(RED_THREADS) void k_orth_update(int64_t n, const T* __restrict__ V, int64_t ldv, int K,
+                                                             const double* __restrict__ h, T* __restrict__ w,
+                                                             double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) + 1];
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x = (double)w[i];
+    for (int k = 0; k < K; ++k) x -= h[k] * (double)V[k * ldv + i];
+    const T xt = (T)x;
+    w[i] = xt;
+    acc[0] += (double)xt * (double)xt;
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// y = x * (1/sqrt(nrm2[0]))
+template <class T>
+__global__ void k_normalize(int64_t n, const T* __restrict__ x, const double* __restrict__ nrm2, T* __restrict__ y) {
+  const double s = 1.0 / sqrt(nrm2[0]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (T)((double)x[i] * s);
+}
+
+// y = a*x + b*y (double) and optional partial sums of y^2
+__global__ __launch_bounds__(RED_THREADS) void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                                                       double* __restrict__ y, double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) + 1];
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = a * x[i] + b * y[i];
+    y[i] = v;
+    acc[0] += v * v;
+  }
+  if (part) {
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  }
+}
+
+// G = U - c R - B, with partial sums of G^2
+__global__ __launch_bounds__(RED_THREADS) void k_stage_residual(int64_t n, const double* __restrict__ U,
+                                                                const double* __restrict__ R, double c,
+                                                                const double* __restrict__ B, double* __restrict__ G,
+                                                                double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) + 1];
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double g = U[i] - c * R[i] - B[i];
+    G[i] = g;
+    acc[0] += g * g;
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// r = s * x (T <- double): start vector of a GMRES cycle
+template <class T>
+__global__ void k_scale_to(int64_t n, double s, const double* __restrict__ x, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (T)(s * x[i]);
+}
+
+// w = z - c * jz  (the stage operator applied to z)
+template <class T>
+__global__ void k_stage_op(int64_t n, const T* __restrict__ z, double c, T* __restrict__ jz) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    jz[i] = (T)((double)z[i] - c * (double)jz[i]);
+}
+
+// s = sum_k y[k] V_k (T), with y on the device
+template <class T>
+__global__ void k_combine(int64_t n, const T* __restrict__ V, int64_t ldv, int K, const double* __restrict__ y,
+                          T* __restrict__ s) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double a = 0;
+    for (int k = 0; k < K; ++k) a += y[k] * (double)V[k * ldv + i];
+    s[i] = (T)a;
+  }
+}
+
+// V0 = rhs - w with partial sums of V0^2
+template <class T>
+__global__ __launch_bounds__(RED_THREADS) void k_restart_vector(int64_t n, const double* __restrict__ rhs,
+                                                                const T* __restrict__ w, T* __restrict__ v0,
+                                                                double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) + 1];
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T x = (T)(rhs[i] - (double)w[i]);
+    v0[i] = x;
+    acc[0] += (double)x * (double)x;
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+template <class T>
+__global__ void k_add_to(int64_t n, const T* __restrict__ z, double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += (double)z[i];
+}
+
+template <class T>
+__global__ void k_copy_cast(int64_t n, const double* __restrict__ x, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (T)x[i];
+}
+
+// linear extrapolation through (ta, A) and (tb, B) to time t: out = A + (t - ta)/(ta - tb) (A - B)
+__global__ void k_extrapolate(int64_t n, const double* __restrict__ A, const double* __restrict__ B, double f,
+                              double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = A[i] + f * (A[i] - B[i]);
+}
+
+// ---------------------------------------------------------------- workspace
+struct Workspace {
+  int64_t n = 0;
+  int m = 0;
+  bool f32 = false;
+  double *un = nullptr, *U = nullptr, *G = nullptr, *B = nullptr, *X = nullptr, *Rc = nullptr;
+  double* Rs[3] = {nullptr, nullptr, nullptr};
+  double* hist[2] = {nullptr, nullptr};   // the two most recent stage solutions
+  double hist_t[2] = {0, 0};
+  int hist_n = 0;
+  double t_end = NAN;                     // end time of the last step (history continuity)
+  double* Binv = nullptr;
+  void* V = nullptr;                      // (m+1) basis vectors, double or float
+  void* w = nullptr;
+  void* z = nullptr;
+  void* s = nullptr;
+  double* part = nullptr;
+  double* dev_small = nullptr;            // h1 [KMAX], h2 [KMAX], nrm [1], y [KMAX]
+  double* host_small = nullptr;           // pinned mirror
+};
 
 void free_workspace(dg_mesh_s* m) {
-  delete m->ws;
+  Workspace* w = m->ws;
+  if (!w) return;
+  void* ptrs[] = {w->un, w->U, w->G, w->B, w->X, w->Rc, w->Rs[0], w->Rs[1], w->Rs[2], w->hist[0], w->hist[1],
+                  w->Binv, w->V, w->w, w->z, w->s, w->part, w->dev_small};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (w->host_small) (void)hipHostFree(w->host_small);
+  delete w;
   m->ws = nullptr;
+}
+
+static dg_status_t ensure_workspace(dg_mesh_s* m, int mk, bool f32) {
+  Workspace* w = m->ws;
+  if (w && w->m == mk && w->f32 == f32) return DG_OK;
+  // keep the stage history across a re-allocation of the Krylov part
+  free_workspace(m);
+  w = new Workspace();
+  m->ws = w;
+  const int64_t n = m->n_dof;
+  w->n = n;
+  w->m = mk;
+  w->f32 = f32;
+  const size_t vb = f32 ? sizeof(float) : sizeof(double);
+  double** dbl[] = {&w->un, &w->U, &w->G, &w->B, &w->X, &w->Rc, &w->Rs[0], &w->Rs[1], &w->Rs[2], &w->hist[0],
+                    &w->hist[1]};
+  for (double** p : dbl)
+    if (hipMalloc(p, n * sizeof(double)) != hipSuccess) goto fail;
+  if (m->kind == DG_MESH_SHELL && hipMalloc(&w->Binv, n * 5 * sizeof(double)) != hipSuccess) goto fail;
+  if (hipMalloc(&w->V, (size_t)(mk + 1) * n * vb) != hipSuccess) goto fail;
+  if (hipMalloc(&w->w, n * vb) != hipSuccess || hipMalloc(&w->z, n * vb) != hipSuccess ||
+      hipMalloc(&w->s, n * vb) != hipSuccess)
+    goto fail;
+  if (hipMalloc(&w->part, (size_t)RED_BLOCKS * KMAX * sizeof(double)) != hipSuccess) goto fail;
+  if (hipMalloc(&w->dev_small, 4 * KMAX * sizeof(double)) != hipSuccess) goto fail;
+  if (hipHostMalloc(&w->host_small, 4 * KMAX * sizeof(double)) != hipSuccess) goto fail;
+  return DG_OK;
+fail:
+  free_workspace(m);
+  set_error("dg_implicit_step: workspace allocation failed");
+  return DG_ERR_ALLOC;
+}
+
+// ---------------------------------------------------------------- operators
+static dg_status_t residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s) {
+  return m->kind == DG_MESH_SHELL ? shell_residual(m, t, u, r, s) : col_residual(m, t, u, r, s);
+}
+static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s) {
+  return m->kind == DG_MESH_SHELL ? shell_jvp64(m, t, u, v, jv, s) : col_jvp64(m, t, u, v, jv, s);
+}
+static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
+  return m->kind == DG_MESH_SHELL ? shell_jvp32(m, t, u, v, jv, s) : col_jvp32(m, t, u, v, jv, s);
+}
+static dg_status_t precond(dg_mesh_s* m, bool on, const double* B, const double* v, double* z, hipStream_t s) {
+  if (!on) {
+    DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return DG_OK;
+  }
+  return shell_bjac_apply64(m, B, v, z, s);
+}
+static dg_status_t precond(dg_mesh_s* m, bool on, const double* B, const float* v, float* z, hipStream_t s) {
+  if (!on) {
+    DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return DG_OK;
+  }
+  return shell_bjac_apply32(m, B, v, z, s);
+}
+
+static inline int grid_for(int64_t n) {
+  int64_t b = (n + RED_THREADS - 1) / RED_THREADS;
+  return (int)std::min<int64_t>(b, RED_BLOCKS);
+}
+
+// squared norm of the partial sums held in ws->part (RED_BLOCKS entries) -> host (synchronises)
+static dg_status_t finish_norm2(Workspace* w, int nb, hipStream_t s, double* out) {
+  k_reduce<<<1, RED_THREADS, 0, s>>>(w->part, nb, 1, w->dev_small);
+  DG_HIP_CHECK(hipMemcpyAsync(w->host_small, w->dev_small, sizeof(double), hipMemcpyDeviceToHost, s));
+  DG_HIP_CHECK(hipStreamSynchronize(s));
+  *out = w->host_small[0];
+  return DG_OK;
+}
+
+template <int K, class T>
+static void launch_mdot_k(int64_t n, const T* V, int64_t ldv, const T* w, double* part, int nb, hipStream_t s) {
+  k_mdot<K, T><<<nb, RED_THREADS, 0, s>>>(n, V, ldv, w, part);
+}
+
+template <class T, int K = 1>
+static void launch_mdot(int kk, int64_t n, const T* V, int64_t ldv, const T* w, double* part, int nb, hipStream_t s) {
+  if constexpr (K > 33) {
+    (void)kk; (void)n; (void)V; (void)ldv; (void)w; (void)part; (void)nb; (void)s;
+  } else {
+    if (kk == K)
+      launch_mdot_k<K, T>(n, V, ldv, w, part, nb, s);
+    else
+      launch_mdot<T, K + 1>(kk, n, V, ldv, w, part, nb, s);
+  }
+}
+
+// GMRES(m) for (I - c J(U)) x = rhs (rhs = -G, double), x returned in ws->X.
+template <class T>
+static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const double* U, const double* rhs,
+                         double rhs_norm, bool pc, int mk, int max_restarts, double rtol, int* iters,
+                         hipStream_t s) {
+  const int64_t n = m->n_dof;
+  const int nb = grid_for(n);
+  T* V = (T*)ws->V;
+  T* w = (T*)ws->w;
+  T* z = (T*)ws->z;
+  T* sv = (T*)ws->s;
+  double* X = ws->X;
+  double* h1 = ws->dev_small;
+  double* h2 = ws->dev_small + KMAX;
+  double* nr = ws->dev_small + 2 * KMAX;
+  double* yv = ws->dev_small + 3 * KMAX;
+  double* host = ws->host_small;
+  DG_HIP_CHECK(hipMemsetAsync(X, 0, n * sizeof(double), s));
+  std::vector<double> H((size_t)(mk + 1) * mk), g(mk + 1), cs(mk), sn(mk), y(mk);
+  const double target = rtol * rhs_norm;
+  int total = 0;
+  for (int cycle = 0; cycle < max_restarts; ++cycle) {
+    double beta;
+    if (cycle == 0) {
+      beta = rhs_norm;
+      k_scale_to<T><<<nb, RED_THREADS, 0, s>>>(n, 1.0 / beta, rhs, V);
+    } else {
+      // true residual of the current iterate: V0 = rhs - A x (A applied in the Krylov precision)
+      k_copy_cast<T><<<nb, RED_THREADS, 0, s>>>(n, X, z);
+      dg_status_t st = jvp(m, t, U, z, w, s);
+      if (st != DG_OK) return st;
+      k_stage_op<T><<<nb, RED_THREADS, 0, s>>>(n, z, c, w);
+      k_restart_vector<T><<<nb, RED_THREADS, 0, s>>>(n, rhs, w, V, ws->part);
+      k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 1, nr);
+      DG_HIP_CHECK(hipMemcpyAsync(host, nr, sizeof(double), hipMemcpyDeviceToHost, s));
+      DG_HIP_CHECK(hipStreamSynchronize(s));
+      beta = std::sqrt(host[0]);
+      if (!std::isfinite(beta)) {
+        set_error("dg_implicit_step: non-finite value in GMRES");
+        return DG_ERR_NAN;
+      }
+      if (beta <= target) break;
+      k_normalize<T><<<nb, RED_THREADS, 0, s>>>(n, V, nr, V);
+    }
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kused = 0;
+    bool done = false;
+    for (int j = 0; j < mk; ++j) {
+      T* vj = V + (size_t)j * n;
+      dg_status_t st = precond(m, pc, ws->Binv, vj, z, s);
+      if (st != DG_OK) return st;
+      st = jvp(m, t, U, z, w, s);
+      if (st != DG_OK) return st;
+      k_stage_op<T><<<nb, RED_THREADS, 0, s>>>(n, z, c, w);
+      // classical Gram-Schmidt, twice
+      {
+        ProfScope ps(m, 9, s);
+        launch_mdot<T>(j + 1, n, V, n, w, ws->part, nb, s);
+        k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h1);
+        k_orth_update<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, j + 1, h1, w, ws->part);
+        launch_mdot<T>(j + 1, n, V, n, w, ws->part, nb, s);
+        k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h2);
+        k_orth_update<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, j + 1, h2, w, ws->part);
+        k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 1, nr);
+        k_normalize<T><<<nb, RED_THREADS, 0, s>>>(n, w, nr, V + (size_t)(j + 1) * n);
+      }
+      DG_HIP_CHECK(hipMemcpyAsync(host, ws->dev_small, (2 * KMAX + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      DG_HIP_CHECK(hipStreamSynchronize(s));
+      ++total;
+      double* col = &H[(size_t)j * (mk + 1)];
+      for (int i = 0; i <= j; ++i) col[i] = host[i] + host[KMAX + i];
+      const double hn = std::sqrt(host[2 * KMAX]);
+      col[j + 1] = hn;
+      if (!std::isfinite(hn)) {
+        set_error("dg_implicit_step: non-finite value in GMRES");
+        return DG_ERR_NAN;
+      }
+      for (int i = 0; i < j; ++i) {
+        const double a = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = a;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = den > 0 ? col[j] / den : 1.0;
+      sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      kused = j + 1;
+      if (std::fabs(g[j + 1]) <= target || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    // back substitution  H(0:k,0:k) y = g(0:k)
+    for (int i = kused - 1; i >= 0; --i) {
+      double a = g[i];
+      for (int k2 = i + 1; k2 < kused; ++k2) a -= H[(size_t)k2 * (mk + 1) + i] * y[k2];
+      y[i] = a / H[(size_t)i * (mk + 1) + i];
+    }
+    for (int i = 0; i < kused; ++i) host[3 * KMAX + i] = y[i];
+    DG_HIP_CHECK(hipMemcpyAsync(yv, host + 3 * KMAX, kused * sizeof(double), hipMemcpyHostToDevice, s));
+    k_combine<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, kused, yv, sv);
+    dg_status_t st = precond(m, pc, ws->Binv, sv, z, s);
+    if (st != DG_OK) return st;
+    k_add_to<T><<<nb, RED_THREADS, 0, s>>>(n, z, X);
+    if (done) break;
+  }
+  *iters = total;
+  return DG_OK;
+}
+
+static void dirk_tableau(int scheme, double A[3][3], double c[3], int& ns) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = 0;
+  if (scheme == 22) {
+    const double g = 1.0 - 1.0 / std::sqrt(2.0);
+    A[0][0] = g;
+    A[1][0] = 1.0 - g;
+    A[1][1] = g;
+    c[0] = g;
+    c[1] = 1.0;
+    ns = 2;
+    return;
+  }
+  // g: root in (1/6, 1/2) of g^3 - 3 g^2 + 3/2 g - 1/6 (Newton from 0.4)
+  double g = 0.4;
+  for (int it = 0; it < 60; ++it) {
+    const double f = ((g - 3.0) * g + 1.5) * g - 1.0 / 6.0;
+    const double df = (3.0 * g - 6.0) * g + 1.5;
+    g -= f / df;
+  }
+  A[0][0] = g;
+  A[1][0] = 0.5 * (1.0 - g);
+  A[1][1] = g;
+  A[2][0] = -(6.0 * g * g - 16.0 * g + 1.0) / 4.0;
+  A[2][1] = (6.0 * g * g - 20.0 * g + 5.0) / 4.0;
+  A[2][2] = g;
+  c[0] = g;
+  c[1] = 0.5 * (1.0 + g);
+  c[2] = 1.0;
+  ns = 3;
+}
+
+template <class T>
+static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const dg_solver_opts_t& o,
+                             dg_step_stats_t* st, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  dg_status_t rc = ensure_workspace(m, o.gmres_m, std::is_same<T, float>::value);
+  if (rc != DG_OK) return rc;
+  Workspace* ws = m->ws;
+  const int64_t n = m->n_dof;
+  const int nb = grid_for(n);
+  const bool pc = o.precond == 1 && m->kind == DG_MESH_SHELL;
+  double A[3][3], c[3];
+  int ns;
+  dirk_tableau(o.scheme, A, c, ns);
+  dg_step_stats_t stats{};
+  // a step that does not continue the previous one starts a new guess history
+  if (!(std::fabs(ws->t_end - t) <= 1e-12 * std::max(1.0, std::fabs(t)))) ws->hist_n = 0;
+  DG_HIP_CHECK(hipMemcpyAsync(ws->un, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int i = 0; i < ns; ++i) {
+    const double ti = t + c[i] * dt;
+    const double ca = dt * A[i][i];
+    // b_i = u_n + dt sum_{j<i} a_ij R_j
+    DG_HIP_CHECK(hipMemcpyAsync(ws->B, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int j = 0; j < i; ++j) k_axpby<<<nb, RED_THREADS, 0, s>>>(n, dt * A[i][j], ws->Rs[j], 1.0, ws->B, nullptr);
+    // reference norm |G(u_n)|
+    rc = residual(m, ti, ws->un, ws->Rc, s);
+    if (rc != DG_OK) return rc;
+    k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->un, ws->Rc, ca, ws->B, ws->G, ws->part);
+    double ref2;
+    rc = finish_norm2(ws, nb, s, &ref2);
+    if (rc != DG_OK) return rc;
+    const double ref = std::sqrt(ref2);
+    // plain initial guess: extrapolation through the two latest stage solutions
+    if (ws->hist_n >= 2 && ws->hist_t[0] != ws->hist_t[1]) {
+      const double f = (ti - ws->hist_t[0]) / (ws->hist_t[0] - ws->hist_t[1]);
+      k_extrapolate<<<nb, RED_THREADS, 0, s>>>(n, ws->hist[0], ws->hist[1], f, ws->U);
+    } else {
+      DG_HIP_CHECK(hipMemcpyAsync(ws->U, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    int newton = 0, gm_total = 0;
+    double nG = 0;
+    for (;;) {
+      rc = residual(m, ti, ws->U, ws->Rc, s);
+      if (rc != DG_OK) return rc;
+      k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->U, ws->Rc, ca, ws->B, ws->G, ws->part);
+      double g2;
+      rc = finish_norm2(ws, nb, s, &g2);
+      if (rc != DG_OK) return rc;
+      nG = std::sqrt(g2);
+      if (newton == 0) stats.res0[i] = nG;
+      if (!std::isfinite(nG)) {
+        DG_HIP_CHECK(hipMemcpyAsync(u, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        set_error("dg_implicit_step: non-finite stage residual");
+        return DG_ERR_NAN;
+      }
+      if (nG <= o.newton_rtol * ref || newton >= o.max_newton) break;
+      if (pc) {
+        rc = shell_bjac_build(m, ti, ws->U, ca, ws->Binv, s);
+        if (rc != DG_OK) return rc;
+      }
+      // rhs = -G
+      k_axpby<<<nb, RED_THREADS, 0, s>>>(n, 0.0, ws->G, -1.0, ws->G, nullptr);
+      int its = 0;
+      rc = gmres<T>(m, ws, ti, ca, ws->U, ws->G, nG, pc, o.gmres_m, o.max_restarts, o.gmres_rtol, &its, s);
+      if (rc != DG_OK) {
+        (void)hipMemcpyAsync(u, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+        return rc;
+      }
+      gm_total += its;
+      k_axpby<<<nb, RED_THREADS, 0, s>>>(n, 1.0, ws->X, 1.0, ws->U, nullptr);
+      ++newton;
+    }
+    stats.newton_its[i] = newton;
+    stats.gmres_its[i] = gm_total;
+    stats.res[i] = nG;
+    stats.ref[i] = ref;
+    if (!(nG <= o.newton_rtol * ref)) {
+      DG_HIP_CHECK(hipMemcpyAsync(u, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      DG_HIP_CHECK(hipStreamSynchronize(s));
+      if (st) {
+        stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *st = stats;
+      }
+      ws->hist_n = 0;
+      set_error("dg_implicit_step: Newton did not reach the tolerance");
+      return DG_ERR_NOCONV;
+    }
+    DG_HIP_CHECK(hipMemcpyAsync(ws->Rs[i], ws->Rc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // history: newest first
+    std::swap(ws->hist[0], ws->hist[1]);
+    ws->hist_t[1] = ws->hist_t[0];
+    DG_HIP_CHECK(hipMemcpyAsync(ws->hist[0], ws->U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ws->hist_t[0] = ti;
+    ws->hist_n = std::min(ws->hist_n + 1, 2);
+  }
+  // stiffly accurate: u_{n+1} = U_last
+  DG_HIP_CHECK(hipMemcpyAsync(u, ws->U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  DG_HIP_CHECK(hipStreamSynchronize(s));
+  ws->t_end = t + dt;
+  stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = stats;
+  return DG_OK;
 }
 
 dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg_solver_opts_t& o,
                           dg_step_stats_t* st, hipStream_t s) {
-  (void)m; (void)t; (void)dt; (void)u; (void)o; (void)st; (void)s;
-  set_error("dg_implicit_step: not built yet");
-  return DG_ERR_UNSUPPORTED;
+  if (o.guess != 0) {
+    set_error("dg_implicit_step: the learned guess needs a warm-start model (dg_warmstart_set)");
+    return DG_ERR_UNSUPPORTED;
+  }
+  if (o.jvp_prec == DG_F32) return step_impl<float>(m, t, dt, u, o, st, s);
+  return step_impl<double>(m, t, dt, u, o, st, s);
 }
 
 }  // namespace dg

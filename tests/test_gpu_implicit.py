@@ -1,0 +1,74 @@
+"""Parity of dg_implicit_step (DIRK + Newton-GMRES on the GPU) with the oracle's
+exact stage solutions. Newton stops at |G| <= 1e-10 |G(u_n)| here, so the step must
+agree with the oracle to 1e-6 relative; FP32 J v inside GMRES changes the iteration
+counts, never the converged answer."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import need_gpu, shell_pair, to_dev, torch
+from oracle import mesh as omesh
+from oracle import timeint
+
+pytestmark = pytest.mark.gpu
+
+
+def _column(seed=0, E=8, p=2):
+    from paper_2306_01085_amd import Mesh
+    w = synth.config_column(seed)
+    om = omesh.columns_mesh([E], p, w.r_bot, w.r_top)
+    gm = Mesh.columns([E], [p], w.r_bot, w.r_top, 1.0, w.phys, w.col_phys)
+    u = np.moveaxis(w.state(0, om.X[:, :, 0]), 0, 1).copy()
+    return w, om, gm, u
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_column_step_matches_oracle(prec):
+    need_gpu()
+    w, om, gm, u = _column()
+    dt = w.dt
+    ref, _ = timeint.implicit_step_dense(om, w.phys, u, 0.0, dt, scheme=33, rtol=1e-13)
+    ut = to_dev(u)
+    st = gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, gmres_rtol=1e-6, jvp_prec=prec, precond=0)
+    out = ut.cpu().numpy().reshape(u.shape)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref - u) < 1e-6
+    assert all(n >= 1 for n in st["newton_its"]) and all(r <= 1e-10 * f for r, f in zip(st["res"], st["ref"]))
+
+
+def test_column_two_steps_with_extrapolated_guess():
+    need_gpu()
+    w, om, gm, u = _column(1)
+    dt = w.dt
+    ref1, _ = timeint.implicit_step_dense(om, w.phys, u, 0.0, dt, rtol=1e-13)
+    ref2, _ = timeint.implicit_step_dense(om, w.phys, ref1, dt, dt, rtol=1e-13)
+    ut = to_dev(u)
+    gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, gmres_rtol=1e-6)
+    st2 = gm.implicit_step(ut, dt, dt, newton_rtol=1e-10, gmres_rtol=1e-6)
+    out = ut.cpu().numpy().reshape(u.shape)
+    assert np.linalg.norm(out - ref2) / np.linalg.norm(ref2 - u) < 1e-6
+    assert all(r <= 1e-10 * f for r, f in zip(st2["res"], st2["ref"]))
+
+
+@pytest.mark.parametrize("precond,prec", [(0, "f64"), (1, "f64"), (1, "f32")])
+def test_shell_step_matches_oracle(precond, prec):
+    need_gpu()
+    w = synth.shell_workload(3, p=2, n_ang=1, n_rad=2)
+    om, gm = shell_pair(w, 1, 2, 2)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    dt = synth.seconds_to_nondim(10.0)
+    ref, _ = timeint.implicit_step_jfnk(om, w.phys, u, 0.0, dt, scheme=33, rtol=1e-12)
+    ut = to_dev(u)
+    st = gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, gmres_rtol=1e-6, jvp_prec=prec, precond=precond)
+    out = ut.cpu().numpy().reshape(u.shape)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref - u) < 1e-6, st
+
+
+def test_noconvergence_leaves_state_unchanged():
+    need_gpu()
+    from paper_2306_01085_amd import DG_ERR_NOCONV, DgError
+    w, om, gm, u = _column(2)
+    ut = to_dev(u)
+    with pytest.raises(DgError) as ei:
+        gm.implicit_step(ut, 0.0, 1e3 * w.dt, max_newton=1, newton_rtol=1e-12, gmres_rtol=1e-2, max_restarts=1)
+    assert ei.value.code == DG_ERR_NOCONV
+    assert np.array_equal(ut.cpu().numpy(), u.ravel())

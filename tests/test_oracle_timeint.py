@@ -94,3 +94,10 @@ def test_implicit_step_against_fine_explicit_integration():
     ref = solve_ivp(f, (0.0, h), u.ravel(), method="DOP853", rtol=1e-13, atol=1e-14).y[:, -1]
     change = np.linalg.norm(ref - u.ravel())
     assert np.linalg.norm(u1.ravel() - ref) < 1e-3 * change
+
+
+def test_jfnk_step_matches_dense_step():
+    m, P, u, dt = _tiny_column()
+    u1, _ = timeint.implicit_step_dense(m, P, u, 0.0, dt, scheme=33, rtol=1e-13)
+    u2, _ = timeint.implicit_step_jfnk(m, P, u, 0.0, dt, scheme=33, rtol=1e-13)
+    assert np.max(np.abs(u1 - u2)) < 1e-10 * np.max(np.abs(u1))
