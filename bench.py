@@ -36,6 +36,23 @@ def workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
+def shell_state(w, X):
+    """state at the library's nodes X [E, N, 3] (element e = cell * n_rad + layer, node
+    j = cz * n^2 + angular node): angular directions are shared by every layer and
+    every radial node of a cell, so the separable generator runs on (cell, angular
+    node) x (layer, cz)"""
+    import synth
+    n = w.p + 1
+    N2 = n * n
+    A = 6 * w.n_ang ** 2
+    Xg = X.reshape(A, w.n_rad, n, N2, 3)
+    unit = Xg[:, 0, 0] / np.linalg.norm(Xg[:, 0, 0], axis=-1, keepdims=True)      # [A, N2, 3]
+    radii = np.linalg.norm(Xg[0, :, :, 0], axis=-1)                               # [n_rad, n]
+    u = synth.shell_state_product(w.T_inf, w.pert, unit.reshape(-1, 3), radii.ravel())   # [5, A*N2, n_rad*n]
+    u = u.reshape(5, A, N2, w.n_rad, n)
+    return np.ascontiguousarray(np.transpose(u, (1, 3, 0, 4, 2))).reshape(A * w.n_rad, 5, n * N2)
+
+
 def pass1_bytes(w, prec_bytes=8):
     """algorithmic HBM bytes of one launch of the element pass (pass 1): read the
     state (plus the tangent for J v), write the partial residual, write the face
@@ -110,7 +127,7 @@ def main():
     mesh = Mesh.shell(p=w.p, n_ang=w.n_ang, n_rad=w.n_rad, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch,
                       phys=w.phys)
     X = mesh.nodes().reshape(w.n_elem, -1, 3)
-    u_np = np.moveaxis(w.state_fn()(X), 0, 1).copy()
+    u_np = shell_state(w, X)
     u = torch.from_numpy(u_np.ravel()).to(dev)
     v = torch.from_numpy(synth.tangent(u_np.shape, 1).ravel()).to(dev)
     v32 = v.float()

@@ -163,6 +163,13 @@ dg_status_t dg_implicit_step(dg_mesh_t mesh, double t, double dt, double* u, int
 dg_status_t dg_profile_enable(dg_mesh_t mesh, int32_t on);
 dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_host, int32_t n, int32_t reset);
 
+/* Tuning knobs of the launch configuration (host values, no effect on results):
+ *   "shell_pass1_config" 0..5: elements per block and register budget of the shell's
+ *   element pass (0: 256-thread blocks; 1/2: one/two elements per block; 3/4: one/two
+ *   elements with a register budget for 3 waves per SIMD; 5: one element, 4 waves).
+ * Returns DG_ERR_ARG for an unknown name or value. */
+dg_status_t dg_set_option(dg_mesh_t mesh, const char* name, int64_t value);
+
 const char* dg_last_error(void);
 int32_t dg_version(void);
 

@@ -78,15 +78,16 @@ _lib.dg_jvp.argtypes = [_vp, C.c_double, _vp, _vp, _vp, C.c_int64, C.c_int32, _v
 _lib.dg_implicit_step.argtypes = [_vp, C.c_double, C.c_double, _vp, C.c_int64, C.POINTER(SolverOpts),
                                   C.POINTER(StepStats), _vp]
 _lib.dg_profile_enable.argtypes = [_vp, C.c_int32]
+_lib.dg_set_option.argtypes = [_vp, C.c_char_p, C.c_int64]
 _lib.dg_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int32]
 for _f in ("dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh_info", "dg_mesh_nodes",
            "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_profile_enable",
-           "dg_profile_read"):
+           "dg_profile_read", "dg_set_option"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTED = ["dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh_info", "dg_mesh_nodes",
             "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_last_error", "dg_version",
-            "dg_profile_enable", "dg_profile_read"]
+            "dg_profile_enable", "dg_profile_read", "dg_set_option"]
 PROFILE_SLOTS = {0: "shell_pass1_R", 1: "shell_pass2_R", 2: "shell_pass1_jvp64", 3: "shell_pass2_jvp64",
                  4: "shell_pass1_jvp32", 5: "shell_pass2_jvp32", 6: "columns_R", 7: "columns_jvp64",
                  8: "columns_jvp32", 9: "gmres_arnoldi", 10: "bjac_build", 11: "bjac_apply", 12: "vector_ops"}
@@ -184,6 +185,9 @@ class Mesh:
         P, keep = make_physics(phys, col_phys)
         _check(_lib.dg_mesh_set_physics(self._h, C.byref(P)), "dg_mesh_set_physics")
         self.phys = dict(phys)
+
+    def set_option(self, name, value):
+        _check(_lib.dg_set_option(self._h, name.encode(), int(value)), "dg_set_option")
 
     def profile(self, on=True):
         _check(_lib.dg_profile_enable(self._h, 1 if on else 0), "dg_profile_enable")

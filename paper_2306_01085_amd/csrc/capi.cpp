@@ -106,6 +106,19 @@ dg_status_t dg_profile_read(dg_mesh_t m, double* ms, int64_t* counts, int32_t n,
   return DG_OK;
 }
 
+dg_status_t dg_set_option(dg_mesh_t m, const char* name, int64_t value) {
+  if (!m || !name) {
+    set_error("dg_set_option: null argument");
+    return DG_ERR_ARG;
+  }
+  if (std::strcmp(name, "shell_pass1_config") == 0 && value >= 0 && value <= 5) {
+    m->tune_p1 = (int)value;
+    return DG_OK;
+  }
+  set_error(std::string("dg_set_option: unknown option or value: ") + name);
+  return DG_ERR_ARG;
+}
+
 dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys, void* stream, dg_mesh_t* out) {
   if (!desc || !phys || !out) {
     set_error("dg_mesh_create: null argument");

@@ -182,15 +182,17 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
   ColDev C = m->cols();
   ProfScope ps(m, prof_base, s);
   const GllC gc[3] = {make_gllc(2), make_gllc(3), make_gllc(4)};
+  PhysC ph = m->phys;
+  sun_direction(ph, t);
   for (int pi = 0; pi < 3; ++pi) {
     const int ne = m->plist_n[pi];
     if (!ne) continue;
     const int blocks = (ne + 127) / 128;
     const int* el = m->d_plist[pi];
     switch (pi + 2) {
-      case 2: col_pass1<2, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, m->phys, gc[0], t, u, v, out, fn); break;
-      case 3: col_pass1<3, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, m->phys, gc[1], t, u, v, out, fn); break;
-      default: col_pass1<4, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, m->phys, gc[2], t, u, v, out, fn); break;
+      case 2: col_pass1<2, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[0], t, u, v, out, fn); break;
+      case 3: col_pass1<3, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[1], t, u, v, out, fn); break;
+      default: col_pass1<4, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[2], t, u, v, out, fn); break;
     }
   }
   for (int pi = 0; pi < 3; ++pi) {
@@ -199,9 +201,9 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
     const int blocks = (ne + 127) / 128;
     const int* el = m->d_plist[pi];
     switch (pi + 2) {
-      case 2: col_pass2<2, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, m->phys, gc[0], u, v, fn, out); break;
-      case 3: col_pass2<3, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, m->phys, gc[1], u, v, fn, out); break;
-      default: col_pass2<4, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, m->phys, gc[2], u, v, fn, out); break;
+      case 2: col_pass2<2, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[0], u, v, fn, out); break;
+      case 3: col_pass2<3, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[1], u, v, fn, out); break;
+      default: col_pass2<4, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[2], u, v, fn, out); break;
     }
   }
   DG_HIP_CHECK(hipGetLastError());

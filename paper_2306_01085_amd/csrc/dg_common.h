@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 namespace dg {
 
 // ---------------------------------------------------------------- dual numbers
@@ -91,6 +93,7 @@ struct PhysC {
   double om[3], cent, cor;           // rotation vector, Fr^2/gamma, 2 Fr/sqrt(gamma)
   double heat_amp, heat_qm, heat_rm, heat_inv_H;
   double sun_lat, sun_lon0, sun_rate;
+  double sun_dir[3];                 // sub-solar unit vector at the evaluation time (set per launch)
   int bc_mode;
   double bc_state[5];
 };
@@ -209,6 +212,7 @@ __device__ inline void boundary_state(const PhysC& P, const S* u, S* ub) {
 }
 
 // Chapman-shaped day-side heating at position x, time t (depends on x and t only)
+// P.sun_dir must hold the sub-solar direction at time t (sun_direction below)
 template <int D>
 __device__ inline double heating(const PhysC& P, const double* x, double t) {
   if (P.heat_amp == 0.0) return 0.0;
@@ -216,14 +220,20 @@ __device__ inline double heating(const PhysC& P, const double* x, double t) {
   for (int k = 0; k < D; ++k) r2 += x[k] * x[k];
   const double r = sqrt(r2);
   double cchi = 1.0;
-  if (D == 3) {
-    const double lon = P.sun_lon0 - P.sun_rate * t;
-    const double cl = cos(P.sun_lat);
-    cchi = (x[0] * cl * cos(lon) + x[1] * cl * sin(lon) + x[D - 1] * sin(P.sun_lat)) / r;
-  }
+  if (D == 3) cchi = (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[D - 1] * P.sun_dir[2]) / r;
+  (void)t;
   if (!(cchi > 0.0)) return 0.0;
   const double z = (r - P.heat_rm) * P.heat_inv_H;
   return P.heat_amp * P.heat_qm * exp(1.0 - z - exp(-z) / cchi);
+}
+
+// the sub-solar direction at time t: longitude sun_lon0 - sun_rate t, latitude sun_lat
+inline void sun_direction(PhysC& P, double t) {
+  const double lon = P.sun_lon0 - P.sun_rate * t;
+  const double cl = std::cos(P.sun_lat);
+  P.sun_dir[0] = cl * std::cos(lon);
+  P.sun_dir[1] = cl * std::sin(lon);
+  P.sun_dir[2] = std::sin(P.sun_lat);
 }
 
 }  // namespace dg

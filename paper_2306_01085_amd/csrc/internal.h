@@ -94,6 +94,7 @@ struct dg_mesh_s {
   float* d_fn32 = nullptr;
   int64_t fn_len = 0;
   dg::Workspace* ws = nullptr;
+  int tune_p1 = 5;                       // pass-1 launch configuration (dg_set_option)
   // per-kernel event timing (dg_profile_enable / dg_profile_read)
   bool prof = false;
   struct ProfEv { int id; hipEvent_t a, b; };

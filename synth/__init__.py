@@ -153,18 +153,23 @@ class ShellPerturbation:
     amp: float = 1e-3
     lmax: int = 8
 
-    def __call__(self, xyz):
-        x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
-        r = np.sqrt(x * x + y * y + z * z)
-        theta = np.arccos(np.clip(z / r, -1, 1))
-        phi = np.arctan2(y, x)
+    def angular(self, unit):
+        """sum_lm c_lm Y_lm at unit vectors [..., 3] -> [5, ...]"""
+        theta = np.arccos(np.clip(unit[..., 2], -1, 1))
+        phi = np.arctan2(unit[..., 1], unit[..., 0])
         Y = []
         for l in range(1, self.lmax + 1):
             for m in range(-l, l + 1):
                 Y.append(_real_sph_harm(l, m, theta, phi))
         Y = np.stack(Y, axis=-1)                  # [..., 80]
-        radial = np.sin(math.pi * (r - R_BOT) / (R_TOP - R_BOT))
-        return self.amp * np.einsum("...j,kj->k...", Y, self.coef) * radial
+        return np.einsum("...j,kj->k...", Y, self.coef)
+
+    def radial(self, r):
+        return self.amp * np.sin(math.pi * (np.asarray(r) - R_BOT) / (R_TOP - R_BOT))
+
+    def __call__(self, xyz):
+        r = np.linalg.norm(xyz, axis=-1)
+        return self.angular(xyz / r[..., None]) * self.radial(r)
 
 
 def shell_state_fn(T_inf, pert: ShellPerturbation | None):
@@ -185,6 +190,29 @@ def shell_state_fn(T_inf, pert: ShellPerturbation | None):
         U = sq[..., None] * v
         return np.stack([lr, U[..., 0], U[..., 1], U[..., 2], sq * T])
     return fn
+
+
+def shell_state_product(T_inf, pert, unit, radii):
+    """the same state as shell_state_fn on the product of M angular directions
+    (unit [M, 3]) and K radii ([K]): returns [5, M, K]. The perturbation is separable
+    (angular harmonics times a radial sine), so it is evaluated once per direction."""
+    unit = np.asarray(unit, dtype=np.float64)
+    radii = np.asarray(radii, dtype=np.float64)
+    lr = hydrostatic_logrho(radii, T_inf)[None, :]
+    T = bates_T(radii, T_inf)[None, :]
+    if pert is not None:
+        ang = pert.angular(unit)                    # [5, M]
+        rad = pert.radial(radii)                    # [K]
+        dd = ang[:, :, None] * rad[None, None, :]   # [5, M, K]
+        lr = lr + dd[0]
+        T = T * (1.0 + dd[1])
+        v = dd[2:5]
+    else:
+        lr = np.broadcast_to(lr, (len(unit), len(radii)))
+        T = np.broadcast_to(T, lr.shape)
+        v = np.zeros((3,) + lr.shape)
+    sq = np.exp(0.5 * lr)
+    return np.stack([lr, sq * v[0], sq * v[1], sq * v[2], sq * T])
 
 
 # --------------------------------------------------------------------------
