@@ -66,6 +66,7 @@ typedef struct {
   int32_t n_col;           /* columns: number of independent radial columns */
   const int32_t* col_nelem;/* columns: host [n_col] elements per column (>= 1) */
   const int32_t* col_p;    /* columns: host [n_col] degree per column, 2..4 */
+  const double* col_stretch; /* columns: optional host [n_col] growth ratio per column (NULL: stretch) */
 } dg_mesh_desc_t;
 
 /* Nondimensional physics (eq. fluxSWNondimensional, section 2.5). */
@@ -152,6 +153,22 @@ typedef struct {
 dg_status_t dg_implicit_step(dg_mesh_t mesh, double t, double dt, double* u, int64_t n_dof,
                              const dg_solver_opts_t* opts, dg_step_stats_t* stats, void* stream);
 
+/* Batched columns (the radial 1D model, section 4.1.3, used for parametric sweeps in
+ * section 4.2): advance EVERY column of a column mesh by n_steps DIRK steps
+ * (opts->scheme) from t0 in ONE persistent launch. Each wavefront takes columns from
+ * an atomic queue ordered by decreasing cost and runs the whole time loop of a
+ * column: Newton on every stage with the exact block-tridiagonal Jacobian of the 1D
+ * residual (assembled by 3-colour probing with dual numbers, factored by block LU,
+ * reused across the stages of a step). Stops a column at |G| <= newton_rtol |G(u_n)|
+ * per stage; opts->max_newton bounds the iterations per stage (gmres_*, jvp_prec,
+ * precond and guess are not used). u: device double [n_dof], in/out.
+ * newton_host / status_host: optional host [n_col] outputs (Newton iterations of the
+ * call; 0 ok, 4 no convergence, 5 non-finite). A failed column keeps its input state.
+ * Synchronises `stream`. Returns DG_ERR_NOCONV / DG_ERR_NAN if any column failed. */
+dg_status_t dg_columns_integrate(dg_mesh_t mesh, double t0, double dt, int32_t n_steps, double* u, int64_t n_dof,
+                                 const dg_solver_opts_t* opts, int32_t* newton_host, int32_t* status_host,
+                                 void* stream);
+
 /* ---- event timing of the library's own launches (tracing subsystem) ----
  * When enabled, every launch group is bracketed by hipEvents on the stream it runs on.
  * dg_profile_read synchronises those events and returns, per slot, the accumulated
@@ -159,7 +176,7 @@ dg_status_t dg_implicit_step(dg_mesh_t mesh, double t, double dt, double* u, int
  * Slots: 0 shell pass 1 (R), 1 shell pass 2 (R), 2 / 3 shell passes of J v FP64,
  * 4 / 5 shell passes of J v FP32, 6 columns R, 7 columns J v FP64, 8 columns J v FP32,
  * 9 GMRES Arnoldi (orthogonalisation), 10 block-Jacobi build, 11 block-Jacobi apply,
- * 12 vector updates. */
+ * 12 vector updates, 13 batched columns. */
 dg_status_t dg_profile_enable(dg_mesh_t mesh, int32_t on);
 dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_host, int32_t n, int32_t reset);
 
@@ -167,6 +184,7 @@ dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_hos
  *   "shell_pass1_config" 0..5: elements per block and register budget of the shell's
  *   element pass (0: 256-thread blocks; 1/2: one/two elements per block; 3/4: one/two
  *   elements with a register budget for 3 waves per SIMD; 5: one element, 4 waves).
+ *   "columns_grid" >= 1: number of persistent wavefronts of dg_columns_integrate.
  * Returns DG_ERR_ARG for an unknown name or value. */
 dg_status_t dg_set_option(dg_mesh_t mesh, const char* name, int64_t value);
 

@@ -35,6 +35,9 @@ def dirk_tableau(scheme):
 
 
 def newton_dense(Gfun, Jfun, U0, ref_norm, rtol=1e-13, maxit=30):
+    """Newton to |G| <= rtol |G(u_n)|; an iterate whose residual has stopped falling
+    (the round-off floor of the residual evaluation) is accepted once it is below
+    1e-10 |G(u_n)|"""
     U = U0.copy()
     hist = []
     for it in range(maxit):
@@ -42,6 +45,8 @@ def newton_dense(Gfun, Jfun, U0, ref_norm, rtol=1e-13, maxit=30):
         nG = np.linalg.norm(G)
         hist.append(nG)
         if nG <= rtol * ref_norm:
+            return U, it, hist
+        if len(hist) >= 3 and nG > 0.5 * hist[-2] and nG <= 1e-10 * ref_norm:
             return U, it, hist
         Jm = Jfun(U)
         U = U - np.linalg.solve(Jm, G.ravel()).reshape(U.shape)
@@ -122,11 +127,13 @@ def newton_jfnk(mesh, P, Gfun, U0, ti, aii_dt, ref_norm, rtol=1e-12, maxit=40, g
     the dense Jacobian); same stage equation and stopping rule as newton_dense"""
     from . import jac
     U = U0.copy()
+    prev = np.inf
     for it in range(maxit):
         G = Gfun(U)
         nG = np.linalg.norm(G)
-        if nG <= rtol * ref_norm:
+        if nG <= rtol * ref_norm or (nG > 0.5 * prev and nG <= 1e-10 * ref_norm):
             return U, it
+        prev = nG
         Aop = lambda v: v - aii_dt * jac.jvp_complex(mesh, P, U, v.reshape(U.shape), ti).ravel()
         dx, _ = gmres(Aop, -G.ravel(), m=60, rtol=gmres_rtol, max_restarts=200)
         U = U + dx.reshape(U.shape)

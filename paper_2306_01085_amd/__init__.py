@@ -33,7 +33,8 @@ class DgError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("p", C.c_int32), ("n_ang", C.c_int32), ("n_rad", C.c_int32),
                 ("r_bot", C.c_double), ("r_top", C.c_double), ("stretch", C.c_double),
-                ("n_col", C.c_int32), ("col_nelem", C.POINTER(C.c_int32)), ("col_p", C.POINTER(C.c_int32))]
+                ("n_col", C.c_int32), ("col_nelem", C.POINTER(C.c_int32)), ("col_p", C.POINTER(C.c_int32)),
+                ("col_stretch", C.POINTER(C.c_double))]
 
 
 class Physics(C.Structure):
@@ -77,17 +78,19 @@ _lib.dg_residual.argtypes = [_vp, C.c_double, _vp, _vp, C.c_int64, _vp]
 _lib.dg_jvp.argtypes = [_vp, C.c_double, _vp, _vp, _vp, C.c_int64, C.c_int32, _vp]
 _lib.dg_implicit_step.argtypes = [_vp, C.c_double, C.c_double, _vp, C.c_int64, C.POINTER(SolverOpts),
                                   C.POINTER(StepStats), _vp]
+_lib.dg_columns_integrate.argtypes = [_vp, C.c_double, C.c_double, C.c_int32, _vp, C.c_int64,
+                                      C.POINTER(SolverOpts), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]
 _lib.dg_profile_enable.argtypes = [_vp, C.c_int32]
 _lib.dg_set_option.argtypes = [_vp, C.c_char_p, C.c_int64]
 _lib.dg_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int32]
 for _f in ("dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh_info", "dg_mesh_nodes",
            "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_profile_enable",
-           "dg_profile_read", "dg_set_option"):
+           "dg_profile_read", "dg_set_option", "dg_columns_integrate"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTED = ["dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh_info", "dg_mesh_nodes",
             "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_last_error", "dg_version",
-            "dg_profile_enable", "dg_profile_read", "dg_set_option"]
+            "dg_profile_enable", "dg_profile_read", "dg_set_option", "dg_columns_integrate"]
 PROFILE_SLOTS = {0: "shell_pass1_R", 1: "shell_pass2_R", 2: "shell_pass1_jvp64", 3: "shell_pass2_jvp64",
                  4: "shell_pass1_jvp32", 5: "shell_pass2_jvp32", 6: "columns_R", 7: "columns_jvp64",
                  8: "columns_jvp32", 9: "gmres_arnoldi", 10: "bjac_build", 11: "bjac_apply", 12: "vector_ops"}
@@ -166,13 +169,16 @@ class Mesh:
 
     @classmethod
     def columns(cls, nelem, p, r_bot, r_top, stretch, phys, col_phys=None, stream=None):
+        """stretch: one growth ratio for every column, or an array with one per column"""
         ne = np.ascontiguousarray(np.asarray(nelem, dtype=np.int32))
         pp = np.ascontiguousarray(np.broadcast_to(np.asarray(p, dtype=np.int32), ne.shape))
-        d = MeshDesc(kind=0, p=0, n_ang=0, n_rad=0, r_bot=r_bot, r_top=r_top, stretch=stretch, n_col=len(ne),
+        sa = np.ascontiguousarray(np.broadcast_to(np.asarray(stretch, dtype=np.float64), ne.shape))
+        d = MeshDesc(kind=0, p=0, n_ang=0, n_rad=0, r_bot=r_bot, r_top=r_top, stretch=float(sa[0]), n_col=len(ne),
                      col_nelem=ne.ctypes.data_as(C.POINTER(C.c_int32)),
-                     col_p=pp.ctypes.data_as(C.POINTER(C.c_int32)))
+                     col_p=pp.ctypes.data_as(C.POINTER(C.c_int32)),
+                     col_stretch=sa.ctypes.data_as(C.POINTER(C.c_double)))
         m = cls(d, phys, col_phys, stream)
-        m.col_nelem, m.col_p = ne, pp
+        m.col_nelem, m.col_p, m.col_stretch = ne, pp, sa
         return m
 
     def __del__(self):
@@ -243,6 +249,26 @@ class Mesh:
                                      C.byref(st), _stream(stream))
         _check(code, "dg_implicit_step")
         return st.as_dict()
+
+
+def _columns_integrate(self, u, t0, dt, n_steps, scheme=33, max_newton=20, newton_rtol=1e-8, stream=None,
+                       raise_on_failure=True):
+    """advance every column by n_steps DIRK steps in one persistent launch; returns
+    (Newton iterations per column, status per column)"""
+    import torch
+    o = SolverOpts(scheme=scheme, gmres_m=1, max_newton=max_newton, max_restarts=1, newton_rtol=newton_rtol,
+                   gmres_rtol=1e-3, jvp_prec=DG_F64, precond=0, guess=0)
+    its = np.zeros(self.n_col, dtype=np.int32)
+    st = np.zeros(self.n_col, dtype=np.int32)
+    code = _lib.dg_columns_integrate(self._h, float(t0), float(dt), int(n_steps), _ptr(u, torch.float64), u.numel(),
+                                     C.byref(o), its.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     st.ctypes.data_as(C.POINTER(C.c_int32)), _stream(stream))
+    if code != DG_OK and raise_on_failure:
+        raise DgError(code, "dg_columns_integrate")
+    return its, st
+
+
+Mesh.columns_integrate = _columns_integrate
 
 
 def library_path():

@@ -1,0 +1,102 @@
+"""Autotuner of launch configurations, with a JSON cache.
+
+tune_columns: picks the number of persistent wavefronts of dg_columns_integrate
+for a column batch by timing short trial integrations (on a scratch copy of the
+state) for each candidate; tune_shell_pass1: picks the element-pass configuration
+of the shell residual. Results are cached in a JSON file keyed by the workload's
+shape (DG_TUNE_CACHE, default ~/.cache/dgthermo_tuning.json) and re-applied
+without timing on later calls.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+_CACHE = os.environ.get("DG_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "dgthermo_tuning.json"))
+
+
+def _load():
+    try:
+        with open(_CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    try:
+        os.makedirs(os.path.dirname(_CACHE), exist_ok=True)
+        tmp = _CACHE + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, _CACHE)
+    except OSError:
+        pass
+
+
+def columns_key(mesh):
+    ne = np.asarray(mesh.col_nelem)
+    pp = np.asarray(mesh.col_p)
+    hist = [int(np.sum(ne[pp == p])) for p in (2, 3, 4)]
+    return "columns:%d:%d:%d:%d" % (len(ne), *hist)
+
+
+def tune_columns(mesh, u, t0, dt, steps=1, candidates=(256, 512, 1024, 2048, 4096), force=False, log=None):
+    """choose 'columns_grid' for this batch; returns (best grid, {grid: seconds})"""
+    import torch
+    key = columns_key(mesh)
+    cache = _load()
+    if key in cache and not force:
+        mesh.set_option("columns_grid", cache[key]["grid"])
+        return cache[key]["grid"], cache[key].get("times", {})
+    times = {}
+    scratch = torch.empty_like(u)
+    for g in candidates:
+        g = int(min(g, mesh.n_col)) if g > mesh.n_col else int(g)
+        if str(g) in times:
+            continue
+        mesh.set_option("columns_grid", g)
+        scratch.copy_(u)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mesh.columns_integrate(scratch, t0, dt, steps, raise_on_failure=False)
+        torch.cuda.synchronize()
+        times[str(g)] = time.perf_counter() - t
+        if log:
+            log("columns_grid %d: %.3f s" % (g, times[str(g)]))
+    best = int(min(times, key=times.get))
+    mesh.set_option("columns_grid", best)
+    cache[key] = {"grid": best, "times": times}
+    _store(cache)
+    return best, times
+
+
+def tune_shell_pass1(mesh, u, t=0.0, reps=10, configs=range(6), force=False, log=None):
+    """choose 'shell_pass1_config' by the element pass's own event timing"""
+    key = "shell:%d:%d:%d" % (mesh.p, mesh.n_elem, mesh.n_dof)
+    cache = _load()
+    if key in cache and not force:
+        mesh.set_option("shell_pass1_config", cache[key]["config"])
+        return cache[key]["config"], cache[key].get("times", {})
+    import torch
+    r = torch.empty_like(u)
+    times = {}
+    for c in configs:
+        mesh.set_option("shell_pass1_config", c)
+        mesh.residual(u, t, out=r)
+        mesh.profile(True)
+        for _ in range(reps):
+            mesh.residual(u, t, out=r)
+        pr = mesh.profile_read()
+        mesh.profile(False)
+        times[str(c)] = pr["shell_pass1_R"][0] / reps
+        if log:
+            log("shell_pass1_config %d: %.1f us" % (c, 1e3 * times[str(c)]))
+    best = int(min(times, key=times.get))
+    mesh.set_option("shell_pass1_config", best)
+    cache[key] = {"config": best, "times": times}
+    _store(cache)
+    return best, times

@@ -51,8 +51,10 @@ static bool phys_ok(const dg_physics_t& p) {
 }
 
 static void free_mesh(dg_mesh_s* m) {
-  void* ptrs[] = {m->d_ang, m->d_edges, m->d_cnbr, m->d_cface, m->d_cmap, m->d_off,  m->d_prev, m->d_next,
-                  m->d_geo, m->d_col,   m->d_cpar, m->d_fn64,  m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2]};
+  void* ptrs[] = {m->d_ang,  m->d_edges,  m->d_cnbr,  m->d_cface,     m->d_cmap,      m->d_off,
+                  m->d_prev, m->d_next,   m->d_geo,   m->d_col,       m->d_cpar,      m->d_fn64,
+                  m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2], m->d_bstate, m->d_coloff,
+                  m->d_cols_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   free_workspace(m);
@@ -113,6 +115,10 @@ dg_status_t dg_set_option(dg_mesh_t m, const char* name, int64_t value) {
   }
   if (std::strcmp(name, "shell_pass1_config") == 0 && value >= 0 && value <= 5) {
     m->tune_p1 = (int)value;
+    return DG_OK;
+  }
+  if (std::strcmp(name, "columns_grid") == 0 && value >= 1 && value <= 65536) {
+    m->tune_cols_grid = (int)value;
     return DG_OK;
   }
   set_error(std::string("dg_set_option: unknown option or value: ") + name);
@@ -287,6 +293,18 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
     return DG_ERR_ARG;
   }
   return implicit_step(m, t, dt, u, *opts, stats, (hipStream_t)stream);
+}
+
+dg_status_t dg_columns_integrate(dg_mesh_t m, double t0, double dt, int32_t n_steps, double* u, int64_t n_dof,
+                                 const dg_solver_opts_t* opts, int32_t* newton_host, int32_t* status_host,
+                                 void* stream) {
+  if (!m || !u || !opts || m->kind != DG_MESH_COLUMNS || n_dof != m->n_dof || !(dt > 0) || n_steps < 0 ||
+      (opts->scheme != 33 && opts->scheme != 22) || opts->max_newton < 1 || !(opts->newton_rtol > 0)) {
+    set_error("dg_columns_integrate: invalid argument (needs a column mesh)");
+    return DG_ERR_ARG;
+  }
+  if (n_steps == 0) return DG_OK;
+  return columns_integrate(m, t0, dt, n_steps, u, *opts, newton_host, status_host, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -4,6 +4,10 @@
 // form. One thread per element; the same two-pass split as the shell kernels
 // (pass 1: everything an element can do alone, writing its face traces F.n;
 // pass 2: neighbour halves and the interior-face stabilisation).
+#include <algorithm>
+#include <string>
+#include <vector>
+
 #include "internal.h"
 
 namespace dg {
@@ -23,118 +27,122 @@ __device__ inline PhysC column_phys(const ColDev& C, const PhysC& ph, int col) {
   return P;
 }
 
+// one element of a column: DOF offsets of itself and of its neighbours (-1 on a
+// boundary), its bottom radius and thickness, and its slot in the face-trace array
+struct ColElem {
+  int64_t off, off_prev, off_next;
+  double r0, h;
+  int64_t fslot, fslot_prev, fslot_next;   // Fn[(fslot*2 + side)*3 + c]
+};
+
 template <int P, class S, class SU, class TV, class OT>
-__global__ __launch_bounds__(128) void col_pass1(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc, double t,
-                                                 const SU* __restrict__ u, const TV* __restrict__ v,
-                                                 OT* __restrict__ R, OT* __restrict__ Fn) {
+__device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& Pc, const GllC& gc, double t,
+                                      const SU* __restrict__ u, const TV* __restrict__ v, OT* __restrict__ R,
+                                      OT* __restrict__ Fn) {
   typedef typename Base<S>::type T;
   constexpr int n = P + 1;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ne) return;
-  const int e = elist[idx];
-  const PhysC Pc = column_phys(C, ph, C.col[e]);
   const double* D = gc.D;
   const double* xg = gc.x;
   const double w_end = gc.w[0];
-  const int64_t off = C.off[e];
-  const double r0 = C.geo[2 * e], h = C.geo[2 * e + 1];
+  const int64_t off = ce.off;
+  const double r0 = ce.r0, h = ce.h;
   const double Jac = 0.5 * h, invJ = 1.0 / Jac, lfac = 1.0 / (w_end * Jac);
-  const int ep = C.prev[e], en = C.next[e];
+  const bool hp = ce.off_prev >= 0, hn = ce.off_next >= 0;
+  const int64_t e = ce.fslot;
   S uu[3][n];
   for (int c = 0; c < 3; ++c)
     for (int i = 0; i < n; ++i) uu[c][i] = Io<S>::ld(u, v, off + c * n + i);
-  S q[3][n][1];
-  for (int c = 0; c < 3; ++c)
-    for (int i = 0; i < n; ++i) {
-      S s = S(T(0));
-      for (int l = 0; l < n; ++l) s = s + uu[c][l] * T(D[i * n + l]);
-      q[c][i][0] = s * T(invJ);
-    }
-  // lift of (u_hat - u): lower face (Sn = -1), upper face (Sn = +1)
+  // face traces u_hat - u at the two end nodes (lift of the gradient)
+  S dlo[3], dhi[3];
   {
     S u0[3], ub[3];
     for (int c = 0; c < 3; ++c) u0[c] = uu[c][0];
-    if (ep >= 0) {
-      const int64_t o2 = C.off[ep];
-      for (int c = 0; c < 3; ++c) ub[c] = T(0.5) * (Io<S>::ld(u, v, o2 + c * n + (n - 1)) + u0[c]);
+    if (hp) {
+      for (int c = 0; c < 3; ++c) dlo[c] = T(0.5) * (Io<S>::ld(u, v, ce.off_prev + c * n + (n - 1)) - u0[c]);
     } else {
       boundary_state<1, S>(Pc, u0, ub);
+      for (int c = 0; c < 3; ++c) dlo[c] = ub[c] - u0[c];
     }
-    for (int c = 0; c < 3; ++c) q[c][0][0] = q[c][0][0] - (ub[c] - u0[c]) * T(lfac);
-    S ut[3];
-    for (int c = 0; c < 3; ++c) ut[c] = uu[c][n - 1];
-    bool have = true;
-    if (en >= 0) {
-      const int64_t o2 = C.off[en];
-      for (int c = 0; c < 3; ++c) ub[c] = T(0.5) * (Io<S>::ld(u, v, o2 + c * n) + ut[c]);
+    for (int c = 0; c < 3; ++c) u0[c] = uu[c][n - 1];
+    if (hn) {
+      for (int c = 0; c < 3; ++c) dhi[c] = T(0.5) * (Io<S>::ld(u, v, ce.off_next + c * n) - u0[c]);
     } else if (Pc.bc_mode == 1) {
-      boundary_state<1, S>(Pc, ut, ub);
+      boundary_state<1, S>(Pc, u0, ub);
+      for (int c = 0; c < 3; ++c) dhi[c] = ub[c] - u0[c];
     } else {
-      have = false;
+      for (int c = 0; c < 3; ++c) dhi[c] = S(T(0));
     }
-    if (have)
-      for (int c = 0; c < 3; ++c) q[c][n - 1][0] = q[c][n - 1][0] + (ub[c] - ut[c]) * T(lfac);
   }
-  S F[3][n][1], Sr[3][n];
+  // node by node: q_i, flux and source, accumulated into the divergence of every node
+  S Rl[3][n];
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < n; ++i) Rl[c][i] = S(T(0));
+  S Flo[3], Fhi[3], qlo[3][1], qhi[3][1];
   for (int i = 0; i < n; ++i) {
     S ui[3], qi[3][1], Fi[3][1], Si[3];
-    for (int c = 0; c < 3; ++c) { ui[c] = uu[c][i]; qi[c][0] = q[c][i][0]; }
+    for (int c = 0; c < 3; ++c) {
+      ui[c] = uu[c][i];
+      S g = S(T(0));
+      for (int l = 0; l < n; ++l) g = g + uu[c][l] * T(D[i * n + l]);
+      g = g * T(invJ);
+      if (i == 0) g = g - dlo[c] * T(lfac);
+      if (i == n - 1) g = g + dhi[c] * T(lfac);
+      qi[c][0] = g;
+    }
     const double x = r0 + 0.5 * (xg[i] + 1.0) * h;
     const double Q = heating<1>(Pc, &x, t);
     flux_source<1, S>(Pc, ui, qi, &x, Q, Fi, Si);
-    for (int c = 0; c < 3; ++c) { F[c][i][0] = Fi[c][0]; Sr[c][i] = Si[c]; }
-  }
-  S Rl[3][n];
-  for (int c = 0; c < 3; ++c)
-    for (int i = 0; i < n; ++i) {
-      S dv = S(T(0));
-      for (int l = 0; l < n; ++l) dv = dv + F[c][l][0] * T(D[i * n + l]);
-      Rl[c][i] = Sr[c][i] - dv * T(invJ);
-    }
-  // lower face
-  if (ep >= 0) {
     for (int c = 0; c < 3; ++c) {
-      const S fsn = -F[c][0][0];
+      Rl[c][i] = Rl[c][i] + Si[c];
+      for (int r = 0; r < n; ++r) Rl[c][r] = Rl[c][r] - Fi[c][0] * T(D[r * n + i] * invJ);
+      if (i == 0) { Flo[c] = Fi[c][0]; qlo[c][0] = qi[c][0]; }
+      if (i == n - 1) { Fhi[c] = Fi[c][0]; qhi[c][0] = qi[c][0]; }
+    }
+  }
+  // lower face
+  if (hp) {
+    for (int c = 0; c < 3; ++c) {
+      const S fsn = -Flo[c];
       Rl[c][0] = Rl[c][0] + T(0.5 * lfac) * fsn;
-      Fn[((int64_t)e * 2 + 0) * 3 + c] = outc(fsn);
+      Fn[(e * 2 + 0) * 3 + c] = outc(fsn);
     }
   } else {
-    S u0[3], ub[3], qi[3][1], Fb[3][1], Sb[3], sm, se;
-    for (int c = 0; c < 3; ++c) { u0[c] = uu[c][0]; qi[c][0] = q[c][0][0]; }
+    S u0[3], ub[3], Fb[3][1], Sb[3], sm, se;
+    for (int c = 0; c < 3; ++c) u0[c] = uu[c][0];
     boundary_state<1, S>(Pc, u0, ub);
     const double x = r0;
-    flux_source<1, S>(Pc, ub, qi, &x, 0.0, Fb, Sb);
+    flux_source<1, S>(Pc, ub, qlo, &x, 0.0, Fb, Sb);
     sigma<1, S>(Pc, ub, sm, se);
     for (int c = 0; c < 3; ++c) {
       const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
-      const S fd = -(F[c][0][0] - Fb[c][0]);
+      const S fd = -(Flo[c] - Fb[c][0]);
       Rl[c][0] = Rl[c][0] + (fd - sg * (u0[c] - ub[c])) * T(lfac);
     }
   }
   // upper face
-  if (en >= 0) {
+  if (hn) {
     for (int c = 0; c < 3; ++c) {
-      const S fsn = F[c][n - 1][0];
+      const S fsn = Fhi[c];
       Rl[c][n - 1] = Rl[c][n - 1] + T(0.5 * lfac) * fsn;
-      Fn[((int64_t)e * 2 + 1) * 3 + c] = outc(fsn);
+      Fn[(e * 2 + 1) * 3 + c] = outc(fsn);
     }
   } else {
-    S ut[3], qi[3][1];
-    for (int c = 0; c < 3; ++c) { ut[c] = uu[c][n - 1]; qi[c][0] = q[c][n - 1][0]; }
+    S ut[3];
+    for (int c = 0; c < 3; ++c) ut[c] = uu[c][n - 1];
     if (Pc.bc_mode == 1) {
       S ub[3], Fb[3][1], Sb[3], sm, se;
       boundary_state<1, S>(Pc, ut, ub);
       const double x = r0 + h;
-      flux_source<1, S>(Pc, ub, qi, &x, 0.0, Fb, Sb);
+      flux_source<1, S>(Pc, ub, qhi, &x, 0.0, Fb, Sb);
       sigma<1, S>(Pc, ub, sm, se);
       for (int c = 0; c < 3; ++c) {
         const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
-        Rl[c][n - 1] = Rl[c][n - 1] + ((F[c][n - 1][0] - Fb[c][0]) - sg * (ut[c] - ub[c])) * T(lfac);
+        Rl[c][n - 1] = Rl[c][n - 1] + ((Fhi[c] - Fb[c][0]) - sg * (ut[c] - ub[c])) * T(lfac);
       }
     } else {
       S Fi[3][1];
       flux_inviscid<1, S>(Pc, ut, Fi);
-      for (int c = 0; c < 3; ++c) Rl[c][n - 1] = Rl[c][n - 1] + (F[c][n - 1][0] - Fi[c][0]) * T(lfac);
+      for (int c = 0; c < 3; ++c) Rl[c][n - 1] = Rl[c][n - 1] + (Fhi[c] - Fi[c][0]) * T(lfac);
     }
   }
   for (int c = 0; c < 3; ++c)
@@ -142,25 +150,19 @@ __global__ __launch_bounds__(128) void col_pass1(ColDev C, const int* __restrict
 }
 
 template <int P, class S, class SU, class TV, class OT>
-__global__ __launch_bounds__(128) void col_pass2(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
-                                                 const SU* __restrict__ u, const TV* __restrict__ v,
-                                                 const OT* __restrict__ Fn, OT* __restrict__ R) {
+__device__ __forceinline__ void col_elem_pass2(const ColElem& ce, const PhysC& Pc, const GllC& gc, const SU* __restrict__ u,
+                                      const TV* __restrict__ v, const OT* __restrict__ Fn, OT* __restrict__ R) {
   typedef typename Base<S>::type T;
   constexpr int n = P + 1;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ne) return;
-  const int e = elist[idx];
-  const PhysC Pc = column_phys(C, ph, C.col[e]);
   const double w_end = gc.w[0];
-  const int64_t off = C.off[e];
-  const double h = C.geo[2 * e + 1];
-  const double lfac = 1.0 / (w_end * 0.5 * h);
+  const int64_t off = ce.off;
+  const double lfac = 1.0 / (w_end * 0.5 * ce.h);
   for (int side = 0; side < 2; ++side) {
-    const int nb = side ? C.next[e] : C.prev[e];
-    if (nb < 0) continue;
+    const int64_t o2 = side ? ce.off_next : ce.off_prev;
+    if (o2 < 0) continue;
+    const int64_t nb = side ? ce.fslot_next : ce.fslot_prev;
     const int i = side ? n - 1 : 0;
     const int inb = side ? 0 : n - 1;
-    const int64_t o2 = C.off[nb];
     S ui[3], uh[3];
     for (int c = 0; c < 3; ++c) {
       ui[c] = Io<S>::ld(u, v, off + c * n + i);
@@ -170,10 +172,44 @@ __global__ __launch_bounds__(128) void col_pass2(ColDev C, const int* __restrict
     sigma<1, S>(Pc, uh, sm, se);
     for (int c = 0; c < 3; ++c) {
       const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
-      const OT fnb = Fn[((int64_t)nb * 2 + (1 - side)) * 3 + c];
+      const OT fnb = Fn[(nb * 2 + (1 - side)) * 3 + c];
       R[off + c * n + i] += OT(lfac) * (OT(0.5) * fnb - outc(sg * (ui[c] - uh[c])));
     }
   }
+}
+
+__device__ inline ColElem col_elem_of(const ColDev& C, int e) {
+  ColElem ce;
+  ce.off = C.off[e];
+  const int ep = C.prev[e], en = C.next[e];
+  ce.off_prev = ep >= 0 ? C.off[ep] : -1;
+  ce.off_next = en >= 0 ? C.off[en] : -1;
+  ce.r0 = C.geo[2 * e];
+  ce.h = C.geo[2 * e + 1];
+  ce.fslot = e;
+  ce.fslot_prev = ep;
+  ce.fslot_next = en;
+  return ce;
+}
+
+template <int P, class S, class SU, class TV, class OT>
+__global__ __launch_bounds__(128) void col_pass1(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
+                                                 double t, const SU* __restrict__ u, const TV* __restrict__ v,
+                                                 OT* __restrict__ R, OT* __restrict__ Fn) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ne) return;
+  const int e = elist[idx];
+  col_elem_pass1<P, S>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, t, u, v, R, Fn);
+}
+
+template <int P, class S, class SU, class TV, class OT>
+__global__ __launch_bounds__(128) void col_pass2(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
+                                                 const SU* __restrict__ u, const TV* __restrict__ v,
+                                                 const OT* __restrict__ Fn, OT* __restrict__ R) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ne) return;
+  const int e = elist[idx];
+  col_elem_pass2<P, S>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, u, v, Fn, R);
 }
 
 template <class S, class SU, class TV, class OT>
@@ -218,6 +254,473 @@ dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, 
 }
 dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
   return launch_cols<Dual<float>, double, float, float>(m, t, u, v, jv, m->d_fn32, s, 8);
+}
+
+
+// ======================================================================== batched columns
+// Many independent columns advanced by n_steps DIRK steps in ONE persistent launch.
+// Every 64-thread workgroup (one wavefront) pops column ids from an atomic queue
+// ordered by decreasing cost and runs the whole time loop of that column:
+//  * stage equations G_i(U) = U - dt a_ii R(U) - b_i = 0 solved by Newton;
+//  * the Jacobian of R is block tridiagonal in 1D (the LDG lift is collocated at
+//    the face node, so R of an element depends on its own and its two neighbours'
+//    states only); it is assembled exactly by 3-colour probing with dual numbers
+//    (3 * 3(p+1) directional derivatives), then I - dt a_ii J is factored by block
+//    LU (Gauss-Jordan inverses of the diagonal blocks, partial pivoting);
+//  * a_ii is the same for every stage (singly diagonal), so one factorization per
+//    step serves the chord-Newton iterations of all stages; it is refreshed at the
+//    current iterate when a stage stalls.
+// The converged stage solutions are those of the implicit step; only the iteration
+// path differs from GMRES.
+namespace {
+
+struct ColBatch {
+  int n_col;
+  const int* order;
+  int* counter;
+  const int* col_E;
+  const int* col_p;
+  const int64_t* col_off;
+  const int* col_e0;
+  const double* geo;
+  const double* cpar;
+  double* u;
+  double t0, dt;
+  int n_steps, n_stages;
+  double A[3][3], c[3];
+  int max_newton;
+  double rtol;
+  double* ws;
+  int64_t ws_stride;
+  int max_dof;
+  int* newton_total;
+  int* status;
+  int* jac_builds;
+};
+
+__device__ inline double wave_allsum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+template <int P, class S, class TV, class OT>
+__device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
+                              const double* u, const TV* v, OT* out, OT* fn) {
+  constexpr int b = 3 * (P + 1);
+  const int lane = threadIdx.x;
+  for (int el = lane; el < E; el += 64) {
+    ColElem ce;
+    ce.off = (int64_t)el * b;
+    ce.off_prev = el > 0 ? (int64_t)(el - 1) * b : -1;
+    ce.off_next = el < E - 1 ? (int64_t)(el + 1) * b : -1;
+    ce.r0 = B.geo[2 * (e0 + el)];
+    ce.h = B.geo[2 * (e0 + el) + 1];
+    ce.fslot = el;
+    ce.fslot_prev = el - 1;
+    ce.fslot_next = el + 1;
+    col_elem_pass1<P, S>(ce, Pc, gc, t, u, v, out, fn);
+  }
+  __syncthreads();
+  for (int el = lane; el < E; el += 64) {
+    ColElem ce;
+    ce.off = (int64_t)el * b;
+    ce.off_prev = el > 0 ? (int64_t)(el - 1) * b : -1;
+    ce.off_next = el < E - 1 ? (int64_t)(el + 1) * b : -1;
+    ce.r0 = B.geo[2 * (e0 + el)];
+    ce.h = B.geo[2 * (e0 + el) + 1];
+    ce.fslot = el;
+    ce.fslot_prev = el - 1;
+    ce.fslot_next = el + 1;
+    col_elem_pass2<P, S>(ce, Pc, gc, u, v, fn, out);
+  }
+  __syncthreads();
+}
+
+// G = U - ca R - Bv; returns |G|^2 (all lanes)
+__device__ inline double colw_stage_residual(int nd, const double* U, const double* R, double ca, const double* Bv,
+                                             double* G) {
+  double acc = 0;
+  for (int i = threadIdx.x; i < nd; i += 64) {
+    const double g = U[i] - ca * R[i] - Bv[i];
+    G[i] = g;
+    acc += g * g;
+  }
+  __syncthreads();
+  return wave_allsum(acc);
+}
+
+// in-place inverse of a b x b block (row-major) by Gauss-Jordan with partial pivoting
+template <int b>
+__device__ __forceinline__ void colw_invert(double* blk, double (*M)[2 * b], double* fac, int* piv_s) {
+  const int lane = threadIdx.x;
+  for (int idx = lane; idx < b * 2 * b; idx += 64) {
+    const int r = idx / (2 * b), c = idx % (2 * b);
+    M[r][c] = c < b ? blk[r * b + c] : (c - b == r ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    if (lane == 0) {
+      int piv = k;
+      double best = fabs(M[k][k]);
+      for (int r = k + 1; r < b; ++r)
+        if (fabs(M[r][k]) > best) {
+          best = fabs(M[r][k]);
+          piv = r;
+        }
+      *piv_s = piv;
+    }
+    __syncthreads();
+    const int piv = *piv_s;
+    if (piv != k)
+      for (int c = lane; c < 2 * b; c += 64) {
+        const double tmp = M[k][c];
+        M[k][c] = M[piv][c];
+        M[piv][c] = tmp;
+      }
+    __syncthreads();
+    const double inv = 1.0 / M[k][k];
+    __syncthreads();
+    for (int c = lane; c < 2 * b; c += 64) M[k][c] *= inv;
+    if (lane < b) fac[lane] = M[lane][k];
+    __syncthreads();
+    for (int idx = lane; idx < b * 2 * b; idx += 64) {
+      const int r = idx / (2 * b), c = idx % (2 * b);
+      if (r != k) M[r][c] -= fac[r] * M[k][c];
+    }
+    __syncthreads();
+  }
+  for (int idx = lane; idx < b * b; idx += 64) blk[idx] = M[idx / b][b + idx % b];
+  __syncthreads();
+}
+
+template <int P>
+__device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
+                                      double ca, const double* U, double* V, double* Jv, double* fnT, double* Lo,
+                                      double* Di, double* Up) {
+  constexpr int b = 3 * (P + 1);
+  constexpr int bb = b * b;
+  const int lane = threadIdx.x;
+  const int nd = E * b;
+  __shared__ double M[b][2 * b];
+  __shared__ double fac[b];
+  __shared__ double tmp[bb];
+  __shared__ int piv_s;
+  for (int kap = 0; kap < 3; ++kap)
+    for (int l = 0; l < b; ++l) {
+      for (int i = lane; i < nd; i += 64) V[i] = (((i / b) % 3 == kap) && (i % b == l)) ? 1.0 : 0.0;
+      __syncthreads();
+      colw_residual<P, Dual<double>, double, double>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
+      for (int idx = lane; idx < E * b; idx += 64) {
+        const int ep = idx / b, r = idx % b;
+        for (int d = -1; d <= 1; ++d) {
+          const int e = ep + d;
+          if (e < 0 || e >= E || e % 3 != kap) continue;
+          double* blk = (d == -1) ? Lo : (d == 0 ? Di : Up);
+          blk[(int64_t)ep * bb + r * b + l] = (d == 0 && r == l ? 1.0 : 0.0) - ca * Jv[ep * b + r];
+        }
+      }
+      __syncthreads();
+    }
+  // block LU: Di <- inverse of the Schur complements, Up <- W = Dinv * Up
+  for (int e = 0; e < E; ++e) {
+    double* D = Di + (int64_t)e * bb;
+    if (e > 0) {
+      const double* L = Lo + (int64_t)e * bb;
+      const double* W = Up + (int64_t)(e - 1) * bb;
+      for (int idx = lane; idx < bb; idx += 64) {
+        const int r = idx / b, c = idx % b;
+        double s = 0;
+        for (int k = 0; k < b; ++k) s += L[r * b + k] * W[k * b + c];
+        tmp[idx] = s;
+      }
+      __syncthreads();
+      for (int idx = lane; idx < bb; idx += 64) D[idx] -= tmp[idx];
+      __syncthreads();
+    }
+    colw_invert<b>(D, M, fac, &piv_s);
+    if (e < E - 1) {
+      double* Uu = Up + (int64_t)e * bb;
+      for (int idx = lane; idx < bb; idx += 64) {
+        const int r = idx / b, c = idx % b;
+        double s = 0;
+        for (int k = 0; k < b; ++k) s += D[r * b + k] * Uu[k * b + c];
+        tmp[idx] = s;
+      }
+      __syncthreads();
+      for (int idx = lane; idx < bb; idx += 64) Uu[idx] = tmp[idx];
+      __syncthreads();
+    }
+  }
+}
+
+// solve (I - ca J) X = rhs with the factored blocks; rhs in X on entry
+template <int P>
+__device__ __forceinline__ void colw_solve(int E, const double* Lo, const double* Di, const double* Up, double* X) {
+  constexpr int b = 3 * (P + 1);
+  constexpr int bb = b * b;
+  const int lane = threadIdx.x;
+  __shared__ double y[b];
+  for (int e = 0; e < E; ++e) {
+    double* xe = X + e * b;
+    if (e > 0 && lane < b) {
+      const double* L = Lo + (int64_t)e * bb;
+      const double* xp = X + (e - 1) * b;
+      double s = 0;
+      for (int k = 0; k < b; ++k) s += L[lane * b + k] * xp[k];
+      xe[lane] -= s;
+    }
+    __syncthreads();
+    if (lane < b) {
+      const double* D = Di + (int64_t)e * bb;
+      double s = 0;
+      for (int k = 0; k < b; ++k) s += D[lane * b + k] * xe[k];
+      y[lane] = s;
+    }
+    __syncthreads();
+    if (lane < b) xe[lane] = y[lane];
+    __syncthreads();
+  }
+  for (int e = E - 2; e >= 0; --e) {
+    if (lane < b) {
+      const double* W = Up + (int64_t)e * bb;
+      const double* xn = X + (e + 1) * b;
+      double s = 0;
+      for (int k = 0; k < b; ++k) s += W[lane * b + k] * xn[k];
+      X[e * b + lane] -= s;
+    }
+    __syncthreads();
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC& ph, const GllC& gc) {
+  constexpr int b = 3 * (P + 1);
+  const int lane = threadIdx.x;
+  const int E = B.col_E[col];
+  const int e0 = B.col_e0[col];
+  const int nd = E * b;
+  PhysC Pc = ph;
+  {
+    const double* cp = B.cpar + 5 * col;
+    Pc.heat_amp = cp[0];
+    Pc.heat_qm = cp[1];
+    Pc.heat_rm = cp[2];
+    Pc.heat_inv_H = cp[3];
+    Pc.lam = cp[4];
+  }
+  double* w = B.ws + (int64_t)blockIdx.x * B.ws_stride;
+  const int64_t md = B.max_dof;
+  double* U = w;
+  double* G = U + md;
+  double* Bv = G + md;
+  double* un = Bv + md;
+  double* X = un + md;
+  double* Rc = X + md;
+  double* Rs = Rc + md;           // 3 stage residuals
+  double* V = Rs + 3 * md;
+  double* Jv = V + md;
+  double* fn = Jv + md;           // [maxE][2][3]
+  double* fnT = fn + md;
+  double* Lo = fnT + md;
+  const int64_t blk_len = (int64_t)(md / b + 1) * b * b;
+  double* Di = Lo + blk_len;
+  double* Up = Di + blk_len;
+  double* ug = B.u + B.col_off[col];
+  for (int i = lane; i < nd; i += 64) un[i] = ug[i];
+  __syncthreads();
+  const double ca = B.dt * B.A[0][0];
+  int newton_total = 0, builds = 0, status = 0;
+  for (int step = 0; step < B.n_steps && status == 0; ++step) {
+    const double t = B.t0 + step * B.dt;
+    // chord Jacobian at the start of the step
+    colw_build_and_factor<P>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
+    ++builds;
+    for (int i = lane; i < nd; i += 64) U[i] = un[i];
+    __syncthreads();
+    for (int s = 0; s < B.n_stages && status == 0; ++s) {
+      const double ti = t + B.c[s] * B.dt;
+      for (int i = lane; i < nd; i += 64) {
+        double bv = un[i];
+        for (int j = 0; j < s; ++j) bv += B.dt * B.A[s][j] * Rs[j * md + i];
+        Bv[i] = bv;
+      }
+      __syncthreads();
+      colw_residual<P, double, double, double>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
+      const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, G));
+      int it = 0, since_build = 0;
+      for (;;) {
+        colw_residual<P, double, double, double>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
+        const double nG = sqrt(colw_stage_residual(nd, U, Rc, ca, Bv, G));
+        if (!isfinite(nG)) {
+          status = 5;
+          break;
+        }
+        if (nG <= B.rtol * ref) break;
+        if (it >= B.max_newton) {
+          status = 4;
+          break;
+        }
+        if (since_build >= 6) {
+          colw_build_and_factor<P>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
+          ++builds;
+          since_build = 0;
+        }
+        for (int i = lane; i < nd; i += 64) X[i] = -G[i];
+        __syncthreads();
+        colw_solve<P>(E, Lo, Di, Up, X);
+        for (int i = lane; i < nd; i += 64) U[i] += X[i];
+        __syncthreads();
+        ++it;
+        ++since_build;
+      }
+      newton_total += it;
+      for (int i = lane; i < nd; i += 64) Rs[s * md + i] = Rc[i];
+      __syncthreads();
+    }
+    if (status == 0) {
+      for (int i = lane; i < nd; i += 64) un[i] = U[i];
+      __syncthreads();
+    }
+  }
+  if (status == 0)
+    for (int i = lane; i < nd; i += 64) ug[i] = un[i];
+  if (lane == 0) {
+    B.newton_total[col] = newton_total;
+    B.status[col] = status;
+    B.jac_builds[col] = builds;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_columns_persistent(ColBatch B, PhysC ph, GllC g2, GllC g3, GllC g4) {
+  __shared__ int s_k;
+  for (;;) {
+    if (threadIdx.x == 0) s_k = atomicAdd(B.counter, 1);
+    __syncthreads();
+    const int k = s_k;
+    __syncthreads();
+    if (k >= B.n_col) break;
+    const int col = B.order[k];
+    switch (B.col_p[col]) {
+      case 2: colw_run<2>(B, col, ph, g2); break;
+      case 3: colw_run<3>(B, col, ph, g3); break;
+      default: colw_run<4>(B, col, ph, g4); break;
+    }
+  }
+}
+
+dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, double* u, const dg_solver_opts_t& o,
+                              int32_t* newton_host, int32_t* status_host, hipStream_t s) {
+  ColBatch B{};
+  const int nc = m->n_col;
+  if (!m->d_bstate) {
+    std::vector<int> colE(nc), colp(nc), e0(nc);
+    std::vector<int64_t> off(nc);
+    int acc = 0;
+    for (int c = 0; c < nc; ++c) {
+      colE[c] = m->col_nelem[c];
+      colp[c] = m->col_p[c];
+      e0[c] = acc;
+      acc += colE[c];
+      off[c] = m->col_off[c];
+    }
+    std::vector<int> order(nc);
+    for (int c = 0; c < nc; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return (double)colE[a] * (colp[a] + 1) * (colp[a] + 1) > (double)colE[b] * (colp[b] + 1) * (colp[b] + 1);
+    });
+    DG_HIP_CHECK(hipMalloc(&m->d_bstate, (size_t)nc * 8 * sizeof(int) + 64));
+    int* base = m->d_bstate;
+    DG_HIP_CHECK(hipMemcpy(base, colE.data(), nc * sizeof(int), hipMemcpyHostToDevice));
+    DG_HIP_CHECK(hipMemcpy(base + nc, colp.data(), nc * sizeof(int), hipMemcpyHostToDevice));
+    DG_HIP_CHECK(hipMemcpy(base + 2 * nc, e0.data(), nc * sizeof(int), hipMemcpyHostToDevice));
+    DG_HIP_CHECK(hipMemcpy(base + 3 * nc, order.data(), nc * sizeof(int), hipMemcpyHostToDevice));
+    DG_HIP_CHECK(hipMalloc(&m->d_coloff, nc * sizeof(int64_t)));
+    DG_HIP_CHECK(hipMemcpy(m->d_coloff, off.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice));
+    int maxd = 0;
+    for (int c = 0; c < nc; ++c) maxd = std::max(maxd, colE[c] * 3 * (colp[c] + 1));
+    m->col_max_dof = maxd;
+  }
+  int* base = m->d_bstate;
+  const int slots = std::max(1, std::min(nc, m->tune_cols_grid));
+  const int64_t md = m->col_max_dof;
+  const int64_t blk = (md / 9 + 1) * 15 * 15;   // generous: b >= 9 so md/b <= md/9 elements
+  const int64_t stride = 14 * md + 3 * blk + 64;
+  if (m->cols_ws_len < stride * slots) {
+    if (m->d_cols_ws) (void)hipFree(m->d_cols_ws);
+    m->d_cols_ws = nullptr;
+    m->cols_ws_len = 0;
+    DG_HIP_CHECK(hipMalloc(&m->d_cols_ws, (size_t)stride * slots * sizeof(double)));
+    m->cols_ws_len = stride * slots;
+  }
+  B.n_col = nc;
+  B.col_E = base;
+  B.col_p = base + nc;
+  B.col_e0 = base + 2 * nc;
+  B.order = base + 3 * nc;
+  B.newton_total = base + 4 * nc;
+  B.status = base + 5 * nc;
+  B.jac_builds = base + 6 * nc;
+  B.counter = base + 7 * nc;
+  B.col_off = m->d_coloff;
+  B.geo = m->d_geo;
+  B.cpar = m->d_cpar;
+  B.u = u;
+  B.t0 = t0;
+  B.dt = dt;
+  B.n_steps = n_steps;
+  B.max_newton = o.max_newton;
+  B.rtol = o.newton_rtol;
+  B.ws = m->d_cols_ws;
+  B.ws_stride = stride;
+  B.max_dof = (int)md;
+  // DIRK tableau
+  {
+    double A[3][3] = {}, c[3] = {};
+    if (o.scheme == 22) {
+      const double g = 1.0 - 1.0 / std::sqrt(2.0);
+      A[0][0] = g; A[1][0] = 1.0 - g; A[1][1] = g;
+      c[0] = g; c[1] = 1.0;
+      B.n_stages = 2;
+    } else {
+      double g = 0.4;
+      for (int it = 0; it < 60; ++it) {
+        const double f = ((g - 3.0) * g + 1.5) * g - 1.0 / 6.0;
+        const double df = (3.0 * g - 6.0) * g + 1.5;
+        g -= f / df;
+      }
+      A[0][0] = g; A[1][0] = 0.5 * (1.0 - g); A[1][1] = g;
+      A[2][0] = -(6.0 * g * g - 16.0 * g + 1.0) / 4.0; A[2][1] = (6.0 * g * g - 20.0 * g + 5.0) / 4.0; A[2][2] = g;
+      c[0] = g; c[1] = 0.5 * (1.0 + g); c[2] = 1.0;
+      B.n_stages = 3;
+    }
+    for (int i = 0; i < 3; ++i) {
+      B.c[i] = c[i];
+      for (int j = 0; j < 3; ++j) B.A[i][j] = A[i][j];
+    }
+  }
+  DG_HIP_CHECK(hipMemsetAsync(B.counter, 0, sizeof(int), s));
+  PhysC ph = m->phys;
+  sun_direction(ph, t0);
+  {
+    ProfScope ps(m, 13, s);
+    k_columns_persistent<<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+  }
+  DG_HIP_CHECK(hipGetLastError());
+  DG_HIP_CHECK(hipStreamSynchronize(s));
+  if (newton_host) DG_HIP_CHECK(hipMemcpy(newton_host, B.newton_total, nc * sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<int> st(nc);
+  DG_HIP_CHECK(hipMemcpy(st.data(), B.status, nc * sizeof(int), hipMemcpyDeviceToHost));
+  if (status_host)
+    for (int c = 0; c < nc; ++c) status_host[c] = st[c];
+  for (int c = 0; c < nc; ++c)
+    if (st[c] != 0) {
+      set_error("dg_columns_integrate: column " + std::to_string(c) + " failed (status " + std::to_string(st[c]) + ")");
+      return st[c] == 5 ? DG_ERR_NAN : DG_ERR_NOCONV;
+    }
+  return DG_OK;
 }
 
 }  // namespace dg

@@ -94,6 +94,13 @@ struct dg_mesh_s {
   float* d_fn32 = nullptr;
   int64_t fn_len = 0;
   dg::Workspace* ws = nullptr;
+  // batched-column solver state (dg_columns_integrate)
+  int* d_bstate = nullptr;               // [8][n_col] ints: E, p, first element, order, stats, counter
+  int64_t* d_coloff = nullptr;
+  double* d_cols_ws = nullptr;
+  int64_t cols_ws_len = 0;
+  int col_max_dof = 0;
+  int tune_cols_grid = 2048;             // persistent wavefronts (dg_set_option "columns_grid")
   int tune_p1 = 5;                       // pass-1 launch configuration (dg_set_option)
   // per-kernel event timing (dg_profile_enable / dg_profile_read)
   bool prof = false;
@@ -138,6 +145,8 @@ dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, f
 dg_status_t shell_bjac_build(dg_mesh_s* m, double t, const double* u, double dta, double* Binv, hipStream_t s);
 dg_status_t shell_bjac_apply64(dg_mesh_s* m, const double* B, const double* v, double* z, hipStream_t s);
 dg_status_t shell_bjac_apply32(dg_mesh_s* m, const double* B, const float* v, float* z, hipStream_t s);
+dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, double* u, const dg_solver_opts_t& o,
+                              int32_t* newton_host, int32_t* status_host, hipStream_t s);
 void fill_phys(PhysC& P, const dg_physics_t& in);
 dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg_solver_opts_t& o,
                           dg_step_stats_t* st, hipStream_t s);

@@ -345,7 +345,12 @@ dg_status_t build_columns(dg_mesh_s* m, const dg_mesh_desc_t& d, const dg_physic
   m->h_geo.resize(2 * E);
   int64_t e = 0;
   for (int c = 0; c < d.n_col; ++c) {
-    std::vector<double> edges = radial_edges(d.r_bot, d.r_top, m->col_nelem[c], d.stretch);
+    const double sc = d.col_stretch ? d.col_stretch[c] : d.stretch;
+    if (!(sc > 0)) {
+      set_error("dg_mesh_create: column stretch must be positive");
+      return DG_ERR_ARG;
+    }
+    std::vector<double> edges = radial_edges(d.r_bot, d.r_top, m->col_nelem[c], sc);
     int64_t o = m->col_off[c];
     const int p = m->col_p[c];
     for (int k = 0; k < m->col_nelem[c]; ++k, ++e) {

@@ -225,7 +225,7 @@ class ColumnWorkload:
     T_inf: np.ndarray          # [n_col]
     phys: dict                 # shared physics
     col_phys: dict             # per-column arrays: heat_amp, heat_qm, heat_rm, heat_H, lam
-    stretch: float = 1.0
+    stretch: float | np.ndarray = 1.0    # one growth ratio, or one per column
     r_bot: float = R_BOT
     r_top: float = R_TOP
     dt: float = seconds_to_nondim(10.0)
@@ -279,9 +279,30 @@ def column_workload(seed=0, n_elem=64, p=2, n_col=1, stretch=1.0, name="column")
     return _columns(name, np.full(n_col, n_elem), np.full(n_col, p), T_inf, z_pk, amp, stretch)
 
 
+def graded_stretch(n_elem, first_km=2.5, length_km=500.0):
+    """growth ratio that gives a first element of first_km on a column of n_elem
+    elements (the 1D mesh of section 4.1.3 grows geometrically from 2.5 km); 1 when
+    uniform elements are already that thin. Bisection on the (decreasing) first
+    element length L (s - 1)/(s^n - 1)."""
+    if length_km / n_elem <= first_km:
+        return 1.0
+    first = lambda s: length_km * (s - 1.0) / (s ** n_elem - 1.0)
+    lo, hi = 1.0 + 1e-12, 2.0
+    while first(hi) > first_km:
+        hi = 1.0 + 2.0 * (hi - 1.0)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if first(mid) > first_km:
+            lo = mid
+        else:
+            hi = mid
+    return float(0.5 * (lo + hi))
+
+
 def column_batch_workload(seed=0, n_col=4096, name="column-batch") -> ColumnWorkload:
     """The parametric sweep: n_col columns, elements ~ U{32..256}, p ~ U{2,3,4},
-    T_inf ~ U(600, 1500) K, heating multiplier ~ U(0.5, 3), z_m ~ U(150, 250) km."""
+    T_inf ~ U(600, 1500) K, heating multiplier ~ U(0.5, 3), z_m ~ U(150, 250) km.
+    Every column is graded geometrically from a 2.5 km first element."""
     rng = np.random.default_rng(seed)
     nelem = rng.integers(32, 257, n_col)
     p = rng.integers(2, 5, n_col)
@@ -289,6 +310,7 @@ def column_batch_workload(seed=0, n_col=4096, name="column-batch") -> ColumnWork
     amp = rng.uniform(0.5, 3.0, n_col)
     z_pk = rng.uniform(150.0, 250.0, n_col)
     w = _columns(name, nelem, p, T_inf, z_pk, amp, 1.0)
+    w.stretch = np.array([graded_stretch(int(e)) for e in nelem])
     w.n_steps = 100
     return w
 

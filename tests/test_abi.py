@@ -32,6 +32,6 @@ def test_struct_layout_matches_header():
     """the ctypes mirrors have the sizes the C compiler gives the structs"""
     import paper_2306_01085_amd as pkg
     # doubles/pointers are 8-byte aligned; int32 fields are padded accordingly
-    assert ctypes.sizeof(pkg.MeshDesc) == 4 * 4 + 3 * 8 + 8 + 2 * 8
+    assert ctypes.sizeof(pkg.MeshDesc) == 4 * 4 + 3 * 8 + 8 + 3 * 8
     assert ctypes.sizeof(pkg.SolverOpts) == 4 * 4 + 2 * 8 + 3 * 4 + 4
     assert ctypes.sizeof(pkg.StepStats) == 9 * 4 + 4 + 9 * 8 + 8
