@@ -169,6 +169,54 @@ dg_status_t dg_columns_integrate(dg_mesh_t mesh, double t0, double dt, int32_t n
                                  const dg_solver_opts_t* opts, int32_t* newton_host, int32_t* status_host,
                                  void* stream);
 
+/* ---- learned Newton warm start (the per-element network and its use) ----
+ * A network maps per-element features to a correction of the plain extrapolated
+ * stage guess: n_in -> 128 -> 128 -> n_out, ReLU hidden layers. Precision contract:
+ * weights, the input and the hidden activations are rounded to bfloat16 where they
+ * enter a matrix product (bf16 MFMA); biases and accumulation are FP32; training
+ * keeps FP32 master weights (Adam) and treats the roundings as the identity in the
+ * backward pass. Parameters are packed as W1 [128][n_in], b1 [128], W2 [128][128],
+ * b2 [128], W3 [n_out][128], b3 [n_out] (row-major, FP32 on the host). */
+typedef struct dg_mlp_s* dg_mlp_t;
+/* n_in a multiple of 8, n_hidden = 128, n_out a multiple of 32; params_host: packed FP32 */
+dg_status_t dg_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, const float* params_host, dg_mlp_t* out);
+dg_status_t dg_mlp_destroy(dg_mlp_t mlp);
+int64_t dg_mlp_param_count(dg_mlp_t mlp);
+/* FP32 master parameters to a host array of dg_mlp_param_count entries (synchronises) */
+dg_status_t dg_mlp_get_params(dg_mlp_t mlp, float* params_host, int64_t len);
+/* y = net(x): x device FP32 [n][n_in], y device FP32 [n][n_out]. Enqueue only. */
+dg_status_t dg_mlp_forward(dg_mlp_t mlp, const float* x, int64_t n, float* y, void* stream);
+/* mean-squared-error loss against t (device FP32 [n][n_out]) and its gradient, kept in
+ * the handle for dg_mlp_adam_step; loss_host / grad_host (packed) are optional host
+ * outputs (either one synchronises the stream). */
+dg_status_t dg_mlp_grad(dg_mlp_t mlp, const float* x, const float* t, int64_t n, double* loss_host, float* grad_host,
+                        void* stream);
+/* one Adam update of the master parameters with the last gradient (bias-corrected). */
+dg_status_t dg_mlp_adam_step(dg_mlp_t mlp, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* x[r][k] = (x[r][k] - mean[k]) / scale[k] for a device FP32 [n][width] array in place
+ * (standardisation of recorded training rows); mean / scale: host [width]. Synchronises. */
+dg_status_t dg_affine_rows(float* x, int64_t n, int32_t width, const float* mean_host, const float* scale_host,
+                           void* stream);
+
+/* Attach a trained network to a shell mesh for opts->guess = 1 (NULL detaches). The
+ * features of element e at stage i are [U_a, U_a - U_b, b_i - U_a] (U_a, U_b the two
+ * latest stage solutions, b_i the stage right-hand side; 3 x 5 x N values, node-major
+ * per field as in the state layout), standardised with x_mean / x_scale (host [n_in]);
+ * the output de-standardised with y_mean / y_scale (host [n_out], n_out = 5 N) is
+ * added to the plain guess. The guess with the smaller |G| is used (the other one is
+ * the fallback, reported in dg_step_stats_t.fallback). The network is not owned. */
+dg_status_t dg_warmstart_set(dg_mesh_t mesh, dg_mlp_t mlp, const float* x_mean_host, const float* x_scale_host,
+                             const float* y_mean_host, const float* y_scale_host);
+/* Record training pairs during later dg_implicit_step calls on a shell mesh: for one
+ * element in `every` (deterministic), after each stage converges, the raw features
+ * (as above, unstandardised) go to x_dev [capacity][n_in] and the raw target
+ * U_i - U_plain to y_dev [capacity][n_out] (device FP32, caller-owned) until capacity
+ * rows are written. capacity = 0 stops recording. dg_warmstart_recorded returns the
+ * number of rows written so far. */
+dg_status_t dg_warmstart_record(dg_mesh_t mesh, float* x_dev, float* y_dev, int64_t capacity, int32_t every);
+dg_status_t dg_warmstart_recorded(dg_mesh_t mesh, int64_t* count_host);
+
 /* ---- event timing of the library's own launches (tracing subsystem) ----
  * When enabled, every launch group is bracketed by hipEvents on the stream it runs on.
  * dg_profile_read synchronises those events and returns, per slot, the accumulated

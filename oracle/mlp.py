@@ -1,7 +1,10 @@
 """Per-element warm-start network: x (960) -> 128 -> 128 -> out (320), ReLU hidden layers.
 
-Weights and inputs are rounded to bfloat16 (round to nearest even) before use; all
-arithmetic is FP64. Loss: mean squared error over the batch and outputs.
+Precision contract: weights, the input and both hidden activations are rounded to
+bfloat16 (round to nearest even) where they enter a matrix product; biases and all
+accumulation are full precision (FP64 here). The backward pass treats the
+roundings as the identity (straight-through). Loss: mean squared error over the
+batch and outputs.
 Adam: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; w -= lr mhat / (sqrt(vhat) + eps)
 with the usual bias corrections.
 """
@@ -17,20 +20,21 @@ def bf16_round(x):
     return b.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def forward(params, x):
+def forward(params, x, round_hidden=True):
     W1, b1, W2, b2, W3, b3 = [bf16_round(p) if i % 2 == 0 else p for i, p in enumerate(params)]
+    rh = bf16_round if round_hidden else (lambda a: a)
     x = bf16_round(x)
     z1 = x @ W1.T + b1
-    h1 = np.maximum(z1, 0.0)
+    h1 = rh(np.maximum(z1, 0.0))
     z2 = h1 @ W2.T + b2
-    h2 = np.maximum(z2, 0.0)
+    h2 = rh(np.maximum(z2, 0.0))
     y = h2 @ W3.T + b3
     return y, (x, z1, h1, z2, h2)
 
 
-def loss_and_grad(params, x, target):
+def loss_and_grad(params, x, target, round_hidden=True):
     W1, b1, W2, b2, W3, b3 = [bf16_round(p) if i % 2 == 0 else p for i, p in enumerate(params)]
-    y, (xr, z1, h1, z2, h2) = forward(params, x)
+    y, (xr, z1, h1, z2, h2) = forward(params, x, round_hidden)
     n = y.size
     diff = y - target
     loss = np.sum(diff * diff) / n

@@ -80,17 +80,34 @@ _lib.dg_implicit_step.argtypes = [_vp, C.c_double, C.c_double, _vp, C.c_int64, C
                                   C.POINTER(StepStats), _vp]
 _lib.dg_columns_integrate.argtypes = [_vp, C.c_double, C.c_double, C.c_int32, _vp, C.c_int64,
                                       C.POINTER(SolverOpts), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]
+_fp = C.POINTER(C.c_float)
+_lib.dg_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, _fp, C.POINTER(_vp)]
+_lib.dg_mlp_destroy.argtypes = [_vp]
+_lib.dg_mlp_param_count.argtypes = [_vp]
+_lib.dg_mlp_param_count.restype = C.c_int64
+_lib.dg_mlp_get_params.argtypes = [_vp, _fp, C.c_int64]
+_lib.dg_mlp_forward.argtypes = [_vp, _vp, C.c_int64, _vp, _vp]
+_lib.dg_mlp_grad.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(C.c_double), _fp, _vp]
+_lib.dg_mlp_adam_step.argtypes = [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]
+_lib.dg_affine_rows.argtypes = [_vp, C.c_int64, C.c_int32, _fp, _fp, _vp]
+_lib.dg_warmstart_set.argtypes = [_vp, _vp, _fp, _fp, _fp, _fp]
+_lib.dg_warmstart_record.argtypes = [_vp, _vp, _vp, C.c_int64, C.c_int32]
+_lib.dg_warmstart_recorded.argtypes = [_vp, C.POINTER(C.c_int64)]
 _lib.dg_profile_enable.argtypes = [_vp, C.c_int32]
 _lib.dg_set_option.argtypes = [_vp, C.c_char_p, C.c_int64]
 _lib.dg_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int32]
 for _f in ("dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh_info", "dg_mesh_nodes",
            "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_profile_enable",
-           "dg_profile_read", "dg_set_option", "dg_columns_integrate"):
+           "dg_profile_read", "dg_set_option", "dg_columns_integrate", "dg_mlp_create", "dg_mlp_destroy",
+           "dg_mlp_get_params", "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_adam_step", "dg_affine_rows",
+           "dg_warmstart_set", "dg_warmstart_record", "dg_warmstart_recorded"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTED = ["dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh_info", "dg_mesh_nodes",
             "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_last_error", "dg_version",
-            "dg_profile_enable", "dg_profile_read", "dg_set_option", "dg_columns_integrate"]
+            "dg_profile_enable", "dg_profile_read", "dg_set_option", "dg_columns_integrate", "dg_mlp_create",
+            "dg_mlp_destroy", "dg_mlp_param_count", "dg_mlp_get_params", "dg_mlp_forward", "dg_mlp_grad",
+            "dg_mlp_adam_step", "dg_affine_rows", "dg_warmstart_set", "dg_warmstart_record", "dg_warmstart_recorded"]
 PROFILE_SLOTS = {0: "shell_pass1_R", 1: "shell_pass2_R", 2: "shell_pass1_jvp64", 3: "shell_pass2_jvp64",
                  4: "shell_pass1_jvp32", 5: "shell_pass2_jvp32", 6: "columns_R", 7: "columns_jvp64",
                  8: "columns_jvp32", 9: "gmres_arnoldi", 10: "bjac_build", 11: "bjac_apply", 12: "vector_ops"}
@@ -269,6 +286,104 @@ def _columns_integrate(self, u, t0, dt, n_steps, scheme=33, max_newton=20, newto
 
 
 Mesh.columns_integrate = _columns_integrate
+
+
+def _f32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Network:
+    """the warm-start network n_in -> 128 -> 128 -> n_out held by the library"""
+
+    def __init__(self, n_in, n_out, params):
+        self.n_in, self.n_out = int(n_in), int(n_out)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(q, np.float32).ravel() for q in params]))
+        self._h = C.c_void_p()
+        _check(_lib.dg_mlp_create(self.n_in, 128, self.n_out, _f32p(flat), C.byref(self._h)), "dg_mlp_create")
+        self.n_params = _lib.dg_mlp_param_count(self._h)
+        assert self.n_params == flat.size
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.dg_mlp_destroy(h)
+            self._h = C.c_void_p()
+
+    def _unpack(self, flat):
+        H, ni, no = 128, self.n_in, self.n_out
+        sizes = [H * ni, H, H * H, H, no * H, no]
+        shapes = [(H, ni), (H,), (H, H), (H,), (no, H), (no,)]
+        out, o = [], 0
+        for sz, sh in zip(sizes, shapes):
+            out.append(flat[o:o + sz].reshape(sh))
+            o += sz
+        return out
+
+    def params(self):
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib.dg_mlp_get_params(self._h, _f32p(flat), flat.size), "dg_mlp_get_params")
+        return self._unpack(flat)
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((n, self.n_out), dtype=torch.float32, device=x.device)
+        _check(_lib.dg_mlp_forward(self._h, _ptr(x, torch.float32), n, _ptr(out, torch.float32), _stream(stream)),
+               "dg_mlp_forward")
+        return out
+
+    def grad(self, x, t, want_grads=False, stream=None):
+        """loss and (optionally) the packed gradient, which the next adam_step uses"""
+        import torch
+        loss = C.c_double()
+        g = np.zeros(self.n_params, dtype=np.float32) if want_grads else None
+        _check(_lib.dg_mlp_grad(self._h, _ptr(x, torch.float32), _ptr(t, torch.float32), x.shape[0], C.byref(loss),
+                                _f32p(g) if want_grads else None, _stream(stream)), "dg_mlp_grad")
+        return (loss.value, self._unpack(g)) if want_grads else loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib.dg_mlp_adam_step(self._h, lr, beta1, beta2, eps, _stream(stream)), "dg_mlp_adam_step")
+
+
+def affine_rows(x, mean, scale, stream=None):
+    import torch
+    m = np.ascontiguousarray(mean, dtype=np.float32)
+    s = np.ascontiguousarray(scale, dtype=np.float32)
+    _check(_lib.dg_affine_rows(_ptr(x, torch.float32), x.shape[0], x.shape[1], _f32p(m), _f32p(s), _stream(stream)),
+           "dg_affine_rows")
+
+
+def _warmstart_set(self, net, x_mean=None, x_scale=None, y_mean=None, y_scale=None):
+    if net is None:
+        _check(_lib.dg_warmstart_set(self._h, None, None, None, None, None), "dg_warmstart_set")
+        self._ws_keep = None
+        return
+    arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (x_mean, x_scale, y_mean, y_scale)]
+    _check(_lib.dg_warmstart_set(self._h, net._h, *[_f32p(a) for a in arrs]), "dg_warmstart_set")
+    self._ws_keep = (net, arrs)
+
+
+def _warmstart_record(self, x, y, capacity, every):
+    import torch
+    if capacity == 0:
+        _check(_lib.dg_warmstart_record(self._h, None, None, 0, 1), "dg_warmstart_record")
+        self._rec_keep = None
+        return
+    _check(_lib.dg_warmstart_record(self._h, _ptr(x, torch.float32), _ptr(y, torch.float32), capacity, every),
+           "dg_warmstart_record")
+    self._rec_keep = (x, y)
+
+
+def _warmstart_recorded(self):
+    c = C.c_int64()
+    _check(_lib.dg_warmstart_recorded(self._h, C.byref(c)), "dg_warmstart_recorded")
+    return c.value
+
+
+Mesh.warmstart_set = _warmstart_set
+Mesh.warmstart_record = _warmstart_record
+Mesh.warmstart_recorded = _warmstart_recorded
 
 
 def library_path():

@@ -54,7 +54,7 @@ static void free_mesh(dg_mesh_s* m) {
   void* ptrs[] = {m->d_ang,  m->d_edges,  m->d_cnbr,  m->d_cface,     m->d_cmap,      m->d_off,
                   m->d_prev, m->d_next,   m->d_geo,   m->d_col,       m->d_cpar,      m->d_fn64,
                   m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2], m->d_bstate, m->d_coloff,
-                  m->d_cols_ws};
+                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   free_workspace(m);
@@ -288,7 +288,8 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
   }
   if ((opts->scheme != 33 && opts->scheme != 22) || opts->gmres_m < 1 || opts->gmres_m > 32 ||
       opts->max_newton < 1 || opts->max_restarts < 1 || !(opts->newton_rtol > 0) || !(opts->gmres_rtol > 0) ||
-      (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32) || opts->precond < 0 || opts->precond > 1) {
+      (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32) || opts->precond < 0 || opts->precond > 1 ||
+      opts->guess < 0 || opts->guess > 1) {
     set_error("dg_implicit_step: invalid solver options");
     return DG_ERR_ARG;
   }

@@ -101,7 +101,17 @@ struct dg_mesh_s {
   int64_t cols_ws_len = 0;
   int col_max_dof = 0;
   int tune_cols_grid = 2048;             // persistent wavefronts (dg_set_option "columns_grid")
-  int tune_p1 = 5;                       // pass-1 launch configuration (dg_set_option)
+  int tune_p1 = 5;
+  // learned warm start (dg_warmstart_set / dg_warmstart_record)
+  struct dg_mlp_s* ws_mlp = nullptr;
+  float* ws_norm = nullptr;              // device: x_mean [n_in], x_scale [n_in], y_mean [n_out], y_scale [n_out]
+  float* ws_X = nullptr;                 // device features [E][n_in]
+  float* ws_Y = nullptr;                 // device outputs [E][n_out]
+  float* rec_x = nullptr;
+  float* rec_y = nullptr;
+  int64_t rec_cap = 0, rec_count = 0;
+  int rec_every = 1;
+  int64_t rec_phase = 0;                       // pass-1 launch configuration (dg_set_option)
   // per-kernel event timing (dg_profile_enable / dg_profile_read)
   bool prof = false;
   struct ProfEv { int id; hipEvent_t a, b; };
@@ -147,6 +157,9 @@ dg_status_t shell_bjac_apply64(dg_mesh_s* m, const double* B, const double* v, d
 dg_status_t shell_bjac_apply32(dg_mesh_s* m, const double* B, const float* v, float* z, hipStream_t s);
 dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, double* u, const dg_solver_opts_t& o,
                               int32_t* newton_host, int32_t* status_host, hipStream_t s);
+dg_status_t mlp_forward(struct dg_mlp_s* m, const float* X, int64_t n, float* Y, hipStream_t s, bool keep);
+int mlp_n_in(const struct dg_mlp_s* m);
+int mlp_n_out(const struct dg_mlp_s* m);
 void fill_phys(PhysC& P, const dg_physics_t& in);
 dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg_solver_opts_t& o,
                           dg_step_stats_t* st, hipStream_t s);

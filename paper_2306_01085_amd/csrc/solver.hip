@@ -202,12 +202,67 @@ __global__ void k_extrapolate(int64_t n, const double* __restrict__ A, const dou
     out[i] = A[i] + f * (A[i] - B[i]);
 }
 
+// ---------------------------------------------------------------- learned warm start
+// features of element e: [U_a, U_a - U_b, b - U_a] per field and node (3 x 5 x N), standardised
+__global__ void k_ws_features(int64_t E, int N, const double* __restrict__ Ua, const double* __restrict__ Ub,
+                              const double* __restrict__ Bv, const float* __restrict__ mean,
+                              const float* __restrict__ scale, float* __restrict__ X) {
+  const int64_t nin = 15 * (int64_t)N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * nin) return;
+  const int64_t e = idx / nin;
+  const int k = (int)(idx % nin);
+  const int grp = k / (5 * N), cj = k % (5 * N);
+  const int64_t g = e * 5 * N + cj;
+  double x;
+  if (grp == 0)
+    x = Ua[g];
+  else if (grp == 1)
+    x = Ua[g] - Ub[g];
+  else
+    x = Bv[g] - Ua[g];
+  X[idx] = mean ? (float)((x - (double)mean[k]) / (double)scale[k]) : (float)x;
+}
+
+// U = Up + y * y_scale + y_mean
+__global__ void k_ws_apply(int64_t n, const double* __restrict__ Up, const float* __restrict__ Y,
+                           const float* __restrict__ ym, const float* __restrict__ ys, int nout, double* __restrict__ U) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = (int)(i % nout);
+  U[i] = Up[i] + (double)Y[i] * (double)ys[k] + (double)ym[k];
+}
+
+// training pairs of the selected elements e = phase + every * r: raw features and
+// target U - Up, written at rows row0 + r (r < nrows)
+__global__ void k_ws_record(int64_t nrows, int64_t phase, int every, int N, const double* __restrict__ Ua,
+                            const double* __restrict__ Ub, const double* __restrict__ Bv,
+                            const double* __restrict__ U, const double* __restrict__ Up, float* __restrict__ rx,
+                            float* __restrict__ ry, int64_t row0) {
+  const int64_t nin = 15 * (int64_t)N, nout = 5 * (int64_t)N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nrows * (nin + nout)) return;
+  const int64_t r = idx / (nin + nout);
+  const int k = (int)(idx % (nin + nout));
+  const int64_t e = phase + (int64_t)every * r;
+  if (k < nin) {
+    const int grp = k / (5 * N), cj = k % (5 * N);
+    const int64_t g = e * 5 * N + cj;
+    const double x = grp == 0 ? Ua[g] : (grp == 1 ? Ua[g] - Ub[g] : Bv[g] - Ua[g]);
+    rx[(row0 + r) * nin + k] = (float)x;
+  } else {
+    const int kk = k - (int)nin;
+    const int64_t g = e * nout + kk;
+    ry[(row0 + r) * nout + kk] = (float)(U[g] - Up[g]);
+  }
+}
+
 // ---------------------------------------------------------------- workspace
 struct Workspace {
   int64_t n = 0;
   int m = 0;
   bool f32 = false;
-  double *un = nullptr, *U = nullptr, *G = nullptr, *B = nullptr, *X = nullptr, *Rc = nullptr;
+  double *un = nullptr, *U = nullptr, *G = nullptr, *B = nullptr, *X = nullptr, *Rc = nullptr, *Up = nullptr;
   double* Rs[3] = {nullptr, nullptr, nullptr};
   double* hist[2] = {nullptr, nullptr};   // the two most recent stage solutions
   double hist_t[2] = {0, 0};
@@ -227,7 +282,7 @@ void free_workspace(dg_mesh_s* m) {
   Workspace* w = m->ws;
   if (!w) return;
   void* ptrs[] = {w->un, w->U, w->G, w->B, w->X, w->Rc, w->Rs[0], w->Rs[1], w->Rs[2], w->hist[0], w->hist[1],
-                  w->Binv, w->V, w->w, w->z, w->s, w->part, w->dev_small};
+                  w->Binv, w->V, w->w, w->z, w->s, w->part, w->dev_small, w->Up};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->host_small) (void)hipHostFree(w->host_small);
@@ -248,7 +303,7 @@ static dg_status_t ensure_workspace(dg_mesh_s* m, int mk, bool f32) {
   w->f32 = f32;
   const size_t vb = f32 ? sizeof(float) : sizeof(double);
   double** dbl[] = {&w->un, &w->U, &w->G, &w->B, &w->X, &w->Rc, &w->Rs[0], &w->Rs[1], &w->Rs[2], &w->hist[0],
-                    &w->hist[1]};
+                    &w->hist[1], &w->Up};
   for (double** p : dbl)
     if (hipMalloc(p, n * sizeof(double)) != hipSuccess) goto fail;
   if (m->kind == DG_MESH_SHELL && hipMalloc(&w->Binv, n * 5 * sizeof(double)) != hipSuccess) goto fail;
@@ -500,11 +555,39 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
     if (rc != DG_OK) return rc;
     const double ref = std::sqrt(ref2);
     // plain initial guess: extrapolation through the two latest stage solutions
-    if (ws->hist_n >= 2 && ws->hist_t[0] != ws->hist_t[1]) {
+    const bool have_hist = ws->hist_n >= 2 && ws->hist_t[0] != ws->hist_t[1];
+    if (have_hist) {
       const double f = (ti - ws->hist_t[0]) / (ws->hist_t[0] - ws->hist_t[1]);
       k_extrapolate<<<nb, RED_THREADS, 0, s>>>(n, ws->hist[0], ws->hist[1], f, ws->U);
     } else {
       DG_HIP_CHECK(hipMemcpyAsync(ws->U, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    DG_HIP_CHECK(hipMemcpyAsync(ws->Up, ws->U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // learned guess: the network's correction of the plain guess, kept only if it lowers |G|
+    if (o.guess == 1 && m->ws_mlp && have_hist) {
+      const int N = m->N, nin = 15 * N, nout = 5 * N;
+      const int64_t E = m->n_elem;
+      k_ws_features<<<(unsigned)((E * nin + 255) / 256), 256, 0, s>>>(E, N, ws->hist[0], ws->hist[1], ws->B,
+                                                                       m->ws_norm, m->ws_norm + nin, m->ws_X);
+      rc = mlp_forward(m->ws_mlp, m->ws_X, E, m->ws_Y, s, false);
+      if (rc != DG_OK) return rc;
+      k_ws_apply<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, ws->Up, m->ws_Y, m->ws_norm + 2 * nin,
+                                                             m->ws_norm + 2 * nin + nout, nout, ws->U);
+      double gl2, gp2;
+      rc = residual(m, ti, ws->U, ws->Rc, s);
+      if (rc != DG_OK) return rc;
+      k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->U, ws->Rc, ca, ws->B, ws->G, ws->part);
+      rc = finish_norm2(ws, nb, s, &gl2);
+      if (rc != DG_OK) return rc;
+      rc = residual(m, ti, ws->Up, ws->Rc, s);
+      if (rc != DG_OK) return rc;
+      k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->Up, ws->Rc, ca, ws->B, ws->G, ws->part);
+      rc = finish_norm2(ws, nb, s, &gp2);
+      if (rc != DG_OK) return rc;
+      if (!(gl2 < gp2)) {
+        DG_HIP_CHECK(hipMemcpyAsync(ws->U, ws->Up, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        stats.fallback[i] = 1;
+      }
     }
     int newton = 0, gm_total = 0;
     double nG = 0;
@@ -555,6 +638,20 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       return DG_ERR_NOCONV;
     }
     DG_HIP_CHECK(hipMemcpyAsync(ws->Rs[i], ws->Rc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // training pairs for the warm-start network (before the history moves on)
+    if (m->rec_cap > m->rec_count && have_hist && m->kind == DG_MESH_SHELL) {
+      const int every = m->rec_every;
+      const int64_t phase = m->rec_phase % every;
+      const int64_t sel = (m->n_elem - phase + every - 1) / every;
+      const int64_t rows = std::min(sel, m->rec_cap - m->rec_count);
+      const int64_t tot = rows * 20 * (int64_t)m->N;
+      if (rows > 0)
+        k_ws_record<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(rows, phase, every, m->N, ws->hist[0], ws->hist[1],
+                                                                  ws->B, ws->U, ws->Up, m->rec_x, m->rec_y,
+                                                                  m->rec_count);
+      m->rec_count += rows;
+      m->rec_phase += 1;
+    }
     // history: newest first
     std::swap(ws->hist[0], ws->hist[1]);
     ws->hist_t[1] = ws->hist_t[0];
@@ -573,8 +670,8 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
 
 dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg_solver_opts_t& o,
                           dg_step_stats_t* st, hipStream_t s) {
-  if (o.guess != 0) {
-    set_error("dg_implicit_step: the learned guess needs a warm-start model (dg_warmstart_set)");
+  if (o.guess == 1 && !m->ws_mlp) {
+    set_error("dg_implicit_step: the learned guess needs a warm-start network (dg_warmstart_set)");
     return DG_ERR_UNSUPPORTED;
   }
   if (o.jvp_prec == DG_F32) return step_impl<float>(m, t, dt, u, o, st, s);

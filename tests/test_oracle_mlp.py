@@ -25,8 +25,11 @@ def _small_problem(seed=0):
 
 
 def test_backward_matches_finite_differences():
+    """with unrounded activations the loss is smooth in the biases: finite differences
+    pin the backward formulas; the rounded (straight-through) variant is pinned against
+    torch autograd below"""
     params, x, y = _small_problem()
-    loss, grads = mlp.loss_and_grad(params, x, y)
+    loss, grads = mlp.loss_and_grad(params, x, y, round_hidden=False)
     # differentiate w.r.t. the bf16-rounded weights: perturb biases (fp64) exactly,
     # and weights through a copy that bypasses the rounding by using exact bf16 steps
     h = 1e-6
@@ -37,17 +40,23 @@ def test_backward_matches_finite_differences():
             pm = [q.copy() for q in params]
             pp[k][idx] += h
             pm[k][idx] -= h
-            fd = (mlp.loss_and_grad(pp, x, y)[0] - mlp.loss_and_grad(pm, x, y)[0]) / (2 * h)
+            fd = (mlp.loss_and_grad(pp, x, y, round_hidden=False)[0]
+                  - mlp.loss_and_grad(pm, x, y, round_hidden=False)[0]) / (2 * h)
             assert abs(fd - grads[k][idx]) < 1e-7 * (1 + abs(fd))
     # weights: rounded weights are piecewise constant in the raw weight, so check the
     # gradient against a torch autograd evaluation on the rounded values
     tp = [torch.tensor(mlp.bf16_round(q) if i % 2 == 0 else q, requires_grad=True) for i, q in enumerate(params)]
     xt = torch.tensor(mlp.bf16_round(x))
-    h1 = torch.relu(xt @ tp[0].T + tp[1])
-    h2 = torch.relu(h1 @ tp[2].T + tp[3])
+
+    def rnd(h):   # bfloat16 rounding, identity in the backward pass
+        return h + (h.to(torch.bfloat16).to(torch.float64) - h).detach()
+
+    h1 = rnd(torch.relu(xt @ tp[0].T + tp[1]))
+    h2 = rnd(torch.relu(h1 @ tp[2].T + tp[3]))
     out = h2 @ tp[4].T + tp[5]
     lt = ((out - torch.tensor(y)) ** 2).mean()
     lt.backward()
+    loss, grads = mlp.loss_and_grad(params, x, y)
     assert abs(lt.item() - loss) < 1e-12
     for i in range(6):
         assert np.allclose(tp[i].grad.numpy(), grads[i], rtol=1e-10, atol=1e-13)
