@@ -4,9 +4,12 @@ Default workload: the cubed-sphere shell 6 x 16 x 16 angular x 16 radial element
 (stretch 1.15), p = 3, 5 fields: 24,576 elements, 7,864,320 DOF. A step is one
 evaluation of the residual R(u) (the operator every Newton, GMRES and DIRK stage
 is built from); J(u)v in FP64 and FP32 is timed the same way and reported beside
-it. Inputs are resident in HBM before the timed region. Prints one JSON line.
+it, and so are the implicit DIRK(3,3) step on the same shell (FP64 and FP32 J v)
+and the batch of 4096 radial columns advanced 100 steps in one launch. Inputs are
+resident in HBM before the timed regions. Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload shell-p3|shell-p4]
+                    [--only residual] [--mode warmstart]
 """
 import argparse
 import json
@@ -101,6 +104,124 @@ def cpu_baseline(w, budget_s=20.0):
                       % (n_ang, n_ang, n_rad, w.p, ndof, len(times))}
 
 
+def implicit_steps(w, mesh, u, n_steps):
+    """seconds per DIRK(3,3) step of dt = 60 s at a 1e-8 relative Newton tolerance,
+    GMRES(30) without preconditioner, plain extrapolated guess: FP64 vs FP32 J v"""
+    import torch
+    res = {"dt_s": 60.0, "newton_rtol": 1e-8, "gmres": "GMRES(30), CGS2, no preconditioner", "steps": n_steps}
+    for prec in ("f64", "f32"):
+        x = u.clone()
+        t = 0.0
+        secs, newton, gmres = [], [], []
+        for _ in range(n_steps):
+            st = mesh.implicit_step(x, t, w.dt, jvp_prec=prec, precond=0, max_newton=15, max_restarts=40)
+            t += w.dt
+            secs.append(st["seconds"])
+            newton.append(sum(st["newton_its"]))
+            gmres.append(sum(st["gmres_its"]))
+        res[prec] = {"s_per_step": float(np.mean(secs)), "newton_per_step": float(np.mean(newton)),
+                     "gmres_per_step": float(np.mean(gmres))}
+        del x
+        torch.cuda.empty_cache()
+    return res
+
+
+def column_batch(n_steps=None, check_cols=2, check_steps=2):
+    """the batched radial-column sweep: 4096 columns advanced n_steps DIRK(3,3) steps of
+    10 s in one persistent launch (autotuned grid), columns/s; plus the relative error
+    of sampled columns after check_steps steps against the oracle's exact stages"""
+    import torch
+
+    import synth
+    from paper_2306_01085_amd import Mesh
+    from paper_2306_01085_amd import autotune
+    w = synth.column_batch_workload(0)
+    n_steps = n_steps or w.n_steps
+    gm = Mesh.columns(w.nelem, w.p, w.r_bot, w.r_top, w.stretch, w.phys, w.col_phys)
+    r = gm.nodes()
+    off = gm.col_offsets()
+    u0 = np.empty(gm.n_dof)
+    for c in range(gm.n_col):
+        rc = r[off[c] // 3:off[c + 1] // 3].reshape(w.nelem[c], w.p[c] + 1)
+        u0[off[c]:off[c + 1]] = np.moveaxis(w.state(c, rc), 0, 1).ravel()
+    u = torch.from_numpy(u0).cuda()
+    grid, _ = autotune.tune_columns(gm, u, 0.0, w.dt, steps=1)
+    x = u.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, st = gm.columns_integrate(x, 0.0, w.dt, n_steps, raise_on_failure=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"n_col": gm.n_col, "n_dof": gm.n_dof, "steps": n_steps, "seconds": el, "columns_per_s": gm.n_col / el,
+           "grid": grid, "newton_per_step_mean": float(its.mean() / n_steps), "failed": int((st != 0).sum())}
+    # error of sampled columns after check_steps steps: the smallest columns keep the
+    # dense oracle affordable
+    from oracle import mesh as omesh
+    from oracle import timeint
+    y = u.clone()
+    gm.columns_integrate(y, 0.0, w.dt, check_steps, newton_rtol=1e-10, raise_on_failure=False)
+    yc = y.cpu().numpy()
+    errs = []
+    for c in np.argsort(w.nelem * (w.p + 1))[:check_cols]:
+        om = omesh.columns_mesh([int(w.nelem[c])], int(w.p[c]), w.r_bot, w.r_top, float(w.stretch[c]))
+        P = dict(w.phys)
+        for k in w.col_phys:
+            P[k] = float(w.col_phys[k][c])
+        ref = u0[off[c]:off[c + 1]].reshape(-1, 3, w.p[c] + 1).copy()
+        start = ref.copy()
+        for s in range(check_steps):
+            ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-12)
+        got = yc[off[c]:off[c + 1]].reshape(ref.shape)
+        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref - start)))
+    out["sampled_error"] = {"columns": check_cols, "steps": check_steps, "max_rel_err": max(errs),
+                            "measure": "|u_gpu - u_oracle| / |u_oracle - u_0|"}
+    return out
+
+
+def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epochs=8):
+    """train the warm-start network on stages the method generates from the shell state
+    (dt = 60 s, FP64 J v), then run the next eval_steps steps twice from the same state,
+    plain and learned, with FP64 and with FP32 J v"""
+    import torch
+
+    from paper_2306_01085_amd import Network
+    from paper_2306_01085_amd import warmstart as wsm
+    opts = dict(newton_rtol=1e-8, precond=0, max_newton=15, max_restarts=40)
+    nin, nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
+    cap = (3 * train_steps) * ((w.n_elem + every - 1) // every)
+    t_rec = time.perf_counter()
+    X, Y, rows, rec_stats = wsm.record(mesh, u, 0.0, w.dt, train_steps, every=every, capacity=cap, **opts)
+    t_rec = time.perf_counter() - t_rec
+    norms = wsm.standardise(X, Y, rows)
+    net = Network(nin, nout, wsm.init_params(np.random.default_rng(0), nin, nout))
+    t_tr = time.perf_counter()
+    tr, va = wsm.train(net, X, Y, rows, epochs=epochs, batch=8192, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t_tr
+    del X, Y
+    torch.cuda.empty_cache()
+    mesh.warmstart_set(net, *norms)
+    t0 = train_steps * w.dt
+    out = {"metric": "s per implicit step, learned/mixed vs plain @1e-8", "unit": "s", "higher_is_better": False,
+           "config": {"workload": w.name, "n_dof": w.n_dof, "dt_s": 60.0, "train_steps": train_steps,
+                      "train_rows": rows, "eval_steps": eval_steps, "epochs": epochs},
+           "record_seconds": t_rec, "train_seconds": t_tr, "train_loss": tr, "val_loss": va}
+    for prec in ("f64", "f32"):
+        sp, sl, up, ul = wsm.compare(mesh, u, t0, w.dt, eval_steps, jvp_prec=prec, **opts)
+        agg = lambda ss, k: float(np.mean([sum(s[k]) for s in ss]))
+        out[prec] = {
+            "plain": {"s_per_step": float(np.mean([s["seconds"] for s in sp])),
+                      "newton": agg(sp, "newton_its"), "gmres": agg(sp, "gmres_its")},
+            "learned": {"s_per_step": float(np.mean([s["seconds"] for s in sl])),
+                        "newton": agg(sl, "newton_its"), "gmres": agg(sl, "gmres_its"),
+                        "fallback_stages": int(sum(sum(s["fallback"]) for s in sl))},
+            "state_rel_diff": float(torch.linalg.norm(up - ul).item() / torch.linalg.norm(up - u).item()),
+        }
+    out["value"] = out["f32"]["learned"]["s_per_step"]
+    out["vs_plain_f64"] = out["f64"]["plain"]["s_per_step"] / out["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +231,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of known size (calibrates HBM counters)")
+    ap.add_argument("--only", default="all", choices=["all", "residual"],
+                    help="residual: only the R(u) timing (for counter runs)")
+    ap.add_argument("--mode", default="default", choices=["default", "warmstart"])
+    ap.add_argument("--implicit-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -148,9 +273,25 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
+    if args.mode == "warmstart":
+        del r, jv, jv32, v, v32
+        print(json.dumps(warmstart_experiment(w, mesh, u)), flush=True)
+        return
+
     f_r = lambda: mesh.residual(u, t, out=r)
     f_j64 = lambda: mesh.jvp(u, v, t, "f64", out=jv)
     f_j32 = lambda: mesh.jvp(u, v32, t, "f32", out=jv32)
+    if args.only == "residual":
+        for _ in range(args.warmup):
+            f_r()
+        ms_r = timed(f_r, args.steps)
+        if args.copy_probe:
+            src = torch.empty(2 ** 28 // 8, dtype=torch.float64, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"residual_ms": ms_r, "gdofs": w.n_dof / ms_r / 1e6}), flush=True)
+        return
     for _ in range(args.warmup):
         f_r(); f_j64(); f_j32()
     torch.cuda.synchronize()
@@ -202,6 +343,11 @@ def main():
                      "algorithmic_bytes_per_launch": b1, "avg_launch_ms": p1_ms},
         "finite": ok,
     }
+    log("implicit steps")
+    out["implicit_step"] = implicit_steps(w, mesh, u, args.implicit_steps)
+    del r, jv, jv32, v, v32
+    log("column batch")
+    out["columns"] = column_batch()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)

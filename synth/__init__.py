@@ -90,21 +90,20 @@ _GL_X, _GL_W = np.polynomial.legendre.leggauss(24)
 def hydrostatic_logrho(r, T_inf, r_ref=R_BOT):
     """log(rho/rho0) of the hydrostatic rest state with temperature bates_T and
     gravity g = -(r_ref/r)^2 (m = 1):  d(rho T)/dr = -rho (r_ref/r)^2, rho(r_ref) = 1.
-    Integrated with composite 24-point Gauss-Legendre between sorted radii."""
+    Integrated with composite 24-point Gauss-Legendre between sorted radii (every gap
+    split into equal panels no longer than 0.5 in H0 units)."""
     r = np.asarray(r, dtype=np.float64)
     flat = r.ravel()
     uniq, inv = np.unique(flat, return_inverse=True)
     pts = np.concatenate([[r_ref], uniq])
     a, b = pts[:-1], pts[1:]
-    # subdivide each gap so that no panel is longer than 0.5 (in H0 units)
-    integ = np.zeros(len(uniq))
-    nsub = np.maximum(1, np.ceil(np.abs(b - a) / 0.5).astype(int))
-    for i in range(len(uniq)):
-        edges = np.linspace(a[i], b[i], nsub[i] + 1)
-        lo, hi = edges[:-1, None], edges[1:, None]
-        x = 0.5 * (hi + lo) + 0.5 * (hi - lo) * _GL_X[None, :]
-        f = (r_ref / x) ** 2 / bates_T(x, T_inf)
-        integ[i] = np.sum(0.5 * (hi - lo)[:, 0] * (f @ _GL_W))
+    nsub = max(1, int(np.ceil(np.max(np.abs(b - a)) / 0.5)))
+    frac = np.arange(nsub + 1) / nsub
+    edges = a[:, None] + (b - a)[:, None] * frac[None, :]
+    lo, hi = edges[:, :-1], edges[:, 1:]
+    x = 0.5 * (hi + lo)[..., None] + 0.5 * (hi - lo)[..., None] * _GL_X
+    f = (r_ref / x) ** 2 / bates_T(x, T_inf)
+    integ = np.sum(0.5 * (hi - lo) * (f @ _GL_W), axis=1)
     cum = np.cumsum(integ)
     lr = -np.log(bates_T(uniq, T_inf)) - cum
     return lr[inv].reshape(r.shape)
