@@ -254,6 +254,9 @@ def main():
     X = mesh.nodes().reshape(w.n_elem, -1, 3)
     u_np = shell_state(w, X)
     u = torch.from_numpy(u_np.ravel()).to(dev)
+    from paper_2306_01085_amd import autotune
+    p1_cfg, _ = autotune.tune_shell_pass1(mesh, u)
+    log("element-pass configuration %d" % p1_cfg)
     v = torch.from_numpy(synth.tangent(u_np.shape, 1).ravel()).to(dev)
     v32 = v.float()
     del u_np, X
@@ -333,7 +336,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n_dof": ndof, "n_elem": w.n_elem, "p": w.p, "fields": 5,
-                   "step": "one R(u) evaluation"},
+                   "step": "one R(u) evaluation", "pass1_config": p1_cfg},
         "jvp_f64_gdofs": ndof / (ms_j64 * 1e-3) / 1e9,
         "jvp_f32_gdofs": ndof / (ms_j32 * 1e-3) / 1e9,
         "kernels_ms": {k: v_[0] / v_[1] for k, v_ in prof.items()},

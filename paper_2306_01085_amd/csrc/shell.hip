@@ -192,6 +192,20 @@ __device__ inline void slot_node(int f, int m, int& a, int& b, int& cz) {
   }
 }
 
+// The interior-face stabilisation is single valued up to its sign: with
+// u_hat = (u + u^-)/2 the term on this side is -|Sn| sigma(u_hat)(u - u_hat) and on the
+// neighbour's side -|Sn| sigma(u_hat)(u^- - u_hat) = +|Sn| sigma(u_hat)(u - u_hat). Of
+// the two elements of a face, the one with the smaller index (the face's owner)
+// evaluates sigma once and folds the neighbour's share into the trace it sends, so
+// the trace slot of a face node holds F.Sn - 2 Z with Z = |Sn| sigma(u_hat)(u_hat - u)
+// (Z = 0 when the receiving element is the owner).
+
+// the r-th set bit of mask (r counted from 0)
+__device__ inline int nth_bit(int mask, int r) {
+  for (int i = 0; i < r; ++i) mask &= mask - 1;
+  return __ffs(mask) - 1;
+}
+
 // EPB: elements per block; OCC: minimum waves per SIMD the register allocation must allow
 template <int P, int EPB, int OCC, class S, class SU, class TV, class OT>
 __global__ __launch_bounds__(Shape<P>::TPE * EPB) __attribute__((amdgpu_waves_per_eu(OCC)))
@@ -200,10 +214,12 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   typedef Shape<P> Sh;
   typedef typename Base<S>::type T;
   constexpr int n = Sh::n, N = Sh::N, N2 = Sh::N2, TPE = Sh::TPE;
+  static_assert(3 * N <= 6 * 5 * N2, "flux staging must fit in the trace buffer");
   __shared__ double s_ang[EPB][13][N2];
   __shared__ S s_u[EPB][5][N];
-  __shared__ S s_G[EPB][3][5][N];
-  __shared__ S s_f[EPB][6][5][N2];   // per face slot: u_hat - u, later the stabilisation term
+  __shared__ S s_f[EPB][6][5][N2];   // per face slot: u_hat - u; later the flux staging of phase E
+  __shared__ S s_z[EPB][5][5][N2];   // Z of the owned faces, in the order of their face index
+  __shared__ int s_nb[EPB][6][N2];   // trace slot of the neighbour's matching face node
   __shared__ double D[n * n];
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
@@ -225,12 +241,22 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
     }
   const double rk = live ? M.edges[k] : 0.0;
   const double hk = live ? M.edges[k + 1] - rk : 1.0;
+  // owned interior faces (bit f): the neighbour has the larger element index
+  int own = 0;
+  if (live) {
+    for (int f = 0; f < 4; ++f)
+      if (M.cnbr[cell * 4 + f] * M.n_rad + k > e) own |= 1 << f;
+    if (k < M.n_rad - 1) own |= 1 << 5;
+  }
+  const int n_own = __popc(own);
   __syncthreads();
 
-  // ---- phase B (face-node tasks): numerical trace u_hat - u of every face slot
+  // ---- phase B (face-node tasks, owned faces first): numerical trace u_hat - u of every
+  // face slot, the neighbour's trace slot, and Z on the owned faces
   if (live)
     for (int tsk = j; tsk < 6 * N2; tsk += TPE) {
-      const int f = tsk / N2, m = tsk % N2;
+      const int r = tsk / N2, m = tsk % N2;
+      const int f = (r < n_own) ? nth_bit(own, r) : nth_bit(~own & 63, r - n_own);
       int a, b, cz;
       slot_node<P>(f, m, a, b, cz);
       const int jo = a + n * b + N2 * cz;
@@ -240,6 +266,23 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       const int en = face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
       if (en >= 0) {
         for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uo[c]);
+        s_nb[le][f][m] = (en * 6 + fn) * 5 * N2 + mn;
+        if (r < n_own) {
+          const int dd = f >> 1;
+          const int ja = a + n * b;
+          const double rc = rk + 0.5 * (gc.x[cz] + 1.0) * hk;
+          const double fac = (dd < 2) ? rc * 0.5 * hk : rc * rc;
+          const double A0 = s_ang[le][3 * dd][ja], A1 = s_ang[le][3 * dd + 1][ja], A2 = s_ang[le][3 * dd + 2][ja];
+          const double Smag = fac * sqrt(A0 * A0 + A1 * A1 + A2 * A2);
+          S uh[5];
+          for (int c = 0; c < 5; ++c) uh[c] = uo[c] + du[c];
+          S sm, se;
+          sigma<3, S>(ph, uh, sm, se);
+          for (int c = 0; c < 5; ++c) {
+            const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
+            s_z[le][r][c][m] = T(Smag) * sg * du[c];
+          }
+        }
       } else if (ph.bc_mode == 1 || f == 4) {
         S ub[5];
         boundary_state<3, S>(ph, uo, ub);
@@ -253,7 +296,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
 
   // ---- phase C (node threads): gradient, pointwise flux and source, contravariant fluxes
   NodeGeo g;
-  S Sr[5];
+  S Sr[5], G[5][3];
   const int a = j % n, b = (j / n) % n, cz = j / N2;
   if (active) {
     g = node_geo<P>(M, gc, s_ang[le], k, j);
@@ -299,102 +342,87 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du * T(sd * Ja[dd][d]);
       }
     }
+    // boundary faces: the terms (F - F_hat).Sn are completed here. On the lower face (and
+    // every boundary face in bc_mode 1), F_hat.Sn = F(u_b, q).Sn + |Sn| sigma(u_b)(u - u_b)
+    // is taken before the node's own flux so that q need not outlive it.
+    const bool bot = (k == 0 && cz == 0);
+    const bool top = (k == M.n_rad - 1 && cz == n - 1);
+    const bool dir = bot || (top && ph.bc_mode == 1);
+    const double bside = bot ? -1.0 : 1.0;
+    double Sn[3];
+    for (int d = 0; d < 3; ++d) Sn[d] = bside * Ja[2][d];
+    S Bc[5];
+    if (dir) {
+      const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
+      S ub[5], Fb[5][3], Sb[5];
+      boundary_state<3, S>(ph, uu, ub);
+      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb);
+      S sm, se;
+      sigma<3, S>(ph, ub, sm, se);
+      for (int c = 0; c < 5; ++c) {
+        const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
+        Bc[c] = -(Fb[c][0] * T(Sn[0]) + Fb[c][1] * T(Sn[1]) + Fb[c][2] * T(Sn[2])) - T(Smag) * sg * (uu[c] - ub[c]);
+      }
+    }
     const double Q = heating<3>(ph, g.x, t);
     S F[5][3];
     flux_source<3, S>(ph, uu, q, g.x, Q, F, Sr);
+    if (dir) {
+      for (int c = 0; c < 5; ++c)
+        Sr[c] = Sr[c] + (F[c][0] * T(Sn[0]) + F[c][1] * T(Sn[1]) + F[c][2] * T(Sn[2]) + Bc[c]) * T(lfac);
+    } else if (top) {
+      // adiabatic, zero normal stress: F_hat.n = F_inviscid.n, so (F - F_hat).n = F_viscous.n
+      S Fi[5][3];
+      flux_inviscid<3, S>(ph, uu, Fi);
+      for (int c = 0; c < 5; ++c) {
+        const S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
+                     (F[c][2] - Fi[c][2]) * T(Sn[2]);
+        Sr[c] = Sr[c] + fd * T(lfac);
+      }
+    }
     for (int c = 0; c < 5; ++c)
-      for (int dd = 0; dd < 3; ++dd)
-        s_G[le][dd][c][j] = F[c][0] * T(Ja[dd][0]) + F[c][1] * T(Ja[dd][1]) + F[c][2] * T(Ja[dd][2]);
-    // complete terms of the boundary faces: (F - F_hat).Sn with the boundary state
-    const bool bot = (k == 0 && cz == 0);
-    const bool top = (k == M.n_rad - 1 && cz == n - 1);
-    if (bot || top) {
-      const double side = bot ? -1.0 : 1.0;
-      double Sn[3];
-      for (int d = 0; d < 3; ++d) Sn[d] = side * Ja[2][d];
-      const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
-      if (bot || ph.bc_mode == 1) {
-        S ub[5], Fb[5][3], Sb[5];
-        boundary_state<3, S>(ph, uu, ub);
-        flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb);
-        S sm, se;
-        sigma<3, S>(ph, ub, sm, se);
-        for (int c = 0; c < 5; ++c) {
-          const S fd = (F[c][0] - Fb[c][0]) * T(Sn[0]) + (F[c][1] - Fb[c][1]) * T(Sn[1]) +
-                       (F[c][2] - Fb[c][2]) * T(Sn[2]);
-          const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
-          Sr[c] = Sr[c] + (fd - T(Smag) * sg * (uu[c] - ub[c])) * T(lfac);
-        }
-      } else {
-        // adiabatic, zero normal stress: F_hat.n = F_inviscid.n, so (F - F_hat).n = F_viscous.n
-        S Fi[5][3];
-        flux_inviscid<3, S>(ph, uu, Fi);
-        for (int c = 0; c < 5; ++c) {
-          const S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
-                       (F[c][2] - Fi[c][2]) * T(Sn[2]);
-          Sr[c] = Sr[c] + fd * T(lfac);
-        }
-      }
-    }
+      for (int dd = 0; dd < 3; ++dd) G[c][dd] = F[c][0] * T(Ja[dd][0]) + F[c][1] * T(Ja[dd][1]) + F[c][2] * T(Ja[dd][2]);
   }
-  __syncthreads();
 
-  // ---- phase D (face-node tasks): stabilisation -|Sn| sigma(u_hat)(u - u_hat) / (w_end J) into the
-  // slot, and this side's F.Sn sent to the neighbour's incoming slot
-  if (live)
-    for (int tsk = j; tsk < 6 * N2; tsk += TPE) {
-      const int f = tsk / N2, m = tsk % N2;
-      if ((f == 4 && k == 0) || (f == 5 && k == M.n_rad - 1)) continue;   // boundary: done in phase C
-      int fa, fb, fcz;
-      slot_node<P>(f, m, fa, fb, fcz);
-      const int jo = fa + n * fb + N2 * fcz;
+  // ---- phase E (node threads): interior-face terms of this side and the traces sent to
+  // the neighbours, then the volume divergence one field at a time
+  const double invJ = active ? 1.0 / g.Jac : 0.0;
+  const double lfac = invJ / w_end;
+  if (active) {
+    const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
+    for (int f = 0; f < 6; ++f) {
+      if (!on[f]) continue;
+      const int m = face_slot<P>(f, a, b, cz);
       const int dd = f >> 1;
-      const int ja = fa + n * fb;
-      const double rc = rk + 0.5 * (gc.x[fcz] + 1.0) * hk;
-      const double fac = (dd < 2) ? rc * 0.5 * hk : rc * rc;
-      const double A0 = s_ang[le][3 * dd][ja], A1 = s_ang[le][3 * dd + 1][ja], A2 = s_ang[le][3 * dd + 2][ja];
-      const double Smag = fac * sqrt(A0 * A0 + A1 * A1 + A2 * A2);
-      const double lf = 1.0 / (w_end * rc * rc * 0.5 * hk * s_ang[le][9][ja]);
-      S uo[5], uh[5];
+      const T side = (f & 1) ? T(1) : T(-1);
+      const int nb = s_nb[le][f][m];
+      const bool mine = (own >> f) & 1;
+      const int r = __popc(own & ((1 << f) - 1));
       for (int c = 0; c < 5; ++c) {
-        uo[c] = s_u[le][c][jo];
-        uh[c] = uo[c] + s_f[le][f][c][m];
-      }
-      S sm, se;
-      sigma<3, S>(ph, uh, sm, se);
-      int jn, fn, mn;
-      const int en = face_neighbour<P>(M, cell, k, f, fa, fb, fcz, jn, fn, mn);
-      const double side = (f & 1) ? 1.0 : -1.0;
-      for (int c = 0; c < 5; ++c) {
-        const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
-        s_f[le][f][c][m] = T(-lf * Smag) * sg * (uo[c] - uh[c]);
-        Fn[(((int64_t)en * 6 + fn) * 5 + c) * N2 + mn] = outp(T(side) * s_G[le][dd][c][jo]);
+        const S Fs = side * G[c][dd];
+        const S z = mine ? s_z[le][r][c][m] : S(T(0));
+        Sr[c] = Sr[c] + (T(0.5) * Fs + z) * T(lfac);
+        Fn[(int64_t)nb + c * N2] = outp(Fs - T(2) * z);
       }
     }
-  __syncthreads();
-  if (!active) return;
-
-  // ---- phase E (node threads): volume divergence, own half of the interior faces, stabilisation
-  const double invJ = 1.0 / g.Jac;
-  const double hl = 0.5 * invJ / w_end;
+  }
+  __syncthreads();   // every u_hat - u has been read: the trace buffer becomes the flux staging
+  S (*s_G)[N] = reinterpret_cast<S (*)[N]>(&s_f[le][0][0][0]);
   for (int c = 0; c < 5; ++c) {
-    S dv = S(T(0));
-    for (int i = 0; i < n; ++i) {
-      dv = dv + s_G[le][0][c][i + n * b + N2 * cz] * T(D[a * n + i]);
-      dv = dv + s_G[le][1][c][a + n * i + N2 * cz] * T(D[b * n + i]);
-      dv = dv + s_G[le][2][c][g.ja + N2 * i] * T(D[cz * n + i]);
+    if (active)
+      for (int dd = 0; dd < 3; ++dd) s_G[dd][j] = G[c][dd];
+    __syncthreads();
+    if (active) {
+      S dv = S(T(0));
+      for (int i = 0; i < n; ++i) {
+        dv = dv + s_G[0][i + n * b + N2 * cz] * T(D[a * n + i]);
+        dv = dv + s_G[1][a + n * i + N2 * cz] * T(D[b * n + i]);
+        dv = dv + s_G[2][g.ja + N2 * i] * T(D[cz * n + i]);
+      }
+      R[base + c * N + j] = outp(Sr[c] - dv * T(invJ));
     }
-    Sr[c] = Sr[c] - dv * T(invJ);
+    __syncthreads();
   }
-  const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
-  for (int f = 0; f < 6; ++f) {
-    if (!on[f]) continue;
-    const int m = face_slot<P>(f, a, b, cz);
-    const int dd = f >> 1;
-    const double sh = ((f & 1) ? 1.0 : -1.0) * hl;
-    for (int c = 0; c < 5; ++c) Sr[c] = Sr[c] + T(sh) * s_G[le][dd][c][j] + s_f[le][f][c][m];
-  }
-  for (int c = 0; c < 5; ++c) R[base + c * N + j] = outp(Sr[c]);
 }
 
 // pass 2: R += (F^-.(-Sn))/(2 w_end J) on every interior face node, reading the
@@ -462,6 +490,10 @@ static dg_status_t launch(dg_mesh_s* m, double t, const SU* u, const TV* v, OT* 
                           int prof_base) {
   ShellDev M = m->shell();
   const int E = M.E;
+  if ((int64_t)E * 30 * (m->p + 1) * (m->p + 1) >= INT32_MAX) {
+    set_error("shell mesh too large for 32-bit trace-slot indices");
+    return DG_ERR_UNSUPPORTED;
+  }
   const GllC gc = make_gllc(m->p);
   PhysC ph = m->phys;
   sun_direction(ph, t);
