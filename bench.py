@@ -68,6 +68,26 @@ def pass1_bytes(w, prec_bytes=8):
     return E * per_elem + A * 13 * N2 * 8
 
 
+def pass1_flops(p):
+    """algorithmic FP64 operations of the element pass per node (an FMA counts 2, an
+    exp, log, sqrt or division 1), n = p + 1 nodes per direction, phi = 6/n face slots
+    per node:
+      line coefficients 16n; gradient 5(14n + 9); lift 30 phi; pointwise flux and
+      source 246, heating 18, node geometry 20; contravariant fluxes 75; divergence
+      5(6n + 2); face slots (trace 10, sigma and Z on the owned half 45/2, own half and
+      sent trace 35) 67.5 phi"""
+    n = p + 1
+    phi = 6.0 / n
+    return 16 * n + 5 * (14 * n + 9) + 30 * phi + 246 + 18 + 20 + 75 + 5 * (6 * n + 2) + 67.5 * phi
+
+
+# HBM counter scale factors measured on MI355X with a 256 MiB device copy (rocprofv3
+# --pmc FETCH_SIZE / WRITE_SIZE): FETCH_SIZE reads half the bytes a kernel fetches,
+# WRITE_SIZE the bytes it writes
+FETCH_SCALE = 2.0
+WRITE_SCALE = 1.0
+
+
 def residual_bytes(w):
     """algorithmic HBM bytes of one full R(u) (both passes): pass 1 as above; pass 2
     reads the neighbours' traces and face-node states and updates R on face nodes"""
@@ -77,6 +97,16 @@ def residual_bytes(w):
     E = w.n_elem
     p2 = E * (6 * 5 * N2 * 8 + 5 * N * 8 + 2 * 5 * Nface * 8)
     return pass1_bytes(w) + p2
+
+
+# HBM bytes per launch of the element pass (FP64 R) from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of `bench.py --only residual --copy-probe`, scaled as above, keyed by
+# workload and launch configuration; valid for the kernel source they were taken on
+PASS1_TRAFFIC = {}
+
+
+def traffic(workload, cfg):
+    return PASS1_TRAFFIC.get((workload, cfg))
 
 
 def cpu_baseline(w, budget_s=20.0):
@@ -321,7 +351,8 @@ def main():
     p1_ms = prof["shell_pass1_R"][0] / prof["shell_pass1_R"][1]
     p2_ms = prof["shell_pass2_R"][0] / prof["shell_pass2_R"][1]
     b1 = pass1_bytes(w)
-    achieved = b1 / (p1_ms * 1e-3) / 1e9
+    fl1 = pass1_flops(w.p) * w.n_elem * (w.p + 1) ** 3
+    achieved = fl1 / (p1_ms * 1e-3) / 1e12
     out = {
         "metric": "GDOF/s for DG R(u) & JVP; s per implicit step, learned/mixed vs plain @1e-8",
         "value": ndof / (ms_r * 1e-3) / 1e9,
@@ -341,9 +372,12 @@ def main():
         "jvp_f32_gdofs": ndof / (ms_j32 * 1e-3) / 1e9,
         "kernels_ms": {k: v_[0] / v_[1] for k, v_ in prof.items()},
         "residual_effective_gbs": residual_bytes(w) / (ms_r * 1e-3) / 1e9,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "shell_pass1 (R, f64)",
-                     "algorithmic_bytes_per_launch": b1, "avg_launch_ms": p1_ms},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic(args.workload, p1_cfg),
+                     "kernel": "shell_pass1 (R, f64)", "algorithmic_flops_per_launch": fl1,
+                     "avg_launch_ms": p1_ms, "algorithmic_bytes_per_launch": b1,
+                     "hbm_gbs_algorithmic": b1 / (p1_ms * 1e-3) / 1e9,
+                     "hbm_frac_algorithmic": b1 / (p1_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "finite": ok,
     }
     log("implicit steps")

@@ -101,7 +101,7 @@ struct dg_mesh_s {
   int64_t cols_ws_len = 0;
   int col_max_dof = 0;
   int tune_cols_grid = 2048;             // persistent wavefronts (dg_set_option "columns_grid")
-  int tune_p1 = 3;
+  int tune_p1 = 2;
   // learned warm start (dg_warmstart_set / dg_warmstart_record)
   struct dg_mlp_s* ws_mlp = nullptr;
   float* ws_norm = nullptr;              // device: x_mean [n_in], x_scale [n_in], y_mean [n_out], y_scale [n_out]

@@ -348,11 +348,11 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
     const bool bot = (k == 0 && cz == 0);
     const bool top = (k == M.n_rad - 1 && cz == n - 1);
     const bool dir = bot || (top && ph.bc_mode == 1);
-    const double bside = bot ? -1.0 : 1.0;
-    double Sn[3];
-    for (int d = 0; d < 3; ++d) Sn[d] = bside * Ja[2][d];
+    const double bside = bot ? -rc2 : rc2;
     S Bc[5];
     if (dir) {
+      double Sn[3];
+      for (int d = 0; d < 3; ++d) Sn[d] = bside * g.A3[d];
       const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
       S ub[5], Fb[5][3], Sb[5];
       boundary_state<3, S>(ph, uu, ub);
@@ -367,21 +367,31 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
     const double Q = heating<3>(ph, g.x, t);
     S F[5][3];
     flux_source<3, S>(ph, uu, q, g.x, Q, F, Sr);
-    if (dir) {
-      for (int c = 0; c < 5; ++c)
-        Sr[c] = Sr[c] + (F[c][0] * T(Sn[0]) + F[c][1] * T(Sn[1]) + F[c][2] * T(Sn[2]) + Bc[c]) * T(lfac);
-    } else if (top) {
-      // adiabatic, zero normal stress: F_hat.n = F_inviscid.n, so (F - F_hat).n = F_viscous.n
-      S Fi[5][3];
-      flux_inviscid<3, S>(ph, uu, Fi);
-      for (int c = 0; c < 5; ++c) {
-        const S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
-                     (F[c][2] - Fi[c][2]) * T(Sn[2]);
-        Sr[c] = Sr[c] + fd * T(lfac);
+    // the metric terms are read again from LDS rather than kept in registers across the flux
+    __asm__ __volatile__("" ::: "memory");
+    const double (*ang)[N2] = s_ang[le];
+    if (dir || top) {
+      double Sn[3];
+      for (int d = 0; d < 3; ++d) Sn[d] = bside * ang[6 + d][g.ja];
+      if (dir) {
+        for (int c = 0; c < 5; ++c)
+          Sr[c] = Sr[c] + (F[c][0] * T(Sn[0]) + F[c][1] * T(Sn[1]) + F[c][2] * T(Sn[2]) + Bc[c]) * T(lfac);
+      } else {
+        // adiabatic, zero normal stress: F_hat.n = F_inviscid.n, so (F - F_hat).n = F_viscous.n
+        S Fi[5][3];
+        flux_inviscid<3, S>(ph, uu, Fi);
+        for (int c = 0; c < 5; ++c) {
+          const S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
+                       (F[c][2] - Fi[c][2]) * T(Sn[2]);
+          Sr[c] = Sr[c] + fd * T(lfac);
+        }
       }
     }
-    for (int c = 0; c < 5; ++c)
-      for (int dd = 0; dd < 3; ++dd) G[c][dd] = F[c][0] * T(Ja[dd][0]) + F[c][1] * T(Ja[dd][1]) + F[c][2] * T(Ja[dd][2]);
+    for (int dd = 0; dd < 3; ++dd) {
+      const double fac = (dd < 2) ? rrp : rc2;
+      const double J0 = fac * ang[3 * dd][g.ja], J1 = fac * ang[3 * dd + 1][g.ja], J2 = fac * ang[3 * dd + 2][g.ja];
+      for (int c = 0; c < 5; ++c) G[c][dd] = F[c][0] * T(J0) + F[c][1] * T(J1) + F[c][2] * T(J2);
+    }
   }
 
   // ---- phase E (node threads): interior-face terms of this side and the traces sent to
