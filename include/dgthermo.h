@@ -134,6 +134,11 @@ typedef struct {
   int32_t jvp_prec;        /* dg_prec_t of J v inside GMRES */
   int32_t precond;         /* 0: none, 1: block Jacobi */
   int32_t guess;           /* 0: previous state (first step) / extrapolation, 1: learned warm start */
+  double filter_rate;      /* >= 0. After every step the highest Legendre mode of each element is
+                              multiplied by exp(-filter_rate dt) in every direction (tensor-product
+                              modal filter, applied to u_{n+1}); 0 leaves the DIRK step unfiltered.
+                              Not part of the paper's method: it damps the intra-element mode that
+                              the collocated (under-integrated) products let grow. */
 } dg_solver_opts_t;
 
 typedef struct {

@@ -11,7 +11,11 @@ with sigma = lambda_max I + sigma_d(u_hat) (physics.sigma).
 Boundary faces (section 2.3, the details being the stated reading):
   lower (tag 1): u_b = (varrho, 0, T_bot sqrt(rho)); u_hat = u_b;
                  F_hat.n = F(u_b, q).n + sigma(u_b) (u - u_b)
-  upper (tag 2): u_hat = u; F_hat.n = F_inviscid(u).n (zero normal stress, adiabatic)
+  upper (tag 2): u_hat = u; F_hat.n = F_inviscid(u).n (zero normal stress, adiabatic,
+                 the advective fluxes open) plus the penalty sigma (u - u_b) of eq. (LDG2)
+                 with u_b = u less its normal momentum and sigma = lambda_max on the
+                 momentum: lambda (U.n) n |Sn|, which takes the acoustic energy leaving
+                 through the open top out of the system
   bc_mode 1 (test problems): every boundary is a Dirichlet state u_D (a constant
                  vector, or P["bc_fn"](x)), treated like the lower boundary with u_b = u_D.
 
@@ -44,6 +48,16 @@ def boundary_value(mesh, P, uin, Xf):
         ud = np.asarray(P["bc_state"][: P["d"] + 2], dtype=uin.dtype)
         return np.broadcast_to(ud[:, None, None], uin.shape).copy()
     return _arr(ph.bottom_state(uin, P, np), uin[0])
+
+
+def top_penalty(P, uin, Sn, Smag, d):
+    """lambda (U.Sn) Sn / |Sn| in the momentum rows, zero elsewhere: the term
+    sigma (u - u_b) |Sn| of the upper face with u_b = u less its normal momentum"""
+    Un = sum(uin[1 + k] * Sn[k] for k in range(d)) / Smag
+    out = np.zeros_like(uin)
+    for k in range(d):
+        out[1 + k] = P["lam"] * Un * Sn[k]
+    return out
 
 
 def traces(mesh, P, u):
@@ -132,7 +146,7 @@ def residual(mesh, P, u, t=0.0, q=None):
         sigb = _arr(ph.sigma(ub, P, np), ub[0])
         Fh_dir = _dot_n(Fb, Sn, d) + Smag * sigb * (uin - ub)
         Fi_top = _arr2(ph.flux_inviscid(uin, P, np), uin[0])
-        Fh_top = _dot_n(Fi_top, Sn, d)
+        Fh_top = _dot_n(Fi_top, Sn, d) + top_penalty(P, uin, Sn, Smag, d)
         tag = mesh.tag[:, fi][None, :, None]
         if P.get("bc_mode", 0) == 1:
             Fh = np.where(tag > 0, Fh_dir, Fh_int)
@@ -196,7 +210,7 @@ def conservation_terms(mesh, P, u, t=0.0):
         Fb = _arr2(ph.flux(ub, qin, P, np), ub[0])
         sigb = _arr(ph.sigma(ub, P, np), ub[0])
         Fh_dir = _dot_n(Fb, Sn, d) + Smag * sigb * (uin - ub)
-        Fh_top = _dot_n(_arr2(ph.flux_inviscid(uin, P, np), uin[0]), Sn, d)
+        Fh_top = _dot_n(_arr2(ph.flux_inviscid(uin, P, np), uin[0]), Sn, d) + top_penalty(P, uin, Sn, Smag, d)
         t_ = tag[None, :, None]
         if P.get("bc_mode", 0) == 1:
             Fh = np.where(t_ > 0, Fh_dir, 0.0)

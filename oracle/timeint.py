@@ -12,6 +12,11 @@ b_i = u_n + dt sum_{j<i} a_ij R(U_j, t + c_j dt); u_{n+1} = U_last.
 
 The exact stage solution used for parity is a dense Newton (numpy LU on the
 complex-step Jacobian) iterated to a residual of 1e-13 relative to |G(u_n)|.
+
+Optional modal filter (not part of the paper's method): after a step, the
+coefficient of the degree-p Legendre polynomial of every element, in every
+direction, is multiplied by sigma = exp(-filter_rate dt); filter_rate = 0 is the
+plain DIRK step.
 """
 import numpy as np
 
@@ -53,8 +58,27 @@ def newton_dense(Gfun, Jfun, U0, ref_norm, rtol=1e-13, maxit=30):
     raise RuntimeError("dense Newton did not converge: %s" % hist[-5:])
 
 
-def implicit_step_dense(mesh, P, u, t, dt, scheme=33, rtol=1e-13, guesses=None):
-    """one DIRK step with every stage solved by dense Newton. Returns (u_new, stages)."""
+def filter_matrix(x, p, sigma):
+    """1D nodal filter on the points x: to Legendre coefficients (Vandermonde inverse),
+    scale the degree-p coefficient by sigma, back to nodal values"""
+    V = np.polynomial.legendre.legvander(x, p)
+    return V @ np.diag(np.r_[np.ones(p), sigma]) @ np.linalg.inv(V)
+
+
+def modal_filter(mesh, u, sigma):
+    """the tensor-product filter applied to every element of u [E, f, N]"""
+    ref = mesh.ref
+    F1 = filter_matrix(ref.x1, ref.p, sigma)
+    n, d = ref.n, mesh.d
+    v = u.reshape(u.shape[:2] + (n,) * d)          # node index a + n b + n^2 c -> axes (c, b, a)
+    for ax in range(d):
+        v = np.moveaxis(np.tensordot(v, F1, axes=([2 + ax], [1])), -1, 2 + ax)
+    return v.reshape(u.shape)
+
+
+def implicit_step_dense(mesh, P, u, t, dt, scheme=33, rtol=1e-13, guesses=None, filter_rate=0.0):
+    """one DIRK step with every stage solved by dense Newton, then the optional modal
+    filter. Returns (u_new, stages)."""
     A, b, c = dirk_tableau(scheme)
     s = len(c)
     Rs, Us = [], []
@@ -69,7 +93,8 @@ def implicit_step_dense(mesh, P, u, t, dt, scheme=33, rtol=1e-13, guesses=None):
         Ui, _, _ = newton_dense(G, Jf, U0, ref, rtol)
         Us.append(Ui)
         Rs.append(dg.residual(mesh, P, Ui, ti))
-    return Us[-1], Us
+    un = modal_filter(mesh, Us[-1], np.exp(-filter_rate * dt)) if filter_rate > 0 else Us[-1]
+    return un, Us
 
 
 def gmres(Aop, rhs, x0=None, m=30, rtol=1e-10, max_restarts=50, M=None):
@@ -140,8 +165,9 @@ def newton_jfnk(mesh, P, Gfun, U0, ti, aii_dt, ref_norm, rtol=1e-12, maxit=40, g
     raise RuntimeError("JFNK Newton did not converge")
 
 
-def implicit_step_jfnk(mesh, P, u, t, dt, scheme=33, rtol=1e-12):
-    """one DIRK step with every stage solved by matrix-free Newton-GMRES to rtol"""
+def implicit_step_jfnk(mesh, P, u, t, dt, scheme=33, rtol=1e-12, filter_rate=0.0):
+    """one DIRK step with every stage solved by matrix-free Newton-GMRES to rtol, then
+    the optional modal filter"""
     A, b, c = dirk_tableau(scheme)
     Rs, Us = [], []
     for i in range(len(c)):
@@ -152,4 +178,5 @@ def implicit_step_jfnk(mesh, P, u, t, dt, scheme=33, rtol=1e-12):
         Ui, _ = newton_jfnk(mesh, P, G, u, ti, dt * aii, np.linalg.norm(G(u)), rtol)
         Us.append(Ui)
         Rs.append(dg.residual(mesh, P, Ui, ti))
-    return Us[-1], Us
+    un = modal_filter(mesh, Us[-1], np.exp(-filter_rate * dt)) if filter_rate > 0 else Us[-1]
+    return un, Us

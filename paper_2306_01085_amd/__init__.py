@@ -52,7 +52,7 @@ class Physics(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("gmres_m", C.c_int32), ("max_newton", C.c_int32),
                 ("max_restarts", C.c_int32), ("newton_rtol", C.c_double), ("gmres_rtol", C.c_double),
-                ("jvp_prec", C.c_int32), ("precond", C.c_int32), ("guess", C.c_int32)]
+                ("jvp_prec", C.c_int32), ("precond", C.c_int32), ("guess", C.c_int32), ("filter_rate", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -256,11 +256,11 @@ class Mesh:
         return out
 
     def implicit_step(self, u, t, dt, scheme=33, gmres_m=30, max_newton=20, max_restarts=20, newton_rtol=1e-8,
-                      gmres_rtol=1e-3, jvp_prec="f64", precond=1, guess=0, stream=None):
+                      gmres_rtol=1e-3, jvp_prec="f64", precond=1, guess=0, filter_rate=0.0, stream=None):
         import torch
         o = SolverOpts(scheme=scheme, gmres_m=gmres_m, max_newton=max_newton, max_restarts=max_restarts,
                        newton_rtol=newton_rtol, gmres_rtol=gmres_rtol, jvp_prec=_PREC[jvp_prec], precond=precond,
-                       guess=guess)
+                       guess=guess, filter_rate=filter_rate)
         st = StepStats()
         code = _lib.dg_implicit_step(self._h, float(t), float(dt), _ptr(u, torch.float64), u.numel(), C.byref(o),
                                      C.byref(st), _stream(stream))
@@ -268,13 +268,13 @@ class Mesh:
         return st.as_dict()
 
 
-def _columns_integrate(self, u, t0, dt, n_steps, scheme=33, max_newton=20, newton_rtol=1e-8, stream=None,
-                       raise_on_failure=True):
+def _columns_integrate(self, u, t0, dt, n_steps, scheme=33, max_newton=20, newton_rtol=1e-8, filter_rate=0.0,
+                       stream=None, raise_on_failure=True):
     """advance every column by n_steps DIRK steps in one persistent launch; returns
     (Newton iterations per column, status per column)"""
     import torch
     o = SolverOpts(scheme=scheme, gmres_m=1, max_newton=max_newton, max_restarts=1, newton_rtol=newton_rtol,
-                   gmres_rtol=1e-3, jvp_prec=DG_F64, precond=0, guess=0)
+                   gmres_rtol=1e-3, jvp_prec=DG_F64, precond=0, guess=0, filter_rate=filter_rate)
     its = np.zeros(self.n_col, dtype=np.int32)
     st = np.zeros(self.n_col, dtype=np.int32)
     code = _lib.dg_columns_integrate(self._h, float(t0), float(dt), int(n_steps), _ptr(u, torch.float64), u.numel(),

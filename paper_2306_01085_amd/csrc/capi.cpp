@@ -289,7 +289,7 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
   if ((opts->scheme != 33 && opts->scheme != 22) || opts->gmres_m < 1 || opts->gmres_m > 32 ||
       opts->max_newton < 1 || opts->max_restarts < 1 || !(opts->newton_rtol > 0) || !(opts->gmres_rtol > 0) ||
       (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32) || opts->precond < 0 || opts->precond > 1 ||
-      opts->guess < 0 || opts->guess > 1) {
+      opts->guess < 0 || opts->guess > 1 || !(opts->filter_rate >= 0) || !std::isfinite(opts->filter_rate)) {
     set_error("dg_implicit_step: invalid solver options");
     return DG_ERR_ARG;
   }
@@ -300,7 +300,8 @@ dg_status_t dg_columns_integrate(dg_mesh_t m, double t0, double dt, int32_t n_st
                                  const dg_solver_opts_t* opts, int32_t* newton_host, int32_t* status_host,
                                  void* stream) {
   if (!m || !u || !opts || m->kind != DG_MESH_COLUMNS || n_dof != m->n_dof || !(dt > 0) || n_steps < 0 ||
-      (opts->scheme != 33 && opts->scheme != 22) || opts->max_newton < 1 || !(opts->newton_rtol > 0)) {
+      (opts->scheme != 33 && opts->scheme != 22) || opts->max_newton < 1 || !(opts->newton_rtol > 0) ||
+      !(opts->filter_rate >= 0) || !std::isfinite(opts->filter_rate)) {
     set_error("dg_columns_integrate: invalid argument (needs a column mesh)");
     return DG_ERR_ARG;
   }

@@ -140,9 +140,14 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
         Rl[c][n - 1] = Rl[c][n - 1] + ((Fhi[c] - Fb[c][0]) - sg * (ut[c] - ub[c])) * T(lfac);
       }
     } else {
+      // adiabatic, zero normal stress, open, with the penalty lambda U on the momentum
       S Fi[3][1];
       flux_inviscid<1, S>(Pc, ut, Fi);
-      for (int c = 0; c < 3; ++c) Rl[c][n - 1] = Rl[c][n - 1] + (Fhi[c] - Fi[c][0]) * T(lfac);
+      for (int c = 0; c < 3; ++c) {
+        S fd = Fhi[c] - Fi[c][0];
+        if (c == 1) fd = fd - T(Pc.lam) * ut[1];
+        Rl[c][n - 1] = Rl[c][n - 1] + fd * T(lfac);
+      }
     }
   }
   for (int c = 0; c < 3; ++c)
@@ -246,6 +251,41 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
   return DG_OK;
 }
 
+// modal filter of every column element (one thread per element and field), in place
+template <int P>
+__global__ __launch_bounds__(128) void col_filter(ColDev C, const int* __restrict__ elist, int ne, FiltC f,
+                                                  double* __restrict__ u) {
+  constexpr int n = P + 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 3 * ne) return;
+  const int e = elist[idx / 3];
+  double* x = u + C.off[e] + (idx % 3) * n;
+  double y[n];
+  for (int a = 0; a < n; ++a) {
+    y[a] = 0.0;
+    for (int i = 0; i < n; ++i) y[a] += f.F[a * n + i] * x[i];
+  }
+  for (int a = 0; a < n; ++a) x[a] = y[a];
+}
+
+dg_status_t col_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s) {
+  ColDev C = m->cols();
+  for (int pi = 0; pi < 3; ++pi) {
+    const int ne = m->plist_n[pi];
+    if (!ne) continue;
+    const int blocks = (3 * ne + 127) / 128;
+    const int* el = m->d_plist[pi];
+    const FiltC f = make_filter(pi + 2, sigma);
+    switch (pi + 2) {
+      case 2: col_filter<2><<<blocks, 128, 0, s>>>(C, el, ne, f, u); break;
+      case 3: col_filter<3><<<blocks, 128, 0, s>>>(C, el, ne, f, u); break;
+      default: col_filter<4><<<blocks, 128, 0, s>>>(C, el, ne, f, u); break;
+    }
+  }
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+
 dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s) {
   return launch_cols<double, double, double, double>(m, t, u, (const double*)nullptr, r, m->d_fn64, s, 6);
 }
@@ -296,6 +336,8 @@ struct ColBatch {
   int* newton_total;
   int* status;
   int* jac_builds;
+  int filter;          // 1: modal filter after every step
+  FiltC filt[3];       // for p = 2, 3, 4
 };
 
 __device__ inline double wave_allsum(double x) {
@@ -494,7 +536,8 @@ __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double
 
 template <int P>
 __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC& ph, const GllC& gc) {
-  constexpr int b = 3 * (P + 1);
+  constexpr int n = P + 1;
+  constexpr int b = 3 * n;
   const int lane = threadIdx.x;
   const int E = B.col_E[col];
   const int e0 = B.col_e0[col];
@@ -580,6 +623,19 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
     if (status == 0) {
       for (int i = lane; i < nd; i += 64) un[i] = U[i];
       __syncthreads();
+      if (B.filter) {
+        const double* F = B.filt[P - 2].F;
+        for (int k = lane; k < 3 * E; k += 64) {
+          double* x = un + k * n;   // element k / 3, field k % 3
+          double y[n];
+          for (int a = 0; a < n; ++a) {
+            y[a] = 0.0;
+            for (int i = 0; i < n; ++i) y[a] += F[a * n + i] * x[i];
+          }
+          for (int a = 0; a < n; ++a) x[a] = y[a];
+        }
+        __syncthreads();
+      }
     }
   }
   if (status == 0)
@@ -673,6 +729,8 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   B.n_steps = n_steps;
   B.max_newton = o.max_newton;
   B.rtol = o.newton_rtol;
+  B.filter = o.filter_rate > 0 ? 1 : 0;
+  for (int pi = 0; pi < 3; ++pi) B.filt[pi] = make_filter(pi + 2, std::exp(-o.filter_rate * dt));
   B.ws = m->d_cols_ws;
   B.ws_stride = stride;
   B.max_dof = (int)md;

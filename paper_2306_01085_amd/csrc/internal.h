@@ -37,6 +37,15 @@ struct GllC {
 };
 GllC make_gllc(int p);
 
+// modal filter of degree p on the GLL nodes: F = I - (1 - sigma) P_p(x_a) c_p(i), where
+// c_p(i) = w_i P_p(x_i) / sum_j w_j P_p(x_j)^2 extracts the coefficient of the Legendre
+// polynomial P_p (GLL quadrature is exact for P_k P_p with k < p, so the lower modes
+// are untouched); F[a*n + i]
+struct FiltC {
+  double F[25];
+};
+FiltC make_filter(int p, double sigma);
+
 // device view of the shell geometry and connectivity (kernel argument)
 struct ShellDev {
   int n_ang, n_rad, E;
@@ -152,6 +161,9 @@ dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v,
 dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
 dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+// modal filter (highest Legendre mode x sigma per direction), in place on u
+dg_status_t shell_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s);
+dg_status_t col_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s);
 dg_status_t shell_bjac_build(dg_mesh_s* m, double t, const double* u, double dta, double* Binv, hipStream_t s);
 dg_status_t shell_bjac_apply64(dg_mesh_s* m, const double* B, const double* v, double* z, hipStream_t s);
 dg_status_t shell_bjac_apply32(dg_mesh_s* m, const double* B, const float* v, float* z, hipStream_t s);

@@ -100,6 +100,29 @@ GllC make_gllc(int p) {
   return c;
 }
 
+FiltC make_filter(int p, double sigma) {
+  Gll g = make_gll(p);
+  const int n = g.n;
+  std::vector<double> Pp(n);
+  for (int i = 0; i < n; ++i) {
+    // Bonnet recursion (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}
+    double p0 = 1.0, p1 = g.x[i];
+    for (int k = 1; k < p; ++k) {
+      const double p2 = ((2.0 * k + 1.0) * g.x[i] * p1 - k * p0) / (k + 1.0);
+      p0 = p1;
+      p1 = p2;
+    }
+    Pp[i] = (p == 0) ? 1.0 : p1;
+  }
+  double nrm = 0;
+  for (int i = 0; i < n; ++i) nrm += g.w[i] * Pp[i] * Pp[i];
+  FiltC f{};
+  for (int a = 0; a < n; ++a)
+    for (int i = 0; i < n; ++i)
+      f.F[a * n + i] = (a == i ? 1.0 : 0.0) - (1.0 - sigma) * Pp[a] * g.w[i] * Pp[i] / nrm;
+  return f;
+}
+
 std::vector<double> radial_edges(double r_bot, double r_top, int n, double stretch) {
   std::vector<double> h(n), e(n + 1);
   if (std::fabs(stretch - 1.0) < 1e-15) {

@@ -377,12 +377,16 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         for (int c = 0; c < 5; ++c)
           Sr[c] = Sr[c] + (F[c][0] * T(Sn[0]) + F[c][1] * T(Sn[1]) + F[c][2] * T(Sn[2]) + Bc[c]) * T(lfac);
       } else {
-        // adiabatic, zero normal stress: F_hat.n = F_inviscid.n, so (F - F_hat).n = F_viscous.n
+        // adiabatic, zero normal stress, open: F_hat.Sn = F_inviscid.Sn + lambda (U.Sn) Sn/|Sn|
+        // (the penalty on the normal momentum), so (F - F_hat).Sn = F_viscous.Sn - penalty
         S Fi[5][3];
         flux_inviscid<3, S>(ph, uu, Fi);
+        const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
+        const S Un = (uu[1] * T(Sn[0]) + uu[2] * T(Sn[1]) + uu[3] * T(Sn[2])) * T(ph.lam / Smag);
         for (int c = 0; c < 5; ++c) {
-          const S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
-                       (F[c][2] - Fi[c][2]) * T(Sn[2]);
+          S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
+                 (F[c][2] - Fi[c][2]) * T(Sn[2]);
+          if (c >= 1 && c <= 3) fd = fd - Un * T(Sn[c - 1]);
           Sr[c] = Sr[c] + fd * T(lfac);
         }
       }
@@ -540,6 +544,60 @@ dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v,
   return launch<Dual<float>, double, float, float>(m, t, u, v, jv, m->d_fn32, s, 4);
 }
 
+// tensor-product modal filter of every element: the 1D filter F applied along the three
+// directions in turn (LDS-staged), in place on u [E][5][N]
+template <int P>
+__global__ __launch_bounds__(256) void shell_filter(int E, FiltC f, double* __restrict__ u) {
+  typedef Shape<P> Sh;
+  constexpr int n = Sh::n, N = Sh::N, N2 = Sh::N2, TPE = Sh::TPE, EPB = Sh::EPB;
+  __shared__ double s_x[EPB][N];
+  __shared__ double F[n * n];
+  const int le = threadIdx.x / TPE;
+  const int j = threadIdx.x % TPE;
+  const int e = blockIdx.x * EPB + le;
+  const bool active = e < E && j < N;
+  if (threadIdx.x < n * n) F[threadIdx.x] = f.F[threadIdx.x];
+  const int a = j % n, b = (j / n) % n, cz = j / N2;
+  const int64_t base = (int64_t)e * 5 * N;
+  for (int c = 0; c < 5; ++c) {
+    double x = active ? u[base + c * N + j] : 0.0;
+    if (active) s_x[le][j] = x;
+    __syncthreads();
+    if (active) {
+      x = 0.0;
+      for (int i = 0; i < n; ++i) x += F[a * n + i] * s_x[le][i + n * b + N2 * cz];
+    }
+    __syncthreads();
+    if (active) s_x[le][j] = x;
+    __syncthreads();
+    if (active) {
+      x = 0.0;
+      for (int i = 0; i < n; ++i) x += F[b * n + i] * s_x[le][a + n * i + N2 * cz];
+    }
+    __syncthreads();
+    if (active) s_x[le][j] = x;
+    __syncthreads();
+    if (active) {
+      x = 0.0;
+      for (int i = 0; i < n; ++i) x += F[cz * n + i] * s_x[le][a + n * b + N2 * i];
+      u[base + c * N + j] = x;
+    }
+    __syncthreads();
+  }
+}
+
+dg_status_t shell_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s) {
+  const int E = (int)m->n_elem;
+  const FiltC f = make_filter(m->p, sigma);
+  switch (m->p) {
+    case 2: shell_filter<2><<<(E + Shape<2>::EPB - 1) / Shape<2>::EPB, 256, 0, s>>>(E, f, u); break;
+    case 3: shell_filter<3><<<(E + Shape<3>::EPB - 1) / Shape<3>::EPB, 256, 0, s>>>(E, f, u); break;
+    default: shell_filter<4><<<(E + Shape<4>::EPB - 1) / Shape<4>::EPB, 256, 0, s>>>(E, f, u); break;
+  }
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+
 // Node block-Jacobi blocks of the stage matrix I - dta J(u): for every node, the 5x5
 // derivative of R at the node with respect to the node's own state through its
 // pointwise flux and source (the gradient q held fixed), the diagonal entries of the
@@ -614,6 +672,9 @@ __global__ __launch_bounds__(256) void shell_bjac(ShellDev M, PhysC ph, GllC gc,
           if (r == c) col -= 0.5 * lfac * sqrt(Sn2) * sg;
         } else if (f == 4 || ph.bc_mode == 1) {
           if (r == c && r > 0) col -= lfac * sqrt(Sn2) * sg;
+        } else if (r >= 1 && r <= 3 && c >= 1 && c <= 3) {
+          // upper face: lambda (U.Sn) Sn / |Sn|
+          col -= lfac * ph.lam * fac3[dd] * Am3[dd][r - 1] * fac3[dd] * Am3[dd][c - 1] / sqrt(Sn2);
         }
       }
       blk[r][c] = (r == c ? 1.0 : 0.0) - dta * col;

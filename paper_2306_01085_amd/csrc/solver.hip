@@ -589,8 +589,8 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
         stats.fallback[i] = 1;
       }
     }
-    int newton = 0, gm_total = 0;
-    double nG = 0;
+    int newton = 0, gm_total = 0, halvings = 0;
+    double nG = 0, prev = 0, alpha = 1.0;
     for (;;) {
       rc = residual(m, ti, ws->U, ws->Rc, s);
       if (rc != DG_OK) return rc;
@@ -600,6 +600,13 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       if (rc != DG_OK) return rc;
       nG = std::sqrt(g2);
       if (newton == 0) stats.res0[i] = nG;
+      // backtracking: a Newton update that leaves a non-finite or larger residual is halved
+      if (newton > 0 && !(nG <= prev) && halvings < 6) {
+        alpha *= 0.5;
+        k_axpby<<<nb, RED_THREADS, 0, s>>>(n, -alpha, ws->X, 1.0, ws->U, nullptr);
+        ++halvings;
+        continue;
+      }
       if (!std::isfinite(nG)) {
         DG_HIP_CHECK(hipMemcpyAsync(u, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s));
         set_error("dg_implicit_step: non-finite stage residual");
@@ -621,6 +628,9 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       gm_total += its;
       k_axpby<<<nb, RED_THREADS, 0, s>>>(n, 1.0, ws->X, 1.0, ws->U, nullptr);
       ++newton;
+      prev = nG;
+      alpha = 1.0;
+      halvings = 0;
     }
     stats.newton_its[i] = newton;
     stats.gmres_its[i] = gm_total;
@@ -659,8 +669,13 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
     ws->hist_t[0] = ti;
     ws->hist_n = std::min(ws->hist_n + 1, 2);
   }
-  // stiffly accurate: u_{n+1} = U_last
+  // stiffly accurate: u_{n+1} = U_last, then the optional modal filter
   DG_HIP_CHECK(hipMemcpyAsync(u, ws->U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (o.filter_rate > 0) {
+    const double sigma = std::exp(-o.filter_rate * dt);
+    rc = (m->kind == DG_MESH_SHELL) ? shell_filter_apply(m, sigma, u, s) : col_filter_apply(m, sigma, u, s);
+    if (rc != DG_OK) return rc;
+  }
   DG_HIP_CHECK(hipStreamSynchronize(s));
   ws->t_end = t + dt;
   stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -80,3 +80,24 @@ def test_batched_failure_keeps_input_state():
     its, st = gm.columns_integrate(ut, 0.0, 1e4 * w.dt, 1, max_newton=1, newton_rtol=1e-14, raise_on_failure=False)
     assert np.all((st == 4) | (st == 5))
     assert np.array_equal(ut.cpu().numpy(), u0)
+
+
+def test_batched_columns_filtered_match_oracle():
+    """the persistent integrator with the modal filter after every step"""
+    need_gpu()
+    nelem = [5, 8, 6]
+    p = [2, 3, 4]
+    w, gm, cols = _batch(13, nelem, p)
+    u0 = np.concatenate([c[2].ravel() for c in cols])
+    ut = to_dev(u0)
+    rate, n_steps = 0.5, 3
+    its, st = gm.columns_integrate(ut, 0.0, w.dt, n_steps, newton_rtol=1e-11, filter_rate=rate)
+    assert np.all(st == 0)
+    out = ut.cpu().numpy()
+    off = gm.col_offsets()
+    for c, (om, P, u) in enumerate(cols):
+        ref = u.copy()
+        for s in range(n_steps):
+            ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-13, filter_rate=rate)
+        got = out[off[c]:off[c + 1]].reshape(u.shape)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref - u) < 1e-6, c

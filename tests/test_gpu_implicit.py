@@ -72,3 +72,28 @@ def test_noconvergence_leaves_state_unchanged():
         gm.implicit_step(ut, 0.0, 1e3 * w.dt, max_newton=1, newton_rtol=1e-12, gmres_rtol=1e-2, max_restarts=1)
     assert ei.value.code == DG_ERR_NOCONV
     assert np.array_equal(ut.cpu().numpy(), u.ravel())
+
+
+def test_filtered_steps_match_oracle():
+    """the optional modal filter after each step: two filtered column steps and one
+    filtered shell step against the oracle's filtered steps"""
+    need_gpu()
+    rate = 0.7
+    w, om, gm, u = _column(4, E=6, p=3)
+    ref = u.copy()
+    for s in range(2):
+        ref, _ = timeint.implicit_step_dense(om, w.phys, ref, s * w.dt, w.dt, rtol=1e-13, filter_rate=rate)
+    ut = to_dev(u)
+    for s in range(2):
+        gm.implicit_step(ut, s * w.dt, w.dt, newton_rtol=1e-10, gmres_rtol=1e-6, precond=0, filter_rate=rate)
+    out = ut.cpu().numpy().reshape(u.shape)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref - u) < 1e-6
+    ws = synth.shell_workload(5, p=2, n_ang=1, n_rad=2)
+    om3, gm3 = shell_pair(ws, 1, 2, 2)
+    u3 = np.moveaxis(ws.state_fn()(om3.X), 0, 1).copy()
+    dt = synth.seconds_to_nondim(10.0)
+    ref3, _ = timeint.implicit_step_jfnk(om3, ws.phys, u3, 0.0, dt, rtol=1e-12, filter_rate=rate)
+    ut3 = to_dev(u3)
+    gm3.implicit_step(ut3, 0.0, dt, newton_rtol=1e-10, gmres_rtol=1e-6, precond=0, filter_rate=rate)
+    out3 = ut3.cpu().numpy().reshape(u3.shape)
+    assert np.linalg.norm(out3 - ref3) / np.linalg.norm(ref3 - u3) < 1e-6

@@ -101,3 +101,28 @@ def test_jfnk_step_matches_dense_step():
     u1, _ = timeint.implicit_step_dense(m, P, u, 0.0, dt, scheme=33, rtol=1e-13)
     u2, _ = timeint.implicit_step_jfnk(m, P, u, 0.0, dt, scheme=33, rtol=1e-13)
     assert np.max(np.abs(u1 - u2)) < 1e-10 * np.max(np.abs(u1))
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_modal_filter_closed_form(p):
+    """the filter keeps every tensor polynomial below degree p in each variable and
+    multiplies the degree-p Legendre factor of each variable by sigma (closed form on
+    the reference element, 3D and 1D)"""
+    from numpy.polynomial import legendre as L
+    from oracle import mesh as omesh
+    sigma = 0.37
+    Pp = lambda x: L.legval(x, np.r_[np.zeros(p), 1.0])
+    om = omesh.shell_mesh(p, 1, 1, 1.0, 1.5)
+    x1 = om.ref.x1
+    a, b, c = (x1[i] for i in om.ref.idx)
+    low = 0.3 + a ** (p - 1) * b - 0.7 * b * c ** (p - 1) + a * b * c
+    u = np.stack([low, Pp(a) * b, Pp(a) * Pp(b) * Pp(c), Pp(c) + low, Pp(b) * a ** (p - 1)])[None]
+    want = np.stack([low, sigma * Pp(a) * b, sigma ** 3 * Pp(a) * Pp(b) * Pp(c), sigma * Pp(c) + low,
+                     sigma * Pp(b) * a ** (p - 1)])[None]
+    got = timeint.modal_filter(om, u, sigma)
+    assert np.max(np.abs(got - want)) < 1e-13
+    col = omesh.columns_mesh([3], p, 1.0, 2.0)
+    xc = col.ref.x1
+    uc = np.tile(np.stack([xc ** (p - 1), Pp(xc), 1.0 + Pp(xc)]), (3, 1, 1))
+    wc = np.tile(np.stack([xc ** (p - 1), sigma * Pp(xc), 1.0 + sigma * Pp(xc)]), (3, 1, 1))
+    assert np.max(np.abs(timeint.modal_filter(col, uc, sigma) - wc)) < 1e-13
