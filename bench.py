@@ -134,17 +134,22 @@ def cpu_baseline(w, budget_s=20.0):
                       % (n_ang, n_ang, n_rad, w.p, ndof, len(times))}
 
 
+FILTER_RATE = 0.5   # modal filter after every implicit step (per unit nondimensional time)
+
+
 def implicit_steps(w, mesh, u, n_steps):
     """seconds per DIRK(3,3) step of dt = 60 s at a 1e-8 relative Newton tolerance,
     GMRES(30) without preconditioner, plain extrapolated guess: FP64 vs FP32 J v"""
     import torch
-    res = {"dt_s": 60.0, "newton_rtol": 1e-8, "gmres": "GMRES(30), CGS2, no preconditioner", "steps": n_steps}
+    res = {"dt_s": 60.0, "newton_rtol": 1e-8, "gmres": "GMRES(30), CGS2, no preconditioner", "steps": n_steps,
+           "filter_rate": FILTER_RATE}
     for prec in ("f64", "f32"):
         x = u.clone()
         t = 0.0
         secs, newton, gmres = [], [], []
         for _ in range(n_steps):
-            st = mesh.implicit_step(x, t, w.dt, jvp_prec=prec, precond=0, max_newton=15, max_restarts=40)
+            st = mesh.implicit_step(x, t, w.dt, jvp_prec=prec, precond=0, max_newton=15, max_restarts=40,
+                                    filter_rate=FILTER_RATE)
             t += w.dt
             secs.append(st["seconds"])
             newton.append(sum(st["newton_its"]))
@@ -179,17 +184,19 @@ def column_batch(n_steps=None, check_cols=2, check_steps=2):
     x = u.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    its, st = gm.columns_integrate(x, 0.0, w.dt, n_steps, raise_on_failure=False)
+    its, st = gm.columns_integrate(x, 0.0, w.dt, n_steps, filter_rate=FILTER_RATE, raise_on_failure=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    out = {"n_col": gm.n_col, "n_dof": gm.n_dof, "steps": n_steps, "seconds": el, "columns_per_s": gm.n_col / el,
+    out = {"n_col": gm.n_col, "n_dof": gm.n_dof, "steps": n_steps, "filter_rate": FILTER_RATE, "seconds": el,
+           "columns_per_s": gm.n_col / el,
            "grid": grid, "newton_per_step_mean": float(its.mean() / n_steps), "failed": int((st != 0).sum())}
     # error of sampled columns after check_steps steps: the smallest columns keep the
     # dense oracle affordable
     from oracle import mesh as omesh
     from oracle import timeint
     y = u.clone()
-    gm.columns_integrate(y, 0.0, w.dt, check_steps, newton_rtol=1e-10, raise_on_failure=False)
+    gm.columns_integrate(y, 0.0, w.dt, check_steps, newton_rtol=1e-10, filter_rate=FILTER_RATE,
+                         raise_on_failure=False)
     yc = y.cpu().numpy()
     errs = []
     for c in np.argsort(w.nelem * (w.p + 1))[:check_cols]:
@@ -200,7 +207,7 @@ def column_batch(n_steps=None, check_cols=2, check_steps=2):
         ref = u0[off[c]:off[c + 1]].reshape(-1, 3, w.p[c] + 1).copy()
         start = ref.copy()
         for s in range(check_steps):
-            ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-12)
+            ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-12, filter_rate=FILTER_RATE)
         got = yc[off[c]:off[c + 1]].reshape(ref.shape)
         errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref - start)))
     out["sampled_error"] = {"columns": check_cols, "steps": check_steps, "max_rel_err": max(errs),
@@ -216,7 +223,7 @@ def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epoc
 
     from paper_2306_01085_amd import Network
     from paper_2306_01085_amd import warmstart as wsm
-    opts = dict(newton_rtol=1e-8, precond=0, max_newton=15, max_restarts=40)
+    opts = dict(newton_rtol=1e-8, precond=0, max_newton=15, max_restarts=40, filter_rate=FILTER_RATE)
     nin, nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
     cap = (3 * train_steps) * ((w.n_elem + every - 1) // every)
     t_rec = time.perf_counter()
@@ -244,7 +251,10 @@ def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epoc
                       "newton": agg(sp, "newton_its"), "gmres": agg(sp, "gmres_its")},
             "learned": {"s_per_step": float(np.mean([s["seconds"] for s in sl])),
                         "newton": agg(sl, "newton_its"), "gmres": agg(sl, "gmres_its"),
-                        "fallback_stages": int(sum(sum(s["fallback"]) for s in sl))},
+                        "fallback_stages": int(sum(sum(s["fallback"]) for s in sl)),
+                        "mean_guess_scale": float(np.mean([g for s in sl for g in s["guess_scale"]])),
+                        "res0_over_plain": float(np.mean([a / b for s1, s2 in zip(sl, sp)
+                                                          for a, b in zip(s1["res0"], s2["res0"]) if b > 0]))},
             "state_rel_diff": float(torch.linalg.norm(up - ul).item() / torch.linalg.norm(up - u).item()),
         }
     out["value"] = out["f32"]["learned"]["s_per_step"]
@@ -265,6 +275,9 @@ def main():
                     help="residual: only the R(u) timing (for counter runs)")
     ap.add_argument("--mode", default="default", choices=["default", "warmstart"])
     ap.add_argument("--implicit-steps", type=int, default=2)
+    ap.add_argument("--ws-train-steps", type=int, default=60)
+    ap.add_argument("--ws-eval-steps", type=int, default=8)
+    ap.add_argument("--ws-epochs", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -308,7 +321,8 @@ def main():
 
     if args.mode == "warmstart":
         del r, jv, jv32, v, v32
-        print(json.dumps(warmstart_experiment(w, mesh, u)), flush=True)
+        print(json.dumps(warmstart_experiment(w, mesh, u, train_steps=args.ws_train_steps,
+                                              eval_steps=args.ws_eval_steps, epochs=args.ws_epochs)), flush=True)
         return
 
     f_r = lambda: mesh.residual(u, t, out=r)

@@ -148,6 +148,7 @@ typedef struct {
   double res0[3];          /* |G(guess)| per stage */
   double res[3];           /* final |G| per stage */
   double ref[3];           /* |G(u_n)| per stage (the reference norm) */
+  double guess_scale[3];   /* learned guess: the factor applied to the network's correction */
   double seconds;          /* wall time of the call */
 } dg_step_stats_t;
 
@@ -208,9 +209,12 @@ dg_status_t dg_affine_rows(float* x, int64_t n, int32_t width, const float* mean
  * features of element e at stage i are [U_a, U_a - U_b, b_i - U_a] (U_a, U_b the two
  * latest stage solutions, b_i the stage right-hand side; 3 x 5 x N values, node-major
  * per field as in the state layout), standardised with x_mean / x_scale (host [n_in]);
- * the output de-standardised with y_mean / y_scale (host [n_out], n_out = 5 N) is
- * added to the plain guess. The guess with the smaller |G| is used (the other one is
- * the fallback, reported in dg_step_stats_t.fallback). The network is not owned. */
+ * the output de-standardised with y_mean / y_scale (host [n_out], n_out = 5 N) is the
+ * correction D of the plain guess U_p. The guess is U_p + alpha D with alpha in [0, 2]
+ * minimising the linearised stage residual |G(U_p) + alpha (I - dt a_ii J(U_p)) D|
+ * (one FP64 J v; reported in dg_step_stats_t.guess_scale); it is kept only if its |G|
+ * is below |G(U_p)| (otherwise U_p: dg_step_stats_t.fallback). The network is not
+ * owned. */
 dg_status_t dg_warmstart_set(dg_mesh_t mesh, dg_mlp_t mlp, const float* x_mean_host, const float* x_scale_host,
                              const float* y_mean_host, const float* y_scale_host);
 /* Record training pairs during later dg_implicit_step calls on a shell mesh: for one

@@ -58,7 +58,7 @@ class SolverOpts(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("newton_its", C.c_int32 * 3), ("gmres_its", C.c_int32 * 3), ("fallback", C.c_int32 * 3),
                 ("res0", C.c_double * 3), ("res", C.c_double * 3), ("ref", C.c_double * 3),
-                ("seconds", C.c_double)]
+                ("guess_scale", C.c_double * 3), ("seconds", C.c_double)]
 
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k != "seconds" else self.seconds) for k, _ in self._fields_}

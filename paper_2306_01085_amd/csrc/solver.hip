@@ -142,6 +142,19 @@ __global__ __launch_bounds__(RED_THREADS) void k_stage_residual(int64_t n, const
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// partial sums of a.b and b.b (two accumulators per block)
+__global__ __launch_bounds__(RED_THREADS) void k_dot2(int64_t n, const double* __restrict__ a,
+                                                      const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) * 2 + 2];
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    acc[0] += a[i] * b[i];
+    acc[1] += b[i] * b[i];
+  }
+  block_sum<2>(acc, red);
+  if (threadIdx.x < 2) part[blockIdx.x * 2 + threadIdx.x] = red[threadIdx.x];
+}
+
 // r = s * x (T <- double): start vector of a GMRES cycle
 template <class T>
 __global__ void k_scale_to(int64_t n, double s, const double* __restrict__ x, T* __restrict__ y) {
@@ -573,16 +586,33 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       if (rc != DG_OK) return rc;
       k_ws_apply<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, ws->Up, m->ws_Y, m->ws_norm + 2 * nin,
                                                              m->ws_norm + 2 * nin + nout, nout, ws->U);
+      // the network's correction D = U - U_p, scaled by the alpha that minimises the
+      // linearised stage residual |G(U_p) + alpha (I - dt a_ii J(U_p)) D|
+      k_axpby<<<nb, RED_THREADS, 0, s>>>(n, 1.0, ws->U, 0.0, ws->X, nullptr);
+      k_axpby<<<nb, RED_THREADS, 0, s>>>(n, -1.0, ws->Up, 1.0, ws->X, nullptr);
       double gl2, gp2;
-      rc = residual(m, ti, ws->U, ws->Rc, s);
-      if (rc != DG_OK) return rc;
-      k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->U, ws->Rc, ca, ws->B, ws->G, ws->part);
-      rc = finish_norm2(ws, nb, s, &gl2);
-      if (rc != DG_OK) return rc;
       rc = residual(m, ti, ws->Up, ws->Rc, s);
       if (rc != DG_OK) return rc;
       k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->Up, ws->Rc, ca, ws->B, ws->G, ws->part);
       rc = finish_norm2(ws, nb, s, &gp2);
+      if (rc != DG_OK) return rc;
+      rc = jvp(m, ti, ws->Up, ws->X, ws->Rc, s);
+      if (rc != DG_OK) return rc;
+      k_stage_op<double><<<nb, RED_THREADS, 0, s>>>(n, ws->X, ca, ws->Rc);
+      k_dot2<<<nb, RED_THREADS, 0, s>>>(n, ws->G, ws->Rc, ws->part);
+      k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 2, ws->dev_small);
+      DG_HIP_CHECK(hipMemcpyAsync(ws->host_small, ws->dev_small, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      DG_HIP_CHECK(hipStreamSynchronize(s));
+      const double gd = ws->host_small[0], dd = ws->host_small[1];
+      double alpha = (dd > 0 && std::isfinite(gd)) ? -gd / dd : 0.0;
+      alpha = std::min(std::max(alpha, 0.0), 2.0);
+      stats.guess_scale[i] = alpha;
+      k_axpby<<<nb, RED_THREADS, 0, s>>>(n, 1.0, ws->Up, 0.0, ws->U, nullptr);
+      k_axpby<<<nb, RED_THREADS, 0, s>>>(n, alpha, ws->X, 1.0, ws->U, nullptr);
+      rc = residual(m, ti, ws->U, ws->Rc, s);
+      if (rc != DG_OK) return rc;
+      k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->U, ws->Rc, ca, ws->B, ws->G, ws->part);
+      rc = finish_norm2(ws, nb, s, &gl2);
       if (rc != DG_OK) return rc;
       if (!(gl2 < gp2)) {
         DG_HIP_CHECK(hipMemcpyAsync(ws->U, ws->Up, n * sizeof(double), hipMemcpyDeviceToDevice, s));
