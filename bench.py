@@ -101,12 +101,33 @@ def residual_bytes(w):
 
 # HBM bytes per launch of the element pass (FP64 R) from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs of `bench.py --only residual --copy-probe`, scaled as above, keyed by
-# workload and launch configuration; valid for the kernel source they were taken on
-PASS1_TRAFFIC = {}
+# workload and launch configuration, with the hash of the kernel sources they were taken
+# on (a changed kernel reports null until measured again)
+PASS1_TRAFFIC = {
+    ("shell-p3", 2): {"src": "79a85f780219d936", "fetch_kib": 55055.4, "write_kib": 151680.0,
+                      "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_counters.txt"},
+}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2306_01085_amd/csrc/shell.hip", "paper_2306_01085_amd/csrc/dg_common.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic(workload, cfg):
-    return PASS1_TRAFFIC.get((workload, cfg))
+    """(HBM bytes per launch, detail) or (None, reason)"""
+    t = PASS1_TRAFFIC.get((workload, cfg))
+    if t is None:
+        return None, "no counter run for this workload and configuration"
+    if t["src"] != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    fetch = t["fetch_kib"] * 1024 * FETCH_SCALE
+    write = t["write_kib"] * 1024 * WRITE_SCALE
+    return fetch + write, {"fetch_bytes": fetch, "write_bytes": write, "profile": t["profile"]}
 
 
 def cpu_baseline(w, budget_s=20.0):
@@ -366,6 +387,7 @@ def main():
     p2_ms = prof["shell_pass2_R"][0] / prof["shell_pass2_R"][1]
     b1 = pass1_bytes(w)
     fl1 = pass1_flops(w.p) * w.n_elem * (w.p + 1) ** 3
+    tr_bytes, tr_detail = traffic(args.workload, p1_cfg)
     achieved = fl1 / (p1_ms * 1e-3) / 1e12
     out = {
         "metric": "GDOF/s for DG R(u) & JVP; s per implicit step, learned/mixed vs plain @1e-8",
@@ -387,7 +409,7 @@ def main():
         "kernels_ms": {k: v_[0] / v_[1] for k, v_ in prof.items()},
         "residual_effective_gbs": residual_bytes(w) / (ms_r * 1e-3) / 1e9,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic(args.workload, p1_cfg),
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": tr_bytes, "traffic_detail": tr_detail,
                      "kernel": "shell_pass1 (R, f64)", "algorithmic_flops_per_launch": fl1,
                      "avg_launch_ms": p1_ms, "algorithmic_bytes_per_launch": b1,
                      "hbm_gbs_algorithmic": b1 / (p1_ms * 1e-3) / 1e9,
