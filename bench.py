@@ -175,6 +175,8 @@ def implicit_steps(w, mesh, u, n_steps):
             secs.append(st["seconds"])
             newton.append(sum(st["newton_its"]))
             gmres.append(sum(st["gmres_its"]))
+            log("  implicit step (%s J v): %.2f s, Newton %s, GMRES %s" % (prec, st["seconds"], st["newton_its"],
+                                                                       st["gmres_its"]))
         res[prec] = {"s_per_step": float(np.mean(secs)), "newton_per_step": float(np.mean(newton)),
                      "gmres_per_step": float(np.mean(gmres))}
         del x

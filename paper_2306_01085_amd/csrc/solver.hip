@@ -84,6 +84,33 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
   }
 }
 
+// the middle sweep of CGS2: w -= sum_k h[k] V_k, and in the same pass the K dot products
+// V_k . w of the updated (stored) w for the second orthogonalisation
+template <int K, class T>
+__global__ __launch_bounds__(RED_THREADS) void k_orth_mdot(int64_t n, const T* __restrict__ V, int64_t ldv,
+                                                           const double* __restrict__ h, T* __restrict__ w,
+                                                           double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) * K + K];
+  double hk[K], acc[K];
+  for (int k = 0; k < K; ++k) {
+    hk[k] = h[k];
+    acc[k] = 0.0;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v[K];
+    double x = (double)w[i];
+    for (int k = 0; k < K; ++k) {
+      v[k] = (double)V[k * ldv + i];
+      x -= hk[k] * v[k];
+    }
+    const T xt = (T)x;
+    w[i] = xt;
+    for (int k = 0; k < K; ++k) acc[k] += v[k] * (double)xt;
+  }
+  block_sum<K>(acc, red);
+  if (threadIdx.x < K) part[blockIdx.x * K + threadIdx.x] = red[threadIdx.x];
+}
+
 // w -= sum_k h[k] V_k ; part = partial sums of w^2 (for the norm)
 template <class T>
 __global__ __launch_bounds__(RED_THREADS) void k_orth_update(int64_t n, const T* __restrict__ V, int64_t ldv, int K,
@@ -379,6 +406,19 @@ static void launch_mdot_k(int64_t n, const T* V, int64_t ldv, const T* w, double
 }
 
 template <class T, int K = 1>
+static void launch_orth_mdot(int kk, int64_t n, const T* V, int64_t ldv, const double* h, T* w, double* part, int nb,
+                             hipStream_t s) {
+  if constexpr (K > 33) {
+    (void)kk; (void)n; (void)V; (void)ldv; (void)h; (void)w; (void)part; (void)nb; (void)s;
+  } else {
+    if (kk == K)
+      k_orth_mdot<K, T><<<nb, RED_THREADS, 0, s>>>(n, V, ldv, h, w, part);
+    else
+      launch_orth_mdot<T, K + 1>(kk, n, V, ldv, h, w, part, nb, s);
+  }
+}
+
+template <class T, int K = 1>
 static void launch_mdot(int kk, int64_t n, const T* V, int64_t ldv, const T* w, double* part, int nb, hipStream_t s) {
   if constexpr (K > 33) {
     (void)kk; (void)n; (void)V; (void)ldv; (void)w; (void)part; (void)nb; (void)s;
@@ -450,8 +490,7 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
         ProfScope ps(m, 9, s);
         launch_mdot<T>(j + 1, n, V, n, w, ws->part, nb, s);
         k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h1);
-        k_orth_update<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, j + 1, h1, w, ws->part);
-        launch_mdot<T>(j + 1, n, V, n, w, ws->part, nb, s);
+        launch_orth_mdot<T>(j + 1, n, V, n, h1, w, ws->part, nb, s);
         k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h2);
         k_orth_update<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, j + 1, h2, w, ws->part);
         k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 1, nr);
