@@ -23,7 +23,7 @@
 
 namespace dg {
 
-constexpr int RED_BLOCKS = 1024;
+constexpr int RED_BLOCKS = 2048;
 constexpr int RED_THREADS = 256;
 constexpr int KMAX = 66;
 
