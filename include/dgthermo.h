@@ -119,7 +119,11 @@ dg_status_t dg_residual(dg_mesh_t mesh, double t, const double* u, double* r, in
  * finite difference of R; dual-number arithmetic gives the same product without the
  * step error). u: device double [n_dof]; v and jv: device arrays [n_dof] of the
  * precision `prec` (DG_F64: double, DG_F32: float); jv must not alias v or u.
- * The arithmetic runs in that precision. Enqueue only. */
+ * The arithmetic runs in that precision. DG_BF16 (degree-3 shells only, else
+ * DG_ERR_UNSUPPORTED): v and jv are float; the tangent's gradient and the divergence
+ * of the linearised flux are bf16 MFMA products (operands rounded to bf16, FP32
+ * accumulation) of the dense reference derivative operators, the rest as DG_F32.
+ * Enqueue only. */
 dg_status_t dg_jvp(dg_mesh_t mesh, double t, const double* u, const void* v, void* jv, int64_t n_dof,
                    dg_prec_t prec, void* stream);
 
@@ -131,7 +135,8 @@ typedef struct {
   int32_t max_restarts;    /* GMRES restarts per Newton iteration */
   double newton_rtol;      /* stop when |G(U)| <= newton_rtol |G(u_n)| (1e-8) */
   double gmres_rtol;       /* inexact Newton: relative GMRES tolerance (1e-3) */
-  int32_t jvp_prec;        /* dg_prec_t of J v inside GMRES */
+  int32_t jvp_prec;        /* dg_prec_t of J v inside GMRES (DG_F32 and DG_BF16 keep FP32 Krylov vectors;
+                              DG_BF16 needs a degree-3 shell) */
   int32_t precond;         /* 0: none, 1: block Jacobi */
   int32_t guess;           /* 0: previous state (first step) / extrapolation, 1: learned warm start */
   double filter_rate;      /* >= 0. After every step the highest Legendre mode of each element is
@@ -233,7 +238,7 @@ dg_status_t dg_warmstart_recorded(dg_mesh_t mesh, int64_t* count_host);
  * Slots: 0 shell pass 1 (R), 1 shell pass 2 (R), 2 / 3 shell passes of J v FP64,
  * 4 / 5 shell passes of J v FP32, 6 columns R, 7 columns J v FP64, 8 columns J v FP32,
  * 9 GMRES Arnoldi (orthogonalisation), 10 block-Jacobi build, 11 block-Jacobi apply,
- * 12 vector updates, 13 batched columns. */
+ * 12 vector updates, 13 batched columns, 14 / 15 shell passes of J v BF16. */
 dg_status_t dg_profile_enable(dg_mesh_t mesh, int32_t on);
 dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_host, int32_t n, int32_t reset);
 

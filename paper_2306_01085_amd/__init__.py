@@ -110,7 +110,8 @@ EXPORTED = ["dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh
             "dg_mlp_adam_step", "dg_affine_rows", "dg_warmstart_set", "dg_warmstart_record", "dg_warmstart_recorded"]
 PROFILE_SLOTS = {0: "shell_pass1_R", 1: "shell_pass2_R", 2: "shell_pass1_jvp64", 3: "shell_pass2_jvp64",
                  4: "shell_pass1_jvp32", 5: "shell_pass2_jvp32", 6: "columns_R", 7: "columns_jvp64",
-                 8: "columns_jvp32", 9: "gmres_arnoldi", 10: "bjac_build", 11: "bjac_apply", 12: "vector_ops"}
+                 8: "columns_jvp32", 9: "gmres_arnoldi", 10: "bjac_build", 11: "bjac_apply", 12: "vector_ops",
+                 13: "columns_batch", 14: "shell_pass1_jvpbf16", 15: "shell_pass2_jvpbf16"}
 
 
 def _check(code, where):
@@ -246,7 +247,7 @@ class Mesh:
 
     def jvp(self, u, v, t=0.0, prec="f64", out=None, stream=None):
         import torch
-        dt = {"f64": torch.float64, "f32": torch.float32}[prec]
+        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}[prec]
         if out is None:
             out = torch.empty(self.n_dof, dtype=dt, device=u.device)
         if not (u.numel() == v.numel() == out.numel()):

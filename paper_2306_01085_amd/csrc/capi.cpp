@@ -54,7 +54,7 @@ static void free_mesh(dg_mesh_s* m) {
   void* ptrs[] = {m->d_ang,  m->d_edges,  m->d_cnbr,  m->d_cface,     m->d_cmap,      m->d_off,
                   m->d_prev, m->d_next,   m->d_geo,   m->d_col,       m->d_cpar,      m->d_fn64,
                   m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2], m->d_bstate, m->d_coloff,
-                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y};
+                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   free_workspace(m);
@@ -161,6 +161,15 @@ dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys,
     set_error("dg_mesh_create: device allocation of the face traces failed");
     free_mesh(m);
     return DG_ERR_ALLOC;
+  }
+  if (m->kind == DG_MESH_SHELL && m->p == 3) {
+    const std::vector<uint16_t> ops = bf16_operators(3);
+    if (hipMalloc(&m->d_bf16op, ops.size() * sizeof(uint16_t)) != hipSuccess ||
+        hipMemcpy(m->d_bf16op, ops.data(), ops.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("dg_mesh_create: device allocation of the bf16 operators failed");
+      free_mesh(m);
+      return DG_ERR_ALLOC;
+    }
   }
   hipError_t e3 = hipStreamSynchronize((hipStream_t)stream);
   if (e3 != hipSuccess) {
@@ -276,6 +285,7 @@ dg_status_t dg_jvp(dg_mesh_t m, double t, const double* u, const void* v, void* 
   if (prec == DG_F32)
     return m->kind == DG_MESH_SHELL ? shell_jvp32(m, t, u, (const float*)v, (float*)jv, s)
                                     : col_jvp32(m, t, u, (const float*)v, (float*)jv, s);
+  if (prec == DG_BF16 && m->kind == DG_MESH_SHELL) return shell_jvp_bf16(m, t, u, (const float*)v, (float*)jv, s);
   set_error("dg_jvp: precision not available");
   return DG_ERR_UNSUPPORTED;
 }
@@ -288,7 +298,8 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
   }
   if ((opts->scheme != 33 && opts->scheme != 22) || opts->gmres_m < 1 || opts->gmres_m > 32 ||
       opts->max_newton < 1 || opts->max_restarts < 1 || !(opts->newton_rtol > 0) || !(opts->gmres_rtol > 0) ||
-      (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32) || opts->precond < 0 || opts->precond > 1 ||
+      (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32 && opts->jvp_prec != DG_BF16) || opts->precond < 0 ||
+      opts->precond > 1 ||
       opts->guess < 0 || opts->guess > 1 || !(opts->filter_rate >= 0) || !std::isfinite(opts->filter_rate)) {
     set_error("dg_implicit_step: invalid solver options");
     return DG_ERR_ARG;

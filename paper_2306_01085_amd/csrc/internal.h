@@ -101,6 +101,8 @@ struct dg_mesh_s {
   // face-flux traces (one buffer per precision)
   double* d_fn64 = nullptr;
   float* d_fn32 = nullptr;
+  uint16_t* d_bf16op = nullptr;   // dense bf16 reference operators of the BF16 J v (p = 3 shells)
+  bool krylov_bf16 = false;       // the implicit step in progress takes the BF16 J v
   int64_t fn_len = 0;
   dg::Workspace* ws = nullptr;
   // batched-column solver state (dg_columns_integrate)
@@ -161,6 +163,8 @@ dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v,
 dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
 dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+dg_status_t shell_jvp_bf16(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+std::vector<uint16_t> bf16_operators(int p);
 // modal filter (highest Legendre mode x sigma per direction), in place on u
 dg_status_t shell_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s);
 dg_status_t col_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s);

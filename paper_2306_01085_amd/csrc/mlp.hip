@@ -13,28 +13,11 @@
 #include <vector>
 
 #include "internal.h"
+#include "mfma_bf16.h"
 
 namespace dg {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef float v16f __attribute__((ext_vector_type(16)));
-
 constexpr int MLP_H = 128;
-
-__host__ __device__ inline uint16_t f2bf(float f) {
-  uint32_t b;
-  memcpy(&b, &f, 4);
-  if ((b & 0x7f800000u) == 0x7f800000u) return (uint16_t)(b >> 16);   // inf / nan
-  const uint32_t lsb = (b >> 16) & 1u;
-  b += 0x7fffu + lsb;
-  return (uint16_t)(b >> 16);
-}
-__host__ __device__ inline float bf2f(uint16_t h) {
-  uint32_t b = ((uint32_t)h) << 16;
-  float f;
-  memcpy(&f, &b, 4);
-  return f;
-}
 
 struct MlpDev {
   int n_in, n_out;
@@ -45,21 +28,6 @@ struct MlpDev {
   const uint16_t* W3;   // [n_out][H]
   const float* b3;
 };
-
-// one 32x32 tile: acc += A(32 x K, rows of a_ld) * B^T (B: 32 x K, rows of b_ld), all bf16
-// A lane layout: row = lane % 32, k = 4 (lane / 32) + v; B likewise with its row = output column
-__device__ inline void mfma_tile_lds_global(v16f& acc, const uint16_t* A, int a_ld, const uint16_t* B, int b_ld, int K) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 31, kq = (lane >> 5) * 4;
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    v4s a, b;
-    for (int v = 0; v < 4; ++v) {
-      a[v] = (short)A[r * a_ld + k0 + kq + v];
-      b[v] = (short)B[r * b_ld + k0 + kq + v];
-    }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-  }
-}
 
 // layer-1 tile: A rows read from the fp32 input and rounded to bf16 on load
 __device__ inline void mfma_tile_input(v16f& acc, const float* X, int64_t m0, int64_t n, int ldx, const uint16_t* B,
@@ -85,8 +53,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev M, int64_t n, const 
                                                      float* __restrict__ Y, float* __restrict__ Z1,
                                                      float* __restrict__ H1, float* __restrict__ Z2,
                                                      float* __restrict__ H2) {
-  __shared__ uint16_t sh[32 * MLP_H];     // hidden layer 1, bf16
-  __shared__ uint16_t sh2[32 * MLP_H];    // hidden layer 2, bf16
+  __shared__ __align__(16) uint16_t sh[32 * MLP_H];     // hidden layer 1, bf16
+  __shared__ __align__(16) uint16_t sh2[32 * MLP_H];    // hidden layer 2, bf16
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t m0 = (int64_t)blockIdx.x * 32;
   const int col = lane & 31;

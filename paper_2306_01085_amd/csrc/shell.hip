@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "mfma_bf16.h"
 
 namespace dg {
 
@@ -542,6 +543,332 @@ dg_status_t shell_jvp64(dg_mesh_s* m, double t, const double* u, const double* v
 }
 dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
   return launch<Dual<float>, double, float, float>(m, t, u, v, jv, m->d_fn32, s, 4);
+}
+
+// ================================================================ BF16-MFMA J(u)v
+// J(u)v with the tangent's tensor-product contractions on bf16 MFMA, FP32 accumulation:
+// the gradient of the tangent, sum_a D_a(J a^a v), and the divergence of the linearised
+// contravariant flux, sum_a D_a dG^a, are products of the dense reference operators
+// D1 = D x I x I, D2 = I x D x I, D3 = I x I x D (64 x 64 at p = 3, bf16 in global
+// memory) with the tangent-derived operands rounded to bf16 in LDS. The state's gradient,
+// the pointwise linearisation (FP32 dual numbers) and the face terms are those of the
+// FP32 J v. Degree 3, two elements (two wavefronts) per block; each wavefront computes a
+// 32-node row tile of both elements' columns.
+constexpr int BF_EPB = 2;
+// operand space: gradient B1 [32][128] and B3 [32][64] (bf16), outputs C1 [64][30] and
+// C3 [64][10] (f32); the divergence's Bd [32][192] (bf16) and Cd [64][10] reuse it
+constexpr int BF_MM_BYTES = 32 * 128 * 2 + 32 * 64 * 2 + 64 * 30 * 4 + 64 * 10 * 4;
+
+__global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, PhysC ph, GllC gc, double t,
+                                                                const double* __restrict__ u,
+                                                                const float* __restrict__ v,
+                                                                const uint16_t* __restrict__ ops,
+                                                                float* __restrict__ R, float* __restrict__ Fn) {
+  typedef Dual<float> S;
+  typedef float T;
+  constexpr int P = 3, n = 4, N = 64, N2 = 16, TPE = 64, EPB = BF_EPB;
+  __shared__ double s_ang[EPB][13][N2];
+  __shared__ S s_u[EPB][5][N];
+  __shared__ S s_f[EPB][6][5][N2];
+  __shared__ S s_z[EPB][5][5][N2];
+  __shared__ int s_nb[EPB][6][N2];
+  __shared__ double D[n * n];
+  __shared__ __align__(16) unsigned char s_mm[BF_MM_BYTES];
+  uint16_t* B1 = (uint16_t*)s_mm;
+  uint16_t* B3 = B1 + 32 * 128;
+  float* C1 = (float*)(B3 + 32 * 64);
+  float* C3 = C1 + 64 * 30;
+  uint16_t* Bd = (uint16_t*)s_mm;
+  float* Cd = (float*)(Bd + 32 * 192);
+  const uint16_t* opG1 = ops;                 // [64][128] = [D1 | D2]
+  const uint16_t* opG3 = ops + 64 * 128;      // [64][64]  = D3
+  const uint16_t* opDv = opG3 + 64 * 64;      // [64][192] = [D1 D2 D3]
+  const int wave = threadIdx.x >> 6;
+  const int le = threadIdx.x / TPE;
+  const int j = threadIdx.x % TPE;
+  const int e = blockIdx.x * EPB + le;
+  const bool live = e < M.E;
+  const bool active = live;
+  const int cell = live ? e / M.n_rad : 0;
+  const int k = live ? e % M.n_rad : 0;
+  if (threadIdx.x < n * n) D[threadIdx.x] = gc.D[threadIdx.x];
+  const double w_end = gc.w[0];
+  if (live)
+    for (int idx = j; idx < 13 * N2; idx += TPE) s_ang[le][idx / N2][idx % N2] = M.ang[(int64_t)cell * 13 * N2 + idx];
+  S uu[5];
+  const int64_t base = (int64_t)e * 5 * N;
+  if (active)
+    for (int c = 0; c < 5; ++c) {
+      uu[c] = load_state<S>(u, v, base + c * N + j);
+      s_u[le][c][j] = uu[c];
+    }
+  const double rk = live ? M.edges[k] : 0.0;
+  const double hk = live ? M.edges[k + 1] - rk : 1.0;
+  int own = 0;
+  if (live) {
+    for (int f = 0; f < 4; ++f)
+      if (M.cnbr[cell * 4 + f] * M.n_rad + k > e) own |= 1 << f;
+    if (k < M.n_rad - 1) own |= 1 << 5;
+  }
+  const int n_own = __popc(own);
+  __syncthreads();
+
+  // ---- face-node tasks (owned faces first): u_hat - u, neighbour slots, Z
+  if (live)
+    for (int tsk = j; tsk < 6 * N2; tsk += TPE) {
+      const int r = tsk / N2, m = tsk % N2;
+      const int f = (r < n_own) ? nth_bit(own, r) : nth_bit(~own & 63, r - n_own);
+      int fa, fb, fcz;
+      slot_node<P>(f, m, fa, fb, fcz);
+      const int jo = fa + n * fb + N2 * fcz;
+      S uo[5], du[5];
+      for (int c = 0; c < 5; ++c) uo[c] = s_u[le][c][jo];
+      int jn, fn, mn;
+      const int en = face_neighbour<P>(M, cell, k, f, fa, fb, fcz, jn, fn, mn);
+      if (en >= 0) {
+        for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uo[c]);
+        s_nb[le][f][m] = (en * 6 + fn) * 5 * N2 + mn;
+        if (r < n_own) {
+          const int dd = f >> 1;
+          const int ja = fa + n * fb;
+          const double rc = rk + 0.5 * (gc.x[fcz] + 1.0) * hk;
+          const double fac = (dd < 2) ? rc * 0.5 * hk : rc * rc;
+          const double A0 = s_ang[le][3 * dd][ja], A1 = s_ang[le][3 * dd + 1][ja], A2 = s_ang[le][3 * dd + 2][ja];
+          const double Smag = fac * sqrt(A0 * A0 + A1 * A1 + A2 * A2);
+          S uh[5];
+          for (int c = 0; c < 5; ++c) uh[c] = uo[c] + du[c];
+          S sm, se;
+          sigma<3, S>(ph, uh, sm, se);
+          for (int c = 0; c < 5; ++c) {
+            const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
+            s_z[le][r][c][m] = T(Smag) * sg * du[c];
+          }
+        }
+      } else if (ph.bc_mode == 1 || f == 4) {
+        S ub[5];
+        boundary_state<3, S>(ph, uo, ub);
+        for (int c = 0; c < 5; ++c) du[c] = ub[c] - uo[c];
+      } else {
+        for (int c = 0; c < 5; ++c) du[c] = S(T(0));
+      }
+      for (int c = 0; c < 5; ++c) s_f[le][f][c][m] = du[c];
+    }
+  // tangent operands of the gradient products: B1[col][k] = A1_d(k) v(k) (k < 64) and
+  // A2_d(k - 64) v(k - 64); B3[col][k] = r_k^2 v(k); col = d * 10 + field * 2 + element
+  const int a = j % n, b = (j / n) % n, cz = j / N2;
+  if (active) {
+    const int ja = a + n * b;
+    const double rj = rk + 0.5 * (gc.x[cz] + 1.0) * hk;
+    for (int c = 0; c < 5; ++c) {
+      const float vd = s_u[le][c][j].d;
+      for (int d = 0; d < 3; ++d) {
+        B1[(d * 10 + c * 2 + le) * 128 + j] = f2bf((float)s_ang[le][d][ja] * vd);
+        B1[(d * 10 + c * 2 + le) * 128 + 64 + j] = f2bf((float)s_ang[le][3 + d][ja] * vd);
+      }
+      B3[(c * 2 + le) * 64 + j] = f2bf((float)(rj * rj) * vd);
+    }
+  }
+  __syncthreads();
+  {
+    v16f acc1, acc3;
+    for (int i = 0; i < 16; ++i) acc1[i] = acc3[i] = 0.f;
+    mfma_tile_lds_global(acc1, opG1 + 32 * wave * 128, 128, B1, 128, 128);
+    mfma_tile_lds_global(acc3, opG3 + 32 * wave * 64, 64, B3, 64, 64);
+    const int col = threadIdx.x & 31;
+    for (int a2 = 0; a2 < 16; ++a2) {
+      const int row = 32 * wave + mfma_out_row(a2);
+      if (col < 30) C1[row * 30 + col] = acc1[a2];
+      if (col < 10) C3[row * 10 + col] = acc3[a2];
+    }
+  }
+  __syncthreads();
+
+  // ---- node threads: gradient (state part on the VALU, tangent part from the products),
+  // lift, pointwise flux and source, boundary faces, contravariant fluxes
+  NodeGeo g;
+  S Sr[5], G[5][3];
+  if (active) {
+    g = node_geo<P>(M, gc, s_ang[le], k, j);
+    const double rrp = g.rc * g.rp, rc2 = g.rc * g.rc;
+    const double invJ = 1.0 / g.Jac;
+    const double lfac = invJ / w_end;
+    const double Ja[3][3] = {{rrp * g.A1[0], rrp * g.A1[1], rrp * g.A1[2]},
+                             {rrp * g.A2[0], rrp * g.A2[1], rrp * g.A2[2]},
+                             {rc2 * g.A3[0], rc2 * g.A3[1], rc2 * g.A3[2]}};
+    float c1[n][3], c2[n][3], c3[n];
+    for (int i = 0; i < n; ++i) {
+      const double ri = rk + 0.5 * (gc.x[i] + 1.0) * hk;
+      c3[i] = (float)(D[cz * n + i] * ri * ri);
+      for (int d = 0; d < 3; ++d) {
+        c1[i][d] = (float)(D[a * n + i] * rrp * s_ang[le][d][i + n * b]);
+        c2[i][d] = (float)(D[b * n + i] * rrp * s_ang[le][3 + d][a + n * i]);
+      }
+    }
+    S q[5][3];
+    for (int c = 0; c < 5; ++c) {
+      float g1[3] = {0.f, 0.f, 0.f}, d3 = 0.f;
+      for (int i = 0; i < n; ++i) {
+        const float u1 = s_u[le][c][i + n * b + N2 * cz].v;
+        const float u2 = s_u[le][c][a + n * i + N2 * cz].v;
+        const float u3 = s_u[le][c][g.ja + N2 * i].v;
+        for (int d = 0; d < 3; ++d) g1[d] += u1 * c1[i][d] + u2 * c2[i][d];
+        d3 += u3 * c3[i];
+      }
+      const float d3t = C3[j * 10 + c * 2 + le];
+      for (int d = 0; d < 3; ++d) {
+        const float g1t = (float)rrp * C1[j * 30 + d * 10 + c * 2 + le];
+        q[c][d].v = (g1[d] + (float)g.A3[d] * d3) * (float)invJ;
+        q[c][d].d = (g1t + (float)g.A3[d] * d3t) * (float)invJ;
+      }
+    }
+    const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0, cz == n - 1};
+    for (int f = 0; f < 6; ++f) {
+      if (!on[f]) continue;
+      const int m = face_slot<P>(f, a, b, cz);
+      const double sd = ((f & 1) ? 1.0 : -1.0) * lfac;
+      const int dd = f >> 1;
+      for (int c = 0; c < 5; ++c) {
+        const S du = s_f[le][f][c][m];
+        for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du * T(sd * Ja[dd][d]);
+      }
+    }
+    const bool bot = (k == 0 && cz == 0);
+    const bool top = (k == M.n_rad - 1 && cz == n - 1);
+    const bool dir = bot || (top && ph.bc_mode == 1);
+    const double bside = bot ? -rc2 : rc2;
+    S Bc[5];
+    if (dir) {
+      double Sn[3];
+      for (int d = 0; d < 3; ++d) Sn[d] = bside * g.A3[d];
+      const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
+      S ub[5], Fb[5][3], Sb[5];
+      boundary_state<3, S>(ph, uu, ub);
+      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb);
+      S sm, se;
+      sigma<3, S>(ph, ub, sm, se);
+      for (int c = 0; c < 5; ++c) {
+        const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
+        Bc[c] = -(Fb[c][0] * T(Sn[0]) + Fb[c][1] * T(Sn[1]) + Fb[c][2] * T(Sn[2])) - T(Smag) * sg * (uu[c] - ub[c]);
+      }
+    }
+    const double Q = heating<3>(ph, g.x, t);
+    S F[5][3];
+    flux_source<3, S>(ph, uu, q, g.x, Q, F, Sr);
+    __asm__ __volatile__("" ::: "memory");
+    const double (*ang)[N2] = s_ang[le];
+    if (dir || top) {
+      double Sn[3];
+      for (int d = 0; d < 3; ++d) Sn[d] = bside * ang[6 + d][g.ja];
+      if (dir) {
+        for (int c = 0; c < 5; ++c)
+          Sr[c] = Sr[c] + (F[c][0] * T(Sn[0]) + F[c][1] * T(Sn[1]) + F[c][2] * T(Sn[2]) + Bc[c]) * T(lfac);
+      } else {
+        S Fi[5][3];
+        flux_inviscid<3, S>(ph, uu, Fi);
+        const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
+        const S Un = (uu[1] * T(Sn[0]) + uu[2] * T(Sn[1]) + uu[3] * T(Sn[2])) * T(ph.lam / Smag);
+        for (int c = 0; c < 5; ++c) {
+          S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
+                 (F[c][2] - Fi[c][2]) * T(Sn[2]);
+          if (c >= 1 && c <= 3) fd = fd - Un * T(Sn[c - 1]);
+          Sr[c] = Sr[c] + fd * T(lfac);
+        }
+      }
+    }
+    for (int dd = 0; dd < 3; ++dd) {
+      const double fac = (dd < 2) ? rrp : rc2;
+      const double J0 = fac * ang[3 * dd][g.ja], J1 = fac * ang[3 * dd + 1][g.ja], J2 = fac * ang[3 * dd + 2][g.ja];
+      for (int c = 0; c < 5; ++c) G[c][dd] = F[c][0] * T(J0) + F[c][1] * T(J1) + F[c][2] * T(J2);
+    }
+  }
+  __syncthreads();   // every node has read C1 and C3: the operand space takes the divergence
+  // divergence operands Bd[col][a * 64 + node] = dG^a (col = field * 2 + element)
+  if (active)
+    for (int c = 0; c < 5; ++c)
+      for (int dd = 0; dd < 3; ++dd) Bd[(c * 2 + le) * 192 + dd * 64 + j] = f2bf(G[c][dd].d);
+  __syncthreads();
+  {
+    v16f accd;
+    for (int i = 0; i < 16; ++i) accd[i] = 0.f;
+    mfma_tile_lds_global(accd, opDv + 32 * wave * 192, 192, Bd, 192, 192);
+    const int col = threadIdx.x & 31;
+    for (int a2 = 0; a2 < 16; ++a2) {
+      const int row = 32 * wave + mfma_out_row(a2);
+      if (col < 10) Cd[row * 10 + col] = accd[a2];
+    }
+  }
+  __syncthreads();
+
+  // ---- node threads: interior-face terms, sent traces, output
+  if (active) {
+    const double invJ = 1.0 / g.Jac;
+    const double lfac = invJ / w_end;
+    const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
+    for (int f = 0; f < 6; ++f) {
+      if (!on[f]) continue;
+      const int m = face_slot<P>(f, a, b, cz);
+      const int dd = f >> 1;
+      const T side = (f & 1) ? T(1) : T(-1);
+      const int nb = s_nb[le][f][m];
+      const bool mine = (own >> f) & 1;
+      const int r = __popc(own & ((1 << f) - 1));
+      for (int c = 0; c < 5; ++c) {
+        const S Fs = side * G[c][dd];
+        const S z = mine ? s_z[le][r][c][m] : S(T(0));
+        Sr[c] = Sr[c] + (T(0.5) * Fs + z) * T(lfac);
+        Fn[(int64_t)nb + c * N2] = (Fs - T(2) * z).d;
+      }
+    }
+    for (int c = 0; c < 5; ++c) R[base + c * N + j] = Sr[c].d - Cd[j * 10 + c * 2 + le] * (float)invJ;
+  }
+}
+
+dg_status_t shell_jvp_bf16(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
+  if (m->p != 3 || !m->d_bf16op) {
+    set_error("dg_jvp: the BF16 J v is available for degree 3 shells");
+    return DG_ERR_UNSUPPORTED;
+  }
+  ShellDev M = m->shell();
+  const GllC gc = make_gllc(3);
+  PhysC ph = m->phys;
+  sun_direction(ph, t);
+  {
+    ProfScope ps(m, 14, s);
+    shell_pass1_bf16<<<(M.E + BF_EPB - 1) / BF_EPB, 64 * BF_EPB, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv,
+                                                                       m->d_fn32);
+  }
+  {
+    ProfScope ps(m, 15, s);
+    shell_pass2<3, float><<<(M.E + Shape<3>::EPB - 1) / Shape<3>::EPB, 256, 0, s>>>(M, gc, m->d_fn32, jv);
+  }
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+
+// the dense bf16 reference operators of the BF16 J v (degree 3): [D1 | D2] (64 x 128),
+// D3 (64 x 64), [D1 D2 D3] (64 x 192), row-major, node j = a + 4 b + 16 c
+std::vector<uint16_t> bf16_operators(int p) {
+  const Gll g = make_gll(p);
+  const int n = p + 1, N = n * n * n;
+  auto Dk = [&](int dir, int j, int k2) -> double {
+    const int a = j % n, b = (j / n) % n, c = j / (n * n);
+    const int a2 = k2 % n, b2 = (k2 / n) % n, c2 = k2 / (n * n);
+    if (dir == 0) return (b == b2 && c == c2) ? g.D[a * n + a2] : 0.0;
+    if (dir == 1) return (a == a2 && c == c2) ? g.D[b * n + b2] : 0.0;
+    return (a == a2 && b == b2) ? g.D[c * n + c2] : 0.0;
+  };
+  std::vector<uint16_t> out((size_t)N * 2 * N + (size_t)N * N + (size_t)N * 3 * N);
+  uint16_t* g1 = out.data();
+  uint16_t* g3 = g1 + N * 2 * N;
+  uint16_t* dv = g3 + N * N;
+  for (int j = 0; j < N; ++j)
+    for (int k2 = 0; k2 < N; ++k2) {
+      g1[j * 2 * N + k2] = f2bf((float)Dk(0, j, k2));
+      g1[j * 2 * N + N + k2] = f2bf((float)Dk(1, j, k2));
+      g3[j * N + k2] = f2bf((float)Dk(2, j, k2));
+      for (int dd = 0; dd < 3; ++dd) dv[j * 3 * N + dd * N + k2] = f2bf((float)Dk(dd, j, k2));
+    }
+  return out;
 }
 
 // tensor-product modal filter of every element: the 1D filter F applied along the three

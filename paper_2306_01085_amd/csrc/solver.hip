@@ -369,7 +369,8 @@ static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const double* v,
   return m->kind == DG_MESH_SHELL ? shell_jvp64(m, t, u, v, jv, s) : col_jvp64(m, t, u, v, jv, s);
 }
 static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
-  return m->kind == DG_MESH_SHELL ? shell_jvp32(m, t, u, v, jv, s) : col_jvp32(m, t, u, v, jv, s);
+  if (m->kind == DG_MESH_SHELL) return m->krylov_bf16 ? shell_jvp_bf16(m, t, u, v, jv, s) : shell_jvp32(m, t, u, v, jv, s);
+  return col_jvp32(m, t, u, v, jv, s);
 }
 static dg_status_t precond(dg_mesh_s* m, bool on, const double* B, const double* v, double* z, hipStream_t s) {
   if (!on) {
@@ -758,7 +759,12 @@ dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg
     set_error("dg_implicit_step: the learned guess needs a warm-start network (dg_warmstart_set)");
     return DG_ERR_UNSUPPORTED;
   }
-  if (o.jvp_prec == DG_F32) return step_impl<float>(m, t, dt, u, o, st, s);
+  if (o.jvp_prec == DG_BF16 && !(m->kind == DG_MESH_SHELL && m->d_bf16op)) {
+    set_error("dg_implicit_step: the BF16 J v is available for degree 3 shells");
+    return DG_ERR_UNSUPPORTED;
+  }
+  m->krylov_bf16 = (o.jvp_prec == DG_BF16);
+  if (o.jvp_prec != DG_F64) return step_impl<float>(m, t, dt, u, o, st, s);
   return step_impl<double>(m, t, dt, u, o, st, s);
 }
 

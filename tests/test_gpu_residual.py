@@ -80,6 +80,35 @@ def test_shell_jvp_parity(p):
     assert np.linalg.norm(jv32 - ref) / np.linalg.norm(ref) < 1e-5
 
 
+def test_shell_jvp_bf16_error():
+    """the BF16-MFMA J v (degree 3): within the stated 3e-2 of the exact product in the
+    2-norm, and the rounding is really in effect (not the FP32 product)"""
+    need_gpu()
+    w = synth.shell_workload(21, p=3, n_ang=2, n_rad=2)
+    om, gm = shell_pair(w, 2, 2, 3)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    v = synth.tangent(u.shape, 5)
+    t = 0.3
+    ref = ojac.jvp_complex(om, w.phys, u, v, t)
+    vb = to_dev(v).float()
+    jb = gm.jvp(to_dev(u), vb, t=t, prec="bf16").cpu().double().numpy().reshape(u.shape)
+    j32 = gm.jvp(to_dev(u), vb, t=t, prec="f32").cpu().double().numpy().reshape(u.shape)
+    err_b = np.linalg.norm(jb - ref) / np.linalg.norm(ref)
+    err_32 = np.linalg.norm(j32 - ref) / np.linalg.norm(ref)
+    assert err_b < 3e-2, err_b
+    assert err_b > 10 * err_32, (err_b, err_32)
+
+
+def test_shell_jvp_bf16_unsupported_degree():
+    need_gpu()
+    from paper_2306_01085_amd import DgError
+    w = synth.shell_workload(22, p=2, n_ang=1, n_rad=2)
+    om, gm = shell_pair(w, 1, 2, 2)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    with pytest.raises(DgError):
+        gm.jvp(to_dev(u), to_dev(u).float(), prec="bf16")
+
+
 def _columns_pair(seed, nelem, p, stretch=1.1):
     from paper_2306_01085_amd import Mesh
     w = synth.column_batch_workload(seed, n_col=len(nelem))
