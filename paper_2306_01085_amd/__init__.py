@@ -201,7 +201,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.dg_mesh_destroy(h)
             self._h = C.c_void_p()
 
@@ -306,7 +306,7 @@ class Network:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.dg_mlp_destroy(h)
             self._h = C.c_void_p()
 
