@@ -164,7 +164,8 @@ def implicit_steps(w, mesh, u, n_steps):
     import torch
 
     from paper_2306_01085_amd import DgError
-    res = {"dt_s": 60.0, "newton_rtol": 1e-8, "gmres": "GMRES(30), CGS2, no preconditioner", "steps": n_steps,
+    res = {"dt_s": 60.0, "newton_rtol": 1e-8,
+           "gmres": "GMRES(30), CGS2, no preconditioner, Eisenstat-Walker tolerances", "steps": n_steps,
            "filter_rate": FILTER_RATE}
     for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ()):
         x = u.clone()
@@ -174,7 +175,7 @@ def implicit_steps(w, mesh, u, n_steps):
         for _ in range(n_steps):
             try:
                 st = mesh.implicit_step(x, t, w.dt, jvp_prec=prec, precond=0, max_newton=15, max_restarts=40,
-                                        filter_rate=FILTER_RATE)
+                                        filter_rate=FILTER_RATE, forcing=1)
             except DgError as ex:
                 failed = str(ex)
                 log("  implicit step (%s J v) failed: %s" % (prec, failed))
@@ -255,7 +256,7 @@ def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epoc
 
     from paper_2306_01085_amd import Network
     from paper_2306_01085_amd import warmstart as wsm
-    opts = dict(newton_rtol=1e-8, precond=0, max_newton=15, max_restarts=40, filter_rate=FILTER_RATE)
+    opts = dict(newton_rtol=1e-8, precond=0, max_newton=15, max_restarts=40, filter_rate=FILTER_RATE, forcing=1)
     nin, nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
     cap = (3 * train_steps) * ((w.n_elem + every - 1) // every)
     t_rec = time.perf_counter()

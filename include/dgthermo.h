@@ -139,6 +139,10 @@ typedef struct {
                               DG_BF16 needs a degree-3 shell) */
   int32_t precond;         /* 0: none, 1: block Jacobi */
   int32_t guess;           /* 0: previous state (first step) / extrapolation, 1: learned warm start */
+  int32_t forcing;         /* GMRES tolerance per Newton iteration: 0 fixed gmres_rtol; 1 Eisenstat-Walker:
+                              eta_0 = 0.1, eta_k = min(0.1, 0.9 (|G_k|/|G_k-1|)^2) (kept >= 0.9 eta_k-1^2
+                              when that exceeds 0.1), and >= 0.5 newton_rtol |G(u_n)| / |G_k| so the last
+                              iteration does not solve past the Newton tolerance */
   double filter_rate;      /* >= 0. After every step the highest Legendre mode of each element is
                               multiplied by exp(-filter_rate dt) in every direction (tensor-product
                               modal filter, applied to u_{n+1}); 0 leaves the DIRK step unfiltered.

@@ -300,7 +300,8 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
       opts->max_newton < 1 || opts->max_restarts < 1 || !(opts->newton_rtol > 0) || !(opts->gmres_rtol > 0) ||
       (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32 && opts->jvp_prec != DG_BF16) || opts->precond < 0 ||
       opts->precond > 1 ||
-      opts->guess < 0 || opts->guess > 1 || !(opts->filter_rate >= 0) || !std::isfinite(opts->filter_rate)) {
+      opts->guess < 0 || opts->guess > 1 || opts->forcing < 0 || opts->forcing > 1 || !(opts->filter_rate >= 0) ||
+      !std::isfinite(opts->filter_rate)) {
     set_error("dg_implicit_step: invalid solver options");
     return DG_ERR_ARG;
   }

@@ -660,7 +660,7 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       }
     }
     int newton = 0, gm_total = 0, halvings = 0;
-    double nG = 0, prev = 0, alpha = 1.0;
+    double nG = 0, prev = 0, alpha = 1.0, eta = 0.1;
     for (;;) {
       rc = residual(m, ti, ws->U, ws->Rc, s);
       if (rc != DG_OK) return rc;
@@ -690,7 +690,19 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       // rhs = -G
       k_axpby<<<nb, RED_THREADS, 0, s>>>(n, 0.0, ws->G, -1.0, ws->G, nullptr);
       int its = 0;
-      rc = gmres<T>(m, ws, ti, ca, ws->U, ws->G, nG, pc, o.gmres_m, o.max_restarts, o.gmres_rtol, &its, s);
+      double rtol = o.gmres_rtol;
+      if (o.forcing == 1) {
+        if (newton > 0) {
+          const double r = nG / prev;
+          double e2 = 0.9 * r * r;
+          const double safe = 0.9 * eta * eta;
+          if (safe > 0.1) e2 = std::max(e2, safe);
+          eta = std::min(0.1, e2);
+        }
+        rtol = std::max(eta, 0.5 * o.newton_rtol * ref / nG);
+        rtol = std::min(rtol, 0.1);
+      }
+      rc = gmres<T>(m, ws, ti, ca, ws->U, ws->G, nG, pc, o.gmres_m, o.max_restarts, rtol, &its, s);
       if (rc != DG_OK) {
         (void)hipMemcpyAsync(u, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s);
         return rc;

@@ -97,3 +97,20 @@ def test_filtered_steps_match_oracle():
     gm3.implicit_step(ut3, 0.0, dt, newton_rtol=1e-10, gmres_rtol=1e-6, precond=0, filter_rate=rate)
     out3 = ut3.cpu().numpy().reshape(u3.shape)
     assert np.linalg.norm(out3 - ref3) / np.linalg.norm(ref3 - u3) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_forcing_keeps_the_answer(prec):
+    """Eisenstat-Walker GMRES tolerances change the iteration path, not the converged
+    step: shell step against the oracle's Newton-GMRES step"""
+    need_gpu()
+    w = synth.shell_workload(6, p=2, n_ang=1, n_rad=2)
+    om, gm = shell_pair(w, 1, 2, 2)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    dt = synth.seconds_to_nondim(30.0)
+    ref, _ = timeint.implicit_step_jfnk(om, w.phys, u, 0.0, dt, scheme=33, rtol=1e-12)
+    ut = to_dev(u)
+    st = gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, jvp_prec=prec, precond=0, forcing=1)
+    out = ut.cpu().numpy().reshape(u.shape)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref - u) < 1e-6, st
+    assert all(r <= 1e-10 * f for r, f in zip(st["res"], st["ref"]))
