@@ -160,35 +160,39 @@ FILTER_RATE = 0.5   # modal filter after every implicit step (per unit nondimens
 
 def implicit_steps(w, mesh, u, n_steps):
     """seconds per DIRK(3,3) step of dt = 60 s at a 1e-8 relative Newton tolerance,
-    GMRES(30) without preconditioner, plain extrapolated guess: FP64 vs FP32 vs BF16 J v"""
+    GMRES(30) right-preconditioned by the radial-line block-Jacobi preconditioner,
+    Eisenstat-Walker GMRES tolerances, plain extrapolated guess: FP64 vs FP32 vs BF16 J v;
+    plus the FP32 run without a preconditioner for comparison"""
     import torch
 
     from paper_2306_01085_amd import DgError
     res = {"dt_s": 60.0, "newton_rtol": 1e-8,
-           "gmres": "GMRES(30), CGS2, no preconditioner, Eisenstat-Walker tolerances", "steps": n_steps,
-           "filter_rate": FILTER_RATE}
-    for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ()):
+           "gmres": "GMRES(30), CGS2, radial-line block-Jacobi preconditioner, Eisenstat-Walker tolerances",
+           "steps": n_steps, "filter_rate": FILTER_RATE}
+    runs = [(prec, 2, prec) for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ())]
+    runs.append(("f32_no_precond", 0, "f32"))
+    for key, pc, prec in runs:
         x = u.clone()
         t = 0.0
         secs, newton, gmres = [], [], []
         failed = None
         for _ in range(n_steps):
             try:
-                st = mesh.implicit_step(x, t, w.dt, jvp_prec=prec, precond=0, max_newton=15, max_restarts=40,
+                st = mesh.implicit_step(x, t, w.dt, jvp_prec=prec, precond=pc, max_newton=15, max_restarts=40,
                                         filter_rate=FILTER_RATE, forcing=1)
             except DgError as ex:
                 failed = str(ex)
-                log("  implicit step (%s J v) failed: %s" % (prec, failed))
+                log("  implicit step (%s) failed: %s" % (key, failed))
                 break
             t += w.dt
             secs.append(st["seconds"])
             newton.append(sum(st["newton_its"]))
             gmres.append(sum(st["gmres_its"]))
-            log("  implicit step (%s J v): %.2f s, Newton %s, GMRES %s" % (prec, st["seconds"], st["newton_its"],
-                                                                       st["gmres_its"]))
-        res[prec] = {"s_per_step": float(np.mean(secs)) if secs else None,
-                     "newton_per_step": float(np.mean(newton)) if newton else None,
-                     "gmres_per_step": float(np.mean(gmres)) if gmres else None, "failed": failed}
+            log("  implicit step (%s): %.3f s, Newton %s, GMRES %s" % (key, st["seconds"], st["newton_its"],
+                                                                   st["gmres_its"]))
+        res[key] = {"s_per_step": float(np.mean(secs)) if secs else None,
+                    "newton_per_step": float(np.mean(newton)) if newton else None,
+                    "gmres_per_step": float(np.mean(gmres)) if gmres else None, "failed": failed}
         del x
         torch.cuda.empty_cache()
     return res
@@ -256,7 +260,7 @@ def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epoc
 
     from paper_2306_01085_amd import Network
     from paper_2306_01085_amd import warmstart as wsm
-    opts = dict(newton_rtol=1e-8, precond=0, max_newton=15, max_restarts=40, filter_rate=FILTER_RATE, forcing=1)
+    opts = dict(newton_rtol=1e-8, precond=2, max_newton=15, max_restarts=40, filter_rate=FILTER_RATE, forcing=1)
     nin, nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
     cap = (3 * train_steps) * ((w.n_elem + every - 1) // every)
     t_rec = time.perf_counter()
@@ -307,7 +311,7 @@ def main():
     ap.add_argument("--only", default="all", choices=["all", "residual"],
                     help="residual: only the R(u) timing (for counter runs)")
     ap.add_argument("--mode", default="default", choices=["default", "warmstart"])
-    ap.add_argument("--implicit-steps", type=int, default=2)
+    ap.add_argument("--implicit-steps", type=int, default=4)
     ap.add_argument("--ws-train-steps", type=int, default=60)
     ap.add_argument("--ws-eval-steps", type=int, default=8)
     ap.add_argument("--ws-epochs", type=int, default=8)

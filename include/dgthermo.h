@@ -137,7 +137,11 @@ typedef struct {
   double gmres_rtol;       /* inexact Newton: relative GMRES tolerance (1e-3) */
   int32_t jvp_prec;        /* dg_prec_t of J v inside GMRES (DG_F32 and DG_BF16 keep FP32 Krylov vectors;
                               DG_BF16 needs a degree-3 shell) */
-  int32_t precond;         /* 0: none, 1: block Jacobi */
+  int32_t precond;         /* shell meshes: 0 none; 1 node 5x5 block Jacobi (q held fixed, rebuilt every
+                              Newton iteration); 2 radial-line block Jacobi: I - dt a_ii J_rad with J_rad
+                              the linearisation that drops the tangent's coupling between different
+                              angular nodes (exact along each radial line), block tridiagonal per line,
+                              built once per step at u_n by 15 (p+1) dual probes, factored by block LU */
   int32_t guess;           /* 0: previous state (first step) / extrapolation, 1: learned warm start */
   int32_t forcing;         /* GMRES tolerance per Newton iteration: 0 fixed gmres_rtol; 1 Eisenstat-Walker:
                               eta_0 = 0.1, eta_k = min(0.1, 0.9 (|G_k|/|G_k-1|)^2) (kept >= 0.9 eta_k-1^2
@@ -241,16 +245,23 @@ dg_status_t dg_warmstart_recorded(dg_mesh_t mesh, int64_t* count_host);
  * milliseconds and launch counts (host arrays of n entries; reset != 0 clears them).
  * Slots: 0 shell pass 1 (R), 1 shell pass 2 (R), 2 / 3 shell passes of J v FP64,
  * 4 / 5 shell passes of J v FP32, 6 columns R, 7 columns J v FP64, 8 columns J v FP32,
- * 9 GMRES Arnoldi (orthogonalisation), 10 block-Jacobi build, 11 block-Jacobi apply,
+ * 9 GMRES Arnoldi (orthogonalisation), 10 / 11 preconditioner build / apply (node or
+ * radial-line block-Jacobi),
  * 12 vector updates, 13 batched columns, 14 / 15 shell passes of J v BF16. */
 dg_status_t dg_profile_enable(dg_mesh_t mesh, int32_t on);
 dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_host, int32_t n, int32_t reset);
 
-/* Tuning knobs of the launch configuration (host values, no effect on results):
+/* Tuning knobs (host values):
  *   "shell_pass1_config" 0..5: elements per block and register budget of the shell's
  *   element pass (0: 256-thread blocks; 1/2: one/two elements per block; 3/4: one/two
  *   elements with a register budget for 3 waves per SIMD; 5: one element, 4 waves).
+ *   No effect on results.
  *   "columns_grid" >= 1: number of persistent wavefronts of dg_columns_integrate.
+ *   No effect on results.
+ *   "line_pc_every" >= 1 (default 1): dg_implicit_step with precond 2 rebuilds the
+ *   radial-line preconditioner from the current state only every this many steps (and
+ *   whenever dt a_ii or the J v precision changes), reusing it in between. It changes the
+ *   GMRES iteration counts, not what Newton converges to (within newton_rtol).
  * Returns DG_ERR_ARG for an unknown name or value. */
 dg_status_t dg_set_option(dg_mesh_t mesh, const char* name, int64_t value);
 

@@ -121,6 +121,10 @@ dg_status_t dg_set_option(dg_mesh_t m, const char* name, int64_t value) {
     m->tune_cols_grid = (int)value;
     return DG_OK;
   }
+  if (std::strcmp(name, "line_pc_every") == 0 && value >= 1 && value <= 1000000) {
+    m->line_pc_every = (int)value;
+    return DG_OK;
+  }
   set_error(std::string("dg_set_option: unknown option or value: ") + name);
   return DG_ERR_ARG;
 }
@@ -299,7 +303,7 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
   if ((opts->scheme != 33 && opts->scheme != 22) || opts->gmres_m < 1 || opts->gmres_m > 32 ||
       opts->max_newton < 1 || opts->max_restarts < 1 || !(opts->newton_rtol > 0) || !(opts->gmres_rtol > 0) ||
       (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32 && opts->jvp_prec != DG_BF16) || opts->precond < 0 ||
-      opts->precond > 1 ||
+      opts->precond > 2 ||
       opts->guess < 0 || opts->guess > 1 || opts->forcing < 0 || opts->forcing > 1 || !(opts->filter_rate >= 0) ||
       !std::isfinite(opts->filter_rate)) {
     set_error("dg_implicit_step: invalid solver options");

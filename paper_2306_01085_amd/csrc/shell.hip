@@ -207,8 +207,14 @@ __device__ inline int nth_bit(int mask, int r) {
   return __ffs(mask) - 1;
 }
 
-// EPB: elements per block; OCC: minimum waves per SIMD the register allocation must allow
-template <int P, int EPB, int OCC, class S, class SU, class TV, class OT>
+// EPB: elements per block; OCC: minimum waves per SIMD the register allocation must allow.
+// RAD (dual numbers only): the radial-line linearisation of the line preconditioner. In
+// the derivative parts the tangent at other angular nodes is taken as zero: across the
+// angular faces (the neighbour's tangent), in the angular line sums of the gradient and
+// of the divergence (only the node's own term); every element takes the stabilisation of
+// its own side of the angular faces and sends no angular traces. Radial coupling is
+// exact. Lines (cell, a, b) are then independent.
+template <int P, int EPB, int OCC, class S, class SU, class TV, class OT, bool RAD = false>
 __global__ __launch_bounds__(Shape<P>::TPE * EPB) __attribute__((amdgpu_waves_per_eu(OCC)))
 void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__ u, const TV* __restrict__ v,
                  OT* __restrict__ R, OT* __restrict__ Fn) {
@@ -246,7 +252,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   int own = 0;
   if (live) {
     for (int f = 0; f < 4; ++f)
-      if (M.cnbr[cell * 4 + f] * M.n_rad + k > e) own |= 1 << f;
+      if (RAD || M.cnbr[cell * 4 + f] * M.n_rad + k > e) own |= 1 << f;
     if (k < M.n_rad - 1) own |= 1 << 5;
   }
   const int n_own = __popc(own);
@@ -267,6 +273,10 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       const int en = face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
       if (en >= 0) {
         for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uo[c]);
+        if constexpr (RAD) {
+          if (f < 4)
+            for (int c = 0; c < 5; ++c) du[c].d = T(-0.5) * uo[c].d;
+        }
         s_nb[le][f][m] = (en * 6 + fn) * 5 * N2 + mn;
         if (r < n_own) {
           const int dd = f >> 1;
@@ -328,6 +338,10 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         const S u3 = s_u[le][c][g.ja + N2 * i];
         for (int d = 0; d < 3; ++d) g1[d] = g1[d] + u1 * T(c1[i][d]) + u2 * T(c2[i][d]);
         d3 = d3 + u3 * T(c3[i]);
+      }
+      if constexpr (RAD) {
+        const T vd = s_u[le][c][j].d;
+        for (int d = 0; d < 3; ++d) g1[d].d = vd * T(c1[a][d] + c2[b][d]);
       }
       for (int d = 0; d < 3; ++d) q[c][d] = (g1[d] + T(g.A3[d]) * d3) * T(invJ);
     }
@@ -417,7 +431,10 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         const S Fs = side * G[c][dd];
         const S z = mine ? s_z[le][r][c][m] : S(T(0));
         Sr[c] = Sr[c] + (T(0.5) * Fs + z) * T(lfac);
-        Fn[(int64_t)nb + c * N2] = outp(Fs - T(2) * z);
+        if (RAD && f < 4)
+          Fn[(int64_t)nb + c * N2] = outp(S(T(0)));
+        else
+          Fn[(int64_t)nb + c * N2] = outp(Fs - T(2) * z);
       }
     }
   }
@@ -433,6 +450,11 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         dv = dv + s_G[0][i + n * b + N2 * cz] * T(D[a * n + i]);
         dv = dv + s_G[1][a + n * i + N2 * cz] * T(D[b * n + i]);
         dv = dv + s_G[2][g.ja + N2 * i] * T(D[cz * n + i]);
+      }
+      if constexpr (RAD) {
+        T dr = G[c][0].d * T(D[a * n + a]) + G[c][1].d * T(D[b * n + b]);
+        for (int i = 0; i < n; ++i) dr += s_G[2][g.ja + N2 * i].d * T(D[cz * n + i]);
+        dv.d = dr;
       }
       R[base + c * N + j] = outp(Sr[c] - dv * T(invJ));
     }
@@ -531,6 +553,48 @@ static dg_status_t launch(dg_mesh_s* m, double t, const SU* u, const TV* v, OT* 
     default: set_error("unsupported degree"); return DG_ERR_ARG;
   }
 #undef DG_LAUNCH
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+
+// J_rad(u) v: the radial-line linearisation (RAD above), FP64
+dg_status_t shell_jvp_radial(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s) {
+  ShellDev M = m->shell();
+  const GllC gc = make_gllc(m->p);
+  PhysC ph = m->phys;
+  sun_direction(ph, t);
+  const int E = M.E;
+#define DG_RAD(P_)                                                                                          \
+  shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, v, \
+                                                                                               jv, m->d_fn64); \
+  shell_pass2<P_, double><<<(E + Shape<P_>::EPB - 1) / Shape<P_>::EPB, 256, 0, s>>>(M, gc, m->d_fn64, jv);
+  switch (m->p) {
+    case 2: DG_RAD(2); break;
+    case 3: DG_RAD(3); break;
+    default: DG_RAD(4); break;
+  }
+#undef DG_RAD
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+
+// the same radial-line linearisation with FP32 dual numbers (preconditioner of FP32 runs)
+dg_status_t shell_jvp_radial32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
+  ShellDev M = m->shell();
+  const GllC gc = make_gllc(m->p);
+  PhysC ph = m->phys;
+  sun_direction(ph, t);
+  const int E = M.E;
+#define DG_RAD32(P_)                                                                                        \
+  shell_pass1<P_, 1, 1, Dual<float>, double, float, float, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, v, jv, \
+                                                                                            m->d_fn32);      \
+  shell_pass2<P_, float><<<(E + Shape<P_>::EPB - 1) / Shape<P_>::EPB, 256, 0, s>>>(M, gc, m->d_fn32, jv);
+  switch (m->p) {
+    case 2: DG_RAD32(2); break;
+    case 3: DG_RAD32(3); break;
+    default: DG_RAD32(4); break;
+  }
+#undef DG_RAD32
   DG_HIP_CHECK(hipGetLastError());
   return DG_OK;
 }

@@ -309,6 +309,11 @@ struct Workspace {
   int hist_n = 0;
   double t_end = NAN;                     // end time of the last step (history continuity)
   double* Binv = nullptr;
+  double *lineLo = nullptr, *lineDi = nullptr, *lineUp = nullptr;   // radial-line preconditioner factors
+  float *lineLo32 = nullptr, *lineDi32 = nullptr, *lineUp32 = nullptr;   // their float copies (FP32 runs)
+  int line_age = -1;      // steps since the line preconditioner was built (-1: not built)
+  double line_dta = 0;    // dt a_ii it was built for
+  bool line_f32 = false;  // the build produced the float copies
   void* V = nullptr;                      // (m+1) basis vectors, double or float
   void* w = nullptr;
   void* z = nullptr;
@@ -322,7 +327,8 @@ void free_workspace(dg_mesh_s* m) {
   Workspace* w = m->ws;
   if (!w) return;
   void* ptrs[] = {w->un, w->U, w->G, w->B, w->X, w->Rc, w->Rs[0], w->Rs[1], w->Rs[2], w->hist[0], w->hist[1],
-                  w->Binv, w->V, w->w, w->z, w->s, w->part, w->dev_small, w->Up};
+                  w->Binv, w->V, w->w, w->z, w->s, w->part, w->dev_small, w->Up, w->lineLo, w->lineDi, w->lineUp,
+                  w->lineLo32, w->lineDi32, w->lineUp32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->host_small) (void)hipHostFree(w->host_small);
@@ -372,19 +378,18 @@ static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const float* v, 
   if (m->kind == DG_MESH_SHELL) return m->krylov_bf16 ? shell_jvp_bf16(m, t, u, v, jv, s) : shell_jvp32(m, t, u, v, jv, s);
   return col_jvp32(m, t, u, v, jv, s);
 }
-static dg_status_t precond(dg_mesh_s* m, bool on, const double* B, const double* v, double* z, hipStream_t s) {
-  if (!on) {
-    DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(double), hipMemcpyDeviceToDevice, s));
-    return DG_OK;
-  }
-  return shell_bjac_apply64(m, B, v, z, s);
+// z = M^-1 v: mode 0 identity, 1 node block-Jacobi, 2 radial-line block-Jacobi
+static dg_status_t precond(dg_mesh_s* m, const Workspace* ws, int mode, const double* v, double* z, hipStream_t s) {
+  if (mode == 1) return shell_bjac_apply64(m, ws->Binv, v, z, s);
+  if (mode == 2) return line_pc_apply(m, ws->lineLo, ws->lineDi, ws->lineUp, v, z, s);
+  DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return DG_OK;
 }
-static dg_status_t precond(dg_mesh_s* m, bool on, const double* B, const float* v, float* z, hipStream_t s) {
-  if (!on) {
-    DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(float), hipMemcpyDeviceToDevice, s));
-    return DG_OK;
-  }
-  return shell_bjac_apply32(m, B, v, z, s);
+static dg_status_t precond(dg_mesh_s* m, const Workspace* ws, int mode, const float* v, float* z, hipStream_t s) {
+  if (mode == 1) return shell_bjac_apply32(m, ws->Binv, v, z, s);
+  if (mode == 2) return line_pc_apply(m, ws->lineLo32, ws->lineDi32, ws->lineUp32, v, z, s);
+  DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return DG_OK;
 }
 
 static inline int grid_for(int64_t n) {
@@ -434,7 +439,7 @@ static void launch_mdot(int kk, int64_t n, const T* V, int64_t ldv, const T* w, 
 // GMRES(m) for (I - c J(U)) x = rhs (rhs = -G, double), x returned in ws->X.
 template <class T>
 static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const double* U, const double* rhs,
-                         double rhs_norm, bool pc, int mk, int max_restarts, double rtol, int* iters,
+                         double rhs_norm, int pc, int mk, int max_restarts, double rtol, int* iters,
                          hipStream_t s) {
   const int64_t n = m->n_dof;
   const int nb = grid_for(n);
@@ -481,7 +486,7 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
     bool done = false;
     for (int j = 0; j < mk; ++j) {
       T* vj = V + (size_t)j * n;
-      dg_status_t st = precond(m, pc, ws->Binv, vj, z, s);
+      dg_status_t st = precond(m, ws, pc, vj, z, s);
       if (st != DG_OK) return st;
       st = jvp(m, t, U, z, w, s);
       if (st != DG_OK) return st;
@@ -535,7 +540,7 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
     for (int i = 0; i < kused; ++i) host[3 * KMAX + i] = y[i];
     DG_HIP_CHECK(hipMemcpyAsync(yv, host + 3 * KMAX, kused * sizeof(double), hipMemcpyHostToDevice, s));
     k_combine<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, kused, yv, sv);
-    dg_status_t st = precond(m, pc, ws->Binv, sv, z, s);
+    dg_status_t st = precond(m, ws, pc, sv, z, s);
     if (st != DG_OK) return st;
     k_add_to<T><<<nb, RED_THREADS, 0, s>>>(n, z, X);
     if (done) break;
@@ -585,7 +590,24 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
   Workspace* ws = m->ws;
   const int64_t n = m->n_dof;
   const int nb = grid_for(n);
-  const bool pc = o.precond == 1 && m->kind == DG_MESH_SHELL;
+  const int pc = (m->kind == DG_MESH_SHELL) ? o.precond : 0;
+  const bool f32 = std::is_same<T, float>::value;
+  if (pc == 2 && (!ws->lineLo || (f32 && !ws->lineLo32))) {
+    const size_t cnt = (size_t)line_pc_doubles(m);
+    bool ok = true;
+    if (!ws->lineLo)
+      ok = hipMalloc(&ws->lineLo, cnt * sizeof(double)) == hipSuccess &&
+           hipMalloc(&ws->lineDi, cnt * sizeof(double)) == hipSuccess &&
+           hipMalloc(&ws->lineUp, cnt * sizeof(double)) == hipSuccess;
+    if (ok && f32)
+      ok = hipMalloc(&ws->lineLo32, cnt * sizeof(float)) == hipSuccess &&
+           hipMalloc(&ws->lineDi32, cnt * sizeof(float)) == hipSuccess &&
+           hipMalloc(&ws->lineUp32, cnt * sizeof(float)) == hipSuccess;
+    if (!ok) {
+      set_error("dg_implicit_step: allocation of the line preconditioner failed");
+      return DG_ERR_ALLOC;
+    }
+  }
   double A[3][3], c[3];
   int ns;
   dirk_tableau(o.scheme, A, c, ns);
@@ -593,6 +615,22 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
   // a step that does not continue the previous one starts a new guess history
   if (!(std::fabs(ws->t_end - t) <= 1e-12 * std::max(1.0, std::fabs(t)))) ws->hist_n = 0;
   DG_HIP_CHECK(hipMemcpyAsync(ws->un, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // radial-line preconditioner: built at (t + c_1 dt, u_n) and kept for line_pc_every steps;
+  // a_ii is the same for every stage of the singly-diagonal schemes
+  if (pc == 2) {
+    const bool stale = ws->line_age < 0 || ws->line_age + 1 >= m->line_pc_every || ws->line_f32 != f32 ||
+                       ws->line_dta != dt * A[0][0];
+    if (stale) {
+      rc = line_pc_build(m, t + c[0] * dt, ws->un, dt * A[0][0], ws->lineLo, ws->lineDi, ws->lineUp, ws->X, ws->Rc,
+                         f32, ws->lineLo32, ws->lineDi32, ws->lineUp32, s);
+      if (rc != DG_OK) return rc;
+      ws->line_age = 0;
+      ws->line_f32 = f32;
+      ws->line_dta = dt * A[0][0];
+    } else {
+      ++ws->line_age;
+    }
+  }
   for (int i = 0; i < ns; ++i) {
     const double ti = t + c[i] * dt;
     const double ca = dt * A[i][i];
@@ -683,7 +721,7 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
         return DG_ERR_NAN;
       }
       if (nG <= o.newton_rtol * ref || newton >= o.max_newton) break;
-      if (pc) {
+      if (pc == 1) {
         rc = shell_bjac_build(m, ti, ws->U, ca, ws->Binv, s);
         if (rc != DG_OK) return rc;
       }

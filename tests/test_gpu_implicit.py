@@ -49,7 +49,7 @@ def test_column_two_steps_with_extrapolated_guess():
     assert all(r <= 1e-10 * f for r, f in zip(st2["res"], st2["ref"]))
 
 
-@pytest.mark.parametrize("precond,prec", [(0, "f64"), (1, "f64"), (1, "f32")])
+@pytest.mark.parametrize("precond,prec", [(0, "f64"), (1, "f64"), (1, "f32"), (2, "f64"), (2, "f32")])
 def test_shell_step_matches_oracle(precond, prec):
     need_gpu()
     w = synth.shell_workload(3, p=2, n_ang=1, n_rad=2)
@@ -107,10 +107,56 @@ def test_adaptive_forcing_keeps_the_answer(prec):
     w = synth.shell_workload(6, p=2, n_ang=1, n_rad=2)
     om, gm = shell_pair(w, 1, 2, 2)
     u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
-    dt = synth.seconds_to_nondim(30.0)
+    dt = synth.seconds_to_nondim(10.0)
     ref, _ = timeint.implicit_step_jfnk(om, w.phys, u, 0.0, dt, scheme=33, rtol=1e-12)
     ut = to_dev(u)
     st = gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, jvp_prec=prec, precond=0, forcing=1)
     out = ut.cpu().numpy().reshape(u.shape)
     assert np.linalg.norm(out - ref) / np.linalg.norm(ref - u) < 1e-6, st
     assert all(r <= 1e-10 * f for r, f in zip(st["res"], st["ref"]))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_line_preconditioner_cuts_gmres(prec):
+    """radially stretched shell: the radial-line block Jacobi reaches the same converged
+    step as no preconditioner with less than half the GMRES iterations"""
+    need_gpu()
+    from paper_2306_01085_amd import Mesh
+    w = synth.shell_workload(7, p=3, n_ang=2, n_rad=8)
+    gm = Mesh.shell(p=3, n_ang=2, n_rad=8, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
+    om = omesh.shell_mesh(3, 2, 8, w.r_bot, w.r_top, w.stretch)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    dt = synth.seconds_to_nondim(10.0)
+    outs, its = [], []
+    for pc in (0, 2):
+        ut = to_dev(u)
+        st = gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, jvp_prec=prec, precond=pc, max_restarts=60,
+                              max_newton=20)
+        outs.append(ut.cpu().numpy())
+        its.append(sum(st["gmres_its"]))
+    assert np.linalg.norm(outs[1] - outs[0]) / np.linalg.norm(outs[0] - u.ravel()) < 1e-6
+    assert its[1] < 0.5 * its[0], its
+
+
+def test_line_preconditioner_reuse_keeps_the_answer():
+    """rebuilding the radial-line preconditioner only every third step changes the
+    iteration counts, not the converged steps: three steps agree with three steps that
+    rebuild it every time"""
+    need_gpu()
+    from paper_2306_01085_amd import DgError, Mesh
+    w = synth.shell_workload(7, p=3, n_ang=2, n_rad=8)
+    om = omesh.shell_mesh(3, 2, 8, w.r_bot, w.r_top, w.stretch)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    dt = synth.seconds_to_nondim(10.0)
+    outs = []
+    for every in (1, 3):
+        gm = Mesh.shell(p=3, n_ang=2, n_rad=8, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
+        gm.set_option("line_pc_every", every)
+        ut = to_dev(u)
+        for k in range(3):
+            gm.implicit_step(ut, k * dt, dt, newton_rtol=1e-10, precond=2, max_restarts=60, max_newton=20)
+        outs.append(ut.cpu().numpy())
+    assert np.linalg.norm(outs[1] - outs[0]) / np.linalg.norm(outs[0] - u.ravel()) < 1e-6
+    gm = Mesh.shell(p=3, n_ang=2, n_rad=8, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
+    with pytest.raises(DgError):
+        gm.set_option("line_pc_every", 0)
