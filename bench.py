@@ -156,13 +156,16 @@ def cpu_baseline(w, budget_s=20.0):
 
 
 FILTER_RATE = 0.5   # modal filter after every implicit step (per unit nondimensional time)
+LINE_PC_EVERY = 4        # the radial-line preconditioner is rebuilt every 4 steps
+LINE_PC_PRECISION = 16   # and its factors are read as bf16 (same GMRES counts as double here)
 
 
 def implicit_steps(w, mesh, u, n_steps):
     """seconds per DIRK(3,3) step of dt = 60 s at a 1e-8 relative Newton tolerance,
     GMRES(30) right-preconditioned by the radial-line block-Jacobi preconditioner,
-    Eisenstat-Walker GMRES tolerances, plain extrapolated guess: FP64 vs FP32 vs BF16 J v;
-    plus the FP32 run without a preconditioner for comparison"""
+    (rebuilt every LINE_PC_EVERY steps, bf16 factors), Eisenstat-Walker GMRES tolerances,
+    plain extrapolated guess: FP64 vs FP32 vs BF16 J v; plus the FP32 run without a
+    preconditioner for comparison"""
     import torch
 
     from paper_2306_01085_amd import DgError
@@ -171,6 +174,10 @@ def implicit_steps(w, mesh, u, n_steps):
            "steps": n_steps, "filter_rate": FILTER_RATE}
     runs = [(prec, 2, prec) for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ())]
     runs.append(("f32_no_precond", 0, "f32"))
+    mesh.set_option("line_pc_every", LINE_PC_EVERY)
+    mesh.set_option("line_pc_precision", LINE_PC_PRECISION)
+    res["line_pc_every"] = LINE_PC_EVERY
+    res["line_pc_precision"] = LINE_PC_PRECISION
     for key, pc, prec in runs:
         x = u.clone()
         t = 0.0
@@ -261,6 +268,9 @@ def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epoc
     from paper_2306_01085_amd import Network
     from paper_2306_01085_amd import warmstart as wsm
     opts = dict(newton_rtol=1e-8, precond=2, max_newton=15, max_restarts=40, filter_rate=FILTER_RATE, forcing=1)
+    # a fresh preconditioner every step, so that the plain and learned runs see the same one
+    mesh.set_option("line_pc_every", 1)
+    mesh.set_option("line_pc_precision", LINE_PC_PRECISION)
     nin, nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
     cap = (3 * train_steps) * ((w.n_elem + every - 1) // every)
     t_rec = time.perf_counter()

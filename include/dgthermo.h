@@ -258,10 +258,17 @@ dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_hos
  *   No effect on results.
  *   "columns_grid" >= 1: number of persistent wavefronts of dg_columns_integrate.
  *   No effect on results.
+ *   "line_solve_config" 0..3: launch configuration of the radial-line preconditioner's
+ *   substitution (0/2: one wavefront per block, 1/3: four; 0/1: loads one matrix ahead,
+ *   2/3: three ahead; default 3). No effect on results.
  *   "line_pc_every" >= 1 (default 1): dg_implicit_step with precond 2 rebuilds the
  *   radial-line preconditioner from the current state only every this many steps (and
  *   whenever dt a_ii or the J v precision changes), reusing it in between. It changes the
  *   GMRES iteration counts, not what Newton converges to (within newton_rtol).
+ *   "line_pc_precision" 64, 32 (default) or 16: storage precision of the radial-line
+ *   preconditioner's factors (double, float, bfloat16) read by its substitution, whatever
+ *   the J v precision; the substitution computes in the precision of the Krylov vectors.
+ *   Like line_pc_every it changes iteration counts, not the converged step.
  * Returns DG_ERR_ARG for an unknown name or value. */
 dg_status_t dg_set_option(dg_mesh_t mesh, const char* name, int64_t value);
 

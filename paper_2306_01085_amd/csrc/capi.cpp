@@ -125,6 +125,14 @@ dg_status_t dg_set_option(dg_mesh_t m, const char* name, int64_t value) {
     m->line_pc_every = (int)value;
     return DG_OK;
   }
+  if (std::strcmp(name, "line_solve_config") == 0 && value >= 0 && value <= 3) {
+    m->tune_lsolve = (int)value;
+    return DG_OK;
+  }
+  if (std::strcmp(name, "line_pc_precision") == 0 && (value == 64 || value == 32 || value == 16)) {
+    m->line_pc_prec = (int)value;
+    return DG_OK;
+  }
   set_error(std::string("dg_set_option: unknown option or value: ") + name);
   return DG_ERR_ARG;
 }

@@ -104,6 +104,8 @@ struct dg_mesh_s {
   uint16_t* d_bf16op = nullptr;   // dense bf16 reference operators of the BF16 J v (p = 3 shells)
   bool krylov_bf16 = false;       // the implicit step in progress takes the BF16 J v
   int line_pc_every = 1;          // rebuild the radial-line preconditioner every this many steps
+  int line_pc_prec = 32;          // storage precision of its factors: 64, 32 or 16 (bf16)
+  int tune_lsolve = 3;            // launch configuration of its substitution (0..3)
   int64_t fn_len = 0;
   dg::Workspace* ws = nullptr;
   // batched-column solver state (dg_columns_integrate)
@@ -170,12 +172,11 @@ std::vector<uint16_t> bf16_operators(int p);
 dg_status_t shell_jvp_radial(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 int64_t line_pc_doubles(const dg_mesh_s* m);
 dg_status_t shell_jvp_radial32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+int64_t line_pc_packed(const dg_mesh_s* m);   // entries of the packed factor array
 dg_status_t line_pc_build(dg_mesh_s* m, double t, const double* u, double dta, double* Lo, double* Di, double* Up,
-                          double* v, void* jr, bool f32, float* Lo32, float* Di32, float* Up32, hipStream_t s);
-dg_status_t line_pc_apply(dg_mesh_s* m, const double* Lo, const double* Di, const double* Up, const double* r,
-                          double* z, hipStream_t s);
-dg_status_t line_pc_apply(dg_mesh_s* m, const float* Lo, const float* Di, const float* Up, const float* r, float* z,
-                          hipStream_t s);
+                          double* v, void* jr, bool f32, int prec, void* P, hipStream_t s);
+dg_status_t line_pc_apply(dg_mesh_s* m, int prec, const void* P, const double* r, double* z, hipStream_t s);
+dg_status_t line_pc_apply(dg_mesh_s* m, int prec, const void* P, const float* r, float* z, hipStream_t s);
 // modal filter (highest Legendre mode x sigma per direction), in place on u
 dg_status_t shell_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s);
 dg_status_t col_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t s);

@@ -11,9 +11,11 @@
 //    two neighbours' probes only);
 //  * factor: block LU per line, one wavefront per line (Schur complements inverted by
 //    Gauss-Jordan with partial pivoting, W = D^-1 U kept for the back substitution);
-//  * apply: forward and back substitution, several lines per wavefront.
-// Blocks are stored column-major (entry (r, c) at c b + r): the probes fill columns, and
-// the lanes of the substitution (one row each) read consecutive addresses.
+//  * apply: forward and back substitution, several lines per wavefront, from a packed
+//    row-major copy of the factors in a selectable storage precision (double, float,
+//    bf16) that the lanes (one row each) read with wide loads.
+// The blocks of the build are column-major (entry (r, c) at c b + r): the probes fill
+// columns with consecutive writes.
 // The radial direction carries the stiffness of the thin layers (vertical acoustics and
 // conduction), so these blocks catch most of it at the cost of a few R-sized sweeps.
 #include "internal.h"
@@ -28,8 +30,9 @@ struct LineDev {
 };
 
 // v = 1 at (field pc, radial node pcz) of every node on layers k = kap (mod 3), else 0
+template <class V>
 __global__ void k_line_probe(int64_t n_dof, int N, int N2, int n, int n_rad, int pc, int pcz, int kap,
-                             double* __restrict__ v) {
+                             V* __restrict__ v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_dof) return;
   const int j = (int)(i % N);
@@ -37,7 +40,7 @@ __global__ void k_line_probe(int64_t n_dof, int N, int N2, int n, int n_rad, int
   const int c = (int)(ec % 5);
   const int64_t e = ec / 5;
   const int k = (int)(e % n_rad);
-  v[i] = (c == pc && j / N2 == pcz && k % 3 == kap) ? 1.0 : 0.0;
+  v[i] = (c == pc && j / N2 == pcz && k % 3 == kap) ? (V)1 : (V)0;
 }
 
 // the response jr of probe (pc, pcz, kap) into block column l = pc * n + pcz. One thread
@@ -162,75 +165,156 @@ __global__ __launch_bounds__(64) void k_line_factor(LineDev L) {
   }
 }
 
-// z = M^-1 r for every line; LPB lines per 64-thread block, lane = line slot * b + row.
-// T: vector type, F: factor type.
-template <int b, class T, class F>
-__global__ __launch_bounds__(64) void k_line_solve(LineDev L, int64_t n_lines, const F* __restrict__ fLo,
-                                                   const F* __restrict__ fDi, const F* __restrict__ fUp,
-                                                   const T* __restrict__ rin, T* __restrict__ z) {
-  constexpr int bb = b * b;
-  constexpr int LPB = 64 / b;
-  extern __shared__ double x[];   // [LPB][n_rad][b]
-  __shared__ double y[LPB * b];
-  const int lane = threadIdx.x;
+// Packed factors for the substitution, one array of the storage type F (double, float or
+// bf16 bits): per line and layer k the three matrices L_k, Dinv_k, W_k, each row-major
+// with the row stride RS = b rounded up to a multiple of 4 (zero padding), so that a
+// lane reads its whole row with 16- or 8-byte loads.
+__host__ __device__ constexpr int line_rs(int b) { return (b + 3) & ~3; }
+
+__device__ inline double line_cv(double v) { return v; }
+__device__ inline float line_cv(float v) { return v; }
+__device__ inline float line_cv(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <class F> __device__ inline F line_st(double v);
+template <> __device__ inline double line_st<double>(double v) { return v; }
+template <> __device__ inline float line_st<float>(double v) { return (float)v; }
+template <> __device__ inline unsigned short line_st<unsigned short>(double v) {
+  // bf16 by round to nearest even of the float value
+  const unsigned u = __float_as_uint((float)v);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// P <- the packed copy of (Lo, Di, Up): one thread per packed entry
+template <class F>
+__global__ void k_line_pack(LineDev L, int64_t n_lines, F* __restrict__ P) {
+  const int RS = line_rs(L.b), MS = L.b * RS;
+  const int64_t total = n_lines * L.n_rad * 3 * (int64_t)MS;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(t % RS);
+    const int r = (int)((t / RS) % L.b);
+    const int64_t lkm = t / MS;
+    const int mat = (int)(lkm % 3);
+    const int64_t lk = lkm / 3;
+    double v = 0;
+    if (q < L.b) {
+      const double* src = mat == 0 ? L.Lo : (mat == 1 ? L.Di : L.Up);
+      v = src[lk * L.bb + (int64_t)q * L.b + r];
+    }
+    P[t] = line_st<F>(v);
+  }
+}
+
+// dst <- the row at src (RS entries of F, RS * sizeof(F) a multiple of 8 and src aligned to it)
+template <int RS, class F>
+__device__ inline void line_row(F (&dst)[RS], const F* __restrict__ src) {
+  constexpr int bytes = RS * (int)sizeof(F);
+  if constexpr (bytes % 16 == 0) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+#pragma unroll
+    for (int i = 0; i < bytes / 16; ++i) {
+      const uint4 w = s4[i];
+      __builtin_memcpy(reinterpret_cast<char*>(dst) + 16 * i, &w, 16);
+    }
+  } else {
+    static_assert(bytes % 8 == 0, "row size");
+    const uint2* s2 = reinterpret_cast<const uint2*>(src);
+#pragma unroll
+    for (int i = 0; i < bytes / 8; ++i) {
+      const uint2 w = s2[i];
+      __builtin_memcpy(reinterpret_cast<char*>(dst) + 8 * i, &w, 8);
+    }
+  }
+}
+
+// ordering of LDS accesses among the lanes of one wavefront (LDS operations of a
+// wavefront complete in issue order; this only keeps the compiler from moving them)
+__device__ inline void line_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// z = M^-1 r for every line. WPB wavefronts per block, 64 / b whole lines per wavefront
+// (lane = line slot * b + row), so that the substitution needs no block barrier.
+// T: vector (and arithmetic) type, F: storage type of the packed factors. D register rows
+// form a ring: the loads of the next D - 1 matrices are in flight while one is applied.
+template <int b, int WPB, int D, class T, class F>
+__global__ __launch_bounds__(64 * WPB) void k_line_solve(LineDev L, int64_t n_lines, const F* __restrict__ P,
+                                                         const T* __restrict__ rin, T* __restrict__ z) {
+  constexpr int RS = line_rs(b), MS = b * RS;
+  constexpr int LPW = 64 / b;
+  constexpr int LPB = LPW * WPB;
+  extern __shared__ unsigned char line_smem[];
+  T* x = reinterpret_cast<T*>(line_smem);   // [LPB][n_rad][b]
+  const int lane = threadIdx.x & 63;
   const int ls = lane / b, r = lane % b;
-  const int64_t line = (int64_t)blockIdx.x * LPB + ls;
-  const bool act = ls < LPB && line < n_lines;
-  const int nb = L.n_rad * b;
+  const int slot = (threadIdx.x >> 6) * LPW + ls;
   const int64_t line0 = (int64_t)blockIdx.x * LPB;
+  const int64_t line = line0 + slot;
+  const bool act = ls < LPW && line < n_lines;
+  const int nr = L.n_rad;
+  const int nb = nr * b;
   // gather: unknown (k, c * n + cz) of line slot q <- r[e = cell n_rad + k][c][ab + N2 cz]
-  for (int idx = lane; idx < LPB * nb; idx += 64) {
+  for (int idx = threadIdx.x; idx < LPB * nb; idx += 64 * WPB) {
     const int q = idx / nb, w = idx % nb;
     const int64_t ln = line0 + q;
     if (ln >= n_lines) continue;
     const int k = w / b, rr = w % b, c = rr / L.n, cz = rr % L.n;
-    const int64_t e = (ln / L.N2) * L.n_rad + k;
-    x[idx] = (double)rin[(e * 5 + c) * L.N + (ln % L.N2) + L.N2 * cz];
+    const int64_t e = (ln / L.N2) * nr + k;
+    x[idx] = rin[(e * 5 + c) * L.N + (ln % L.N2) + L.N2 * cz];
   }
   __syncthreads();
-  double* xl = x + ls * nb;
-  const int64_t base = line * L.n_rad * bb;
-  // forward: x_k <- Dinv_k (x_k - L_k x_{k-1})
-  for (int k = 0; k < L.n_rad; ++k) {
-    double* xk = xl + k * b;
-    if (act && k > 0) {
-      const F* Lc = fLo + base + (int64_t)k * bb;
-      const double* xp = xl + (k - 1) * b;
-      double s = 0;
-      for (int q = 0; q < b; ++q) s += (double)Lc[q * b + r] * xp[q];
-      xk[r] -= s;
+  T* xl = x + (act ? slot : 0) * nb;
+  // The substitution is a stream of nm = 3 nr - 2 matrix applications:
+  //   j = 2k (k < nr):          x_k <- Dinv_k x_k
+  //   j = 2k - 1 (0 < k < nr):  x_k <- x_k - L_k x_{k-1}
+  //   j = 2 nr - 1 + i:         x_k <- x_k - W_k x_{k+1},  k = nr - 2 - i
+  // Row r of the matrix of step j sits at Pl + (layer * 3 + mat) * MS.
+  const F* Pl = P + (act ? line : 0) * (int64_t)nr * 3 * MS + r * RS;
+  const int nm = 3 * nr - 2;
+  auto row_of = [&](int j) -> const F* {
+    j = min(j, nm - 1);   // loads past the end re-read the last matrix
+    if (j < 2 * nr - 1) return Pl + ((int64_t)((j + 1) / 2) * 3 + ((j & 1) ? 0 : 1)) * MS;
+    return Pl + ((int64_t)(nr - 2 - (j - (2 * nr - 1))) * 3 + 2) * MS;
+  };
+  auto step = [&](int j, const F (&R)[RS]) {
+    if (j < 2 * nr - 1 && !(j & 1)) {
+      T* xk = xl + (j / 2) * b;
+      T sum = 0;
+#pragma unroll
+      for (int q = 0; q < b; ++q) sum += (T)line_cv(R[q]) * xk[q];
+      line_wave_sync();
+      if (act) xk[r] = sum;
+    } else {
+      const int k = j < 2 * nr - 1 ? (j + 1) / 2 : nr - 2 - (j - (2 * nr - 1));
+      const T* xo = xl + (j < 2 * nr - 1 ? k - 1 : k + 1) * b;
+      T sum = 0;
+#pragma unroll
+      for (int q = 0; q < b; ++q) sum += (T)line_cv(R[q]) * xo[q];
+      if (act) xl[k * b + r] -= sum;
     }
-    __syncthreads();
-    if (act) {
-      const F* Dc = fDi + base + (int64_t)k * bb;
-      double s = 0;
-      for (int q = 0; q < b; ++q) s += (double)Dc[q * b + r] * xk[q];
-      y[lane] = s;
+    line_wave_sync();
+  };
+  // loads are issued on every lane and every pass (idle lanes read line 0) so that the
+  // wait for one row never covers the younger ones
+  F R[D][RS];
+#pragma unroll
+  for (int d = 0; d < D; ++d) line_row<RS>(R[d], row_of(d));
+  for (int j = 0; j < nm; j += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (j + d < nm) step(j + d, R[d]);
+      line_row<RS>(R[d], row_of(j + d + D));
     }
-    __syncthreads();
-    if (act) xk[r] = y[lane];
-    __syncthreads();
   }
-  // back: x_k <- x_k - W_k x_{k+1}
-  for (int k = L.n_rad - 2; k >= 0; --k) {
-    if (act) {
-      const F* Wc = fUp + base + (int64_t)k * bb;
-      const double* xn = xl + (k + 1) * b;
-      double s = 0;
-      for (int q = 0; q < b; ++q) s += (double)Wc[q * b + r] * xn[q];
-      y[lane] = s;
-    }
-    __syncthreads();
-    if (act) xl[k * b + r] -= y[lane];
-    __syncthreads();
-  }
-  for (int idx = lane; idx < LPB * nb; idx += 64) {
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < LPB * nb; idx += 64 * WPB) {
     const int q = idx / nb, w = idx % nb;
     const int64_t ln = line0 + q;
     if (ln >= n_lines) continue;
     const int k = w / b, rr = w % b, c = rr / L.n, cz = rr % L.n;
-    const int64_t e = (ln / L.N2) * L.n_rad + k;
-    z[(e * 5 + c) * L.N + (ln % L.N2) + L.N2 * cz] = (T)x[idx];
+    const int64_t e = (ln / L.N2) * nr + k;
+    z[(e * 5 + c) * L.N + (ln % L.N2) + L.N2 * cz] = x[idx];
   }
 }
 
@@ -255,16 +339,18 @@ int64_t line_pc_doubles(const dg_mesh_s* m) {
   return lines * m->n_rad * b * b;
 }
 
-__global__ void k_to_float(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = (float)x[i];
+int64_t line_pc_packed(const dg_mesh_s* m) {
+  const int64_t n = m->p + 1, b = 5 * n;
+  const int64_t lines = (m->n_elem / m->n_rad) * n * n;
+  return lines * m->n_rad * 3 * b * line_rs((int)b);
 }
 
-// build and factor at (t, u) for the stage matrix I - dta J; v, jr: scratch [n_dof]
+// build and factor at (t, u) for the stage matrix I - dta J, then pack the factors into P
+// with storage precision prec (64 double, 32 float, 16 bf16); v, jr: scratch [n_dof]
 // (jr: double, or float when f32 is set). With f32 the probes use the FP32 dual-number
-// linearisation and the factors are also written as float to Lo32 / Di32 / Up32.
+// linearisation.
 dg_status_t line_pc_build(dg_mesh_s* m, double t, const double* u, double dta, double* Lo, double* Di, double* Up,
-                          double* v, void* jr, bool f32, float* Lo32, float* Di32, float* Up32, hipStream_t s) {
+                          double* v, void* jr, bool f32, int prec, void* P, hipStream_t s) {
   ProfScope ps(m, 10, s);
   const LineDev L = line_dev(m, Lo, Di, Up);
   const int64_t nd = m->n_dof;
@@ -276,59 +362,78 @@ dg_status_t line_pc_build(dg_mesh_s* m, double t, const double* u, double dta, d
   for (int kap = 0; kap < 3; ++kap)
     for (int pc = 0; pc < 5; ++pc)
       for (int pcz = 0; pcz < L.n; ++pcz) {
-        k_line_probe<<<blocks, 256, 0, s>>>(nd, L.N, L.N2, L.n, L.n_rad, pc, pcz, kap, v);
         if (f32) {
-          k_to_float<<<blocks, 256, 0, s>>>(nd, v, (float*)jr + nd);
-          dg_status_t rc = shell_jvp_radial32(m, t, u, (const float*)jr + nd, (float*)jr, s);
+          float* vf = (float*)jr + nd;
+          k_line_probe<float><<<blocks, 256, 0, s>>>(nd, L.N, L.N2, L.n, L.n_rad, pc, pcz, kap, vf);
+          dg_status_t rc = shell_jvp_radial32(m, t, u, vf, (float*)jr, s);
           if (rc != DG_OK) return rc;
           k_line_scatter<float><<<blocks, 256, 0, s>>>(L, pc, pcz, kap, dta, (const float*)jr);
         } else {
+          k_line_probe<double><<<blocks, 256, 0, s>>>(nd, L.N, L.N2, L.n, L.n_rad, pc, pcz, kap, v);
           dg_status_t rc = shell_jvp_radial(m, t, u, v, (double*)jr, s);
           if (rc != DG_OK) return rc;
           k_line_scatter<double><<<blocks, 256, 0, s>>>(L, pc, pcz, kap, dta, (const double*)jr);
         }
       }
-  const unsigned lines = (unsigned)(m->n_elem / m->n_rad * L.N2);
+  const int64_t n_lines = m->n_elem / m->n_rad * L.N2;
   switch (m->p) {
-    case 2: k_line_factor<15><<<lines, 64, 0, s>>>(L); break;
-    case 3: k_line_factor<20><<<lines, 64, 0, s>>>(L); break;
-    default: k_line_factor<25><<<lines, 64, 0, s>>>(L); break;
+    case 2: k_line_factor<15><<<(unsigned)n_lines, 64, 0, s>>>(L); break;
+    case 3: k_line_factor<20><<<(unsigned)n_lines, 64, 0, s>>>(L); break;
+    default: k_line_factor<25><<<(unsigned)n_lines, 64, 0, s>>>(L); break;
   }
-  if (f32) {
-    const unsigned g = 4096;
-    k_to_float<<<g, 256, 0, s>>>(nblk, Lo, Lo32);
-    k_to_float<<<g, 256, 0, s>>>(nblk, Di, Di32);
-    k_to_float<<<g, 256, 0, s>>>(nblk, Up, Up32);
-  }
+  const unsigned g = 8192;
+  if (prec == 64) k_line_pack<double><<<g, 256, 0, s>>>(L, n_lines, (double*)P);
+  else if (prec == 32) k_line_pack<float><<<g, 256, 0, s>>>(L, n_lines, (float*)P);
+  else k_line_pack<unsigned short><<<g, 256, 0, s>>>(L, n_lines, (unsigned short*)P);
   DG_HIP_CHECK(hipGetLastError());
   return DG_OK;
 }
 
-template <class T, class F>
-static dg_status_t line_pc_apply_t(dg_mesh_s* m, const F* Lo, const F* Di, const F* Up, const T* r, T* z,
-                                   hipStream_t s) {
+template <int b, int WPB, int D, class T>
+static void line_solve_launch(const LineDev& L, int64_t lines, int prec, const void* P, const T* r, T* z,
+                              hipStream_t s) {
+  constexpr int lpb = (64 / b) * WPB;
+  const unsigned grid = (unsigned)((lines + lpb - 1) / lpb);
+  const size_t shm = (size_t)lpb * L.n_rad * b * sizeof(T);
+  const unsigned th = 64 * WPB;
+  if (prec == 64) k_line_solve<b, WPB, D, T, double><<<grid, th, shm, s>>>(L, lines, (const double*)P, r, z);
+  else if (prec == 32) k_line_solve<b, WPB, D, T, float><<<grid, th, shm, s>>>(L, lines, (const float*)P, r, z);
+  else k_line_solve<b, WPB, D, T, unsigned short><<<grid, th, shm, s>>>(L, lines, (const unsigned short*)P, r, z);
+}
+
+// launch configurations of the substitution (the "line_solve_config" option):
+// 0: 1 wavefront per block, 2-deep ring; 1: 4 wavefronts, 2-deep; 2: 1 wavefront, 4-deep;
+// 3: 4 wavefronts, 4-deep
+template <int b, class T>
+static void line_solve_cfg(int cfg, const LineDev& L, int64_t lines, int prec, const void* P, const T* r, T* z,
+                           hipStream_t s) {
+  switch (cfg) {
+    case 1: line_solve_launch<b, 4, 2, T>(L, lines, prec, P, r, z, s); break;
+    case 2: line_solve_launch<b, 1, 4, T>(L, lines, prec, P, r, z, s); break;
+    case 3: line_solve_launch<b, 4, 4, T>(L, lines, prec, P, r, z, s); break;
+    default: line_solve_launch<b, 1, 2, T>(L, lines, prec, P, r, z, s); break;
+  }
+}
+
+template <class T>
+static dg_status_t line_pc_apply_t(dg_mesh_s* m, int prec, const void* P, const T* r, T* z, hipStream_t s) {
   ProfScope ps(m, 11, s);
   const LineDev L = line_dev(m, nullptr, nullptr, nullptr);
   const int64_t lines = m->n_elem / m->n_rad * L.N2;
-  const int lpb = 64 / L.b;
-  const unsigned grid = (unsigned)((lines + lpb - 1) / lpb);
-  const size_t shm = (size_t)lpb * L.n_rad * L.b * sizeof(double);
   switch (m->p) {
-    case 2: k_line_solve<15, T, F><<<grid, 64, shm, s>>>(L, lines, Lo, Di, Up, r, z); break;
-    case 3: k_line_solve<20, T, F><<<grid, 64, shm, s>>>(L, lines, Lo, Di, Up, r, z); break;
-    default: k_line_solve<25, T, F><<<grid, 64, shm, s>>>(L, lines, Lo, Di, Up, r, z); break;
+    case 2: line_solve_cfg<15, T>(m->tune_lsolve, L, lines, prec, P, r, z, s); break;
+    case 3: line_solve_cfg<20, T>(m->tune_lsolve, L, lines, prec, P, r, z, s); break;
+    default: line_solve_cfg<25, T>(m->tune_lsolve, L, lines, prec, P, r, z, s); break;
   }
   DG_HIP_CHECK(hipGetLastError());
   return DG_OK;
 }
 
-dg_status_t line_pc_apply(dg_mesh_s* m, const double* Lo, const double* Di, const double* Up, const double* r,
-                          double* z, hipStream_t s) {
-  return line_pc_apply_t<double, double>(m, Lo, Di, Up, r, z, s);
+dg_status_t line_pc_apply(dg_mesh_s* m, int prec, const void* P, const double* r, double* z, hipStream_t s) {
+  return line_pc_apply_t<double>(m, prec, P, r, z, s);
 }
-dg_status_t line_pc_apply(dg_mesh_s* m, const float* Lo, const float* Di, const float* Up, const float* r, float* z,
-                          hipStream_t s) {
-  return line_pc_apply_t<float, float>(m, Lo, Di, Up, r, z, s);
+dg_status_t line_pc_apply(dg_mesh_s* m, int prec, const void* P, const float* r, float* z, hipStream_t s) {
+  return line_pc_apply_t<float>(m, prec, P, r, z, s);
 }
 
 }  // namespace dg

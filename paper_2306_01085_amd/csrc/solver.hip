@@ -310,10 +310,11 @@ struct Workspace {
   double t_end = NAN;                     // end time of the last step (history continuity)
   double* Binv = nullptr;
   double *lineLo = nullptr, *lineDi = nullptr, *lineUp = nullptr;   // radial-line preconditioner factors
-  float *lineLo32 = nullptr, *lineDi32 = nullptr, *lineUp32 = nullptr;   // their float copies (FP32 runs)
+  void* lineP = nullptr;  // the packed factors used by the substitution
+  int lineP_prec = 0;     // their storage precision (64, 32, 16)
   int line_age = -1;      // steps since the line preconditioner was built (-1: not built)
   double line_dta = 0;    // dt a_ii it was built for
-  bool line_f32 = false;  // the build produced the float copies
+  bool line_f32 = false;  // it was built from the FP32 linearisation
   void* V = nullptr;                      // (m+1) basis vectors, double or float
   void* w = nullptr;
   void* z = nullptr;
@@ -328,7 +329,7 @@ void free_workspace(dg_mesh_s* m) {
   if (!w) return;
   void* ptrs[] = {w->un, w->U, w->G, w->B, w->X, w->Rc, w->Rs[0], w->Rs[1], w->Rs[2], w->hist[0], w->hist[1],
                   w->Binv, w->V, w->w, w->z, w->s, w->part, w->dev_small, w->Up, w->lineLo, w->lineDi, w->lineUp,
-                  w->lineLo32, w->lineDi32, w->lineUp32};
+                  w->lineP};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->host_small) (void)hipHostFree(w->host_small);
@@ -381,13 +382,13 @@ static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const float* v, 
 // z = M^-1 v: mode 0 identity, 1 node block-Jacobi, 2 radial-line block-Jacobi
 static dg_status_t precond(dg_mesh_s* m, const Workspace* ws, int mode, const double* v, double* z, hipStream_t s) {
   if (mode == 1) return shell_bjac_apply64(m, ws->Binv, v, z, s);
-  if (mode == 2) return line_pc_apply(m, ws->lineLo, ws->lineDi, ws->lineUp, v, z, s);
+  if (mode == 2) return line_pc_apply(m, ws->lineP_prec, ws->lineP, v, z, s);
   DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(double), hipMemcpyDeviceToDevice, s));
   return DG_OK;
 }
 static dg_status_t precond(dg_mesh_s* m, const Workspace* ws, int mode, const float* v, float* z, hipStream_t s) {
   if (mode == 1) return shell_bjac_apply32(m, ws->Binv, v, z, s);
-  if (mode == 2) return line_pc_apply(m, ws->lineLo32, ws->lineDi32, ws->lineUp32, v, z, s);
+  if (mode == 2) return line_pc_apply(m, ws->lineP_prec, ws->lineP, v, z, s);
   DG_HIP_CHECK(hipMemcpyAsync(z, v, m->n_dof * sizeof(float), hipMemcpyDeviceToDevice, s));
   return DG_OK;
 }
@@ -592,21 +593,24 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
   const int nb = grid_for(n);
   const int pc = (m->kind == DG_MESH_SHELL) ? o.precond : 0;
   const bool f32 = std::is_same<T, float>::value;
-  if (pc == 2 && (!ws->lineLo || (f32 && !ws->lineLo32))) {
+  if (pc == 2 && (!ws->lineLo || ws->lineP_prec != m->line_pc_prec)) {
     const size_t cnt = (size_t)line_pc_doubles(m);
+    const int prec = m->line_pc_prec;
     bool ok = true;
     if (!ws->lineLo)
       ok = hipMalloc(&ws->lineLo, cnt * sizeof(double)) == hipSuccess &&
            hipMalloc(&ws->lineDi, cnt * sizeof(double)) == hipSuccess &&
            hipMalloc(&ws->lineUp, cnt * sizeof(double)) == hipSuccess;
-    if (ok && f32)
-      ok = hipMalloc(&ws->lineLo32, cnt * sizeof(float)) == hipSuccess &&
-           hipMalloc(&ws->lineDi32, cnt * sizeof(float)) == hipSuccess &&
-           hipMalloc(&ws->lineUp32, cnt * sizeof(float)) == hipSuccess;
+    if (ws->lineP) (void)hipFree(ws->lineP);
+    ws->lineP = nullptr;
+    ws->lineP_prec = 0;
+    ws->line_age = -1;
+    if (ok) ok = hipMalloc(&ws->lineP, (size_t)line_pc_packed(m) * (prec / 8)) == hipSuccess;
     if (!ok) {
       set_error("dg_implicit_step: allocation of the line preconditioner failed");
       return DG_ERR_ALLOC;
     }
+    ws->lineP_prec = prec;
   }
   double A[3][3], c[3];
   int ns;
@@ -622,7 +626,7 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
                        ws->line_dta != dt * A[0][0];
     if (stale) {
       rc = line_pc_build(m, t + c[0] * dt, ws->un, dt * A[0][0], ws->lineLo, ws->lineDi, ws->lineUp, ws->X, ws->Rc,
-                         f32, ws->lineLo32, ws->lineDi32, ws->lineUp32, s);
+                         f32, ws->lineP_prec, ws->lineP, s);
       if (rc != DG_OK) return rc;
       ws->line_age = 0;
       ws->line_f32 = f32;

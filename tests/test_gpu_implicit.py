@@ -159,4 +159,58 @@ def test_line_preconditioner_reuse_keeps_the_answer():
     assert np.linalg.norm(outs[1] - outs[0]) / np.linalg.norm(outs[0] - u.ravel()) < 1e-6
     gm = Mesh.shell(p=3, n_ang=2, n_rad=8, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
     with pytest.raises(DgError):
+        gm.set_option("line_pc_precision", 8)
+    gm = Mesh.shell(p=3, n_ang=2, n_rad=8, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
+    with pytest.raises(DgError):
         gm.set_option("line_pc_every", 0)
+
+
+@pytest.mark.parametrize("fprec", [64, 32, 16])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_line_preconditioner_storage_precision(prec, fprec):
+    """the factors' storage precision (double, float, bf16) changes the GMRES path, not
+    the converged step; a p = 2 mesh with 5 layers covers the padded row stride and an
+    odd number of substitution steps"""
+    need_gpu()
+    from paper_2306_01085_amd import Mesh
+    for p, n_rad in ((3, 8), (2, 5)):
+        w = synth.shell_workload(8, p=p, n_ang=2, n_rad=n_rad)
+        om = omesh.shell_mesh(p, 2, n_rad, w.r_bot, w.r_top, w.stretch)
+        u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+        dt = synth.seconds_to_nondim(10.0)
+        outs, its = [], []
+        for pc in (0, 2):
+            gm = Mesh.shell(p=p, n_ang=2, n_rad=n_rad, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
+            gm.set_option("line_pc_precision", fprec)
+            ut = to_dev(u)
+            st = gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, jvp_prec=prec, precond=pc, max_restarts=60,
+                                  max_newton=20)
+            outs.append(ut.cpu().numpy())
+            its.append(sum(st["gmres_its"]))
+        assert np.linalg.norm(outs[1] - outs[0]) / np.linalg.norm(outs[0] - u.ravel()) < 1e-6, (p, fprec)
+        assert its[1] < 0.5 * its[0], (p, fprec, its)
+
+
+@pytest.mark.parametrize("fprec", [32, 16])
+def test_line_solve_configs_are_bitwise_identical(fprec):
+    """the substitution's launch configurations (wavefronts per block, prefetch depth)
+    perform the same arithmetic in the same order: identical steps and iteration counts"""
+    need_gpu()
+    from paper_2306_01085_amd import Mesh
+    for p, n_rad in ((3, 7), (2, 4), (4, 3)):
+        w = synth.shell_workload(9, p=p, n_ang=2, n_rad=n_rad)
+        om = omesh.shell_mesh(p, 2, n_rad, w.r_bot, w.r_top, w.stretch)
+        u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+        dt = synth.seconds_to_nondim(10.0)
+        outs, its = [], []
+        for cfg in range(4):
+            gm = Mesh.shell(p=p, n_ang=2, n_rad=n_rad, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
+            gm.set_option("line_pc_precision", fprec)
+            gm.set_option("line_solve_config", cfg)
+            ut = to_dev(u)
+            st = gm.implicit_step(ut, 0.0, dt, newton_rtol=1e-10, jvp_prec="f32", precond=2, max_restarts=60,
+                                  max_newton=20)
+            outs.append(ut.cpu().numpy())
+            its.append(st["gmres_its"])
+        for o, i in zip(outs[1:], its[1:]):
+            assert np.array_equal(o, outs[0]) and i == its[0], (p, its)
