@@ -104,7 +104,7 @@ def residual_bytes(w):
 # workload and launch configuration, with the hash of the kernel sources they were taken
 # on (a changed kernel reports null until measured again)
 PASS1_TRAFFIC = {
-    ("shell-p3", 2): {"src": "79a85f780219d936", "fetch_kib": 55055.4, "write_kib": 151680.0,
+    ("shell-p3", 2): {"src": "fb5a9765c2db781b", "fetch_kib": 55061.9, "write_kib": 151680.0,
                       "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_counters.txt"},
 }
 
@@ -160,7 +160,17 @@ LINE_PC_EVERY = 4        # the radial-line preconditioner is rebuilt every 4 ste
 LINE_PC_PRECISION = 16   # and its factors are read as bf16 (same GMRES counts as double here)
 
 
-def implicit_steps(w, mesh, u, n_steps):
+def copy_probe(dev):
+    """one plain device copy of 256 MiB: its FETCH_SIZE / WRITE_SIZE readings calibrate
+    the HBM counters of the same run"""
+    import torch
+    src = torch.empty(2 ** 28 // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def implicit_steps(w, mesh, u, n_steps, only=None):
     """seconds per DIRK(3,3) step of dt = 60 s at a 1e-8 relative Newton tolerance,
     GMRES(30) right-preconditioned by the radial-line block-Jacobi preconditioner,
     (rebuilt every LINE_PC_EVERY steps, bf16 factors), Eisenstat-Walker GMRES tolerances,
@@ -174,6 +184,8 @@ def implicit_steps(w, mesh, u, n_steps):
            "steps": n_steps, "filter_rate": FILTER_RATE}
     runs = [(prec, 2, prec) for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ())]
     runs.append(("f32_no_precond", 0, "f32"))
+    if only:
+        runs = [r for r in runs if r[0] in only]
     mesh.set_option("line_pc_every", LINE_PC_EVERY)
     mesh.set_option("line_pc_precision", LINE_PC_PRECISION)
     res["line_pc_every"] = LINE_PC_EVERY
@@ -318,8 +330,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of known size (calibrates HBM counters)")
-    ap.add_argument("--only", default="all", choices=["all", "residual"],
-                    help="residual: only the R(u) timing (for counter runs)")
+    ap.add_argument("--only", default="all", choices=["all", "residual", "implicit"],
+                    help="residual: only the R(u) timing; implicit: only the implicit steps (for counter runs)")
+    ap.add_argument("--implicit-runs", default="f64,f32,bf16,f32_no_precond",
+                    help="which implicit-step runs (with --only implicit)")
     ap.add_argument("--mode", default="default", choices=["default", "warmstart"])
     ap.add_argument("--implicit-steps", type=int, default=4)
     ap.add_argument("--ws-train-steps", type=int, default=60)
@@ -372,6 +386,14 @@ def main():
                                               eval_steps=args.ws_eval_steps, epochs=args.ws_epochs)), flush=True)
         return
 
+    if args.only == "implicit":
+        del r, jv, jv32, v, v32
+        res = implicit_steps(w, mesh, u, args.implicit_steps, only=args.implicit_runs.split(","))
+        if args.copy_probe:
+            copy_probe(dev)
+        print(json.dumps(res), flush=True)
+        return
+
     f_r = lambda: mesh.residual(u, t, out=r)
     f_j64 = lambda: mesh.jvp(u, v, t, "f64", out=jv)
     f_j32 = lambda: mesh.jvp(u, v32, t, "f32", out=jv32)
@@ -382,10 +404,7 @@ def main():
             f_r()
         ms_r = timed(f_r, args.steps)
         if args.copy_probe:
-            src = torch.empty(2 ** 28 // 8, dtype=torch.float64, device=dev).fill_(1.0)
-            dst = torch.empty_like(src)
-            dst.copy_(src)
-            torch.cuda.synchronize()
+            copy_probe(dev)
         print(json.dumps({"residual_ms": ms_r, "gdofs": w.n_dof / ms_r / 1e6}), flush=True)
         return
     for _ in range(args.warmup):
@@ -414,10 +433,7 @@ def main():
     prof.update(mesh.profile_read())
     mesh.profile(False)
     if args.copy_probe:
-        src = torch.empty(2 ** 28 // 8, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        copy_probe(dev)
     ndof = w.n_dof
     p1_ms = prof["shell_pass1_R"][0] / prof["shell_pass1_R"][1]
     p2_ms = prof["shell_pass2_R"][0] / prof["shell_pass2_R"][1]

@@ -125,7 +125,7 @@ dg_status_t dg_set_option(dg_mesh_t m, const char* name, int64_t value) {
     m->line_pc_every = (int)value;
     return DG_OK;
   }
-  if (std::strcmp(name, "line_solve_config") == 0 && value >= 0 && value <= 3) {
+  if (std::strcmp(name, "line_solve_config") == 0 && value >= -1 && value <= 5) {
     m->tune_lsolve = (int)value;
     return DG_OK;
   }

@@ -105,7 +105,7 @@ struct dg_mesh_s {
   bool krylov_bf16 = false;       // the implicit step in progress takes the BF16 J v
   int line_pc_every = 1;          // rebuild the radial-line preconditioner every this many steps
   int line_pc_prec = 32;          // storage precision of its factors: 64, 32 or 16 (bf16)
-  int tune_lsolve = 3;            // launch configuration of its substitution (0..3)
+  int tune_lsolve = -1;           // launch configuration of its substitution (0..5, -1 automatic)
   int64_t fn_len = 0;
   dg::Workspace* ws = nullptr;
   // batched-column solver state (dg_columns_integrate)

@@ -238,12 +238,12 @@ __device__ inline void line_wave_sync() {
 // (lane = line slot * b + row), so that the substitution needs no block barrier.
 // T: vector (and arithmetic) type, F: storage type of the packed factors. D register rows
 // form a ring: the loads of the next D - 1 matrices are in flight while one is applied.
-template <int b, int WPB, int D, class T, class F>
+template <int b, int WPB, int D, int LPB, class T, class F>
 __global__ __launch_bounds__(64 * WPB) void k_line_solve(LineDev L, int64_t n_lines, const F* __restrict__ P,
                                                          const T* __restrict__ rin, T* __restrict__ z) {
   constexpr int RS = line_rs(b), MS = b * RS;
   constexpr int LPW = 64 / b;
-  constexpr int LPB = LPW * WPB;
+  static_assert(LPB <= LPW * WPB, "lines per block");
   extern __shared__ unsigned char line_smem[];
   T* x = reinterpret_cast<T*>(line_smem);   // [LPB][n_rad][b]
   const int lane = threadIdx.x & 63;
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_solve(LineDev L, int64_t n_li
   const int slot = (threadIdx.x >> 6) * LPW + ls;
   const int64_t line0 = (int64_t)blockIdx.x * LPB;
   const int64_t line = line0 + slot;
-  const bool act = ls < LPW && line < n_lines;
+  const bool act = ls < LPW && slot < LPB && line < n_lines;
   const int nr = L.n_rad;
   const int nb = nr * b;
   // gather: unknown (k, c * n + cz) of line slot q <- r[e = cell n_rad + k][c][ab + N2 cz]
@@ -389,29 +389,50 @@ dg_status_t line_pc_build(dg_mesh_s* m, double t, const double* u, double dta, d
   return DG_OK;
 }
 
-template <int b, int WPB, int D, class T>
+constexpr size_t LINE_MAX_LDS = 65536;   // dynamic LDS of one block of the substitution
+
+template <int b, int WPB, int D, int LPB, class T>
 static void line_solve_launch(const LineDev& L, int64_t lines, int prec, const void* P, const T* r, T* z,
                               hipStream_t s) {
-  constexpr int lpb = (64 / b) * WPB;
-  const unsigned grid = (unsigned)((lines + lpb - 1) / lpb);
-  const size_t shm = (size_t)lpb * L.n_rad * b * sizeof(T);
+  const size_t shm = (size_t)LPB * L.n_rad * b * sizeof(T);
+  if (shm > LINE_MAX_LDS) {
+    // tall lines: one wavefront's lines per block (line_pc_apply checks that these fit)
+    if constexpr (WPB > 1) line_solve_launch<b, 1, 2, 64 / b, T>(L, lines, prec, P, r, z, s);
+    return;
+  }
+  const unsigned grid = (unsigned)((lines + LPB - 1) / LPB);
   const unsigned th = 64 * WPB;
-  if (prec == 64) k_line_solve<b, WPB, D, T, double><<<grid, th, shm, s>>>(L, lines, (const double*)P, r, z);
-  else if (prec == 32) k_line_solve<b, WPB, D, T, float><<<grid, th, shm, s>>>(L, lines, (const float*)P, r, z);
-  else k_line_solve<b, WPB, D, T, unsigned short><<<grid, th, shm, s>>>(L, lines, (const unsigned short*)P, r, z);
+  if (prec == 64)
+    k_line_solve<b, WPB, D, LPB, T, double><<<grid, th, shm, s>>>(L, lines, (const double*)P, r, z);
+  else if (prec == 32)
+    k_line_solve<b, WPB, D, LPB, T, float><<<grid, th, shm, s>>>(L, lines, (const float*)P, r, z);
+  else
+    k_line_solve<b, WPB, D, LPB, T, unsigned short><<<grid, th, shm, s>>>(L, lines, (const unsigned short*)P, r, z);
 }
 
 // launch configurations of the substitution (the "line_solve_config" option):
 // 0: 1 wavefront per block, 2-deep ring; 1: 4 wavefronts, 2-deep; 2: 1 wavefront, 4-deep;
-// 3: 4 wavefronts, 4-deep
+// 3: 4 wavefronts, 4-deep; 4 / 5: the (p + 1)^2 lines of one angular cell per block (its
+// vector entries are whole cache lines), 4-deep / 2-deep (at p = 4, whose cell would take
+// 13 wavefronts, the same as 3 / 1)
 template <int b, class T>
 static void line_solve_cfg(int cfg, const LineDev& L, int64_t lines, int prec, const void* P, const T* r, T* z,
                            hipStream_t s) {
+  constexpr int LPW = 64 / b, n = b / 5, N2 = n * n;
+  constexpr int WC = (N2 + LPW - 1) / LPW;   // wavefronts for one cell's lines
   switch (cfg) {
-    case 1: line_solve_launch<b, 4, 2, T>(L, lines, prec, P, r, z, s); break;
-    case 2: line_solve_launch<b, 1, 4, T>(L, lines, prec, P, r, z, s); break;
-    case 3: line_solve_launch<b, 4, 4, T>(L, lines, prec, P, r, z, s); break;
-    default: line_solve_launch<b, 1, 2, T>(L, lines, prec, P, r, z, s); break;
+    case 1: line_solve_launch<b, 4, 2, 4 * LPW, T>(L, lines, prec, P, r, z, s); break;
+    case 2: line_solve_launch<b, 1, 4, LPW, T>(L, lines, prec, P, r, z, s); break;
+    case 3: line_solve_launch<b, 4, 4, 4 * LPW, T>(L, lines, prec, P, r, z, s); break;
+    case 4:
+      if constexpr (WC <= 8) line_solve_launch<b, WC, 4, N2, T>(L, lines, prec, P, r, z, s);
+      else line_solve_launch<b, 4, 4, 4 * LPW, T>(L, lines, prec, P, r, z, s);
+      break;
+    case 5:
+      if constexpr (WC <= 8) line_solve_launch<b, WC, 2, N2, T>(L, lines, prec, P, r, z, s);
+      else line_solve_launch<b, 4, 2, 4 * LPW, T>(L, lines, prec, P, r, z, s);
+      break;
+    default: line_solve_launch<b, 1, 2, LPW, T>(L, lines, prec, P, r, z, s); break;
   }
 }
 
@@ -420,10 +441,16 @@ static dg_status_t line_pc_apply_t(dg_mesh_s* m, int prec, const void* P, const 
   ProfScope ps(m, 11, s);
   const LineDev L = line_dev(m, nullptr, nullptr, nullptr);
   const int64_t lines = m->n_elem / m->n_rad * L.N2;
+  if ((size_t)(64 / L.b) * L.n_rad * L.b * sizeof(T) > LINE_MAX_LDS) {
+    set_error("radial-line preconditioner: too many radial layers for the substitution's LDS");
+    return DG_ERR_ARG;
+  }
+  // automatic choice (measured on the 7.9M-DOF p = 3 shell): cell blocks for double vectors
+  const int cfg = m->tune_lsolve >= 0 ? m->tune_lsolve : (sizeof(T) == 8 ? 4 : 3);
   switch (m->p) {
-    case 2: line_solve_cfg<15, T>(m->tune_lsolve, L, lines, prec, P, r, z, s); break;
-    case 3: line_solve_cfg<20, T>(m->tune_lsolve, L, lines, prec, P, r, z, s); break;
-    default: line_solve_cfg<25, T>(m->tune_lsolve, L, lines, prec, P, r, z, s); break;
+    case 2: line_solve_cfg<15, T>(cfg, L, lines, prec, P, r, z, s); break;
+    case 3: line_solve_cfg<20, T>(cfg, L, lines, prec, P, r, z, s); break;
+    default: line_solve_cfg<25, T>(cfg, L, lines, prec, P, r, z, s); break;
   }
   DG_HIP_CHECK(hipGetLastError());
   return DG_OK;

@@ -203,7 +203,7 @@ def test_line_solve_configs_are_bitwise_identical(fprec):
         u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
         dt = synth.seconds_to_nondim(10.0)
         outs, its = [], []
-        for cfg in range(4):
+        for cfg in range(6):
             gm = Mesh.shell(p=p, n_ang=2, n_rad=n_rad, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
             gm.set_option("line_pc_precision", fprec)
             gm.set_option("line_solve_config", cfg)
