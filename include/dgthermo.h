@@ -141,7 +141,8 @@ typedef struct {
                               Newton iteration); 2 radial-line block Jacobi: I - dt a_ii J_rad with J_rad
                               the linearisation that drops the tangent's coupling between different
                               angular nodes (exact along each radial line), block tridiagonal per line,
-                              built once per step at u_n by 15 (p+1) dual probes, factored by block LU */
+                              built at u_n by 15 (p+1) dual probes (every step, or every
+                              "line_pc_every" steps), factored by block LU */
   int32_t guess;           /* 0: previous state (first step) / extrapolation, 1: learned warm start */
   int32_t forcing;         /* GMRES tolerance per Newton iteration: 0 fixed gmres_rtol; 1 Eisenstat-Walker:
                               eta_0 = 0.1, eta_k = min(0.1, 0.9 (|G_k|/|G_k-1|)^2) (kept >= 0.9 eta_k-1^2
@@ -152,6 +153,13 @@ typedef struct {
                               modal filter, applied to u_{n+1}); 0 leaves the DIRK step unfiltered.
                               Not part of the paper's method: it damps the intra-element mode that
                               the collocated (under-integrated) products let grow. */
+  int32_t n_rb;            /* 0..8, reduced basis of section 3.2 (0: off). The n_rb most recent Newton
+                              updates d_j (kept across stages and steps; emptied when dt a_ii changes or
+                              a step does not continue the previous one) and z_j = A d_j (A = I - dt a_ii J
+                              at the iterate where d_j was solved, one J v each) give GMRES the initial
+                              guess W c(rhs) and the preconditioner v -> W c(v) + P^-1 (v - Z c(v)),
+                              c(v) = (Z^T Z)^+ Z^T v, P the preconditioner chosen by precond. Changes the
+                              GMRES path, not the converged step. */
 } dg_solver_opts_t;
 
 typedef struct {

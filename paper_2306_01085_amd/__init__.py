@@ -53,7 +53,7 @@ class SolverOpts(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("gmres_m", C.c_int32), ("max_newton", C.c_int32),
                 ("max_restarts", C.c_int32), ("newton_rtol", C.c_double), ("gmres_rtol", C.c_double),
                 ("jvp_prec", C.c_int32), ("precond", C.c_int32), ("guess", C.c_int32), ("forcing", C.c_int32),
-                ("filter_rate", C.c_double)]
+                ("filter_rate", C.c_double), ("n_rb", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -258,11 +258,12 @@ class Mesh:
         return out
 
     def implicit_step(self, u, t, dt, scheme=33, gmres_m=30, max_newton=20, max_restarts=20, newton_rtol=1e-8,
-                      gmres_rtol=1e-3, jvp_prec="f64", precond=1, guess=0, filter_rate=0.0, forcing=0, stream=None):
+                      gmres_rtol=1e-3, jvp_prec="f64", precond=1, guess=0, filter_rate=0.0, forcing=0, n_rb=0,
+                      stream=None):
         import torch
         o = SolverOpts(scheme=scheme, gmres_m=gmres_m, max_newton=max_newton, max_restarts=max_restarts,
                        newton_rtol=newton_rtol, gmres_rtol=gmres_rtol, jvp_prec=_PREC[jvp_prec], precond=precond,
-                       guess=guess, forcing=forcing, filter_rate=filter_rate)
+                       guess=guess, forcing=forcing, filter_rate=filter_rate, n_rb=n_rb)
         st = StepStats()
         code = _lib.dg_implicit_step(self._h, float(t), float(dt), _ptr(u, torch.float64), u.numel(), C.byref(o),
                                      C.byref(st), _stream(stream))

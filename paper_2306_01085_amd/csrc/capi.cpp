@@ -313,7 +313,7 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
       (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32 && opts->jvp_prec != DG_BF16) || opts->precond < 0 ||
       opts->precond > 2 ||
       opts->guess < 0 || opts->guess > 1 || opts->forcing < 0 || opts->forcing > 1 || !(opts->filter_rate >= 0) ||
-      !std::isfinite(opts->filter_rate)) {
+      !std::isfinite(opts->filter_rate) || opts->n_rb < 0 || opts->n_rb > 8) {
     set_error("dg_implicit_step: invalid solver options");
     return DG_ERR_ARG;
   }

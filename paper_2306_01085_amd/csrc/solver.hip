@@ -242,6 +242,59 @@ __global__ void k_extrapolate(int64_t n, const double* __restrict__ A, const dou
     out[i] = A[i] + f * (A[i] - B[i]);
 }
 
+// ---------------------------------------------------------------- reduced basis (section 3.2)
+constexpr int RB_MAX = 8;
+
+// c = Gp d (k x k, row-major), one block
+__global__ void k_rb_coef(int k, const double* __restrict__ Gp, const double* __restrict__ d, double* __restrict__ c) {
+  const int i = threadIdx.x;
+  if (i >= k) return;
+  double a = 0;
+  for (int j = 0; j < k; ++j) a += Gp[i * k + j] * d[j];
+  c[i] = a;
+}
+
+// r = v - sum_j c_j Z_j and x = sum_j c_j W_j; with r == x (no base preconditioner) the
+// sum r + x is written instead
+template <class T>
+__global__ void k_rb_split(int64_t n, int k, const T* __restrict__ Z, const T* __restrict__ W,
+                           const double* __restrict__ c, const T* __restrict__ v, T* r, T* x) {
+  double cc[RB_MAX];
+  for (int j = 0; j < k; ++j) cc[j] = c[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double a = (double)v[i], b = 0;
+    for (int j = 0; j < k; ++j) {
+      a -= cc[j] * (double)Z[j * n + i];
+      b += cc[j] * (double)W[j * n + i];
+    }
+    if (r == x) {
+      r[i] = (T)(a + b);
+    } else {
+      r[i] = (T)a;
+      x[i] = (T)b;
+    }
+  }
+}
+
+// X = sum_j c_j W_j (the GMRES initial guess, double)
+template <class T>
+__global__ void k_rb_guess(int64_t n, int k, const T* __restrict__ W, const double* __restrict__ c,
+                           double* __restrict__ X) {
+  double cc[RB_MAX];
+  for (int j = 0; j < k; ++j) cc[j] = c[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double b = 0;
+    for (int j = 0; j < k; ++j) b += cc[j] * (double)W[j * n + i];
+    X[i] = b;
+  }
+}
+
+template <class T>
+__global__ void k_add_T(int64_t n, const T* __restrict__ x, T* __restrict__ z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = (T)((double)z[i] + (double)x[i]);
+}
+
 // ---------------------------------------------------------------- learned warm start
 // features of element e: [U_a, U_a - U_b, b - U_a] per field and node (3 x 5 x N), standardised
 __global__ void k_ws_features(int64_t E, int N, const double* __restrict__ Ua, const double* __restrict__ Ub,
@@ -315,6 +368,16 @@ struct Workspace {
   int line_age = -1;      // steps since the line preconditioner was built (-1: not built)
   double line_dta = 0;    // dt a_ii it was built for
   bool line_f32 = false;  // it was built from the FP32 linearisation
+  // reduced basis: W (updates) and Z = A W, rb_cap vectors each in the Krylov precision, a ring
+  // of rb_count valid slots; G = Z^T Z on the host, its pseudo-inverse on the device
+  void* rbW = nullptr;
+  void* rbZ = nullptr;
+  void* rbT = nullptr;                    // one scratch vector
+  int rb_cap = 0, rb_count = 0, rb_head = 0, rb_n = 0;
+  double rb_dta = 0;
+  double rb_G[RB_MAX * RB_MAX] = {};
+  double* rb_dev = nullptr;               // Gp [RB_MAX^2], d [RB_MAX], c [RB_MAX]
+  double* rb_host = nullptr;              // pinned staging of Gp
   void* V = nullptr;                      // (m+1) basis vectors, double or float
   void* w = nullptr;
   void* z = nullptr;
@@ -329,10 +392,11 @@ void free_workspace(dg_mesh_s* m) {
   if (!w) return;
   void* ptrs[] = {w->un, w->U, w->G, w->B, w->X, w->Rc, w->Rs[0], w->Rs[1], w->Rs[2], w->hist[0], w->hist[1],
                   w->Binv, w->V, w->w, w->z, w->s, w->part, w->dev_small, w->Up, w->lineLo, w->lineDi, w->lineUp,
-                  w->lineP};
+                  w->lineP, w->rbW, w->rbZ, w->rbT, w->rb_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w->host_small) (void)hipHostFree(w->host_small);
+  if (w->rb_host) (void)hipHostFree(w->rb_host);
   delete w;
   m->ws = nullptr;
 }
@@ -437,10 +501,140 @@ static void launch_mdot(int kk, int64_t n, const T* V, int64_t ldv, const T* w, 
   }
 }
 
-// GMRES(m) for (I - c J(U)) x = rhs (rhs = -G, double), x returned in ws->X.
+// ---- reduced basis: the pseudo-inverse of the Gram matrix (cyclic Jacobi, k <= RB_MAX)
+static void rb_pinv(const double* G, int k, double rcond, double* Gp) {
+  double a[RB_MAX][RB_MAX], v[RB_MAX][RB_MAX];
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      a[i][j] = G[i * RB_MAX + j];
+      v[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) off += a[i][j] * a[i][j];
+    if (off == 0) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        if (a[p][q] == 0) continue;
+        const double th = (a[q][q] - a[p][p]) / (2 * a[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+        const double c = 1 / std::sqrt(t * t + 1), sn = t * c;
+        for (int r = 0; r < k; ++r) {   // columns p, q
+          const double ap = a[r][p], aq = a[r][q];
+          a[r][p] = c * ap - sn * aq;
+          a[r][q] = sn * ap + c * aq;
+        }
+        for (int r = 0; r < k; ++r) {   // rows p, q
+          const double ap = a[p][r], aq = a[q][r];
+          a[p][r] = c * ap - sn * aq;
+          a[q][r] = sn * ap + c * aq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vp = v[r][p], vq = v[r][q];
+          v[r][p] = c * vp - sn * vq;
+          v[r][q] = sn * vp + c * vq;
+        }
+      }
+  }
+  double lmax = 0;
+  for (int i = 0; i < k; ++i) lmax = std::max(lmax, a[i][i]);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double g = 0;
+      for (int l = 0; l < k; ++l)
+        if (a[l][l] > rcond * lmax && a[l][l] > 0) g += v[i][l] * v[j][l] / a[l][l];
+      Gp[i * k + j] = g;
+    }
+}
+
+// c = (Z^T Z)^+ Z^T v on the device (rb_dev: Gp, d, c)
+template <class T>
+static void rb_coefficients(dg_mesh_s* m, Workspace* ws, const T* v, hipStream_t s) {
+  const int64_t n = m->n_dof;
+  const int nb = grid_for(n);
+  const int k = ws->rb_count;
+  double* d = ws->rb_dev + RB_MAX * RB_MAX;
+  launch_mdot<T>(k, n, (const T*)ws->rbZ, n, v, ws->part, nb, s);
+  k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
+  k_rb_coef<<<1, 64, 0, s>>>(k, ws->rb_dev, d, d + RB_MAX);
+}
+
+// z = W c(v) + P^-1 (v - Z c(v)); scratch: a free vector of the Krylov precision
+template <class T>
+static dg_status_t precond_rb(dg_mesh_s* m, Workspace* ws, int pc, const T* v, T* z, T* scratch, hipStream_t s) {
+  const int k = ws->rb_count;
+  if (k == 0) return precond(m, ws, pc, v, z, s);
+  const int64_t n = m->n_dof;
+  const int nb = grid_for(n);
+  rb_coefficients<T>(m, ws, v, s);
+  const double* c = ws->rb_dev + RB_MAX * RB_MAX + RB_MAX;
+  const T* Z = (const T*)ws->rbZ;
+  const T* W = (const T*)ws->rbW;
+  if (pc == 0) {
+    k_rb_split<T><<<nb, RED_THREADS, 0, s>>>(n, k, Z, W, c, v, z, z);
+    return DG_OK;
+  }
+  T* x = (T*)ws->rbT;
+  k_rb_split<T><<<nb, RED_THREADS, 0, s>>>(n, k, Z, W, c, v, scratch, x);
+  dg_status_t st = precond(m, ws, pc, scratch, z, s);
+  if (st != DG_OK) return st;
+  k_add_T<T><<<nb, RED_THREADS, 0, s>>>(n, x, z);
+  return DG_OK;
+}
+
+// X = W c(rhs): the GMRES initial guess from the reduced basis
+template <class T>
+static void rb_initial_guess(dg_mesh_s* m, Workspace* ws, const double* rhs, double* X, hipStream_t s) {
+  const int64_t n = m->n_dof;
+  const int nb = grid_for(n);
+  k_copy_cast<T><<<nb, RED_THREADS, 0, s>>>(n, rhs, (T*)ws->rbT);
+  rb_coefficients<T>(m, ws, (const T*)ws->rbT, s);
+  k_rb_guess<T><<<nb, RED_THREADS, 0, s>>>(n, ws->rb_count, (const T*)ws->rbW,
+                                           ws->rb_dev + RB_MAX * RB_MAX + RB_MAX, X);
+}
+
+// the Newton update X joins the window with z = (I - c J(U)) X; the Gram matrix and its
+// pseudo-inverse are updated (synchronises)
+template <class T>
+static dg_status_t rb_push(dg_mesh_s* m, Workspace* ws, int n_rb, double t, double c, const double* U,
+                           const double* X, hipStream_t s) {
+  const int64_t n = m->n_dof;
+  const int nb = grid_for(n);
+  const int slot = ws->rb_head;
+  T* Wd = (T*)ws->rbW + (size_t)slot * n;
+  T* Zd = (T*)ws->rbZ + (size_t)slot * n;
+  k_copy_cast<T><<<nb, RED_THREADS, 0, s>>>(n, X, Wd);
+  dg_status_t st = jvp(m, t, U, Wd, Zd, s);
+  if (st != DG_OK) return st;
+  k_stage_op<T><<<nb, RED_THREADS, 0, s>>>(n, Wd, c, Zd);
+  ws->rb_head = (slot + 1) % n_rb;
+  ws->rb_count = std::min(ws->rb_count + 1, n_rb);
+  const int k = ws->rb_count;
+  double* d = ws->rb_dev + RB_MAX * RB_MAX;
+  launch_mdot<T>(k, n, (const T*)ws->rbZ, n, Zd, ws->part, nb, s);
+  k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
+  DG_HIP_CHECK(hipMemcpyAsync(ws->host_small, d, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  DG_HIP_CHECK(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    if (!std::isfinite(ws->host_small[j])) {
+      set_error("dg_implicit_step: non-finite value in the reduced basis");
+      return DG_ERR_NAN;
+    }
+    ws->rb_G[slot * RB_MAX + j] = ws->rb_G[j * RB_MAX + slot] = ws->host_small[j];
+  }
+  const double rcond = std::is_same<T, float>::value ? 1e-7 : 1e-10;
+  rb_pinv(ws->rb_G, k, rcond, ws->rb_host);
+  DG_HIP_CHECK(hipMemcpyAsync(ws->rb_dev, ws->rb_host, (size_t)k * k * sizeof(double), hipMemcpyHostToDevice, s));
+  return DG_OK;
+}
+
+// GMRES(m) for (I - c J(U)) x = rhs (rhs = -G, double), x returned in ws->X; with x0 set,
+// ws->X holds the initial guess on entry. The preconditioner is P (pc) wrapped by the
+// reduced basis when the window holds vectors.
 template <class T>
 static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const double* U, const double* rhs,
-                         double rhs_norm, int pc, int mk, int max_restarts, double rtol, int* iters,
+                         double rhs_norm, int pc, int mk, int max_restarts, double rtol, bool x0, int* iters,
                          hipStream_t s) {
   const int64_t n = m->n_dof;
   const int nb = grid_for(n);
@@ -454,13 +648,13 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
   double* nr = ws->dev_small + 2 * KMAX;
   double* yv = ws->dev_small + 3 * KMAX;
   double* host = ws->host_small;
-  DG_HIP_CHECK(hipMemsetAsync(X, 0, n * sizeof(double), s));
+  if (!x0) DG_HIP_CHECK(hipMemsetAsync(X, 0, n * sizeof(double), s));
   std::vector<double> H((size_t)(mk + 1) * mk), g(mk + 1), cs(mk), sn(mk), y(mk);
   const double target = rtol * rhs_norm;
   int total = 0;
   for (int cycle = 0; cycle < max_restarts; ++cycle) {
     double beta;
-    if (cycle == 0) {
+    if (cycle == 0 && !x0) {
       beta = rhs_norm;
       k_scale_to<T><<<nb, RED_THREADS, 0, s>>>(n, 1.0 / beta, rhs, V);
     } else {
@@ -487,7 +681,7 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
     bool done = false;
     for (int j = 0; j < mk; ++j) {
       T* vj = V + (size_t)j * n;
-      dg_status_t st = precond(m, ws, pc, vj, z, s);
+      dg_status_t st = precond_rb(m, ws, pc, vj, z, w, s);
       if (st != DG_OK) return st;
       st = jvp(m, t, U, z, w, s);
       if (st != DG_OK) return st;
@@ -541,7 +735,7 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
     for (int i = 0; i < kused; ++i) host[3 * KMAX + i] = y[i];
     DG_HIP_CHECK(hipMemcpyAsync(yv, host + 3 * KMAX, kused * sizeof(double), hipMemcpyHostToDevice, s));
     k_combine<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, kused, yv, sv);
-    dg_status_t st = precond(m, ws, pc, sv, z, s);
+    dg_status_t st = precond_rb(m, ws, pc, sv, z, w, s);
     if (st != DG_OK) return st;
     k_add_to<T><<<nb, RED_THREADS, 0, s>>>(n, z, X);
     if (done) break;
@@ -612,12 +806,38 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
     }
     ws->lineP_prec = prec;
   }
+  if (o.n_rb > ws->rb_cap) {
+    for (void* p : {ws->rbW, ws->rbZ, ws->rbT, (void*)ws->rb_dev})
+      if (p) (void)hipFree(p);
+    if (ws->rb_host) (void)hipHostFree(ws->rb_host);
+    ws->rbW = ws->rbZ = ws->rbT = nullptr;
+    ws->rb_dev = ws->rb_host = nullptr;
+    ws->rb_cap = ws->rb_count = ws->rb_head = 0;
+    const size_t vb = f32 ? sizeof(float) : sizeof(double);
+    const bool ok = hipMalloc(&ws->rbW, (size_t)o.n_rb * n * vb) == hipSuccess &&
+                    hipMalloc(&ws->rbZ, (size_t)o.n_rb * n * vb) == hipSuccess &&
+                    hipMalloc(&ws->rbT, (size_t)n * vb) == hipSuccess &&
+                    hipMalloc(&ws->rb_dev, (RB_MAX * RB_MAX + 2 * RB_MAX) * sizeof(double)) == hipSuccess &&
+                    hipHostMalloc(&ws->rb_host, RB_MAX * RB_MAX * sizeof(double)) == hipSuccess;
+    if (!ok) {
+      set_error("dg_implicit_step: allocation of the reduced basis failed");
+      return DG_ERR_ALLOC;
+    }
+    ws->rb_cap = o.n_rb;
+  }
   double A[3][3], c[3];
   int ns;
   dirk_tableau(o.scheme, A, c, ns);
   dg_step_stats_t stats{};
   // a step that does not continue the previous one starts a new guess history
   if (!(std::fabs(ws->t_end - t) <= 1e-12 * std::max(1.0, std::fabs(t)))) ws->hist_n = 0;
+  // the reduced basis lives as long as the stage operator's dt a_ii, the window size and
+  // the history do
+  if (o.n_rb == 0 || ws->hist_n == 0 || ws->rb_dta != dt * A[0][0] || ws->rb_n != o.n_rb) {
+    ws->rb_count = ws->rb_head = 0;
+    ws->rb_dta = dt * A[0][0];
+    ws->rb_n = o.n_rb;
+  }
   DG_HIP_CHECK(hipMemcpyAsync(ws->un, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // radial-line preconditioner: built at (t + c_1 dt, u_n) and kept for line_pc_every steps;
   // a_ii is the same for every stage of the singly-diagonal schemes
@@ -744,7 +964,10 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
         rtol = std::max(eta, 0.5 * o.newton_rtol * ref / nG);
         rtol = std::min(rtol, 0.1);
       }
-      rc = gmres<T>(m, ws, ti, ca, ws->U, ws->G, nG, pc, o.gmres_m, o.max_restarts, rtol, &its, s);
+      const bool x0 = o.n_rb > 0 && ws->rb_count > 0;
+      if (x0) rb_initial_guess<T>(m, ws, ws->G, ws->X, s);
+      rc = gmres<T>(m, ws, ti, ca, ws->U, ws->G, nG, pc, o.gmres_m, o.max_restarts, rtol, x0, &its, s);
+      if (rc == DG_OK && o.n_rb > 0) rc = rb_push<T>(m, ws, o.n_rb, ti, ca, ws->U, ws->X, s);
       if (rc != DG_OK) {
         (void)hipMemcpyAsync(u, ws->un, n * sizeof(double), hipMemcpyDeviceToDevice, s);
         return rc;

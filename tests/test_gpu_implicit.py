@@ -214,3 +214,48 @@ def test_line_solve_configs_are_bitwise_identical(fprec):
             its.append(st["gmres_its"])
         for o, i in zip(outs[1:], its[1:]):
             assert np.array_equal(o, outs[0]) and i == its[0], (p, its)
+
+
+@pytest.mark.parametrize("precond,prec", [(0, "f64"), (2, "f64"), (2, "f32")])
+def test_reduced_basis_steps_match_oracle(precond, prec):
+    """the reduced-basis GMRES guess and preconditioner (window of 3 updates) change the
+    GMRES path, not the converged steps: two steps against the oracle's JFNK steps"""
+    need_gpu()
+    w = synth.shell_workload(10, p=2, n_ang=1, n_rad=2)
+    om, gm = shell_pair(w, 1, 2, 2)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    dt = synth.seconds_to_nondim(10.0)
+    ref = u
+    for k in range(2):
+        ref, _ = timeint.implicit_step_jfnk(om, w.phys, ref, k * dt, dt, scheme=33, rtol=1e-12)
+    ut = to_dev(u)
+    for k in range(2):
+        st = gm.implicit_step(ut, k * dt, dt, newton_rtol=1e-10, gmres_rtol=1e-6, jvp_prec=prec, precond=precond,
+                              n_rb=3)
+    out = ut.cpu().numpy().reshape(u.shape)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref - u) < 1e-6, st
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_reduced_basis_on_the_stretched_shell(prec):
+    """three steps with and without the reduced basis agree; the window persists across
+    steps (iteration counts are printed for the record)"""
+    need_gpu()
+    from paper_2306_01085_amd import Mesh
+    w = synth.shell_workload(7, p=3, n_ang=2, n_rad=8)
+    om = omesh.shell_mesh(3, 2, 8, w.r_bot, w.r_top, w.stretch)
+    u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    dt = synth.seconds_to_nondim(10.0)
+    outs, its = [], []
+    for n_rb in (0, 4):
+        gm = Mesh.shell(p=3, n_ang=2, n_rad=8, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch, phys=w.phys)
+        ut = to_dev(u)
+        tot = 0
+        for k in range(3):
+            st = gm.implicit_step(ut, k * dt, dt, newton_rtol=1e-10, jvp_prec=prec, precond=2, max_restarts=60,
+                                  max_newton=20, n_rb=n_rb)
+            tot += sum(st["gmres_its"])
+        outs.append(ut.cpu().numpy())
+        its.append(tot)
+    print("GMRES iterations without / with the reduced basis:", its)
+    assert np.linalg.norm(outs[1] - outs[0]) / np.linalg.norm(outs[0] - u.ravel()) < 1e-6
