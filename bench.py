@@ -175,22 +175,24 @@ def implicit_steps(w, mesh, u, n_steps, only=None):
     GMRES(30) right-preconditioned by the radial-line block-Jacobi preconditioner,
     (rebuilt every LINE_PC_EVERY steps, bf16 factors), Eisenstat-Walker GMRES tolerances,
     plain extrapolated guess: FP64 vs FP32 vs BF16 J v; plus the FP32 run without a
-    preconditioner for comparison"""
+    preconditioner and the FP32 run with the reduced basis of the 4 latest Newton updates
+    on top of the line preconditioner"""
     import torch
 
     from paper_2306_01085_amd import DgError
     res = {"dt_s": 60.0, "newton_rtol": 1e-8,
            "gmres": "GMRES(30), CGS2, radial-line block-Jacobi preconditioner, Eisenstat-Walker tolerances",
            "steps": n_steps, "filter_rate": FILTER_RATE}
-    runs = [(prec, 2, prec) for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ())]
-    runs.append(("f32_no_precond", 0, "f32"))
+    runs = [(prec, 2, prec, 0) for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ())]
+    runs.append(("f32_rb4", 2, "f32", 4))   # plus the reduced basis of the 4 latest Newton updates
+    runs.append(("f32_no_precond", 0, "f32", 0))
     if only:
         runs = [r for r in runs if r[0] in only]
     mesh.set_option("line_pc_every", LINE_PC_EVERY)
     mesh.set_option("line_pc_precision", LINE_PC_PRECISION)
     res["line_pc_every"] = LINE_PC_EVERY
     res["line_pc_precision"] = LINE_PC_PRECISION
-    for key, pc, prec in runs:
+    for key, pc, prec, n_rb in runs:
         x = u.clone()
         t = 0.0
         secs, newton, gmres = [], [], []
@@ -198,7 +200,7 @@ def implicit_steps(w, mesh, u, n_steps, only=None):
         for _ in range(n_steps):
             try:
                 st = mesh.implicit_step(x, t, w.dt, jvp_prec=prec, precond=pc, max_newton=15, max_restarts=40,
-                                        filter_rate=FILTER_RATE, forcing=1)
+                                        filter_rate=FILTER_RATE, forcing=1, n_rb=n_rb)
             except DgError as ex:
                 failed = str(ex)
                 log("  implicit step (%s) failed: %s" % (key, failed))
@@ -332,7 +334,7 @@ def main():
                     help="also run one plain device copy of known size (calibrates HBM counters)")
     ap.add_argument("--only", default="all", choices=["all", "residual", "implicit"],
                     help="residual: only the R(u) timing; implicit: only the implicit steps (for counter runs)")
-    ap.add_argument("--implicit-runs", default="f64,f32,bf16,f32_no_precond",
+    ap.add_argument("--implicit-runs", default="f64,f32,bf16,f32_rb4,f32_no_precond",
                     help="which implicit-step runs (with --only implicit)")
     ap.add_argument("--mode", default="default", choices=["default", "warmstart"])
     ap.add_argument("--implicit-steps", type=int, default=4)

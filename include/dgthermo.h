@@ -272,7 +272,8 @@ dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_hos
  *   default -1: 4 for FP64 Krylov vectors, 3 for FP32). No effect on results.
  *   "line_pc_every" >= 1 (default 1): dg_implicit_step with precond 2 rebuilds the
  *   radial-line preconditioner from the current state only every this many steps (and
- *   whenever dt a_ii or the J v precision changes), reusing it in between. It changes the
+ *   whenever dt a_ii or the J v precision changes or a step does not start where the
+ *   previous one ended), reusing it in between. It changes the
  *   GMRES iteration counts, not what Newton converges to (within newton_rtol).
  *   "line_pc_precision" 64, 32 (default) or 16: storage precision of the radial-line
  *   preconditioner's factors (double, float, bfloat16) read by its substitution, whatever

@@ -830,7 +830,10 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
   dirk_tableau(o.scheme, A, c, ns);
   dg_step_stats_t stats{};
   // a step that does not continue the previous one starts a new guess history
-  if (!(std::fabs(ws->t_end - t) <= 1e-12 * std::max(1.0, std::fabs(t)))) ws->hist_n = 0;
+  if (!(std::fabs(ws->t_end - t) <= 1e-12 * std::max(1.0, std::fabs(t)))) {
+    ws->hist_n = 0;
+    ws->line_age = -1;   // and a new radial-line preconditioner
+  }
   // the reduced basis lives as long as the stage operator's dt a_ii, the window size and
   // the history do
   if (o.n_rb == 0 || ws->hist_n == 0 || ws->rb_dta != dt * A[0][0] || ws->rb_n != o.n_rb) {
