@@ -156,7 +156,11 @@ def source(u, q, x, t, P, xp):
         eg = sum(eps[i][k] * gl[k] for k in range(d))
         S.append(acc[i] + 0.5 * div * U[i] - 0.5 * C["inv_gm"] * Th * gl[i]
                  + 0.5 * C["c_visc"] * mu * s * eg)
-    Q = heating(x, t, P, xp)
+    if P.get("heating_model", 0) == 1:
+        from . import euvac
+        Q = euvac.heating(x, t, rho, T, P)
+    else:
+        Q = heating(x, t, P, xp)
     Tg = sum(gT[k] * gl[k] for k in range(d))
     ed = sum(eps[i][k] * gv[i][k] for i in range(d) for k in range(d))
     S.append(Q * s * m + (1.5 - g) * Th * div + 0.5 * C["c_cond"] * kap * s * m * Tg

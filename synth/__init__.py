@@ -72,7 +72,18 @@ def base_physics(d: int) -> dict:
         heat_amp=0.0, heat_qm=0.0, heat_rm=R_BOT, heat_H=1.0,
         sun_lat=0.0, sun_lon0=0.0, sun_rate=FR / math.sqrt(GAMMA),
         bc_mode=0, bc_state=[0.0] * 5,
+        heating_model=0,
     )
+
+
+# EUVAC heating inputs (section 2.2): efficiency, F10.7bar, distance to the Sun (AU), the
+# day of the year (0: keep sun_lat), constant mole fractions of N2, O2, O, He (synthetic:
+# the composition fits are not available), and the two dimensional scales that turn
+# number columns and heating rates into the model's units
+def euvac_physics(f107bar: float = 150.0, day: float = 0.0) -> dict:
+    return dict(euv_eps=0.25, euv_f107=f107bar, euv_sun_dist=1.0, euv_day=day,
+                euv_chi=[0.15, 0.01, 0.80, 0.04],
+                euv_q_scale=RHO_REF / (M_O * Q_UNIT), euv_col_scale=RHO_REF * H0 / M_O)
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,78 @@
+"""Pins of the oracle's EUVAC heating (section 2.2, Table A): the table's total energy
+flux, the declination at solstices and equinoxes, the Smith-Smith Chapman function
+against direct quadrature of the slant column of an exponential atmosphere (day and
+night side), its continuity at the terminator, and energy conservation: a column
+absorbs, integrated over height, exactly the flux that its optical depth removes."""
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+import synth
+from oracle import euvac
+
+
+def test_table_total_energy_flux():
+    """sum_j I_0^j hc/lambda_j at F10.7bar = 150 is 4.89 mW/m^2 (1.223 mW/m^2 with the
+    efficiency 0.25 of section 4), the column heating the prescribed profile is scaled to"""
+    tot = float(np.sum(euvac.photon_flux(150.0) * euvac.photon_energy()))
+    assert abs(tot - 4.89e-3) < 0.005e-3
+    assert abs(0.25 * tot - synth.Q_COLUMN) < 0.001e-3
+    assert len(euvac.TABLE_A) == 37
+
+
+@pytest.mark.parametrize("day,lo,hi", [(172, 23.3, 23.5), (355, -23.5, -23.3), (80, -1.0, 1.0), (266, -1.0, 1.0)])
+def test_declination(day, lo, hi):
+    assert lo < np.rad2deg(euvac.declination(day)) < hi
+
+
+def _chapman_quadrature(x, chi):
+    """int_0^inf exp(x - |r + s sun|) ds in scale heights (|r| = x), straight path"""
+    c = np.cos(chi)
+    f = lambda s: np.exp(x - np.sqrt(x * x + s * s + 2.0 * x * s * c))
+    return quad(f, 0.0, np.inf, limit=400, epsabs=0, epsrel=1e-11)[0]
+
+
+@pytest.mark.parametrize("x", [300.0, 1000.0])
+@pytest.mark.parametrize("chi_deg", [0.0, 30.0, 60.0, 80.0, 89.0, 92.0, 95.0, 97.0])
+def test_chapman_function_against_quadrature(x, chi_deg):
+    """the approximation's error is -1/r~ on the day side (the curvature term it drops);
+    on the night side the grazing term's sqrt(r~ sin chi) taken as sqrt(r~) adds a
+    growing error, 0.3% at 97 degrees for r~ = 1000"""
+    chi = np.deg2rad(chi_deg)
+    C = euvac.chapman(x, np.cos(chi), 10.0)   # |r| / R0 = 10: the path never meets the ground
+    ref = _chapman_quadrature(x, chi)
+    tol = (1.2 if chi_deg <= 90 else 4.0) / x
+    assert abs(C / ref - 1.0) < tol, (C, ref)
+
+
+def test_shadow_and_terminator():
+    x = 800.0
+    eps = 1e-9
+    assert abs(euvac.chapman(x, eps, 1.05) / euvac.chapman(x, -eps, 1.05) - 1) < 1e-6
+    # |sin chi| <= R0/|r|: the straight path to the Sun meets the ground
+    assert np.isinf(euvac.chapman(x, -0.9, 1.05))
+
+
+def test_column_absorbs_what_the_optical_depth_removes():
+    """overhead Sun, exponential column with a constant scale height H (T r^2 constant):
+    int Q dr = (q_scale / col_scale) eps sum_j (hc/lambda_j) I_0^j (1 - exp(-tau_j)) with
+    tau_j the vertical optical depth at the bottom, up to the Chapman function's
+    curvature terms O(1/r~)"""
+    P = synth.base_physics(1)
+    P.update(synth.euvac_physics())
+    P["heating_model"] = 1
+    H = 0.7
+    rb = P["r_ref"]
+    r = rb + np.linspace(0.0, 60.0 * H, 200001)
+    rho_b = 2.0
+    rho = rho_b * np.exp(-(r - rb) / H)
+    T = H * P["m"] * P["r_ref"] ** 2 / r ** 2
+    Q = euvac.heating([r], 0.0, rho, T, P)
+    got = np.trapezoid(Q, r)
+    K, kap = euvac.bin_constants(P)
+    sig = euvac.mixture_cross_section(P["euv_chi"])
+    tau_b = kap * rho_b * H
+    flux = P["euv_eps"] * euvac.photon_energy() * euvac.photon_flux(P["euv_f107"], P["euv_sun_dist"])
+    want = P["euv_q_scale"] / P["euv_col_scale"] * np.sum(flux * (1.0 - np.exp(-tau_b)))
+    assert sig.shape == (37,)
+    assert abs(got / want - 1.0) < 3e-3, (got, want)
