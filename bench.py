@@ -434,6 +434,20 @@ def main():
         f_j64()
     prof.update(mesh.profile_read())
     mesh.profile(False)
+    # the same products with the EUVAC heating (37 bins, Chapman optical depth) in place of
+    # the prescribed profile: a state-dependent source evaluated at every node
+    phys_e = dict(w.phys)
+    phys_e.update(synth.euvac_physics(f107bar=150.0, day=80.0))
+    phys_e["heating_model"] = 1
+    phys_e["heat_amp"] = 0.0
+    mesh.set_physics(phys_e)
+    for _ in range(args.warmup):
+        f_r(); f_j64(); f_j32()
+    euv = {"residual_gdofs": w.n_dof / timed(f_r, args.steps) / 1e6,
+           "jvp_f64_gdofs": w.n_dof / timed(f_j64, args.steps) / 1e6,
+           "jvp_f32_gdofs": w.n_dof / timed(f_j32, args.steps) / 1e6,
+           "heating": "EUVAC, F10.7bar 150, day 80, efficiency 0.25"}
+    mesh.set_physics(w.phys)
     if args.copy_probe:
         copy_probe(dev)
     ndof = w.n_dof
@@ -473,6 +487,7 @@ def main():
         "finite": ok,
     }
     log("implicit steps")
+    out["euvac"] = euv
     out["implicit_step"] = implicit_steps(w, mesh, u, args.implicit_steps)
     del r, jv, jv32, v, v32
     log("column batch")

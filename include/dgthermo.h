@@ -91,6 +91,21 @@ typedef struct {
   const double* col_heat_rm;
   const double* col_heat_H;
   const double* col_lam;
+  /* heating model: 0 the prescribed Chapman-shaped profile above (heat_*); 1 EUVAC (section 2.2,
+     Table A): Q = eps sum_j (hc/lambda_j) I_0^j e^{-tau_j} sum_s n_s phi_s^j over the 37 bins, I_0^j the
+     EUVAC flux at F10.7bar, tau_j the total optical depth n sigma_j H C with the Smith-Smith Chapman
+     function C of the exponential atmosphere (scale height H = k T / (m g)), zero in the Earth's
+     shadow; the composition is the constant mole fractions euv_chi, n = rho / m. State-dependent: it
+     enters R and J v. The shell takes the zenith angle from the sub-solar point (latitude: the
+     declination of day euv_day when euv_day > 0, else sun_lat), columns take cos chi = 1. */
+  int32_t heating_model;
+  double euv_eps;          /* heating efficiency (0.25) */
+  double euv_f107;         /* F10.7bar = (F10.7 + its 81-day mean) / 2 */
+  double euv_sun_dist;     /* distance to the Sun (AU) */
+  double euv_day;          /* day of the year (1 = January 1st), or 0 */
+  double euv_chi[4];       /* mole fractions of N2, O2, O, He */
+  double euv_q_scale;      /* rho0 / (m_O Q_unit): m^-3 per W m^-3 of the model's heating unit */
+  double euv_col_scale;    /* rho0 H0 / m_O: m^-2 per unit nondimensional density x length */
 } dg_physics_t;
 
 /* Create a mesh: builds GLL tables, the factored curved geometry (invariant curl
@@ -99,7 +114,8 @@ typedef struct {
  * mesh goes to the stream passed to each call. */
 dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys, void* stream, dg_mesh_t* out);
 dg_status_t dg_mesh_destroy(dg_mesh_t mesh);
-/* Replace the physics parameters (host struct, copied). */
+/* Replace the physics parameters (host struct, copied). With heating_model 1 it waits for the
+ * device to be idle, then uploads the EUVAC bin constants to the mesh's table. */
 dg_status_t dg_mesh_set_physics(dg_mesh_t mesh, const dg_physics_t* phys);
 
 /* Sizes: total DOF, elements, fields per node, dimension. Any output may be NULL. */

@@ -46,7 +46,10 @@ class Physics(C.Structure):
                 ("bc_mode", C.c_int32), ("bc_state", C.c_double * 5),
                 ("col_heat_amp", C.POINTER(C.c_double)), ("col_heat_qm", C.POINTER(C.c_double)),
                 ("col_heat_rm", C.POINTER(C.c_double)), ("col_heat_H", C.POINTER(C.c_double)),
-                ("col_lam", C.POINTER(C.c_double))]
+                ("col_lam", C.POINTER(C.c_double)),
+                ("heating_model", C.c_int32), ("euv_eps", C.c_double), ("euv_f107", C.c_double),
+                ("euv_sun_dist", C.c_double), ("euv_day", C.c_double), ("euv_chi", C.c_double * 4),
+                ("euv_q_scale", C.c_double), ("euv_col_scale", C.c_double)]
 
 
 class SolverOpts(C.Structure):
@@ -137,6 +140,11 @@ def make_physics(phys: dict, col_phys: dict | None = None):
     P.bc_mode = int(phys.get("bc_mode", 0))
     bs = list(phys.get("bc_state", [0.0] * 5)) + [0.0] * 5
     P.bc_state = (C.c_double * 5)(*[float(x) for x in bs[:5]])
+    P.heating_model = int(phys.get("heating_model", 0))
+    if P.heating_model == 1:
+        for k in ("euv_eps", "euv_f107", "euv_sun_dist", "euv_day", "euv_q_scale", "euv_col_scale"):
+            setattr(P, k, float(phys[k]))
+        P.euv_chi = (C.c_double * 4)(*[float(x) for x in phys["euv_chi"]])
     keep = []
     if col_phys:
         for key, field in (("heat_amp", "col_heat_amp"), ("heat_qm", "col_heat_qm"), ("heat_rm", "col_heat_rm"),

@@ -41,20 +41,45 @@ void fill_phys(PhysC& P, const dg_physics_t& in) {
   P.sun_lat = in.sun_lat;
   P.sun_lon0 = in.sun_lon0;
   P.sun_rate = in.sun_rate;
+  P.euv = in.heating_model == 1 ? 1 : 0;
+  P.euv_tab = nullptr;
+  P.r_ref = in.r_ref;
+  P.euv_hfac = 1.0 / (in.m * in.r_ref * in.r_ref);
+  if (P.euv && in.euv_day > 0) P.sun_lat = euvac_declination(in.euv_day);
   P.bc_mode = in.bc_mode;
   for (int c = 0; c < 5; ++c) P.bc_state[c] = in.bc_state[c];
 }
 
+// the physics of a mesh, with the EUVAC bin constants in a mesh-owned device table
+static dg_status_t set_phys(dg_mesh_s* m, const dg_physics_t& in) {
+  fill_phys(m->phys, in);
+  if (!m->phys.euv) return DG_OK;
+  double tab[74];
+  euvac_constants(in, tab, tab + 37);
+  if (!m->d_euv && hipMalloc(&m->d_euv, sizeof(tab)) != hipSuccess) {
+    set_error("dg_mesh: device allocation of the EUVAC table failed");
+    return DG_ERR_ALLOC;
+  }
+  DG_HIP_CHECK(hipDeviceSynchronize());
+  DG_HIP_CHECK(hipMemcpy(m->d_euv, tab, sizeof(tab), hipMemcpyHostToDevice));
+  m->phys.euv_tab = m->d_euv;
+  return DG_OK;
+}
+
 static bool phys_ok(const dg_physics_t& p) {
+  const bool euv_ok = p.heating_model == 0 ||
+                      (p.heating_model == 1 && p.euv_eps >= 0 && p.euv_sun_dist > 0 && p.euv_q_scale > 0 &&
+                       p.euv_col_scale > 0 && p.euv_chi[0] >= 0 && p.euv_chi[1] >= 0 && p.euv_chi[2] >= 0 &&
+                       p.euv_chi[3] >= 0 && std::isfinite(p.euv_f107) && p.r_ref > 0);
   return p.gamma > 1.0 && p.Gr > 0 && p.Pr > 0 && p.m > 0 && p.heat_H > 0 && std::isfinite(p.lam) &&
-         (p.bc_mode == 0 || p.bc_mode == 1);
+         (p.bc_mode == 0 || p.bc_mode == 1) && euv_ok;
 }
 
 static void free_mesh(dg_mesh_s* m) {
   void* ptrs[] = {m->d_ang,  m->d_edges,  m->d_cnbr,  m->d_cface,     m->d_cmap,      m->d_off,
                   m->d_prev, m->d_next,   m->d_geo,   m->d_col,       m->d_cpar,      m->d_fn64,
                   m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2], m->d_bstate, m->d_coloff,
-                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op};
+                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op, m->d_euv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   free_workspace(m);
@@ -166,7 +191,11 @@ dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys,
     free_mesh(m);
     return st;
   }
-  fill_phys(m->phys, *phys);
+  st = set_phys(m, *phys);
+  if (st != DG_OK) {
+    free_mesh(m);
+    return st;
+  }
   hipError_t e1 = hipMalloc(&m->d_fn64, m->fn_len * sizeof(double));
   hipError_t e2 = hipMalloc(&m->d_fn32, m->fn_len * sizeof(float));
   if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -205,7 +234,8 @@ dg_status_t dg_mesh_set_physics(dg_mesh_t m, const dg_physics_t* phys) {
     set_error("dg_mesh_set_physics: invalid argument");
     return DG_ERR_ARG;
   }
-  fill_phys(m->phys, *phys);
+  const dg_status_t st = set_phys(m, *phys);
+  if (st != DG_OK) return st;
   if (m->kind == DG_MESH_COLUMNS) {
     std::vector<double> cpar(5 * m->n_col);
     for (int c = 0; c < m->n_col; ++c) {

@@ -35,7 +35,8 @@ struct ColElem {
   int64_t fslot, fslot_prev, fslot_next;   // Fn[(fslot*2 + side)*3 + c]
 };
 
-template <int P, class S, class SU, class TV, class OT>
+// EUV: the instantiation contains the EUVAC heating (used when the mesh's heating model is 1)
+template <int P, class S, bool EUV = false, class SU, class TV, class OT>
 __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& Pc, const GllC& gc, double t,
                                       const SU* __restrict__ u, const TV* __restrict__ v, OT* __restrict__ R,
                                       OT* __restrict__ Fn) {
@@ -91,7 +92,7 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
     }
     const double x = r0 + 0.5 * (xg[i] + 1.0) * h;
     const double Q = heating<1>(Pc, &x, t);
-    flux_source<1, S>(Pc, ui, qi, &x, Q, Fi, Si);
+    flux_source<1, S, EUV>(Pc, ui, qi, &x, Q, Fi, Si);
     for (int c = 0; c < 3; ++c) {
       Rl[c][i] = Rl[c][i] + Si[c];
       for (int r = 0; r < n; ++r) Rl[c][r] = Rl[c][r] - Fi[c][0] * T(D[r * n + i] * invJ);
@@ -111,7 +112,7 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
     for (int c = 0; c < 3; ++c) u0[c] = uu[c][0];
     boundary_state<1, S>(Pc, u0, ub);
     const double x = r0;
-    flux_source<1, S>(Pc, ub, qlo, &x, 0.0, Fb, Sb);
+    flux_source<1, S>(Pc, ub, qlo, &x, 0.0, Fb, Sb, false);
     sigma<1, S>(Pc, ub, sm, se);
     for (int c = 0; c < 3; ++c) {
       const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
@@ -133,7 +134,7 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
       S ub[3], Fb[3][1], Sb[3], sm, se;
       boundary_state<1, S>(Pc, ut, ub);
       const double x = r0 + h;
-      flux_source<1, S>(Pc, ub, qhi, &x, 0.0, Fb, Sb);
+      flux_source<1, S>(Pc, ub, qhi, &x, 0.0, Fb, Sb, false);
       sigma<1, S>(Pc, ub, sm, se);
       for (int c = 0; c < 3; ++c) {
         const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
@@ -197,14 +198,14 @@ __device__ inline ColElem col_elem_of(const ColDev& C, int e) {
   return ce;
 }
 
-template <int P, class S, class SU, class TV, class OT>
+template <int P, class S, class SU, class TV, class OT, bool EUV = false>
 __global__ __launch_bounds__(128) void col_pass1(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
                                                  double t, const SU* __restrict__ u, const TV* __restrict__ v,
                                                  OT* __restrict__ R, OT* __restrict__ Fn) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ne) return;
   const int e = elist[idx];
-  col_elem_pass1<P, S>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, t, u, v, R, Fn);
+  col_elem_pass1<P, S, EUV>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, t, u, v, R, Fn);
 }
 
 template <int P, class S, class SU, class TV, class OT>
@@ -230,11 +231,17 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
     if (!ne) continue;
     const int blocks = (ne + 127) / 128;
     const int* el = m->d_plist[pi];
+#define DG_COL_P1(P_, G_)                                                                                  \
+  if (ph.euv)                                                                                             \
+    col_pass1<P_, S, SU, TV, OT, true><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn);        \
+  else                                                                                                    \
+    col_pass1<P_, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn);
     switch (pi + 2) {
-      case 2: col_pass1<2, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[0], t, u, v, out, fn); break;
-      case 3: col_pass1<3, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[1], t, u, v, out, fn); break;
-      default: col_pass1<4, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[2], t, u, v, out, fn); break;
+      case 2: DG_COL_P1(2, gc[0]); break;
+      case 3: DG_COL_P1(3, gc[1]); break;
+      default: DG_COL_P1(4, gc[2]); break;
     }
+#undef DG_COL_P1
   }
   for (int pi = 0; pi < 3; ++pi) {
     const int ne = m->plist_n[pi];
@@ -345,7 +352,7 @@ __device__ inline double wave_allsum(double x) {
   return x;
 }
 
-template <int P, class S, class TV, class OT>
+template <int P, class S, class TV, class OT, bool EUV>
 __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                               const double* u, const TV* v, OT* out, OT* fn) {
   constexpr int b = 3 * (P + 1);
@@ -360,7 +367,7 @@ __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, 
     ce.fslot = el;
     ce.fslot_prev = el - 1;
     ce.fslot_next = el + 1;
-    col_elem_pass1<P, S>(ce, Pc, gc, t, u, v, out, fn);
+    col_elem_pass1<P, S, EUV>(ce, Pc, gc, t, u, v, out, fn);
   }
   __syncthreads();
   for (int el = lane; el < E; el += 64) {
@@ -435,7 +442,7 @@ __device__ __forceinline__ void colw_invert(double* blk, double (*M)[2 * b], dou
   __syncthreads();
 }
 
-template <int P>
+template <int P, bool EUV>
 __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                                       double ca, const double* U, double* V, double* Jv, double* fnT, double* Lo,
                                       double* Di, double* Up) {
@@ -451,7 +458,7 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
     for (int l = 0; l < b; ++l) {
       for (int i = lane; i < nd; i += 64) V[i] = (((i / b) % 3 == kap) && (i % b == l)) ? 1.0 : 0.0;
       __syncthreads();
-      colw_residual<P, Dual<double>, double, double>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
+      colw_residual<P, Dual<double>, double, double, EUV>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
       for (int idx = lane; idx < E * b; idx += 64) {
         const int ep = idx / b, r = idx % b;
         for (int d = -1; d <= 1; ++d) {
@@ -534,7 +541,7 @@ __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double
   }
 }
 
-template <int P>
+template <int P, bool EUV>
 __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC& ph, const GllC& gc) {
   constexpr int n = P + 1;
   constexpr int b = 3 * n;
@@ -576,7 +583,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   for (int step = 0; step < B.n_steps && status == 0; ++step) {
     const double t = B.t0 + step * B.dt;
     // chord Jacobian at the start of the step
-    colw_build_and_factor<P>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
+    colw_build_and_factor<P, EUV>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
     ++builds;
     for (int i = lane; i < nd; i += 64) U[i] = un[i];
     __syncthreads();
@@ -588,11 +595,11 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
         Bv[i] = bv;
       }
       __syncthreads();
-      colw_residual<P, double, double, double>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
+      colw_residual<P, double, double, double, EUV>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
       const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, G));
       int it = 0, since_build = 0;
       for (;;) {
-        colw_residual<P, double, double, double>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
+        colw_residual<P, double, double, double, EUV>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
         const double nG = sqrt(colw_stage_residual(nd, U, Rc, ca, Bv, G));
         if (!isfinite(nG)) {
           status = 5;
@@ -604,7 +611,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
           break;
         }
         if (since_build >= 6) {
-          colw_build_and_factor<P>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
+          colw_build_and_factor<P, EUV>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
           ++builds;
           since_build = 0;
         }
@@ -650,6 +657,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
 
 }  // namespace
 
+template <bool EUV>
 __global__ __launch_bounds__(64) void k_columns_persistent(ColBatch B, PhysC ph, GllC g2, GllC g3, GllC g4) {
   __shared__ int s_k;
   for (;;) {
@@ -660,9 +668,9 @@ __global__ __launch_bounds__(64) void k_columns_persistent(ColBatch B, PhysC ph,
     if (k >= B.n_col) break;
     const int col = B.order[k];
     switch (B.col_p[col]) {
-      case 2: colw_run<2>(B, col, ph, g2); break;
-      case 3: colw_run<3>(B, col, ph, g3); break;
-      default: colw_run<4>(B, col, ph, g4); break;
+      case 2: colw_run<2, EUV>(B, col, ph, g2); break;
+      case 3: colw_run<3, EUV>(B, col, ph, g3); break;
+      default: colw_run<4, EUV>(B, col, ph, g4); break;
     }
   }
 }
@@ -764,7 +772,10 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   sun_direction(ph, t0);
   {
     ProfScope ps(m, 13, s);
-    k_columns_persistent<<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+    if (ph.euv)
+      k_columns_persistent<true><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+    else
+      k_columns_persistent<false><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
   }
   DG_HIP_CHECK(hipGetLastError());
   DG_HIP_CHECK(hipStreamSynchronize(s));

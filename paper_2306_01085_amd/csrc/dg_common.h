@@ -58,6 +58,13 @@ __device__ inline float xsqrt(float a) { return sqrtf(a); }
 template <class T> __device__ inline Dual<T> xexp(Dual<T> a) { T e = xexp(a.v); return {e, e * a.d}; }
 template <class T> __device__ inline Dual<T> xlog(Dual<T> a) { return {xlog(a.v), a.d / a.v}; }
 template <class T> __device__ inline Dual<T> xsqrt(Dual<T> a) { T s = xsqrt(a.v); return {s, a.d * (T(0.5) / s)}; }
+__device__ inline double xerfcx(double a) { return erfcx(a); }
+__device__ inline float xerfcx(float a) { return erfcxf(a); }
+// d/dy erfcx(y) = 2 y erfcx(y) - 2 / sqrt(pi)
+template <class T> __device__ inline Dual<T> xerfcx(Dual<T> a) {
+  const T e = xerfcx(a.v);
+  return {e, (T(2) * a.v * e - T(1.1283791670955126)) * a.d};
+}
 // x^c for x > 0
 __device__ inline double xpow(double a, double c) { return exp(c * log(a)); }
 __device__ inline float xpow(float a, float c) { return expf(c * logf(a)); }
@@ -96,14 +103,57 @@ struct PhysC {
   double sun_dir[3];                 // sub-solar unit vector at the evaluation time (set per launch)
   int bc_mode;
   double bc_state[5];
+  int euv;                           // 1: EUVAC heating (state dependent)
+  const double* euv_tab;             // device [K_0..K_36, kap_0..kap_36]: Q = rho sum_j K_j exp(-kap_j rho H C)
+  double euv_hfac, r_ref;            // H = T r^2 euv_hfac; the lower-boundary radius R0
 };
 
 // ---------------------------------------------------------------- pointwise physics
+// EUVAC heating (section 2.2) at position x for density rho and temperature Tm
+// (nondimensional): Q = rho sum_j K_j exp(-kap_j rho H C), H = Tm r^2 hfac the scale
+// height, C the Smith-Smith Chapman factor of r~ = r / H and the zenith angle (cos chi = 1 in
+// 1D), zero in the Earth's shadow (R0 = r_ref). tab = [K_j, kap_j]. Terms whose optical
+// depth exceeds what the type's exp resolves are dropped (their flux is below 1e-30 of the
+// unattenuated one). Only the kernels instantiated with EUV (flux_source) contain it: the
+// element passes without it keep their register budget.
+template <int D, class S>
+__device__ inline S heating_euvac(const double* __restrict__ tab, double hfac, double r_ref,
+                                                     double s0, double s1, double s2, double x0, double x1,
+                                                     double x2, S rho, S Tm) {
+  typedef typename Base<S>::type T;
+  constexpr T kTauMax = sizeof(T) == 8 ? T(700) : T(80);
+  const double r2 = x0 * x0 + x1 * x1 + x2 * x2;
+  const double r = sqrt(r2);
+  const double cchi = D == 3 ? (x0 * s0 + x1 * s1 + x2 * s2) / r : 1.0;
+  const double schi = sqrt(fmax(0.0, 1.0 - cchi * cchi));
+  const bool day = cchi > 0.0;
+  if (!day && !(schi > r_ref / r)) return S(T(0));
+  const S H = Tm * T(r2 * hfac);
+  const S rt = T(r) / H;
+  const S ex = xerfcx(xsqrt(T(0.5) * rt) * T(fabs(cchi)));
+  const S base = xsqrt(T(1.5707963267948966) * rt);
+  S C;
+  if (day) {
+    C = base * ex;
+  } else {
+    const S arg = rt * T(1.0 - schi);
+    if (!(val(arg) < kTauMax)) return S(T(0));
+    C = base * (T(2) * xexp(arg) - ex);
+  }
+  const S col = rho * H * C;
+  S Q = S(T(0));
+  for (int j = 0; j < 37; ++j) {
+    const S tau = T(tab[37 + j]) * col;
+    if (val(tau) < kTauMax) Q = Q + T(tab[j]) * xexp(-tau);
+  }
+  return rho * Q;
+}
+
 // Flux F[c][k] and source Sr[c] at one node of a D-dimensional problem (f = D + 2
 // fields: varrho, sqrt(rho) v, sqrt(rho) T). x: node position; Q: heating rate there.
-template <int D, class S>
+template <int D, class S, bool EUV = false>
 __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], const double* x, double Q,
-                                   S (*F)[D], S* Sr) {
+                                   S (*F)[D], S* Sr, bool heat = true) {
   typedef typename Base<S>::type T;
   const S lr = u[0];
   const S s = xexp(T(-0.5) * lr);
@@ -165,6 +215,12 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
     for (int k = 0; k < D; ++k)
       if (i + k > 0) ed = ed + eps[i][k] * gv[i][k];
   Sr[D + 1] = T(Q * P.m) * s + T(1.5 - P.gamma) * Th * div + T(0.5) * kas * Tg + T(P.c_diss * P.m) * mu * s * ed;
+  if constexpr (EUV)
+    if (heat && P.euv)
+      Sr[D + 1] = Sr[D + 1] + T(P.m) * s *
+                                heating_euvac<D, S>(P.euv_tab, P.euv_hfac, P.r_ref, P.sun_dir[0], P.sun_dir[1],
+                                                    P.sun_dir[2], x[0], D > 1 ? x[1] : 0.0, D > 2 ? x[D - 1] : 0.0,
+                                                    rho, Tm);
 }
 
 // inviscid part of the flux only (upper boundary)

@@ -37,6 +37,9 @@ struct GllC {
 };
 GllC make_gllc(int p);
 
+// EUVAC heating constants of the 37 bins and the declination of day N_d (euvac.cpp)
+void euvac_constants(const dg_physics_t& in, double* K, double* kap);
+double euvac_declination(double day);
 // modal filter of degree p on the GLL nodes: F = I - (1 - sigma) P_p(x_a) c_p(i), where
 // c_p(i) = w_i P_p(x_i) / sum_j w_j P_p(x_j)^2 extracts the coefficient of the Legendre
 // polynomial P_p (GLL quadrature is exact for P_k P_p with k < p, so the lower modes
@@ -102,6 +105,7 @@ struct dg_mesh_s {
   double* d_fn64 = nullptr;
   float* d_fn32 = nullptr;
   uint16_t* d_bf16op = nullptr;   // dense bf16 reference operators of the BF16 J v (p = 3 shells)
+  double* d_euv = nullptr;        // EUVAC bin constants [K(37), kap(37)] (heating model 1)
   bool krylov_bf16 = false;       // the implicit step in progress takes the BF16 J v
   int line_pc_every = 1;          // rebuild the radial-line preconditioner every this many steps
   int line_pc_prec = 32;          // storage precision of its factors: 64, 32 or 16 (bf16)

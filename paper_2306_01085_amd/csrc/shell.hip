@@ -214,7 +214,8 @@ __device__ inline int nth_bit(int mask, int r) {
 // of the divergence (only the node's own term); every element takes the stabilisation of
 // its own side of the angular faces and sends no angular traces. Radial coupling is
 // exact. Lines (cell, a, b) are then independent.
-template <int P, int EPB, int OCC, class S, class SU, class TV, class OT, bool RAD = false>
+// EUV: the instantiation contains the EUVAC heating (used when the mesh's heating model is 1).
+template <int P, int EPB, int OCC, class S, class SU, class TV, class OT, bool RAD = false, bool EUV = false>
 __global__ __launch_bounds__(Shape<P>::TPE * EPB) __attribute__((amdgpu_waves_per_eu(OCC)))
 void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__ u, const TV* __restrict__ v,
                  OT* __restrict__ R, OT* __restrict__ Fn) {
@@ -371,7 +372,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
       S ub[5], Fb[5][3], Sb[5];
       boundary_state<3, S>(ph, uu, ub);
-      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb);
+      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb, false);
       S sm, se;
       sigma<3, S>(ph, ub, sm, se);
       for (int c = 0; c < 5; ++c) {
@@ -381,7 +382,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
     }
     const double Q = heating<3>(ph, g.x, t);
     S F[5][3];
-    flux_source<3, S>(ph, uu, q, g.x, Q, F, Sr);
+    flux_source<3, S, EUV>(ph, uu, q, g.x, Q, F, Sr);
     // the metric terms are read again from LDS rather than kept in registers across the flux
     __asm__ __volatile__("" ::: "memory");
     const double (*ang)[N2] = s_ang[le];
@@ -492,19 +493,25 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   for (int c = 0; c < 5; ++c) R[base + c * N + j] += hl * acc[c];
 }
 
-template <int P, int EPB, int OCC, class S, class SU, class TV, class OT>
+template <int P, int EPB, int OCC, class S, bool EUV = false, class SU, class TV, class OT>
 static void launch_p1(const ShellDev& M, const PhysC& ph, const GllC& gc, double t, const SU* u, const TV* v, OT* out,
                       OT* fn, hipStream_t s) {
   const int blocks = (M.E + EPB - 1) / EPB;
-  shell_pass1<P, EPB, OCC, S, SU, TV, OT><<<blocks, Shape<P>::TPE * EPB, 0, s>>>(M, ph, gc, t, u, v, out, fn);
+  shell_pass1<P, EPB, OCC, S, SU, TV, OT, false, EUV><<<blocks, Shape<P>::TPE * EPB, 0, s>>>(M, ph, gc, t, u, v, out,
+                                                                                             fn);
 }
 
 // pass-1 launch configurations (elements per block, minimum waves per SIMD): the
 // FP64 residual and the FP32 J v take the tuned table entry of the mesh, the FP64
-// J v (dual numbers, 256 registers) runs one element per block
+// J v (dual numbers, 256 registers) runs one element per block, and so does every pass of
+// a mesh with the EUVAC heating (the one instantiation that contains it)
 template <int P, class S, class SU, class TV, class OT>
 static void dispatch_p1(const dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const GllC& gc, double t,
                         const SU* u, const TV* v, OT* out, OT* fn, hipStream_t s) {
+  if (ph.euv) {
+    launch_p1<P, 1, 1, S, true>(M, ph, gc, t, u, v, out, fn, s);
+    return;
+  }
   if constexpr (std::is_same<S, Dual<double>>::value) {
     launch_p1<P, 1, 1, S>(M, ph, gc, t, u, v, out, fn, s);
     return;
@@ -565,8 +572,12 @@ dg_status_t shell_jvp_radial(dg_mesh_s* m, double t, const double* u, const doub
   sun_direction(ph, t);
   const int E = M.E;
 #define DG_RAD(P_)                                                                                          \
-  shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, v, \
-                                                                                               jv, m->d_fn64); \
+  if (ph.euv)                                                                                              \
+    shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true, true><<<E, Shape<P_>::TPE, 0, s>>>(       \
+        M, ph, gc, t, u, v, jv, m->d_fn64);                                                                \
+  else                                                                                                     \
+    shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, \
+                                                                                                 v, jv, m->d_fn64); \
   shell_pass2<P_, double><<<(E + Shape<P_>::EPB - 1) / Shape<P_>::EPB, 256, 0, s>>>(M, gc, m->d_fn64, jv);
   switch (m->p) {
     case 2: DG_RAD(2); break;
@@ -586,8 +597,12 @@ dg_status_t shell_jvp_radial32(dg_mesh_s* m, double t, const double* u, const fl
   sun_direction(ph, t);
   const int E = M.E;
 #define DG_RAD32(P_)                                                                                        \
-  shell_pass1<P_, 1, 1, Dual<float>, double, float, float, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, v, jv, \
-                                                                                            m->d_fn32);      \
+  if (ph.euv)                                                                                              \
+    shell_pass1<P_, 1, 1, Dual<float>, double, float, float, true, true><<<E, Shape<P_>::TPE, 0, s>>>(           \
+        M, ph, gc, t, u, v, jv, m->d_fn32);                                                                \
+  else                                                                                                     \
+    shell_pass1<P_, 1, 1, Dual<float>, double, float, float, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, v, \
+                                                                                              jv, m->d_fn32); \
   shell_pass2<P_, float><<<(E + Shape<P_>::EPB - 1) / Shape<P_>::EPB, 256, 0, s>>>(M, gc, m->d_fn32, jv);
   switch (m->p) {
     case 2: DG_RAD32(2); break;
@@ -807,7 +822,7 @@ __global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, Phys
       const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
       S ub[5], Fb[5][3], Sb[5];
       boundary_state<3, S>(ph, uu, ub);
-      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb);
+      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb, false);
       S sm, se;
       sigma<3, S>(ph, ub, sm, se);
       for (int c = 0; c < 5; ++c) {
@@ -817,7 +832,7 @@ __global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, Phys
     }
     const double Q = heating<3>(ph, g.x, t);
     S F[5][3];
-    flux_source<3, S>(ph, uu, q, g.x, Q, F, Sr);
+    flux_source<3, S, true>(ph, uu, q, g.x, Q, F, Sr);
     __asm__ __volatile__("" ::: "memory");
     const double (*ang)[N2] = s_ang[le];
     if (dir || top) {
@@ -1042,7 +1057,7 @@ __global__ __launch_bounds__(256) void shell_bjac(ShellDev M, PhysC ph, GllC gc,
       ud[r] = DD(uu[r], r == c ? 1.0 : 0.0);
       for (int d = 0; d < 3; ++d) qd[r][d] = DD(q[r][d], 0.0);
     }
-    flux_source<3, DD>(ph, ud, qd, g.x, Q, Fd, Sd);
+    flux_source<3, DD, true>(ph, ud, qd, g.x, Q, Fd, Sd);
     for (int r = 0; r < 5; ++r) {
       double col = Sd[r].d;
       double gd[3];
