@@ -503,7 +503,8 @@ static void launch_p1(const ShellDev& M, const PhysC& ph, const GllC& gc, double
 
 // pass-1 launch configurations (elements per block, minimum waves per SIMD): the
 // FP64 residual and the FP32 J v take the tuned table entry of the mesh, the FP64
-// J v (dual numbers, 256 registers) runs one element per block, and so does every pass of
+// J v (dual numbers) runs one element per block with a register budget for two waves
+// per SIMD (left free, the allocator reaches 256 + 14 accumulation registers and one wave), and so does every pass of
 // a mesh with the EUVAC heating (the one instantiation that contains it)
 template <int P, class S, class SU, class TV, class OT>
 static void dispatch_p1(const dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const GllC& gc, double t,
@@ -513,7 +514,7 @@ static void dispatch_p1(const dg_mesh_s* m, const ShellDev& M, const PhysC& ph, 
     return;
   }
   if constexpr (std::is_same<S, Dual<double>>::value) {
-    launch_p1<P, 1, 1, S>(M, ph, gc, t, u, v, out, fn, s);
+    launch_p1<P, 1, 2, S>(M, ph, gc, t, u, v, out, fn, s);
     return;
   } else {
   constexpr int maxe = 256 / Shape<P>::TPE;
@@ -576,7 +577,7 @@ dg_status_t shell_jvp_radial(dg_mesh_s* m, double t, const double* u, const doub
     shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true, true><<<E, Shape<P_>::TPE, 0, s>>>(       \
         M, ph, gc, t, u, v, jv, m->d_fn64);                                                                \
   else                                                                                                     \
-    shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, \
+    shell_pass1<P_, 1, 2, Dual<double>, double, double, double, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, \
                                                                                                  v, jv, m->d_fn64); \
   shell_pass2<P_, double><<<(E + Shape<P_>::EPB - 1) / Shape<P_>::EPB, 256, 0, s>>>(M, gc, m->d_fn64, jv);
   switch (m->p) {
