@@ -30,30 +30,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, seed=0):
     import synth
     if name == "shell-p3":
-        return synth.config_shell_p3(0)
+        return synth.config_shell_p3(seed)
     if name == "shell-p4":
-        return synth.config_shell_p4(0)
+        return synth.config_shell_p4(seed)
     raise SystemExit("unknown workload %s" % name)
 
 
 def shell_state(w, X):
-    """state at the library's nodes X [E, N, 3] (element e = cell * n_rad + layer, node
-    j = cz * n^2 + angular node): angular directions are shared by every layer and
-    every radial node of a cell, so the separable generator runs on (cell, angular
-    node) x (layer, cz)"""
+    """state at the library's nodes X [E, N, 3]"""
     import synth
-    n = w.p + 1
-    N2 = n * n
-    A = 6 * w.n_ang ** 2
-    Xg = X.reshape(A, w.n_rad, n, N2, 3)
-    unit = Xg[:, 0, 0] / np.linalg.norm(Xg[:, 0, 0], axis=-1, keepdims=True)      # [A, N2, 3]
-    radii = np.linalg.norm(Xg[0, :, :, 0], axis=-1)                               # [n_rad, n]
-    u = synth.shell_state_product(w.T_inf, w.pert, unit.reshape(-1, 3), radii.ravel())   # [5, A*N2, n_rad*n]
-    u = u.reshape(5, A, N2, w.n_rad, n)
-    return np.ascontiguousarray(np.transpose(u, (1, 3, 0, 4, 2))).reshape(A * w.n_rad, 5, n * N2)
+    return synth.shell_state_at(w, X)
 
 
 def pass1_bytes(w, prec_bytes=8):
@@ -273,22 +262,24 @@ def column_batch(n_steps=None, check_cols=2, check_steps=2):
     return out
 
 
-def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epochs=8):
+def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epochs=8, eval_seed=None):
     """train the warm-start network on stages the method generates from the shell state
-    (dt = 60 s, FP64 J v), then run the next eval_steps steps twice from the same state,
-    plain and learned, with FP64 and with FP32 J v"""
+    (dt = 60 s, FP64 J v), then run eval_steps steps twice from the same state, plain and
+    learned, with FP64 and with FP32 J v: by default the steps that follow the training
+    trajectory; with eval_seed, a held-out trajectory from t = 0 of the workload drawn with
+    that seed (another temperature profile, perturbation and heating peak)"""
     import torch
 
     from paper_2306_01085_amd import Network
     from paper_2306_01085_amd import warmstart as wsm
-    opts = dict(newton_rtol=1e-8, precond=2, max_newton=15, max_restarts=40, filter_rate=FILTER_RATE, forcing=1)
+    opts = dict(newton_rtol=1e-8, precond=2, max_newton=30, max_restarts=40, filter_rate=FILTER_RATE, forcing=1)
     # a fresh preconditioner every step, so that the plain and learned runs see the same one
     mesh.set_option("line_pc_every", 1)
     mesh.set_option("line_pc_precision", LINE_PC_PRECISION)
     nin, nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
     cap = (3 * train_steps) * ((w.n_elem + every - 1) // every)
     t_rec = time.perf_counter()
-    X, Y, rows, rec_stats = wsm.record(mesh, u, 0.0, w.dt, train_steps, every=every, capacity=cap, **opts)
+    X, Y, rows, rec_stats = wsm.record(mesh, u, 0.0, w.dt, train_steps, every=every, capacity=cap, log=log, **opts)
     t_rec = time.perf_counter() - t_rec
     norms = wsm.standardise(X, Y, rows)
     net = Network(nin, nout, wsm.init_params(np.random.default_rng(0), nin, nout))
@@ -300,12 +291,20 @@ def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epoc
     torch.cuda.empty_cache()
     mesh.warmstart_set(net, *norms)
     t0 = train_steps * w.dt
+    eval_desc = "the %d steps after the training trajectory" % eval_steps
+    if eval_seed is not None:
+        we = workload("shell-p3" if w.p == 3 else "shell-p4", eval_seed)
+        mesh.set_physics(we.phys)
+        u = torch.from_numpy(shell_state(we, mesh.nodes().reshape(w.n_elem, -1, 3)).ravel()).to(u.device)
+        t0 = 0.0
+        eval_desc = "%d steps from t = 0 of the seed-%d workload (held out)" % (eval_steps, eval_seed)
     out = {"metric": "s per implicit step, learned/mixed vs plain @1e-8", "unit": "s", "higher_is_better": False,
            "config": {"workload": w.name, "n_dof": w.n_dof, "dt_s": 60.0, "train_steps": train_steps,
-                      "train_rows": rows, "eval_steps": eval_steps, "epochs": epochs},
+                      "train_rows": rows, "train_stages": 3 * train_steps, "eval_steps": eval_steps,
+                      "eval": eval_desc, "epochs": epochs},
            "record_seconds": t_rec, "train_seconds": t_tr, "train_loss": tr, "val_loss": va}
     for prec in ("f64", "f32"):
-        sp, sl, up, ul = wsm.compare(mesh, u, t0, w.dt, eval_steps, jvp_prec=prec, **opts)
+        sp, sl, up, ul = wsm.compare(mesh, u, t0, w.dt, eval_steps, jvp_prec=prec, log=log, **opts)
         agg = lambda ss, k: float(np.mean([sum(s[k]) for s in ss]))
         out[prec] = {
             "plain": {"s_per_step": float(np.mean([s["seconds"] for s in sp])),
@@ -341,6 +340,9 @@ def main():
     ap.add_argument("--ws-train-steps", type=int, default=60)
     ap.add_argument("--ws-eval-steps", type=int, default=8)
     ap.add_argument("--ws-epochs", type=int, default=8)
+    ap.add_argument("--ws-every", type=int, default=4, help="record one element in this many per stage")
+    ap.add_argument("--ws-eval-seed", type=int, default=None,
+                    help="evaluate on a held-out trajectory of the workload drawn with this seed")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -385,7 +387,8 @@ def main():
     if args.mode == "warmstart":
         del r, jv, jv32, v, v32
         print(json.dumps(warmstart_experiment(w, mesh, u, train_steps=args.ws_train_steps,
-                                              eval_steps=args.ws_eval_steps, epochs=args.ws_epochs)), flush=True)
+                                              eval_steps=args.ws_eval_steps, every=args.ws_every,
+                                              epochs=args.ws_epochs, eval_seed=args.ws_eval_seed)), flush=True)
         return
 
     if args.only == "implicit":

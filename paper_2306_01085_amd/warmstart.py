@@ -19,7 +19,7 @@ def init_params(rng, n_in, n_out, hidden=128):
             np.zeros((n_out, hidden)), np.zeros(n_out)]
 
 
-def record(mesh, u, t0, dt, n_steps, every, capacity, **opts):
+def record(mesh, u, t0, dt, n_steps, every, capacity, log=None, **opts):
     """run n_steps implicit steps from (u, t0) recording one element in `every` per
     converged stage; returns (X, Y, rows, per-step stats); u is advanced in place"""
     import torch
@@ -29,9 +29,14 @@ def record(mesh, u, t0, dt, n_steps, every, capacity, **opts):
     mesh.warmstart_record(X, Y, capacity, every)
     stats = []
     t = t0
-    for _ in range(n_steps):
+    for k in range(n_steps):
         stats.append(mesh.implicit_step(u, t, dt, **opts))
         t += dt
+        if log and (k + 1) % 25 == 0:
+            win = stats[-25:]
+            log("recorded %d of %d steps: Newton %.1f (max %d), GMRES %.1f per step" % (
+                k + 1, n_steps, np.mean([sum(s["newton_its"]) for s in win]),
+                max(max(s["newton_its"]) for s in win), np.mean([sum(s["gmres_its"]) for s in win])))
     rows = mesh.warmstart_recorded()
     mesh.warmstart_record(None, None, 0, 1)
     return X, Y, rows, stats
@@ -75,7 +80,7 @@ def train(net: Network, X, Y, rows, epochs=20, batch=4096, lr=1e-3, rng=None, lo
     return tr, va
 
 
-def compare(mesh, u, t0, dt, n_steps, **opts):
+def compare(mesh, u, t0, dt, n_steps, log=None, **opts):
     """the same n_steps from the same state with the plain and with the learned guess;
     returns (plain stats, learned stats, plain final state, learned final state)"""
     out = {}
@@ -83,8 +88,10 @@ def compare(mesh, u, t0, dt, n_steps, **opts):
         x = u.clone()
         t = t0
         st = []
-        for _ in range(n_steps):
+        for k in range(n_steps):
             st.append(mesh.implicit_step(x, t, dt, guess=guess, **opts))
             t += dt
+            if log and (k + 1) % 25 == 0:
+                log("%s guess: %d of %d steps" % ("learned" if guess else "plain", k + 1, n_steps))
         out[guess] = (st, x)
     return out[0][0], out[1][0], out[0][1], out[1][1]

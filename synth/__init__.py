@@ -202,6 +202,22 @@ def shell_state_fn(T_inf, pert: ShellPerturbation | None):
     return fn
 
 
+def shell_state_at(w, X):
+    """the workload's state at shell nodes X [E, N, 3] ordered element e = cell * n_rad +
+    layer, node j = cz * n^2 + angular node: the angular directions are shared by every
+    layer and radial node of a cell, so the separable generator runs on (cell, angular
+    node) x (layer, cz); returns [E, 5, N]"""
+    n = w.p + 1
+    N2 = n * n
+    A = 6 * w.n_ang ** 2
+    Xg = np.asarray(X, dtype=np.float64).reshape(A, w.n_rad, n, N2, 3)
+    unit = Xg[:, 0, 0] / np.linalg.norm(Xg[:, 0, 0], axis=-1, keepdims=True)      # [A, N2, 3]
+    radii = np.linalg.norm(Xg[0, :, :, 0], axis=-1)                               # [n_rad, n]
+    u = shell_state_product(w.T_inf, w.pert, unit.reshape(-1, 3), radii.ravel())  # [5, A*N2, n_rad*n]
+    u = u.reshape(5, A, N2, w.n_rad, n)
+    return np.ascontiguousarray(np.transpose(u, (1, 3, 0, 4, 2))).reshape(A * w.n_rad, 5, n * N2)
+
+
 def shell_state_product(T_inf, pert, unit, radii):
     """the same state as shell_state_fn on the product of M angular directions
     (unit [M, 3]) and K radii ([K]): returns [5, M, K]. The perturbation is separable
