@@ -335,7 +335,9 @@ def main():
                     help="residual: only the R(u) timing; implicit: only the implicit steps (for counter runs)")
     ap.add_argument("--implicit-runs", default="f64,f32,bf16,f32_rb4,f32_no_precond",
                     help="which implicit-step runs (with --only implicit)")
-    ap.add_argument("--mode", default="default", choices=["default", "warmstart"])
+    ap.add_argument("--mode", default="default", choices=["default", "warmstart", "sweep"],
+                    help="sweep: the parametric study of the 1D model (three cases x 75 columns)")
+    ap.add_argument("--sweep-hours", type=float, default=72.0, help="model hours per case (sweep mode)")
     ap.add_argument("--implicit-steps", type=int, default=4)
     ap.add_argument("--ws-train-steps", type=int, default=60)
     ap.add_argument("--ws-eval-steps", type=int, default=8)
@@ -353,6 +355,21 @@ def main():
 
     import synth
     from paper_2306_01085_amd import Mesh
+
+    if args.mode == "sweep":
+        from paper_2306_01085_amd import sweep
+        out = {"metric": "parametric sweep of the 1D model: column-steps/s", "unit": "column-steps/s",
+               "higher_is_better": True, "cases": []}
+        for case in (1, 2, 3):
+            w = synth.sweep_case(case)
+            res = sweep.run_case(w, hours=args.sweep_hours, log=log)
+            res["rho400_spread"] = sweep.summarise(w, res)
+            del res["logrho_400km"]
+            res.update({"f107bar": w.extra["fbar"], "day": w.extra["day"], "elements": int(w.nelem[0]), "p": 2})
+            out["cases"].append(res)
+        out["value"] = sum(c["columns"] * c["steps"] for c in out["cases"]) / sum(c["seconds"] for c in out["cases"])
+        print(json.dumps(out), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     w = workload(args.workload)

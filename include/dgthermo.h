@@ -106,6 +106,12 @@ typedef struct {
   double euv_chi[4];       /* mole fractions of N2, O2, O, He */
   double euv_q_scale;      /* rho0 / (m_O Q_unit): m^-3 per W m^-3 of the model's heating unit */
   double euv_col_scale;    /* rho0 H0 / m_O: m^-2 per unit nondimensional density x length */
+  /* columns: more optional host arrays [n_col] (or NULL for the shared value) */
+  const double* col_alpha0c;   /* multiplier of the molecular conductivity (alpha0 of section 4.3) */
+  const double* col_site;      /* [n_col][3] Earth-fixed unit vector of the column's site: cos chi =
+                                  site . sub-solar direction at time t; NULL: the Sun overhead */
+  const double* col_euv_eps;   /* EUVAC efficiency (heating model 1) */
+  const double* col_euv_f107;  /* EUVAC F10.7bar (heating model 1) */
 } dg_physics_t;
 
 /* Create a mesh: builds GLL tables, the factored curved geometry (invariant curl

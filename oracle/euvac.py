@@ -150,7 +150,7 @@ def sun_vector(t, P):
 def heating(x, t, rho, T, P):
     """nondimensional EUVAC heating rate at nodes x (list of d coordinate arrays) for
     density rho and temperature T (nondimensional; complex allowed); 1D columns take
-    cos chi = 1"""
+    cos chi from their site (P["site"], unit vector), or 1 without one"""
     d = P["d"]
     r2 = sum(np.asarray(x[k]) * np.asarray(x[k]) for k in range(d))
     r = np.sqrt(r2)
@@ -158,7 +158,12 @@ def heating(x, t, rho, T, P):
         sh = sun_vector(t, P)
         cchi = sum(np.asarray(x[k]) * sh[k] for k in range(3)) / r
     else:
-        cchi = np.ones_like(r)
+        site = P.get("site")
+        if site is None or not any(site):
+            cchi = np.ones_like(r)
+        else:
+            sh = sun_vector(t, P)
+            cchi = np.full_like(r, sum(site[k] * sh[k] for k in range(3)))
     H = T * r2 / (P["m"] * P["r_ref"] ** 2)
     C = chapman(r / H, cchi, r / P["r_ref"])
     K, kap = bin_constants(P)

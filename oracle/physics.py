@@ -94,10 +94,30 @@ def flux(u, q, P, xp):
     return [[Fi[c][k] + Fv[c][k] for k in range(P["d"])] for c in range(P["d"] + 2)]
 
 
+def sun_unit(t, P):
+    """sub-solar unit vector at nondimensional time t: latitude sun_lat, longitude
+    sun_lon0 - sun_rate t (the Sun's apparent motion in the Earth-fixed frame)"""
+    lon = P["sun_lon0"] - P["sun_rate"] * t
+    lat = P["sun_lat"]
+    return [np.cos(lat) * np.cos(lon), np.cos(lat) * np.sin(lon), np.sin(lat)]
+
+
+def column_cos_zenith(t, P):
+    """cos chi of a 1D column: the Sun overhead, or, with P["site"] (unit vector of the
+    column's Earth-fixed site), site . sub-solar direction (section 2.2: from the
+    declination, the latitude and the local time)"""
+    site = P.get("site")
+    if site is None or not any(site):
+        return 1.0
+    sh = sun_unit(t, P)
+    return float(sum(site[k] * sh[k] for k in range(3)))
+
+
 def heating(x, t, P, xp):
     """prescribed Chapman-shaped EUV heating rate Q(x, t) (nondimensional, W/m^3 over
     rho0 c_vO T0 a0/H0): Q = amp qm exp(1 - z - e^{-z}/cos chi) on the day side,
-    z = (|r| - rm)/H, zero where cos chi <= 0; 1D columns take cos chi = 1.
+    z = (|r| - rm)/H, zero where cos chi <= 0; 1D columns take cos chi from their site
+    (column_cos_zenith: 1 without a site).
     The solar zenith angle follows section 2.2: cos chi = r_hat . s_hat(t), the
     sub-solar point moving in longitude at the nondimensional rotation rate."""
     d = P["d"]
@@ -108,7 +128,7 @@ def heating(x, t, P, xp):
         sh = [xp.cos(lat) * xp.cos(lon), xp.cos(lat) * xp.sin(lon), xp.sin(lat)]
         cchi = sum(x[k] * sh[k] for k in range(3)) / r
     else:
-        cchi = 1.0 + 0.0 * r
+        cchi = column_cos_zenith(t, P) + 0.0 * r
     z = (r - P["heat_rm"]) / P["heat_H"]
     if xp is np:
         cchi = np.asarray(cchi, dtype=np.float64)

@@ -49,7 +49,9 @@ class Physics(C.Structure):
                 ("col_lam", C.POINTER(C.c_double)),
                 ("heating_model", C.c_int32), ("euv_eps", C.c_double), ("euv_f107", C.c_double),
                 ("euv_sun_dist", C.c_double), ("euv_day", C.c_double), ("euv_chi", C.c_double * 4),
-                ("euv_q_scale", C.c_double), ("euv_col_scale", C.c_double)]
+                ("euv_q_scale", C.c_double), ("euv_col_scale", C.c_double),
+                ("col_alpha0c", C.POINTER(C.c_double)), ("col_site", C.POINTER(C.c_double)),
+                ("col_euv_eps", C.POINTER(C.c_double)), ("col_euv_f107", C.POINTER(C.c_double))]
 
 
 class SolverOpts(C.Structure):
@@ -148,7 +150,8 @@ def make_physics(phys: dict, col_phys: dict | None = None):
     keep = []
     if col_phys:
         for key, field in (("heat_amp", "col_heat_amp"), ("heat_qm", "col_heat_qm"), ("heat_rm", "col_heat_rm"),
-                           ("heat_H", "col_heat_H"), ("lam", "col_lam")):
+                           ("heat_H", "col_heat_H"), ("lam", "col_lam"), ("alpha0c", "col_alpha0c"),
+                           ("site", "col_site"), ("euv_eps", "col_euv_eps"), ("euv_f107", "col_euv_f107")):
             if key in col_phys:
                 arr, ptr = _dbl_array(col_phys[key])
                 keep.append(arr)

@@ -54,6 +54,16 @@ void fill_phys(PhysC& P, const dg_physics_t& in) {
 static dg_status_t set_phys(dg_mesh_s* m, const dg_physics_t& in) {
   fill_phys(m->phys, in);
   if (!m->phys.euv) return DG_OK;
+  if (m->kind == DG_MESH_COLUMNS) {
+    std::vector<double> tab;
+    col_euv_tables(in, m->n_col, tab);
+    if (!m->d_euv_cols && hipMalloc(&m->d_euv_cols, tab.size() * sizeof(double)) != hipSuccess) {
+      set_error("dg_mesh: device allocation of the column EUVAC tables failed");
+      return DG_ERR_ALLOC;
+    }
+    DG_HIP_CHECK(hipDeviceSynchronize());
+    DG_HIP_CHECK(hipMemcpy(m->d_euv_cols, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   double tab[74];
   euvac_constants(in, tab, tab + 37);
   if (!m->d_euv && hipMalloc(&m->d_euv, sizeof(tab)) != hipSuccess) {
@@ -79,7 +89,7 @@ static void free_mesh(dg_mesh_s* m) {
   void* ptrs[] = {m->d_ang,  m->d_edges,  m->d_cnbr,  m->d_cface,     m->d_cmap,      m->d_off,
                   m->d_prev, m->d_next,   m->d_geo,   m->d_col,       m->d_cpar,      m->d_fn64,
                   m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2], m->d_bstate, m->d_coloff,
-                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op, m->d_euv};
+                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op, m->d_euv, m->d_euv_cols};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   free_workspace(m);
@@ -237,14 +247,9 @@ dg_status_t dg_mesh_set_physics(dg_mesh_t m, const dg_physics_t* phys) {
   const dg_status_t st = set_phys(m, *phys);
   if (st != DG_OK) return st;
   if (m->kind == DG_MESH_COLUMNS) {
-    std::vector<double> cpar(5 * m->n_col);
-    for (int c = 0; c < m->n_col; ++c) {
-      cpar[5 * c + 0] = phys->col_heat_amp ? phys->col_heat_amp[c] : phys->heat_amp;
-      cpar[5 * c + 1] = phys->col_heat_qm ? phys->col_heat_qm[c] : phys->heat_qm;
-      cpar[5 * c + 2] = phys->col_heat_rm ? phys->col_heat_rm[c] : phys->heat_rm;
-      cpar[5 * c + 3] = 1.0 / (phys->col_heat_H ? phys->col_heat_H[c] : phys->heat_H);
-      cpar[5 * c + 4] = phys->col_lam ? phys->col_lam[c] : phys->lam;
-    }
+    std::vector<double> cpar;
+    col_params(*phys, m->n_col, cpar);
+    DG_HIP_CHECK(hipDeviceSynchronize());
     DG_HIP_CHECK(hipMemcpy(m->d_cpar, cpar.data(), cpar.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   return DG_OK;

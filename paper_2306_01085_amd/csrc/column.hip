@@ -16,14 +16,24 @@ __device__ inline double outc(double x) { return x; }
 __device__ inline float outc(float x) { return x; }
 template <class T> __device__ inline T outc(Dual<T> x) { return x.d; }
 
-__device__ inline PhysC column_phys(const ColDev& C, const PhysC& ph, int col) {
-  PhysC P = ph;
-  const double* cp = C.cpar + 5 * col;
+// the physics of column col: its parameter block (CPAR values) and EUVAC table
+__device__ inline void set_column_phys(PhysC& P, const double* __restrict__ cpar, const double* euv, int col) {
+  const double* cp = cpar + CPAR * col;
   P.heat_amp = cp[0];
   P.heat_qm = cp[1];
   P.heat_rm = cp[2];
   P.heat_inv_H = cp[3];
   P.lam = cp[4];
+  P.alpha0c = cp[5];
+  P.site[0] = cp[6];
+  P.site[1] = cp[7];
+  P.site[2] = cp[8];
+  if (euv) P.euv_tab = euv + 74 * col;
+}
+
+__device__ inline PhysC column_phys(const ColDev& C, const PhysC& ph, int col) {
+  PhysC P = ph;
+  set_column_phys(P, C.cpar, C.euv, col);
   return P;
 }
 
@@ -331,6 +341,7 @@ struct ColBatch {
   const int* col_e0;
   const double* geo;
   const double* cpar;
+  const double* euv;
   double* u;
   double t0, dt;
   int n_steps, n_stages;
@@ -550,14 +561,8 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   const int e0 = B.col_e0[col];
   const int nd = E * b;
   PhysC Pc = ph;
-  {
-    const double* cp = B.cpar + 5 * col;
-    Pc.heat_amp = cp[0];
-    Pc.heat_qm = cp[1];
-    Pc.heat_rm = cp[2];
-    Pc.heat_inv_H = cp[3];
-    Pc.lam = cp[4];
-  }
+  set_column_phys(Pc, B.cpar, B.euv, col);
+  const bool sited = Pc.site[0] != 0.0 || Pc.site[1] != 0.0 || Pc.site[2] != 0.0;
   double* w = B.ws + (int64_t)blockIdx.x * B.ws_stride;
   const int64_t md = B.max_dof;
   double* U = w;
@@ -582,13 +587,15 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   int newton_total = 0, builds = 0, status = 0;
   for (int step = 0; step < B.n_steps && status == 0; ++step) {
     const double t = B.t0 + step * B.dt;
-    // chord Jacobian at the start of the step
+    // chord Jacobian at the start of the step (a sited column follows the Sun's direction)
+    if (sited) sun_direction_dev(Pc, t + B.c[0] * B.dt);
     colw_build_and_factor<P, EUV>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
     ++builds;
     for (int i = lane; i < nd; i += 64) U[i] = un[i];
     __syncthreads();
     for (int s = 0; s < B.n_stages && status == 0; ++s) {
       const double ti = t + B.c[s] * B.dt;
+      if (sited) sun_direction_dev(Pc, ti);
       for (int i = lane; i < nd; i += 64) {
         double bv = un[i];
         for (int j = 0; j < s; ++j) bv += B.dt * B.A[s][j] * Rs[j * md + i];
@@ -733,6 +740,7 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   B.col_off = m->d_coloff;
   B.geo = m->d_geo;
   B.cpar = m->d_cpar;
+  B.euv = m->d_euv_cols;
   B.u = u;
   B.t0 = t0;
   B.dt = dt;

@@ -106,9 +106,24 @@ struct PhysC {
   int euv;                           // 1: EUVAC heating (state dependent)
   const double* euv_tab;             // device [K_0..K_36, kap_0..kap_36]: Q = rho sum_j K_j exp(-kap_j rho H C)
   double euv_hfac, r_ref;            // H = T r^2 euv_hfac; the lower-boundary radius R0
+  double site[3];                    // 1D: unit vector of the column's site (0: the Sun overhead)
 };
 
 // ---------------------------------------------------------------- pointwise physics
+// cosine of the solar zenith angle at x: the shell from the node's direction, a column
+// from its site's direction (the Sun overhead when no site is set); P.sun_dir holds the
+// sub-solar direction at the evaluation time
+template <int D>
+__device__ inline double cos_zenith(const PhysC& P, const double* x) {
+  if constexpr (D == 3) {
+    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    return (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[2] * P.sun_dir[2]) / r;
+  } else {
+    if (P.site[0] == 0.0 && P.site[1] == 0.0 && P.site[2] == 0.0) return 1.0;
+    return P.site[0] * P.sun_dir[0] + P.site[1] * P.sun_dir[1] + P.site[2] * P.sun_dir[2];
+  }
+}
+
 // EUVAC heating (section 2.2) at position x for density rho and temperature Tm
 // (nondimensional): Q = rho sum_j K_j exp(-kap_j rho H C), H = Tm r^2 hfac the scale
 // height, C the Smith-Smith Chapman factor of r~ = r / H and the zenith angle (cos chi = 1 in
@@ -117,14 +132,11 @@ struct PhysC {
 // unattenuated one). Only the kernels instantiated with EUV (flux_source) contain it: the
 // element passes without it keep their register budget.
 template <int D, class S>
-__device__ inline S heating_euvac(const double* __restrict__ tab, double hfac, double r_ref,
-                                                     double s0, double s1, double s2, double x0, double x1,
-                                                     double x2, S rho, S Tm) {
+__device__ inline S heating_euvac(const double* __restrict__ tab, double hfac, double r_ref, double cchi, double r,
+                                  S rho, S Tm) {
   typedef typename Base<S>::type T;
   constexpr T kTauMax = sizeof(T) == 8 ? T(700) : T(80);
-  const double r2 = x0 * x0 + x1 * x1 + x2 * x2;
-  const double r = sqrt(r2);
-  const double cchi = D == 3 ? (x0 * s0 + x1 * s1 + x2 * s2) / r : 1.0;
+  const double r2 = r * r;
   const double schi = sqrt(fmax(0.0, 1.0 - cchi * cchi));
   const bool day = cchi > 0.0;
   if (!day && !(schi > r_ref / r)) return S(T(0));
@@ -218,9 +230,7 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
   if constexpr (EUV)
     if (heat && P.euv)
       Sr[D + 1] = Sr[D + 1] + T(P.m) * s *
-                                heating_euvac<D, S>(P.euv_tab, P.euv_hfac, P.r_ref, P.sun_dir[0], P.sun_dir[1],
-                                                    P.sun_dir[2], x[0], D > 1 ? x[1] : 0.0, D > 2 ? x[D - 1] : 0.0,
-                                                    rho, Tm);
+                                heating_euvac<D, S>(P.euv_tab, P.euv_hfac, P.r_ref, cos_zenith<D>(P, x), r, rho, Tm);
 }
 
 // inviscid part of the flux only (upper boundary)
@@ -276,11 +286,23 @@ __device__ inline double heating(const PhysC& P, const double* x, double t) {
   for (int k = 0; k < D; ++k) r2 += x[k] * x[k];
   const double r = sqrt(r2);
   double cchi = 1.0;
-  if (D == 3) cchi = (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[D - 1] * P.sun_dir[2]) / r;
+  if constexpr (D == 3)
+    cchi = (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[D - 1] * P.sun_dir[2]) / r;
+  else
+    cchi = cos_zenith<1>(P, x);
   (void)t;
   if (!(cchi > 0.0)) return 0.0;
   const double z = (r - P.heat_rm) * P.heat_inv_H;
   return P.heat_amp * P.heat_qm * exp(1.0 - z - exp(-z) / cchi);
+}
+
+// the same on the device (kernels that advance time themselves)
+__device__ inline void sun_direction_dev(PhysC& P, double t) {
+  const double lon = P.sun_lon0 - P.sun_rate * t;
+  const double cl = cos(P.sun_lat);
+  P.sun_dir[0] = cl * cos(lon);
+  P.sun_dir[1] = cl * sin(lon);
+  P.sun_dir[2] = sin(P.sun_lat);
 }
 
 // the sub-solar direction at time t: longitude sun_lon0 - sun_rate t, latitude sun_lat

@@ -9,6 +9,7 @@
 // Table A's photon fluxes are read with the exponent +13 (m^-2 s^-1), the cross sections
 // in units of 1e-22 m^2; a wavelength range stands for its midpoint.
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 
@@ -83,6 +84,30 @@ void euvac_constants(const dg_physics_t& in, double* K, double* kap) {
     const double I0 = b.f74113 * 1e13 * (scale > 0.8 ? scale : 0.8) / (in.euv_sun_dist * in.euv_sun_dist);
     K[j] = in.euv_eps * (h * c / lam) * I0 * sig * in.euv_q_scale / in.m;
     kap[j] = sig * in.euv_col_scale / in.m;
+  }
+}
+
+void col_params(const dg_physics_t& ph, int n_col, std::vector<double>& cpar) {
+  cpar.assign((size_t)CPAR * n_col, 0.0);
+  for (int c = 0; c < n_col; ++c) {
+    double* p = &cpar[(size_t)CPAR * c];
+    p[0] = ph.col_heat_amp ? ph.col_heat_amp[c] : ph.heat_amp;
+    p[1] = ph.col_heat_qm ? ph.col_heat_qm[c] : ph.heat_qm;
+    p[2] = ph.col_heat_rm ? ph.col_heat_rm[c] : ph.heat_rm;
+    p[3] = 1.0 / (ph.col_heat_H ? ph.col_heat_H[c] : ph.heat_H);
+    p[4] = ph.col_lam ? ph.col_lam[c] : ph.lam;
+    p[5] = ph.col_alpha0c ? ph.col_alpha0c[c] : ph.alpha0c;
+    for (int k = 0; k < 3; ++k) p[6 + k] = ph.col_site ? ph.col_site[3 * c + k] : 0.0;
+  }
+}
+
+void col_euv_tables(const dg_physics_t& ph, int n_col, std::vector<double>& tab) {
+  tab.assign((size_t)74 * n_col, 0.0);
+  dg_physics_t q = ph;
+  for (int c = 0; c < n_col; ++c) {
+    if (ph.col_euv_eps) q.euv_eps = ph.col_euv_eps[c];
+    if (ph.col_euv_f107) q.euv_f107 = ph.col_euv_f107[c];
+    euvac_constants(q, &tab[(size_t)74 * c], &tab[(size_t)74 * c + 37]);
   }
 }
 

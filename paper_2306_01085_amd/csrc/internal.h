@@ -37,6 +37,12 @@ struct GllC {
 };
 GllC make_gllc(int p);
 
+// per-column parameters of a column mesh, CPAR per column: heat_amp, heat_qm, heat_rm,
+// 1 / heat_H, lam, alpha0c, site unit vector (3; zero: the Sun overhead)
+constexpr int CPAR = 9;
+void col_params(const dg_physics_t& ph, int n_col, std::vector<double>& cpar);
+// per-column EUVAC bin constants [n_col][74] (efficiency and F10.7bar per column)
+void col_euv_tables(const dg_physics_t& ph, int n_col, std::vector<double>& tab);
 // EUVAC heating constants of the 37 bins and the declination of day N_d (euvac.cpp)
 void euvac_constants(const dg_physics_t& in, double* K, double* kap);
 double euvac_declination(double day);
@@ -67,7 +73,8 @@ struct ColDev {
   const int* next;       // [E] element above (-1: upper boundary)
   const double* geo;     // [E][2] bottom radius, thickness
   const int* col;        // [E] column of the element
-  const double* cpar;    // [n_col][5] heat_amp, heat_qm, heat_rm, heat_inv_H, lam
+  const double* cpar;    // [n_col][CPAR] per-column parameters (col_params)
+  const double* euv;     // [n_col][74] per-column EUVAC bin constants, or null (the mesh's table)
 };
 
 struct Workspace;   // implicit-step buffers (solver.hip)
@@ -99,6 +106,7 @@ struct dg_mesh_s {
   double* d_geo = nullptr;
   int* d_col = nullptr;
   double* d_cpar = nullptr;
+  double* d_euv_cols = nullptr;   // per-column EUVAC bin constants (heating model 1 on columns)
   int* d_plist[3] = {nullptr, nullptr, nullptr};   // element ids of degree 2, 3, 4
   int plist_n[3] = {0, 0, 0};
   // face-flux traces (one buffer per precision)
@@ -141,7 +149,7 @@ struct dg_mesh_s {
     return dg::ShellDev{n_ang, n_rad, (int)n_elem, d_ang, d_edges, d_cnbr, d_cface, d_cmap};
   }
   dg::ColDev cols() const {
-    return dg::ColDev{(int)n_elem, d_off, d_prev, d_next, d_geo, d_col, d_cpar};
+    return dg::ColDev{(int)n_elem, d_off, d_prev, d_next, d_geo, d_col, d_cpar, d_euv_cols};
   }
 };
 

@@ -388,14 +388,8 @@ dg_status_t build_columns(dg_mesh_s* m, const dg_mesh_desc_t& d, const dg_physic
       plist[p - 2].push_back((int)e);
     }
   }
-  std::vector<double> cpar(5 * d.n_col);
-  for (int c = 0; c < d.n_col; ++c) {
-    cpar[5 * c + 0] = ph.col_heat_amp ? ph.col_heat_amp[c] : ph.heat_amp;
-    cpar[5 * c + 1] = ph.col_heat_qm ? ph.col_heat_qm[c] : ph.heat_qm;
-    cpar[5 * c + 2] = ph.col_heat_rm ? ph.col_heat_rm[c] : ph.heat_rm;
-    cpar[5 * c + 3] = 1.0 / (ph.col_heat_H ? ph.col_heat_H[c] : ph.heat_H);
-    cpar[5 * c + 4] = ph.col_lam ? ph.col_lam[c] : ph.lam;
-  }
+  std::vector<double> cpar;
+  col_params(ph, d.n_col, cpar);
   DG_HIP_CHECK(hipMalloc(&m->d_off, E * sizeof(int64_t)));
   DG_HIP_CHECK(hipMalloc(&m->d_prev, E * sizeof(int)));
   DG_HIP_CHECK(hipMalloc(&m->d_next, E * sizeof(int)));

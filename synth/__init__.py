@@ -325,6 +325,54 @@ def graded_stretch(n_elem, first_km=2.5, length_km=500.0):
     return float(0.5 * (lo + hi))
 
 
+# --------------------------------------------------------------------------
+# the parametric study of the 1D model (section 4.3): EUV efficiency x conductivity
+# multiplier grids, three solar-activity cases and three sites
+SWEEP_EPS = [0.2, 0.225, 0.25, 0.275, 0.3]
+SWEEP_ALPHA0 = [0.5, 0.625, 0.75, 0.875, 1.0]
+SWEEP_SITES = {"Millstone Hill": (42.6347, -71.4883), "Quito": (-0.1859, -78.4663),
+               "Santiago": (-33.3458, -70.6786)}
+# case: (day of the year of the first date, F10.7, its 81-day mean, top altitude km, elements)
+SWEEP_CASES = {1: (79, 150.0, 150.0, 600.0, 28), 2: (80, 70.0, 70.0, 500.0, 26), 3: (166, 150.0, 120.0, 600.0, 28)}
+
+
+def site_vector(lat_deg, lon_deg):
+    """Earth-fixed unit vector of a site"""
+    la, lo = math.radians(lat_deg), math.radians(lon_deg)
+    return [math.cos(la) * math.cos(lo), math.cos(la) * math.sin(lo), math.sin(la)]
+
+
+def sweep_case(case: int) -> ColumnWorkload:
+    """the 75 columns of one case: every (efficiency, conductivity multiplier) pair at each
+    site, p = 2, the case's element count on a geometric mesh with a 2.5 km first element,
+    DIRK(2,2) steps of 30 s from 00 UTC of the case's first day (sub-solar longitude 180
+    degrees at t = 0), EUVAC heating at the case's F10.7bar. The initial state is a
+    hydrostatic Bates column with T_inf = 500 K + 3 K x F10.7bar (synthetic: the paper starts
+    from empirical profiles that are not available)."""
+    day, f107, f81, top_km, n_elem = SWEEP_CASES[case]
+    fbar = 0.5 * (f107 + f81)
+    T_inf = 500.0 + 3.0 * fbar
+    combos = [(site, e, a) for site in SWEEP_SITES for e in SWEEP_EPS for a in SWEEP_ALPHA0]
+    n_col = len(combos)
+    r_top = (R_EARTH + top_km * 1e3) / H0
+    phys = base_physics(1)
+    phys.update(euvac_physics(f107bar=fbar, day=float(day)))
+    phys["heating_model"] = 1
+    phys["sun_lon0"] = math.pi
+    cp = _column_phys(T_inf, 200.0, 0.0)
+    phys.update(cp)
+    col_phys = {k: np.full(n_col, float(v)) for k, v in cp.items()}
+    col_phys["euv_eps"] = np.array([e for _, e, _ in combos])
+    col_phys["alpha0c"] = np.array([a for _, _, a in combos])
+    col_phys["site"] = np.array([site_vector(*SWEEP_SITES[s]) for s, _, _ in combos])
+    w = ColumnWorkload(name="sweep-case%d" % case, nelem=np.full(n_col, n_elem, np.int32),
+                       p=np.full(n_col, 2, np.int32), T_inf=np.full(n_col, T_inf), phys=phys, col_phys=col_phys,
+                       stretch=graded_stretch(n_elem, 2.5, top_km - 100.0), r_top=r_top,
+                       dt=seconds_to_nondim(30.0), n_steps=8640)
+    w.extra = {"combos": combos, "fbar": fbar, "day": day, "r400": (R_EARTH + 400e3) / H0}
+    return w
+
+
 def column_batch_workload(seed=0, n_col=4096, name="column-batch") -> ColumnWorkload:
     """The parametric sweep: n_col columns, elements ~ U{32..256}, p ~ U{2,3,4},
     T_inf ~ U(600, 1500) K, heating multiplier ~ U(0.5, 3), z_m ~ U(150, 250) km.

@@ -101,3 +101,53 @@ def test_batched_columns_filtered_match_oracle():
             ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-13, filter_rate=rate)
         got = out[off[c]:off[c + 1]].reshape(u.shape)
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref - u) < 1e-6, c
+
+
+def test_sweep_columns_match_oracle():
+    """columns of the parametric study: per-column EUV efficiency, F10.7bar, conductivity
+    multiplier and site (zenith angle from the site and the time of day, three sites on
+    the day side and one on the night side at 15 UTC), EUVAC heating: R and J v through
+    the per-element passes, then two DIRK(2,2) steps of 30 s in the persistent launch
+    (the Sun's direction follows the stage times), against the oracle column by column"""
+    need_gpu()
+    from oracle import jac as ojac
+    from oracle import dg as odg
+    from paper_2306_01085_amd import Mesh
+    w = synth.sweep_case(3)
+    pick = [0, 37, 74, 12]
+    nelem = np.full(4, 12, np.int32)   # (6 elements over 500 km do not converge at 30 s, oracle included)
+    p = np.full(4, 2, np.int32)
+    col_phys = {k: np.asarray(v)[pick].copy() for k, v in w.col_phys.items()}
+    col_phys["site"][3] = synth.site_vector(10.0, 150.0)
+    col_phys["euv_f107"] = np.array([150.0, 70.0, 135.0, 110.0])
+    col_phys["alpha0c"] = np.array([0.5, 0.75, 1.0, 0.625])
+    gm = Mesh.columns(nelem, p, w.r_bot, w.r_top, 1.1, w.phys, col_phys)
+    off = gm.col_offsets()
+    t0 = synth.seconds_to_nondim(15 * 3600.0)
+    cols = []
+    for c in range(4):
+        om = omesh.columns_mesh([12], 2, w.r_bot, w.r_top, 1.1)
+        P = dict(w.phys)
+        for k, v in col_phys.items():
+            P[k] = [float(x) for x in v[c]] if k == "site" else float(v[c])
+        cols.append((om, P, np.moveaxis(w.state(c, om.X[:, :, 0]), 0, 1).copy()))
+    u0 = np.concatenate([c[2].ravel() for c in cols])
+    v = synth.tangent(u0.shape, 6)
+    r = gm.residual(to_dev(u0), t=t0).cpu().numpy()
+    jv = gm.jvp(to_dev(u0), to_dev(v), t=t0).cpu().numpy()
+    for c, (om, P, uc) in enumerate(cols):
+        R, scale = odg.residual_parts(om, P, uc, t0)
+        assert np.max(np.abs(r[off[c]:off[c + 1]].reshape(uc.shape) - R)) < 1e-12 * np.max(scale), c
+        ref = ojac.jvp_complex(om, P, uc, v[off[c]:off[c + 1]].reshape(uc.shape), t0)
+        jc = jv[off[c]:off[c + 1]].reshape(uc.shape)
+        assert np.linalg.norm(jc - ref) / np.linalg.norm(ref) < 1e-12, c
+    ut = to_dev(u0)
+    its, st = gm.columns_integrate(ut, t0, w.dt, 2, scheme=22, newton_rtol=1e-11)
+    assert np.all(st == 0)
+    out = ut.cpu().numpy()
+    for c, (om, P, uc) in enumerate(cols):
+        ref = uc.copy()
+        for s in range(2):
+            ref, _ = timeint.implicit_step_dense(om, P, ref, t0 + s * w.dt, w.dt, scheme=22, rtol=1e-13)
+        got = out[off[c]:off[c + 1]].reshape(uc.shape)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref - uc) < 1e-6, c
