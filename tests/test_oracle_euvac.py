@@ -76,3 +76,26 @@ def test_column_absorbs_what_the_optical_depth_removes():
     want = P["euv_q_scale"] / P["euv_col_scale"] * np.sum(flux * (1.0 - np.exp(-tau_b)))
     assert sig.shape == (37,)
     assert abs(got / want - 1.0) < 3e-3, (got, want)
+
+
+@pytest.mark.parametrize("lat,lon,hours", [(42.6347, -71.4883, 3.0), (-33.3458, -70.6786, 17.5), (-0.1859, -78.4663, 11.0)])
+def test_column_zenith_angle_closed_form(lat, lon, hours):
+    """a sited column's cos chi equals section 2.2's sin(delta) sin(theta) + cos(delta)
+    cos(theta) cos(h), h the hour angle between the site and the sub-solar meridian that
+    moves west at the rotation rate (the sweep's convention: sub-solar longitude 180
+    degrees at t = 0)"""
+    from oracle import physics
+    P = synth.base_physics(1)
+    P.update(synth.euvac_physics(day=166.0))
+    P["sun_lon0"] = np.pi
+    P["sun_lat"] = euvac.declination(166.0)
+    P["site"] = synth.site_vector(lat, lon)
+    t = synth.seconds_to_nondim(hours * 3600.0)
+    dec = euvac.declination(166.0)
+    th = np.deg2rad(lat)
+    sub_lon = np.pi - synth.OMEGA0 * hours * 3600.0
+    h = np.deg2rad(lon) - sub_lon
+    want = np.sin(dec) * np.sin(th) + np.cos(dec) * np.cos(th) * np.cos(h)
+    assert abs(physics.column_cos_zenith(t, P) - want) < 1e-12
+    sh = euvac.sun_vector(t, P)
+    assert abs(float(np.dot(P["site"], sh)) - want) < 1e-12
