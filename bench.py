@@ -172,7 +172,7 @@ def implicit_steps(w, mesh, u, n_steps, only=None):
     res = {"dt_s": 60.0, "newton_rtol": 1e-8,
            "gmres": "GMRES(30), CGS2, radial-line block-Jacobi preconditioner, Eisenstat-Walker tolerances",
            "steps": n_steps, "filter_rate": FILTER_RATE}
-    runs = [(prec, 2, prec, 0) for prec in ("f64", "f32") + (("bf16",) if w.p == 3 else ())]
+    runs = [(prec, 2, prec, 0) for prec in ("f64", "f32") + (("bf16",) if w.p in (3, 4) else ())]
     runs.append(("f32_rb4", 2, "f32", 4))   # plus the reduced basis of the 4 latest Newton updates
     runs.append(("f32_no_precond", 0, "f32", 0))
     if only:
@@ -419,8 +419,8 @@ def main():
     f_r = lambda: mesh.residual(u, t, out=r)
     f_j64 = lambda: mesh.jvp(u, v, t, "f64", out=jv)
     f_j32 = lambda: mesh.jvp(u, v32, t, "f32", out=jv32)
-    jvb = torch.empty_like(v32) if w.p == 3 else None
-    f_jb = (lambda: mesh.jvp(u, v32, t, "bf16", out=jvb)) if w.p == 3 else None
+    jvb = torch.empty_like(v32) if w.p in (3, 4) else None
+    f_jb = (lambda: mesh.jvp(u, v32, t, "bf16", out=jvb)) if w.p in (3, 4) else None
     if args.only == "residual":
         for _ in range(args.warmup):
             f_r()

@@ -141,7 +141,7 @@ dg_status_t dg_residual(dg_mesh_t mesh, double t, const double* u, double* r, in
  * finite difference of R; dual-number arithmetic gives the same product without the
  * step error). u: device double [n_dof]; v and jv: device arrays [n_dof] of the
  * precision `prec` (DG_F64: double, DG_F32: float); jv must not alias v or u.
- * The arithmetic runs in that precision. DG_BF16 (degree-3 shells only, else
+ * The arithmetic runs in that precision. DG_BF16 (shells of degree 3 and 4 only, else
  * DG_ERR_UNSUPPORTED): v and jv are float; the tangent's gradient and the divergence
  * of the linearised flux are bf16 MFMA products (operands rounded to bf16, FP32
  * accumulation) of the dense reference derivative operators, the rest as DG_F32.
@@ -158,7 +158,7 @@ typedef struct {
   double newton_rtol;      /* stop when |G(U)| <= newton_rtol |G(u_n)| (1e-8) */
   double gmres_rtol;       /* inexact Newton: relative GMRES tolerance (1e-3) */
   int32_t jvp_prec;        /* dg_prec_t of J v inside GMRES (DG_F32 and DG_BF16 keep FP32 Krylov vectors;
-                              DG_BF16 needs a degree-3 shell) */
+                              DG_BF16 needs a shell of degree 3 or 4) */
   int32_t precond;         /* shell meshes: 0 none; 1 node 5x5 block Jacobi (q held fixed, rebuilt every
                               Newton iteration); 2 radial-line block Jacobi: I - dt a_ii J_rad with J_rad
                               the linearisation that drops the tangent's coupling between different

@@ -213,8 +213,8 @@ dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys,
     free_mesh(m);
     return DG_ERR_ALLOC;
   }
-  if (m->kind == DG_MESH_SHELL && m->p == 3) {
-    const std::vector<uint16_t> ops = bf16_operators(3);
+  if (m->kind == DG_MESH_SHELL && (m->p == 3 || m->p == 4)) {
+    const std::vector<uint16_t> ops = bf16_operators(m->p);
     if (hipMalloc(&m->d_bf16op, ops.size() * sizeof(uint16_t)) != hipSuccess ||
         hipMemcpy(m->d_bf16op, ops.data(), ops.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
       set_error("dg_mesh_create: device allocation of the bf16 operators failed");

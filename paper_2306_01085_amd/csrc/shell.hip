@@ -632,21 +632,28 @@ dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v,
 // D1 = D x I x I, D2 = I x D x I, D3 = I x I x D (64 x 64 at p = 3, bf16 in global
 // memory) with the tangent-derived operands rounded to bf16 in LDS. The state's gradient,
 // the pointwise linearisation (FP32 dual numbers) and the face terms are those of the
-// FP32 J v. Degree 3, two elements (two wavefronts) per block; each wavefront computes a
-// 32-node row tile of both elements' columns.
+// FP32 J v. Degrees 3 and 4, two elements per block; the node dimension is padded to
+// NP = the element's thread count (64 at p = 3, 128 at p = 4 with 125 nodes), so that
+// each wavefront computes one 32-node row tile of both elements' columns.
 constexpr int BF_EPB = 2;
-// operand space: gradient B1 [32][128] and B3 [32][64] (bf16), outputs C1 [64][30] and
-// C3 [64][10] (f32); the divergence's Bd [32][192] (bf16) and Cd [64][10] reuse it
-constexpr int BF_MM_BYTES = 32 * 128 * 2 + 32 * 64 * 2 + 64 * 30 * 4 + 64 * 10 * 4;
+template <int P> struct BfShape {
+  static constexpr int NP = Shape<P>::TPE;                       // padded node count
+  static constexpr int THREADS = BF_EPB * Shape<P>::TPE;
+  // operand space: gradient B1 [32][2NP] and B3 [32][NP] (bf16), outputs C1 [NP][30] and
+  // C3 [NP][10] (f32); the divergence's Bd [32][3NP] (bf16) and Cd [NP][10] reuse it
+  static constexpr int MM_BYTES = 32 * 2 * NP * 2 + 32 * NP * 2 + NP * 30 * 4 + NP * 10 * 4;
+};
 
-__global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, PhysC ph, GllC gc, double t,
-                                                                const double* __restrict__ u,
-                                                                const float* __restrict__ v,
-                                                                const uint16_t* __restrict__ ops,
-                                                                float* __restrict__ R, float* __restrict__ Fn) {
+template <int P>
+__global__ __launch_bounds__(BfShape<P>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) void shell_pass1_bf16(ShellDev M, PhysC ph, GllC gc, double t,
+                                                                       const double* __restrict__ u,
+                                                                       const float* __restrict__ v,
+                                                                       const uint16_t* __restrict__ ops,
+                                                                       float* __restrict__ R, float* __restrict__ Fn) {
   typedef Dual<float> S;
   typedef float T;
-  constexpr int P = 3, n = 4, N = 64, N2 = 16, TPE = 64, EPB = BF_EPB;
+  constexpr int n = Shape<P>::n, N = Shape<P>::N, N2 = Shape<P>::N2, TPE = Shape<P>::TPE, EPB = BF_EPB;
+  constexpr int NP = BfShape<P>::NP, BF_MM_BYTES = BfShape<P>::MM_BYTES;
   __shared__ double s_ang[EPB][13][N2];
   __shared__ S s_u[EPB][5][N];
   __shared__ S s_f[EPB][6][5][N2];
@@ -655,20 +662,20 @@ __global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, Phys
   __shared__ double D[n * n];
   __shared__ __align__(16) unsigned char s_mm[BF_MM_BYTES];
   uint16_t* B1 = (uint16_t*)s_mm;
-  uint16_t* B3 = B1 + 32 * 128;
-  float* C1 = (float*)(B3 + 32 * 64);
-  float* C3 = C1 + 64 * 30;
+  uint16_t* B3 = B1 + 32 * 2 * NP;
+  float* C1 = (float*)(B3 + 32 * NP);
+  float* C3 = C1 + NP * 30;
   uint16_t* Bd = (uint16_t*)s_mm;
-  float* Cd = (float*)(Bd + 32 * 192);
-  const uint16_t* opG1 = ops;                 // [64][128] = [D1 | D2]
-  const uint16_t* opG3 = ops + 64 * 128;      // [64][64]  = D3
-  const uint16_t* opDv = opG3 + 64 * 64;      // [64][192] = [D1 D2 D3]
+  float* Cd = (float*)(Bd + 32 * 3 * NP);
+  const uint16_t* opG1 = ops;                      // [NP][2NP] = [D1 | D2]
+  const uint16_t* opG3 = ops + NP * 2 * NP;        // [NP][NP]  = D3
+  const uint16_t* opDv = opG3 + NP * NP;           // [NP][3NP] = [D1 D2 D3]
   const int wave = threadIdx.x >> 6;
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
   const int e = blockIdx.x * EPB + le;
   const bool live = e < M.E;
-  const bool active = live;
+  const bool active = live && j < N;
   const int cell = live ? e / M.n_rad : 0;
   const int k = live ? e % M.n_rad : 0;
   if (threadIdx.x < n * n) D[threadIdx.x] = gc.D[threadIdx.x];
@@ -733,8 +740,10 @@ __global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, Phys
       }
       for (int c = 0; c < 5; ++c) s_f[le][f][c][m] = du[c];
     }
-  // tangent operands of the gradient products: B1[col][k] = A1_d(k) v(k) (k < 64) and
-  // A2_d(k - 64) v(k - 64); B3[col][k] = r_k^2 v(k); col = d * 10 + field * 2 + element
+  // tangent operands of the gradient products: B1[col][k] = A1_d(k) v(k) (k < NP) and
+  // A2_d(k - NP) v(k - NP); B3[col][k] = r_k^2 v(k); col = d * 10 + field * 2 + element.
+  // The padding nodes N <= k < NP get zeros (the operators' padding columns are zero, and
+  // stale LDS could hold non-finite bits).
   const int a = j % n, b = (j / n) % n, cz = j / N2;
   if (active) {
     const int ja = a + n * b;
@@ -742,18 +751,26 @@ __global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, Phys
     for (int c = 0; c < 5; ++c) {
       const float vd = s_u[le][c][j].d;
       for (int d = 0; d < 3; ++d) {
-        B1[(d * 10 + c * 2 + le) * 128 + j] = f2bf((float)s_ang[le][d][ja] * vd);
-        B1[(d * 10 + c * 2 + le) * 128 + 64 + j] = f2bf((float)s_ang[le][3 + d][ja] * vd);
+        B1[(d * 10 + c * 2 + le) * 2 * NP + j] = f2bf((float)s_ang[le][d][ja] * vd);
+        B1[(d * 10 + c * 2 + le) * 2 * NP + NP + j] = f2bf((float)s_ang[le][3 + d][ja] * vd);
       }
-      B3[(c * 2 + le) * 64 + j] = f2bf((float)(rj * rj) * vd);
+      B3[(c * 2 + le) * NP + j] = f2bf((float)(rj * rj) * vd);
+    }
+  } else if (j >= N) {
+    for (int c = 0; c < 5; ++c) {
+      for (int d = 0; d < 3; ++d) {
+        B1[(d * 10 + c * 2 + le) * 2 * NP + j] = 0;
+        B1[(d * 10 + c * 2 + le) * 2 * NP + NP + j] = 0;
+      }
+      B3[(c * 2 + le) * NP + j] = 0;
     }
   }
   __syncthreads();
   {
     v16f acc1, acc3;
     for (int i = 0; i < 16; ++i) acc1[i] = acc3[i] = 0.f;
-    mfma_tile_lds_global(acc1, opG1 + 32 * wave * 128, 128, B1, 128, 128);
-    mfma_tile_lds_global(acc3, opG3 + 32 * wave * 64, 64, B3, 64, 64);
+    mfma_tile_lds_global(acc1, opG1 + 32 * wave * 2 * NP, 2 * NP, B1, 2 * NP, 2 * NP);
+    mfma_tile_lds_global(acc3, opG3 + 32 * wave * NP, NP, B3, NP, NP);
     const int col = threadIdx.x & 31;
     for (int a2 = 0; a2 < 16; ++a2) {
       const int row = 32 * wave + mfma_out_row(a2);
@@ -862,15 +879,20 @@ __global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, Phys
     }
   }
   __syncthreads();   // every node has read C1 and C3: the operand space takes the divergence
-  // divergence operands Bd[col][a * 64 + node] = dG^a (col = field * 2 + element)
-  if (active)
+  // divergence operands Bd[col][a * NP + node] = dG^a (col = field * 2 + element), zeros
+  // at the padding nodes
+  if (active) {
     for (int c = 0; c < 5; ++c)
-      for (int dd = 0; dd < 3; ++dd) Bd[(c * 2 + le) * 192 + dd * 64 + j] = f2bf(G[c][dd].d);
+      for (int dd = 0; dd < 3; ++dd) Bd[(c * 2 + le) * 3 * NP + dd * NP + j] = f2bf(G[c][dd].d);
+  } else if (j >= N) {
+    for (int c = 0; c < 5; ++c)
+      for (int dd = 0; dd < 3; ++dd) Bd[(c * 2 + le) * 3 * NP + dd * NP + j] = 0;
+  }
   __syncthreads();
   {
     v16f accd;
     for (int i = 0; i < 16; ++i) accd[i] = 0.f;
-    mfma_tile_lds_global(accd, opDv + 32 * wave * 192, 192, Bd, 192, 192);
+    mfma_tile_lds_global(accd, opDv + 32 * wave * 3 * NP, 3 * NP, Bd, 3 * NP, 3 * NP);
     const int col = threadIdx.x & 31;
     for (int a2 = 0; a2 < 16; ++a2) {
       const int row = 32 * wave + mfma_out_row(a2);
@@ -904,49 +926,58 @@ __global__ __launch_bounds__(64 * BF_EPB) void shell_pass1_bf16(ShellDev M, Phys
 }
 
 dg_status_t shell_jvp_bf16(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
-  if (m->p != 3 || !m->d_bf16op) {
-    set_error("dg_jvp: the BF16 J v is available for degree 3 shells");
+  if ((m->p != 3 && m->p != 4) || !m->d_bf16op) {
+    set_error("dg_jvp: the BF16 J v is available for shells of degree 3 and 4");
     return DG_ERR_UNSUPPORTED;
   }
   ShellDev M = m->shell();
-  const GllC gc = make_gllc(3);
+  const GllC gc = make_gllc(m->p);
   PhysC ph = m->phys;
   sun_direction(ph, t);
+  const unsigned blocks = (unsigned)((M.E + BF_EPB - 1) / BF_EPB);
   {
     ProfScope ps(m, 14, s);
-    shell_pass1_bf16<<<(M.E + BF_EPB - 1) / BF_EPB, 64 * BF_EPB, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv,
-                                                                       m->d_fn32);
+    if (m->p == 3)
+      shell_pass1_bf16<3><<<blocks, BfShape<3>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
+    else
+      shell_pass1_bf16<4><<<blocks, BfShape<4>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
   }
   {
     ProfScope ps(m, 15, s);
-    shell_pass2<3, float><<<(M.E + Shape<3>::EPB - 1) / Shape<3>::EPB, 256, 0, s>>>(M, gc, m->d_fn32, jv);
+    if (m->p == 3)
+      shell_pass2<3, float><<<(M.E + Shape<3>::EPB - 1) / Shape<3>::EPB, 256, 0, s>>>(M, gc, m->d_fn32, jv);
+    else
+      shell_pass2<4, float><<<(M.E + Shape<4>::EPB - 1) / Shape<4>::EPB, 256, 0, s>>>(M, gc, m->d_fn32, jv);
   }
   DG_HIP_CHECK(hipGetLastError());
   return DG_OK;
 }
 
-// the dense bf16 reference operators of the BF16 J v (degree 3): [D1 | D2] (64 x 128),
-// D3 (64 x 64), [D1 D2 D3] (64 x 192), row-major, node j = a + 4 b + 16 c
+// the dense bf16 reference operators of the BF16 J v (degrees 3 and 4), zero-padded to NP
+// nodes (64 at p = 3, 128 at p = 4): [D1 | D2] (NP x 2NP), D3 (NP x NP), [D1 D2 D3] (NP x 3NP),
+// row-major, D1 = D x I x I etc. on the element's node order j = a + n b + n^2 c
 std::vector<uint16_t> bf16_operators(int p) {
   const Gll g = make_gll(p);
   const int n = p + 1, N = n * n * n;
+  const int NP = (p == 3) ? BfShape<3>::NP : BfShape<4>::NP;
   auto Dk = [&](int dir, int j, int k2) -> double {
+    if (j >= N || k2 >= N) return 0.0;
     const int a = j % n, b = (j / n) % n, c = j / (n * n);
     const int a2 = k2 % n, b2 = (k2 / n) % n, c2 = k2 / (n * n);
     if (dir == 0) return (b == b2 && c == c2) ? g.D[a * n + a2] : 0.0;
     if (dir == 1) return (a == a2 && c == c2) ? g.D[b * n + b2] : 0.0;
     return (a == a2 && b == b2) ? g.D[c * n + c2] : 0.0;
   };
-  std::vector<uint16_t> out((size_t)N * 2 * N + (size_t)N * N + (size_t)N * 3 * N);
+  std::vector<uint16_t> out((size_t)NP * 2 * NP + (size_t)NP * NP + (size_t)NP * 3 * NP);
   uint16_t* g1 = out.data();
-  uint16_t* g3 = g1 + N * 2 * N;
-  uint16_t* dv = g3 + N * N;
-  for (int j = 0; j < N; ++j)
-    for (int k2 = 0; k2 < N; ++k2) {
-      g1[j * 2 * N + k2] = f2bf((float)Dk(0, j, k2));
-      g1[j * 2 * N + N + k2] = f2bf((float)Dk(1, j, k2));
-      g3[j * N + k2] = f2bf((float)Dk(2, j, k2));
-      for (int dd = 0; dd < 3; ++dd) dv[j * 3 * N + dd * N + k2] = f2bf((float)Dk(dd, j, k2));
+  uint16_t* g3 = g1 + (size_t)NP * 2 * NP;
+  uint16_t* dv = g3 + (size_t)NP * NP;
+  for (int j = 0; j < NP; ++j)
+    for (int k2 = 0; k2 < NP; ++k2) {
+      g1[j * 2 * NP + k2] = f2bf((float)Dk(0, j, k2));
+      g1[j * 2 * NP + NP + k2] = f2bf((float)Dk(1, j, k2));
+      g3[j * NP + k2] = f2bf((float)Dk(2, j, k2));
+      for (int dd = 0; dd < 3; ++dd) dv[j * 3 * NP + dd * NP + k2] = f2bf((float)Dk(dd, j, k2));
     }
   return out;
 }

@@ -1040,7 +1040,7 @@ dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg
     return DG_ERR_UNSUPPORTED;
   }
   if (o.jvp_prec == DG_BF16 && !(m->kind == DG_MESH_SHELL && m->d_bf16op)) {
-    set_error("dg_implicit_step: the BF16 J v is available for degree 3 shells");
+    set_error("dg_implicit_step: the BF16 J v is available for shells of degree 3 and 4");
     return DG_ERR_UNSUPPORTED;
   }
   m->krylov_bf16 = (o.jvp_prec == DG_BF16);

@@ -80,12 +80,14 @@ def test_shell_jvp_parity(p):
     assert np.linalg.norm(jv32 - ref) / np.linalg.norm(ref) < 1e-5
 
 
-def test_shell_jvp_bf16_error():
-    """the BF16-MFMA J v (degree 3): within the stated 3e-2 of the exact product in the
-    2-norm, and the rounding is really in effect (not the FP32 product)"""
+@pytest.mark.parametrize("p,n_ang,n_rad", [(3, 2, 2), (4, 1, 3)])
+def test_shell_jvp_bf16_error(p, n_ang, n_rad):
+    """the BF16-MFMA J v (degrees 3 and 4, the latter with 125 of 128 padded nodes): within
+    the stated 3e-2 of the exact product in the 2-norm, and the rounding is really in
+    effect (not the FP32 product)"""
     need_gpu()
-    w = synth.shell_workload(21, p=3, n_ang=2, n_rad=2)
-    om, gm = shell_pair(w, 2, 2, 3)
+    w = synth.shell_workload(21, p=p, n_ang=n_ang, n_rad=n_rad)
+    om, gm = shell_pair(w, n_ang, n_rad, p)
     u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
     v = synth.tangent(u.shape, 5)
     t = 0.3
