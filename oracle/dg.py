@@ -116,7 +116,7 @@ def residual(mesh, P, u, t=0.0, q=None):
     qn = np.moveaxis(q, 1, 0)                         # [f, E, d, N] -> index as [c][k]
     qn = np.moveaxis(qn, 2, 1)                        # [f, d, E, N]
     xn = np.moveaxis(mesh.X, 2, 0)                    # [d, E, N]
-    F = _arr2(ph.flux(un, qn, P, np), un[0])          # [f, d, E, N]
+    F = _arr2(ph.flux(un, qn, P, np, xn), un[0])      # [f, d, E, N]
     S = _arr(ph.source(un, qn, xn, t, P, np), un[0])  # [f, E, N]
     R = np.zeros((f, E, N), dtype=u.dtype)
     for a in range(d):
@@ -135,17 +135,17 @@ def residual(mesh, P, u, t=0.0, q=None):
         safe = np.where(nb >= 0, nb, 0)
         uout = unodes[:, safe]
         qout = qnodes[:, :, safe]
-        Fout = _arr2(ph.flux(uout, qout, P, np), uout[0])
+        Xf = np.moveaxis(mesh.X[:, nodes, :], 2, 0)                  # [d, E, Nf]
+        Fout = _arr2(ph.flux(uout, qout, P, np, Xf), uout[0])
         uhat = uh[fi]
-        sig = _arr(ph.sigma(uhat, P, np), uhat[0])
+        sig = _arr(ph.sigma(uhat, P, np, Xf), uhat[0])
         Fh_int = 0.5 * (_dot_n(Fin, Sn, d) + _dot_n(Fout, Sn, d)) + Smag * sig * (uin - uhat)
         # boundary versions
-        Xf = np.moveaxis(mesh.X[:, nodes, :], 2, 0)
         ub = boundary_value(mesh, P, uin, Xf)
-        Fb = _arr2(ph.flux(ub, qin, P, np), ub[0])
-        sigb = _arr(ph.sigma(ub, P, np), ub[0])
+        Fb = _arr2(ph.flux(ub, qin, P, np, Xf), ub[0])
+        sigb = _arr(ph.sigma(ub, P, np, Xf), ub[0])
         Fh_dir = _dot_n(Fb, Sn, d) + Smag * sigb * (uin - ub)
-        Fi_top = _arr2(ph.flux_inviscid(uin, P, np), uin[0])
+        Fi_top = _arr2(ph.flux_inviscid(uin, P, np, Xf), uin[0])
         Fh_top = _dot_n(Fi_top, Sn, d) + top_penalty(P, uin, Sn, Smag, d)
         tag = mesh.tag[:, fi][None, :, None]
         if P.get("bc_mode", 0) == 1:
@@ -170,7 +170,7 @@ def residual_parts(mesh, P, u, t=0.0):
     qn = np.moveaxis(np.moveaxis(q, 1, 0), 2, 1)
     xn = np.moveaxis(mesh.X, 2, 0)
     S = _arr(ph.source(un, qn, xn, t, P0, np), un[0])
-    F = _arr2(ph.flux(un, qn, P0, np), un[0])
+    F = _arr2(ph.flux(un, qn, P0, np, xn), un[0])
     V = np.zeros_like(S)
     for a in range(d):
         G = ref.W[None, None, :] * np.einsum("eik,ckei->cei", mesh.Ja[:, :, a, :], F)
@@ -207,10 +207,10 @@ def conservation_terms(mesh, P, u, t=0.0):
         qin = qn[:, :, :, nodes]
         Xf = np.moveaxis(mesh.X[:, nodes, :], 2, 0)
         ub = boundary_value(mesh, P, uin, Xf)
-        Fb = _arr2(ph.flux(ub, qin, P, np), ub[0])
-        sigb = _arr(ph.sigma(ub, P, np), ub[0])
+        Fb = _arr2(ph.flux(ub, qin, P, np, Xf), ub[0])
+        sigb = _arr(ph.sigma(ub, P, np, Xf), ub[0])
         Fh_dir = _dot_n(Fb, Sn, d) + Smag * sigb * (uin - ub)
-        Fh_top = _dot_n(_arr2(ph.flux_inviscid(uin, P, np), uin[0]), Sn, d) + top_penalty(P, uin, Sn, Smag, d)
+        Fh_top = _dot_n(_arr2(ph.flux_inviscid(uin, P, np, Xf), uin[0]), Sn, d) + top_penalty(P, uin, Sn, Smag, d)
         t_ = tag[None, :, None]
         if P.get("bc_mode", 0) == 1:
             Fh = np.where(t_ > 0, Fh_dir, 0.0)

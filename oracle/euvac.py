@@ -15,9 +15,10 @@ day of the year) and the local time; here the sub-solar point is a latitude (the
 declination) and a longitude moving at the rotation rate, as for the prescribed heating.
 
 Readings (the paper is silent or ambiguous):
-  * composition: constant mole fractions chi_s of N2, O2, O, He (the fits of the
-    composition are not available); n_s = chi_s n with n = rho / m-bar, m-bar the model's
-    constant mean molecular mass;
+  * composition: with the constant mean mass, constant mole fractions chi_s of N2, O2,
+    O, He (P["euv_chi"]), n_s = chi_s n with n = rho / m-bar; with the variable
+    composition (P["composition"], composition.py), the number densities of the fitted
+    mass fractions, n_s = rho chi_s(r) / m_s, and H with the mixture's m(r);
   * one attenuation per bin by the total optical depth tau^j = sum_s tau_s^j (the
     formula's per-species index on I is read as the usual total column);
   * Table A's photon fluxes carry the exponent +13 (m^-2 s^-1), its cross sections
@@ -29,10 +30,13 @@ H0, H = T |r|^2 / (m r_ref^2) and
   Q = rho sum_j K_j exp(-kappa_j rho H C),
   K_j = eps (hc/lambda_j) I_0^j sigma_j (rho0 / (m m_O)) / Q_unit,
   kappa_j = sigma_j rho0 H0 / (m m_O),   sigma_j = sum_s chi_s phi_s^j.
-P carries q_scale = rho0 / (m_O Q_unit) and col_scale = rho0 H0 / m_O.
+P carries q_scale = rho0 / (m_O Q_unit) and col_scale = rho0 H0 / m_O. With the variable
+composition sigma_j / m becomes sum_s (chi_s(r) / m_s) phi_s^j at every node.
 """
 import numpy as np
 from scipy.special import erfcx
+
+from . import composition
 
 H_PLANCK = 6.62607015e-34
 C_LIGHT = 2.99792458e8
@@ -164,9 +168,21 @@ def heating(x, t, rho, T, P):
         else:
             sh = sun_vector(t, P)
             cchi = np.full_like(r, sum(site[k] * sh[k] for k in range(3)))
-    H = T * r2 / (P["m"] * P["r_ref"] ** 2)
+    if composition.enabled(P):
+        m = composition.mean_mass(r, P, np)
+        chi = composition.mass_fractions(r, P, np)
+        phi = np.array([row[3:7] for row in TABLE_A]) * 1e-22           # [bin, N2 O2 O He]
+        # sum_s n_s phi_s^j / rho, n_s = rho chi_s / m_s (m_O units)
+        sig_n = sum(np.multiply.outer(phi[:, i], chi[s] / composition.MASS[s])
+                    for i, s in enumerate(composition.SPECIES))          # [bin, nodes]
+        flux = P["euv_eps"] * photon_energy() * photon_flux(P["euv_f107"], P["euv_sun_dist"])
+        K = [flux[j] * P["euv_q_scale"] * sig_n[j] for j in range(len(TABLE_A))]
+        kap = [P["euv_col_scale"] * sig_n[j] for j in range(len(TABLE_A))]
+    else:
+        m = P["m"]
+        K, kap = bin_constants(P)
+    H = T * r2 / (m * P["r_ref"] ** 2)
     C = chapman(r / H, cchi, r / P["r_ref"])
-    K, kap = bin_constants(P)
     Q = 0.0 * rho
     shade = np.isinf(np.real(C))
     Cs = np.where(shade, 0.0, C)

@@ -5,9 +5,13 @@ and Theta = sqrt(rho) T (section 2.4). Fluxes and sources follow eq.
 (fluxSWNondimensional); the acceleration follows the nondimensional form given right
 after it (gravity / gamma, centripetal Fr^2/gamma, Coriolis 2 Fr/sqrt(gamma)); the
 transport coefficients are the molecular + eddy laws of section 2.1.2 normalised by
-their lower-boundary values: mu = sqrt(T m) + nu_r rho, kappa = alpha0c T^0.69 +
-alpha_r rho c_p, with c_v = c_p = 1/m for a constant mean molecular mass m (the
-grad(c_v) source term then vanishes).
+their lower-boundary values: mu = sqrt(T m) + nu_r rho, kappa = alpha0c w T^0.69 +
+alpha_r rho c_p, with c_v = c_p = 1/m. The mean molecular mass m is either a constant
+(P["m"]; the conductivity's species weight w = 1 and the grad(c_v) source term vanishes)
+or, with P["composition"], the chemically frozen mixture of section 2.1.1
+(composition.py): m(r) and w(r) from the fitted mass fractions, and the energy equation
+carries -(1/c_v)(Theta v - conductive flux) . grad c_v. Quantities that depend on m take
+the node positions x.
 
 Every function takes plain component lists and a math namespace `xp` (numpy for
 numbers, including complex numbers for the complex step; sympy for the symbolic
@@ -15,11 +19,20 @@ check of the transformation from eq. (NS1)).
 """
 import numpy as np
 
+from . import composition
 
-def _consts(P, xp):
+
+def mixture(P, xp, x):
+    """(m, conductivity weight) at the points x (list of d coordinate arrays)"""
+    if composition.enabled(P) and x is None:
+        raise ValueError("the variable composition needs the node positions")
+    return composition.at(x, P, xp) if x is not None else (P["m"], 1.0)
+
+
+def _consts(P, xp, m):
     g = P["gamma"]
     return dict(
-        inv_gm=1.0 / (g * P["m"]),
+        inv_gm=1.0 / (g * m),
         c_visc=1.0 / xp.sqrt(g * P["Gr"]),
         c_cond=(1.0 / P["Pr"]) * xp.sqrt(g / P["Gr"]),
         c_diss=(g - 1.0) * xp.sqrt(g / P["Gr"]),
@@ -38,10 +51,10 @@ def primitives(u, P, xp):
     return lr, U, Th, rho, s, v, T
 
 
-def transport(rho, T, P, xp):
-    m = P["m"]
+def transport(rho, T, P, xp, x=None):
+    m, w = mixture(P, xp, x)
     mu = xp.sqrt(T * m) + P["nu_r"] * rho
-    kap = P["alpha0c"] * T ** P.get("kappa_exp", 0.69) + P["alpha_r"] * rho * (1.0 / m)
+    kap = P["alpha0c"] * w * T ** P.get("kappa_exp", 0.69) + P["alpha_r"] * rho * (1.0 / m)
     return mu, kap
 
 
@@ -62,9 +75,9 @@ def strain(gv, d):
     return eps, div
 
 
-def flux_inviscid(u, P, xp):
+def flux_inviscid(u, P, xp, x=None):
     d = P["d"]
-    C = _consts(P, xp)
+    C = _consts(P, xp, mixture(P, xp, x)[0])
     lr, U, Th, rho, s, v, T = primitives(u, P, xp)
     F = [[lr * v[k] for k in range(d)]]
     for i in range(d):
@@ -73,24 +86,25 @@ def flux_inviscid(u, P, xp):
     return F
 
 
-def flux_viscous(u, q, P, xp):
+def flux_viscous(u, q, P, xp, x=None):
     """the diffusive part of F, returned with the sign it has inside F"""
     d = P["d"]
-    C = _consts(P, xp)
+    m = mixture(P, xp, x)[0]
+    C = _consts(P, xp, m)
     lr, U, Th, rho, s, v, T = primitives(u, P, xp)
-    mu, kap = transport(rho, T, P, xp)
+    mu, kap = transport(rho, T, P, xp, x)
     gl, gv, gT = gradients(u, q, P, xp)
     eps, div = strain(gv, d)
     F = [[0.0 * lr for k in range(d)]]
     for i in range(d):
         F.append([-C["c_visc"] * mu * s * eps[i][k] for k in range(d)])
-    F.append([-C["c_cond"] * kap * s * P["m"] * gT[k] for k in range(d)])
+    F.append([-C["c_cond"] * kap * s * m * gT[k] for k in range(d)])
     return F
 
 
-def flux(u, q, P, xp):
-    Fi = flux_inviscid(u, P, xp)
-    Fv = flux_viscous(u, q, P, xp)
+def flux(u, q, P, xp, x=None):
+    Fi = flux_inviscid(u, P, xp, x)
+    Fv = flux_viscous(u, q, P, xp, x)
     return [[Fi[c][k] + Fv[c][k] for k in range(P["d"])] for c in range(P["d"] + 2)]
 
 
@@ -164,10 +178,10 @@ def acceleration_times_sqrt_rho(u, x, P, xp):
 def source(u, q, x, t, P, xp):
     d = P["d"]
     g = P["gamma"]
-    C = _consts(P, xp)
-    m = P["m"]
+    m = mixture(P, xp, x)[0]
+    C = _consts(P, xp, m)
     lr, U, Th, rho, s, v, T = primitives(u, P, xp)
-    mu, kap = transport(rho, T, P, xp)
+    mu, kap = transport(rho, T, P, xp, x)
     gl, gv, gT = gradients(u, q, P, xp)
     eps, div = strain(gv, d)
     S = [(lr - 1.0) * div]
@@ -183,24 +197,31 @@ def source(u, q, x, t, P, xp):
         Q = heating(x, t, P, xp)
     Tg = sum(gT[k] * gl[k] for k in range(d))
     ed = sum(eps[i][k] * gv[i][k] for i in range(d) for k in range(d))
-    S.append(Q * s * m + (1.5 - g) * Th * div + 0.5 * C["c_cond"] * kap * s * m * Tg
-             + C["c_diss"] * mu * s * m * ed)
+    Se = Q * s * m + (1.5 - g) * Th * div + 0.5 * C["c_cond"] * kap * s * m * Tg + C["c_diss"] * mu * s * m * ed
+    if composition.enabled(P):
+        # -(1/c_v) (Theta v - sqrt(gamma/Gr)/Pr kappa/(sqrt(rho) c_v) grad T) . grad c_v
+        r = xp.sqrt(sum(x[k] * x[k] for k in range(d)))
+        cv = composition.specific_heat(r, P, xp)
+        gcv = composition.grad_specific_heat(x, P, xp)
+        Se = Se - sum((Th * v[k] - C["c_cond"] * kap * s / cv * gT[k]) * gcv[k] for k in range(d)) / cv
+    S.append(Se)
     return S
 
 
-def sigma(uhat, P, xp):
+def sigma(uhat, P, xp, x=None):
     """stabilisation of eq. (LDG2): sigma_c = lambda_max I plus the diffusive block
     diag(0, mu/(sqrt(rho) sqrt(gamma Gr)) I_d, kappa/(Pr sqrt(rho) c_v) sqrt(gamma/Gr)),
     evaluated at the numerical trace."""
     d = P["d"]
-    C = _consts(P, xp)
+    m = mixture(P, xp, x)[0]
+    C = _consts(P, xp, m)
     lr, U, Th, rho, s, v, T = primitives(uhat, P, xp)
-    mu, kap = transport(rho, T, P, xp)
+    mu, kap = transport(rho, T, P, xp, x)
     lam = P["lam"]
     sig = [lam + 0.0 * lr]
     for i in range(d):
         sig.append(lam + C["c_visc"] * mu * s)
-    sig.append(lam + C["c_cond"] * kap * s * P["m"])
+    sig.append(lam + C["c_cond"] * kap * s * m)
     return sig
 
 

@@ -86,6 +86,46 @@ def euvac_physics(f107bar: float = 150.0, day: float = 0.0) -> dict:
                 euv_q_scale=RHO_REF / (M_O * Q_UNIT), euv_col_scale=RHO_REF * H0 / M_O)
 
 
+# Variable composition (section 2.1.1): two-exponential fits in |r| of the mass fractions of
+# N2, O2 and He, atomic oxygen closing the sum. The empirical model's averages are not
+# available, so these are synthetic, shaped like them between 100 and 600 km (N2 and O2
+# falling off, He growing, O the balance: mean mass about 28.5 amu at 100 km and 14.3 amu
+# at 600 km). Each term is (value at 100 km, e-folding length in km; negative: growing).
+COMPOSITION_FITS = (
+    ("N2", ((0.90, 180.0), (-0.145, 40.0))),
+    ("O2", ((0.26, 110.0), (-0.03, 30.0))),
+    ("He", ((1.0e-4, -85.0), (1.0e-5, -70.0))),
+)
+SPECIES_MASS = {"N2": 28.0134 / 15.9994, "O2": 31.9988 / 15.9994, "O": 1.0, "He": 4.002602 / 15.9994}
+
+
+def composition_physics() -> dict:
+    """the fit coefficients a_j^s, b_j^s of chi_s = sum_j a_j^s exp(b_j^s |r|) in the
+    model's units (|r| in H0), ordered N2 (j = 1, 2), O2, He"""
+    a, b = [], []
+    for _, terms in COMPOSITION_FITS:
+        for c, L in terms:
+            bj = -H0 / (L * 1e3)
+            a.append(c * math.exp(-bj * R_BOT))
+            b.append(bj)
+    return dict(composition=1, comp_a=a, comp_b=b)
+
+
+def mixture_mass(phys):
+    """the rest state's mean molecular mass m(r) (a callable) for a physics set with the
+    variable composition, else None (m = 1). It shapes the generated input state only."""
+    if not phys.get("composition", 0):
+        return None
+    a, b = phys["comp_a"], phys["comp_b"]
+
+    def m(r):
+        r = np.asarray(r, dtype=np.float64)
+        chi = [a[2 * i] * np.exp(b[2 * i] * r) + a[2 * i + 1] * np.exp(b[2 * i + 1] * r) for i in range(3)]
+        inv = sum(chi[i] / SPECIES_MASS[s] for i, (s, _) in enumerate(COMPOSITION_FITS))
+        return 1.0 / (inv + (1.0 - chi[0] - chi[1] - chi[2]) / SPECIES_MASS["O"])
+    return m
+
+
 # --------------------------------------------------------------------------
 # Bates temperature profile and its hydrostatic log-density
 def bates_T(r, T_inf):
@@ -98,9 +138,11 @@ def bates_T(r, T_inf):
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(24)
 
 
-def hydrostatic_logrho(r, T_inf, r_ref=R_BOT):
-    """log(rho/rho0) of the hydrostatic rest state with temperature bates_T and
-    gravity g = -(r_ref/r)^2 (m = 1):  d(rho T)/dr = -rho (r_ref/r)^2, rho(r_ref) = 1.
+def hydrostatic_logrho(r, T_inf, r_ref=R_BOT, mass=None):
+    """log(rho/rho0) of the hydrostatic rest state with temperature bates_T, gravity
+    g = -(r_ref/r)^2 and mean mass m(r) (`mass`, a callable; None: m = 1):
+    d(rho T / m)/dr = -rho (r_ref/r)^2, rho(r_ref) = 1, so that
+    log rho = log(m / m(r_ref)) - log T - int m / T (r_ref/x)^2 dx.
     Integrated with composite 24-point Gauss-Legendre between sorted radii (every gap
     split into equal panels no longer than 0.5 in H0 units)."""
     r = np.asarray(r, dtype=np.float64)
@@ -114,9 +156,13 @@ def hydrostatic_logrho(r, T_inf, r_ref=R_BOT):
     lo, hi = edges[:, :-1], edges[:, 1:]
     x = 0.5 * (hi + lo)[..., None] + 0.5 * (hi - lo)[..., None] * _GL_X
     f = (r_ref / x) ** 2 / bates_T(x, T_inf)
+    if mass is not None:
+        f = f * mass(x)
     integ = np.sum(0.5 * (hi - lo) * (f @ _GL_W), axis=1)
     cum = np.cumsum(integ)
     lr = -np.log(bates_T(uniq, T_inf)) - cum
+    if mass is not None:
+        lr = lr + np.log(mass(uniq) / mass(r_ref))
     return lr[inv].reshape(r.shape)
 
 
@@ -130,16 +176,20 @@ def chapman_params(T_inf, z_peak_km, amp):
     return dict(heat_amp=float(amp), heat_qm=q_m_si / Q_UNIT, heat_rm=r_m, heat_H=H_q)
 
 
-def sound_speed_max(T_inf):
-    """max over the rest state of |v| + sqrt(T/m): the top of the Bates profile"""
-    return float(math.sqrt(np.max(bates_T(np.array([R_BOT, R_TOP]), T_inf))))
+def sound_speed_max(T_inf, mass=None):
+    """max over the rest state of |v| + sqrt(T/m): the top of the Bates profile (m = 1),
+    or the maximum over radii with the mean mass m(r)"""
+    if mass is None:
+        return float(math.sqrt(np.max(bates_T(np.array([R_BOT, R_TOP]), T_inf))))
+    r = np.linspace(R_BOT, R_TOP, 513)
+    return float(math.sqrt(np.max(bates_T(r, T_inf) / mass(r))))
 
 
 # --------------------------------------------------------------------------
 # state generators (callables of node coordinates)
-def column_state(r, T_inf):
+def column_state(r, T_inf, mass=None):
     """(logrho, sqrt(rho) v_r, sqrt(rho) T) of the hydrostatic rest column"""
-    lr = hydrostatic_logrho(r, T_inf)
+    lr = hydrostatic_logrho(r, T_inf, mass=mass)
     T = bates_T(r, T_inf)
     return np.stack([lr, np.zeros_like(lr), np.exp(0.5 * lr) * T])
 
@@ -182,13 +232,13 @@ class ShellPerturbation:
         return self.angular(xyz / r[..., None]) * self.radial(r)
 
 
-def shell_state_fn(T_inf, pert: ShellPerturbation | None):
+def shell_state_fn(T_inf, pert: ShellPerturbation | None, mass=None):
     """hydrostatic Bates rest state on the shell plus smooth perturbations:
     logrho += d1, T *= (1 + d2), v += (d3, d4, d5) (so U = sqrt(rho) v)."""
     def fn(xyz):
         xyz = np.asarray(xyz, dtype=np.float64)
         r = np.linalg.norm(xyz, axis=-1)
-        lr = hydrostatic_logrho(r, T_inf)
+        lr = hydrostatic_logrho(r, T_inf, mass=mass)
         T = bates_T(r, T_inf)
         v = np.zeros(xyz.shape[:-1] + (3,))
         if pert is not None:
@@ -213,18 +263,19 @@ def shell_state_at(w, X):
     Xg = np.asarray(X, dtype=np.float64).reshape(A, w.n_rad, n, N2, 3)
     unit = Xg[:, 0, 0] / np.linalg.norm(Xg[:, 0, 0], axis=-1, keepdims=True)      # [A, N2, 3]
     radii = np.linalg.norm(Xg[0, :, :, 0], axis=-1)                               # [n_rad, n]
-    u = shell_state_product(w.T_inf, w.pert, unit.reshape(-1, 3), radii.ravel())  # [5, A*N2, n_rad*n]
+    u = shell_state_product(w.T_inf, w.pert, unit.reshape(-1, 3), radii.ravel(),
+                            mixture_mass(w.phys))                                 # [5, A*N2, n_rad*n]
     u = u.reshape(5, A, N2, w.n_rad, n)
     return np.ascontiguousarray(np.transpose(u, (1, 3, 0, 4, 2))).reshape(A * w.n_rad, 5, n * N2)
 
 
-def shell_state_product(T_inf, pert, unit, radii):
+def shell_state_product(T_inf, pert, unit, radii, mass=None):
     """the same state as shell_state_fn on the product of M angular directions
     (unit [M, 3]) and K radii ([K]): returns [5, M, K]. The perturbation is separable
     (angular harmonics times a radial sine), so it is evaluated once per direction."""
     unit = np.asarray(unit, dtype=np.float64)
     radii = np.asarray(radii, dtype=np.float64)
-    lr = hydrostatic_logrho(radii, T_inf)[None, :]
+    lr = hydrostatic_logrho(radii, T_inf, mass=mass)[None, :]
     T = bates_T(radii, T_inf)[None, :]
     if pert is not None:
         ang = pert.angular(unit)                    # [5, M]
@@ -258,7 +309,7 @@ class ColumnWorkload:
     n_steps: int = 200
 
     def state(self, col, r):
-        return column_state(r, self.T_inf[col])
+        return column_state(r, self.T_inf[col], mixture_mass(self.phys))
 
 
 @dataclass
@@ -278,7 +329,7 @@ class ShellWorkload:
     extra: dict = field(default_factory=dict)
 
     def state_fn(self):
-        return shell_state_fn(self.T_inf, self.pert)
+        return shell_state_fn(self.T_inf, self.pert, mixture_mass(self.phys))
 
     @property
     def n_elem(self):
