@@ -467,6 +467,16 @@ def main():
            "jvp_f64_gdofs": w.n_dof / timed(f_j64, args.steps) / 1e6,
            "jvp_f32_gdofs": w.n_dof / timed(f_j32, args.steps) / 1e6,
            "heating": "EUVAC, F10.7bar 150, day 80, efficiency 0.25"}
+    # and with the variable composition (fitted N2, O2, He fractions, O the balance): alone
+    # with the prescribed heating, and together with EUVAC
+    comp = {"fits": "synthetic two-exponential mass fractions (input generators)"}
+    for key, base in (("prescribed_heating", w.phys), ("euvac", phys_e)):
+        mesh.set_physics(dict(base, **synth.composition_physics()))
+        for _ in range(args.warmup):
+            f_r(); f_j64(); f_j32()
+        comp[key] = {"residual_gdofs": w.n_dof / timed(f_r, args.steps) / 1e6,
+                     "jvp_f64_gdofs": w.n_dof / timed(f_j64, args.steps) / 1e6,
+                     "jvp_f32_gdofs": w.n_dof / timed(f_j32, args.steps) / 1e6}
     mesh.set_physics(w.phys)
     if args.copy_probe:
         copy_probe(dev)
@@ -508,6 +518,7 @@ def main():
     }
     log("implicit steps")
     out["euvac"] = euv
+    out["composition"] = comp
     out["implicit_step"] = implicit_steps(w, mesh, u, args.implicit_steps)
     del r, jv, jv32, v, v32
     log("column batch")

@@ -112,6 +112,19 @@ typedef struct {
                                   site . sub-solar direction at time t; NULL: the Sun overhead */
   const double* col_euv_eps;   /* EUVAC efficiency (heating model 1) */
   const double* col_euv_f107;  /* EUVAC F10.7bar (heating model 1) */
+  /* composition 1: the chemically frozen mixture of section 2.1.1 replaces the constant m. The
+     mass fractions of N2, O2 and He are chi_s = a_1^s exp(b_1^s |r|) + a_2^s exp(b_2^s |r|) (|r|
+     nondimensional), O closes the sum to one; m = [sum_s chi_s / m_s]^-1 (masses over m_O:
+     N2 28.0134, O2 31.9988, He 4.002602 over 15.9994), c_v = c_p = 1/m, the molecular
+     conductivity takes the mole-fraction weight sum_s x_s alpha_s / alpha_O (section 2.1.2:
+     alpha = 3.6e-4 for N2 and O2, 5.6e-4 for O and He) as a factor of alpha0c, the energy
+     equation carries the grad c_v term of eq. (fluxSWNondimensional), and EUVAC (heating model 1)
+     takes the species number densities rho chi_s / m_s (euv_chi unused) and H with m(r). The
+     fractions must lie in [0, 1] over the mesh: dg_mesh_create and dg_mesh_set_physics check
+     them at the mesh's nodes and return DG_ERR_ARG otherwise. */
+  int32_t composition;
+  double comp_a[6];        /* a_1, a_2 of N2, then of O2, then of He */
+  double comp_b[6];        /* b_1, b_2 in the same order (per unit nondimensional radius) */
 } dg_physics_t;
 
 /* Create a mesh: builds GLL tables, the factored curved geometry (invariant curl
@@ -121,7 +134,9 @@ typedef struct {
 dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys, void* stream, dg_mesh_t* out);
 dg_status_t dg_mesh_destroy(dg_mesh_t mesh);
 /* Replace the physics parameters (host struct, copied). With heating_model 1 it waits for the
- * device to be idle, then uploads the EUVAC bin constants to the mesh's table. */
+ * device to be idle, then uploads the EUVAC bin constants to the mesh's table. An invalid
+ * parameter set (including mass fractions outside [0, 1] at the mesh's nodes) returns
+ * DG_ERR_ARG and leaves the mesh's physics unchanged. */
 dg_status_t dg_mesh_set_physics(dg_mesh_t mesh, const dg_physics_t* phys);
 
 /* Sizes: total DOF, elements, fields per node, dimension. Any output may be NULL. */

@@ -51,7 +51,8 @@ class Physics(C.Structure):
                 ("euv_sun_dist", C.c_double), ("euv_day", C.c_double), ("euv_chi", C.c_double * 4),
                 ("euv_q_scale", C.c_double), ("euv_col_scale", C.c_double),
                 ("col_alpha0c", C.POINTER(C.c_double)), ("col_site", C.POINTER(C.c_double)),
-                ("col_euv_eps", C.POINTER(C.c_double)), ("col_euv_f107", C.POINTER(C.c_double))]
+                ("col_euv_eps", C.POINTER(C.c_double)), ("col_euv_f107", C.POINTER(C.c_double)),
+                ("composition", C.c_int32), ("comp_a", C.c_double * 6), ("comp_b", C.c_double * 6)]
 
 
 class SolverOpts(C.Structure):
@@ -146,7 +147,11 @@ def make_physics(phys: dict, col_phys: dict | None = None):
     if P.heating_model == 1:
         for k in ("euv_eps", "euv_f107", "euv_sun_dist", "euv_day", "euv_q_scale", "euv_col_scale"):
             setattr(P, k, float(phys[k]))
-        P.euv_chi = (C.c_double * 4)(*[float(x) for x in phys["euv_chi"]])
+        P.euv_chi = (C.c_double * 4)(*[float(x) for x in phys.get("euv_chi", [0.0] * 4)])
+    P.composition = int(phys.get("composition", 0))
+    if P.composition:
+        P.comp_a = (C.c_double * 6)(*[float(x) for x in phys["comp_a"]])
+        P.comp_b = (C.c_double * 6)(*[float(x) for x in phys["comp_b"]])
     keep = []
     if col_phys:
         for key, field in (("heat_amp", "col_heat_amp"), ("heat_qm", "col_heat_qm"), ("heat_rm", "col_heat_rm"),

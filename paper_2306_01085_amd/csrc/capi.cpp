@@ -1,6 +1,7 @@
 // C-ABI entry points of libdgthermo: argument validation, ownership of device
 // buffers, error reporting. Every device computation is delegated to the HIP
 // kernels of shell.hip, column.hip and solver.hip.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -48,10 +49,36 @@ void fill_phys(PhysC& P, const dg_physics_t& in) {
   if (P.euv && in.euv_day > 0) P.sun_lat = euvac_declination(in.euv_day);
   P.bc_mode = in.bc_mode;
   for (int c = 0; c < 5; ++c) P.bc_state[c] = in.bc_state[c];
+  P.comp = in.composition ? 1 : 0;
+  for (int i = 0; i < 6; ++i) {
+    P.comp_a[i] = in.composition ? in.comp_a[i] : 0.0;
+    P.comp_b[i] = in.composition ? in.comp_b[i] : 0.0;
+  }
+}
+
+// radial extent of a mesh
+static void radial_range(const dg_mesh_s* m, double& lo, double& hi) {
+  if (m->kind == DG_MESH_SHELL) {
+    lo = m->h_edges.front();
+    hi = m->h_edges.back();
+    return;
+  }
+  lo = m->h_geo[0];
+  hi = m->h_geo[0] + m->h_geo[1];
+  for (size_t e = 0; 2 * e < m->h_geo.size(); ++e) {
+    lo = std::min(lo, m->h_geo[2 * e]);
+    hi = std::max(hi, m->h_geo[2 * e] + m->h_geo[2 * e + 1]);
+  }
 }
 
 // the physics of a mesh, with the EUVAC bin constants in a mesh-owned device table
 static dg_status_t set_phys(dg_mesh_s* m, const dg_physics_t& in) {
+  double lo, hi;
+  radial_range(m, lo, hi);
+  if (!composition_valid(in, lo, hi)) {
+    set_error("dg_mesh: the composition's mass fractions leave [0, 1] over the mesh");
+    return DG_ERR_ARG;
+  }
   fill_phys(m->phys, in);
   if (!m->phys.euv) return DG_OK;
   if (m->kind == DG_MESH_COLUMNS) {
@@ -64,8 +91,8 @@ static dg_status_t set_phys(dg_mesh_s* m, const dg_physics_t& in) {
     DG_HIP_CHECK(hipDeviceSynchronize());
     DG_HIP_CHECK(hipMemcpy(m->d_euv_cols, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
   }
-  double tab[74];
-  euvac_constants(in, tab, tab + 37);
+  double tab[EUVT];
+  euvac_constants(in, tab);
   if (!m->d_euv && hipMalloc(&m->d_euv, sizeof(tab)) != hipSuccess) {
     set_error("dg_mesh: device allocation of the EUVAC table failed");
     return DG_ERR_ALLOC;

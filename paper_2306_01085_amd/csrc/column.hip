@@ -28,7 +28,7 @@ __device__ inline void set_column_phys(PhysC& P, const double* __restrict__ cpar
   P.site[0] = cp[6];
   P.site[1] = cp[7];
   P.site[2] = cp[8];
-  if (euv) P.euv_tab = euv + 74 * col;
+  if (euv) P.euv_tab = euv + EUVT * col;
 }
 
 __device__ inline PhysC column_phys(const ColDev& C, const PhysC& ph, int col) {
@@ -45,8 +45,8 @@ struct ColElem {
   int64_t fslot, fslot_prev, fslot_next;   // Fn[(fslot*2 + side)*3 + c]
 };
 
-// EUV: the instantiation contains the EUVAC heating (used when the mesh's heating model is 1)
-template <int P, class S, bool EUV = false, class SU, class TV, class OT>
+// XP: the extended physics the instantiation contains (kXpEuv, kXpComp; PhysC::xp_mode)
+template <int P, class S, int XP = 0, class SU, class TV, class OT>
 __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& Pc, const GllC& gc, double t,
                                       const SU* __restrict__ u, const TV* __restrict__ v, OT* __restrict__ R,
                                       OT* __restrict__ Fn) {
@@ -102,7 +102,7 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
     }
     const double x = r0 + 0.5 * (xg[i] + 1.0) * h;
     const double Q = heating<1>(Pc, &x, t);
-    flux_source<1, S, EUV>(Pc, ui, qi, &x, Q, Fi, Si);
+    flux_source<1, S, XP>(Pc, ui, qi, &x, Q, Fi, Si);
     for (int c = 0; c < 3; ++c) {
       Rl[c][i] = Rl[c][i] + Si[c];
       for (int r = 0; r < n; ++r) Rl[c][r] = Rl[c][r] - Fi[c][0] * T(D[r * n + i] * invJ);
@@ -122,8 +122,8 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
     for (int c = 0; c < 3; ++c) u0[c] = uu[c][0];
     boundary_state<1, S>(Pc, u0, ub);
     const double x = r0;
-    flux_source<1, S>(Pc, ub, qlo, &x, 0.0, Fb, Sb, false);
-    sigma<1, S>(Pc, ub, sm, se);
+    flux_source<1, S, XP & kXpComp>(Pc, ub, qlo, &x, 0.0, Fb, Sb, false);
+    sigma<1, S, XP & kXpComp>(Pc, ub, sm, se, x);
     for (int c = 0; c < 3; ++c) {
       const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
       const S fd = -(Flo[c] - Fb[c][0]);
@@ -144,8 +144,8 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
       S ub[3], Fb[3][1], Sb[3], sm, se;
       boundary_state<1, S>(Pc, ut, ub);
       const double x = r0 + h;
-      flux_source<1, S>(Pc, ub, qhi, &x, 0.0, Fb, Sb, false);
-      sigma<1, S>(Pc, ub, sm, se);
+      flux_source<1, S, XP & kXpComp>(Pc, ub, qhi, &x, 0.0, Fb, Sb, false);
+      sigma<1, S, XP & kXpComp>(Pc, ub, sm, se, x);
       for (int c = 0; c < 3; ++c) {
         const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
         Rl[c][n - 1] = Rl[c][n - 1] + ((Fhi[c] - Fb[c][0]) - sg * (ut[c] - ub[c])) * T(lfac);
@@ -153,7 +153,7 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
     } else {
       // adiabatic, zero normal stress, open, with the penalty lambda U on the momentum
       S Fi[3][1];
-      flux_inviscid<1, S>(Pc, ut, Fi);
+      flux_inviscid<1, S, XP & kXpComp>(Pc, ut, Fi, r0 + h);
       for (int c = 0; c < 3; ++c) {
         S fd = Fhi[c] - Fi[c][0];
         if (c == 1) fd = fd - T(Pc.lam) * ut[1];
@@ -165,7 +165,7 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
     for (int i = 0; i < n; ++i) R[off + c * n + i] = outc(Rl[c][i]);
 }
 
-template <int P, class S, class SU, class TV, class OT>
+template <int P, class S, int XP, class SU, class TV, class OT>
 __device__ __forceinline__ void col_elem_pass2(const ColElem& ce, const PhysC& Pc, const GllC& gc, const SU* __restrict__ u,
                                       const TV* __restrict__ v, const OT* __restrict__ Fn, OT* __restrict__ R) {
   typedef typename Base<S>::type T;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void col_elem_pass2(const ColElem& ce, const PhysC& P
       uh[c] = T(0.5) * (ui[c] + Io<S>::ld(u, v, o2 + c * n + inb));
     }
     S sm, se;
-    sigma<1, S>(Pc, uh, sm, se);
+    sigma<1, S, XP & kXpComp>(Pc, uh, sm, se, side ? ce.r0 + ce.h : ce.r0);
     for (int c = 0; c < 3; ++c) {
       const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
       const OT fnb = Fn[(nb * 2 + (1 - side)) * 3 + c];
@@ -208,24 +208,24 @@ __device__ inline ColElem col_elem_of(const ColDev& C, int e) {
   return ce;
 }
 
-template <int P, class S, class SU, class TV, class OT, bool EUV = false>
+template <int P, class S, class SU, class TV, class OT, int XP = 0>
 __global__ __launch_bounds__(128) void col_pass1(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
                                                  double t, const SU* __restrict__ u, const TV* __restrict__ v,
                                                  OT* __restrict__ R, OT* __restrict__ Fn) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ne) return;
   const int e = elist[idx];
-  col_elem_pass1<P, S, EUV>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, t, u, v, R, Fn);
+  col_elem_pass1<P, S, XP>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, t, u, v, R, Fn);
 }
 
-template <int P, class S, class SU, class TV, class OT>
+template <int P, class S, class SU, class TV, class OT, int XP = 0>
 __global__ __launch_bounds__(128) void col_pass2(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
                                                  const SU* __restrict__ u, const TV* __restrict__ v,
                                                  const OT* __restrict__ Fn, OT* __restrict__ R) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ne) return;
   const int e = elist[idx];
-  col_elem_pass2<P, S>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, u, v, Fn, R);
+  col_elem_pass2<P, S, XP>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, u, v, Fn, R);
 }
 
 template <class S, class SU, class TV, class OT>
@@ -242,8 +242,10 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
     const int blocks = (ne + 127) / 128;
     const int* el = m->d_plist[pi];
 #define DG_COL_P1(P_, G_)                                                                                  \
-  if (ph.euv)                                                                                             \
-    col_pass1<P_, S, SU, TV, OT, true><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn);        \
+  if (ph.xp_mode() == (kXpEuv | kXpComp))                                                                 \
+    col_pass1<P_, S, SU, TV, OT, kXpEuv | kXpComp><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn); \
+  else if (ph.xp_mode() == kXpEuv)                                                                        \
+    col_pass1<P_, S, SU, TV, OT, kXpEuv><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn);      \
   else                                                                                                    \
     col_pass1<P_, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn);
     switch (pi + 2) {
@@ -258,11 +260,17 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
     if (!ne) continue;
     const int blocks = (ne + 127) / 128;
     const int* el = m->d_plist[pi];
+#define DG_COL_P2(P_, G_)                                                                                  \
+  if (ph.comp)                                                                                            \
+    col_pass2<P_, S, SU, TV, OT, kXpComp><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, u, v, fn, out);           \
+  else                                                                                                    \
+    col_pass2<P_, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, u, v, fn, out);
     switch (pi + 2) {
-      case 2: col_pass2<2, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[0], u, v, fn, out); break;
-      case 3: col_pass2<3, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[1], u, v, fn, out); break;
-      default: col_pass2<4, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, gc[2], u, v, fn, out); break;
+      case 2: DG_COL_P2(2, gc[0]); break;
+      case 3: DG_COL_P2(3, gc[1]); break;
+      default: DG_COL_P2(4, gc[2]); break;
     }
+#undef DG_COL_P2
   }
   DG_HIP_CHECK(hipGetLastError());
   return DG_OK;
@@ -363,7 +371,7 @@ __device__ inline double wave_allsum(double x) {
   return x;
 }
 
-template <int P, class S, class TV, class OT, bool EUV>
+template <int P, class S, class TV, class OT, int XP>
 __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                               const double* u, const TV* v, OT* out, OT* fn) {
   constexpr int b = 3 * (P + 1);
@@ -378,7 +386,7 @@ __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, 
     ce.fslot = el;
     ce.fslot_prev = el - 1;
     ce.fslot_next = el + 1;
-    col_elem_pass1<P, S, EUV>(ce, Pc, gc, t, u, v, out, fn);
+    col_elem_pass1<P, S, XP>(ce, Pc, gc, t, u, v, out, fn);
   }
   __syncthreads();
   for (int el = lane; el < E; el += 64) {
@@ -391,7 +399,7 @@ __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, 
     ce.fslot = el;
     ce.fslot_prev = el - 1;
     ce.fslot_next = el + 1;
-    col_elem_pass2<P, S>(ce, Pc, gc, u, v, fn, out);
+    col_elem_pass2<P, S, XP>(ce, Pc, gc, u, v, fn, out);
   }
   __syncthreads();
 }
@@ -453,7 +461,7 @@ __device__ __forceinline__ void colw_invert(double* blk, double (*M)[2 * b], dou
   __syncthreads();
 }
 
-template <int P, bool EUV>
+template <int P, int XP>
 __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                                       double ca, const double* U, double* V, double* Jv, double* fnT, double* Lo,
                                       double* Di, double* Up) {
@@ -469,7 +477,7 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
     for (int l = 0; l < b; ++l) {
       for (int i = lane; i < nd; i += 64) V[i] = (((i / b) % 3 == kap) && (i % b == l)) ? 1.0 : 0.0;
       __syncthreads();
-      colw_residual<P, Dual<double>, double, double, EUV>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
+      colw_residual<P, Dual<double>, double, double, XP>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
       for (int idx = lane; idx < E * b; idx += 64) {
         const int ep = idx / b, r = idx % b;
         for (int d = -1; d <= 1; ++d) {
@@ -552,7 +560,7 @@ __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double
   }
 }
 
-template <int P, bool EUV>
+template <int P, int XP>
 __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC& ph, const GllC& gc) {
   constexpr int n = P + 1;
   constexpr int b = 3 * n;
@@ -589,7 +597,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
     const double t = B.t0 + step * B.dt;
     // chord Jacobian at the start of the step (a sited column follows the Sun's direction)
     if (sited) sun_direction_dev(Pc, t + B.c[0] * B.dt);
-    colw_build_and_factor<P, EUV>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
+    colw_build_and_factor<P, XP>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
     ++builds;
     for (int i = lane; i < nd; i += 64) U[i] = un[i];
     __syncthreads();
@@ -602,11 +610,11 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
         Bv[i] = bv;
       }
       __syncthreads();
-      colw_residual<P, double, double, double, EUV>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
+      colw_residual<P, double, double, double, XP>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
       const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, G));
       int it = 0, since_build = 0;
       for (;;) {
-        colw_residual<P, double, double, double, EUV>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
+        colw_residual<P, double, double, double, XP>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
         const double nG = sqrt(colw_stage_residual(nd, U, Rc, ca, Bv, G));
         if (!isfinite(nG)) {
           status = 5;
@@ -618,7 +626,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
           break;
         }
         if (since_build >= 6) {
-          colw_build_and_factor<P, EUV>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
+          colw_build_and_factor<P, XP>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
           ++builds;
           since_build = 0;
         }
@@ -666,7 +674,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
 
 // two waves per SIMD: 256 registers and some scratch spills beat 512 registers at one wave
 // (5% on the 4096-column batch)
-template <bool EUV>
+template <int XP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_columns_persistent(ColBatch B, PhysC ph, GllC g2, GllC g3, GllC g4) {
   __shared__ int s_k;
   for (;;) {
@@ -677,9 +685,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (k >= B.n_col) break;
     const int col = B.order[k];
     switch (B.col_p[col]) {
-      case 2: colw_run<2, EUV>(B, col, ph, g2); break;
-      case 3: colw_run<3, EUV>(B, col, ph, g3); break;
-      default: colw_run<4, EUV>(B, col, ph, g4); break;
+      case 2: colw_run<2, XP>(B, col, ph, g2); break;
+      case 3: colw_run<3, XP>(B, col, ph, g3); break;
+      default: colw_run<4, XP>(B, col, ph, g4); break;
     }
   }
 }
@@ -782,10 +790,12 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   sun_direction(ph, t0);
   {
     ProfScope ps(m, 13, s);
-    if (ph.euv)
-      k_columns_persistent<true><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+    if (ph.xp_mode() == (kXpEuv | kXpComp))
+      k_columns_persistent<kXpEuv | kXpComp><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+    else if (ph.xp_mode() == kXpEuv)
+      k_columns_persistent<kXpEuv><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
     else
-      k_columns_persistent<false><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+      k_columns_persistent<0><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
   }
   DG_HIP_CHECK(hipGetLastError());
   DG_HIP_CHECK(hipStreamSynchronize(s));

@@ -107,7 +107,71 @@ struct PhysC {
   const double* euv_tab;             // device [K_0..K_36, kap_0..kap_36]: Q = rho sum_j K_j exp(-kap_j rho H C)
   double euv_hfac, r_ref;            // H = T r^2 euv_hfac; the lower-boundary radius R0
   double site[3];                    // 1D: unit vector of the column's site (0: the Sun overhead)
+  int comp;                          // 1: variable composition (mixture below), 0: constant m
+  double comp_a[6], comp_b[6];       // chi_s = a_1 e^{b_1 |r|} + a_2 e^{b_2 |r|} of N2, O2, He
+  // which extended-physics instantiation a mesh runs (template flag XP below)
+  __host__ __device__ int xp_mode() const;
 };
+
+// Extended physics of an instantiation (template flag XP, a bit mask): kXpEuv contains the
+// EUVAC heating, kXpComp the variable composition. The kernels without a bit keep their
+// register budget; a mesh with the composition runs kXpEuv | kXpComp (EUVAC then checked
+// at run time), one with EUVAC only kXpEuv, otherwise 0.
+constexpr int kXpEuv = 1, kXpComp = 2;
+__host__ __device__ inline int PhysC::xp_mode() const { return comp ? (kXpEuv | kXpComp) : (euv ? kXpEuv : 0); }
+
+// ---------------------------------------------------------------- mixture
+// Chemically frozen mixture (section 2.1.1): mass fractions of N2, O2 and He from their
+// fits, atomic oxygen the balance. In units of m_O and of oxygen's c_v (all species with
+// the same gamma): c_v = sum_s chi_s / m_s = 1 / m. Mole fractions x_s = m chi_s / m_s
+// weight the species conductivities (section 2.1.2; alpha_N2 = alpha_O2 = 3.6e-4,
+// alpha_O = alpha_He = 5.6e-4), taken relative to alpha_O.
+constexpr double kInvMassN2 = 15.9994 / 28.0134, kInvMassO2 = 15.9994 / 31.9988, kInvMassHe = 15.9994 / 4.002602;
+constexpr double kAlphaMol = 3.6 / 5.6;    // alpha_N2 / alpha_O = alpha_O2 / alpha_O
+
+struct Mix {
+  double m, inv_m, inv_gm;   // mean molecular mass, c_v = 1/m, 1/(gamma m)
+  double kw;                 // conductivity weight sum_s x_s alpha_s / alpha_O
+  double dlnm;               // d ln m / d|r| (the grad c_v term: grad c_v / c_v = -grad ln m)
+  double chi[4];             // mass fractions of N2, O2, O, He (Table A's order)
+};
+
+// the mixture at radius r: the constants of the mesh unless XP has kXpComp and the
+// composition is on
+template <int XP>
+__device__ inline Mix mixture(const PhysC& P, double r) {
+  Mix x;
+  if (!(XP & kXpComp) || !P.comp) {
+    x.m = P.m;
+    x.inv_m = P.inv_m;
+    x.inv_gm = P.inv_gm;
+    x.kw = 1.0;
+    x.dlnm = 0.0;
+    for (int s = 0; s < 4; ++s) x.chi[s] = 0.0;
+    return x;
+  }
+  double c[3], dc[3];
+  for (int s = 0; s < 3; ++s) {
+    const double e0 = P.comp_a[2 * s] * exp(P.comp_b[2 * s] * r);
+    const double e1 = P.comp_a[2 * s + 1] * exp(P.comp_b[2 * s + 1] * r);
+    c[s] = e0 + e1;
+    dc[s] = P.comp_b[2 * s] * e0 + P.comp_b[2 * s + 1] * e1;
+  }
+  const double cO = 1.0 - c[0] - c[1] - c[2];
+  const double nN2 = c[0] * kInvMassN2, nO2 = c[1] * kInvMassO2, nHe = c[2] * kInvMassHe;  // chi_s / m_s
+  x.inv_m = nN2 + nO2 + nHe + cO;
+  x.m = 1.0 / x.inv_m;
+  x.inv_gm = x.inv_m / P.gamma;
+  x.kw = x.m * ((nN2 + nO2) * kAlphaMol + nHe + cO);
+  // d c_v / d|r| with d chi_O = -(d chi_N2 + d chi_O2 + d chi_He)
+  const double dcv = dc[0] * (kInvMassN2 - 1.0) + dc[1] * (kInvMassO2 - 1.0) + dc[2] * (kInvMassHe - 1.0);
+  x.dlnm = -dcv * x.m;
+  x.chi[0] = c[0];
+  x.chi[1] = c[1];
+  x.chi[2] = cO;
+  x.chi[3] = c[2];
+  return x;
+}
 
 // ---------------------------------------------------------------- pointwise physics
 // cosine of the solar zenith angle at x: the shell from the node's direction, a column
@@ -127,13 +191,18 @@ __device__ inline double cos_zenith(const PhysC& P, const double* x) {
 // EUVAC heating (section 2.2) at position x for density rho and temperature Tm
 // (nondimensional): Q = rho sum_j K_j exp(-kap_j rho H C), H = Tm r^2 hfac the scale
 // height, C the Smith-Smith Chapman factor of r~ = r / H and the zenith angle (cos chi = 1 in
-// 1D), zero in the Earth's shadow (R0 = r_ref). tab = [K_j, kap_j]. Terms whose optical
-// depth exceeds what the type's exp resolves are dropped (their flux is below 1e-30 of the
-// unattenuated one). Only the kernels instantiated with EUV (flux_source) contain it: the
-// element passes without it keep their register budget.
-template <int D, class S>
+// 1D), zero in the Earth's shadow (R0 = r_ref). tab (EUVT entries) = [K_j, kap_j, phi'_sj]: with
+// a constant composition K_j and kap_j are the bin constants; with the variable one
+// (comp) kap_j = sum_s chi_s phi'_sj (phi' = col_scale phi_s^j / m_s, chi the local mass
+// fractions: the species number densities rho chi_s / m_s) and K_j = tab[j] kap_j; only the
+// COMP instantiation contains that branch. Terms whose optical depth exceeds what the
+// type's exp resolves are dropped (their flux is below 1e-30 of the unattenuated one). Only
+// the kernels instantiated with kXpEuv (flux_source) contain it: the element passes without
+// it keep their register budget.
+constexpr int EUVT = 6 * 37;
+template <int D, class S, bool COMP>
 __device__ inline S heating_euvac(const double* __restrict__ tab, double hfac, double r_ref, double cchi, double r,
-                                  S rho, S Tm) {
+                                  S rho, S Tm, bool comp, const double (&chi)[4]) {
   typedef typename Base<S>::type T;
   constexpr T kTauMax = sizeof(T) == 8 ? T(700) : T(80);
   const double r2 = r * r;
@@ -154,19 +223,38 @@ __device__ inline S heating_euvac(const double* __restrict__ tab, double hfac, d
   }
   const S col = rho * H * C;
   S Q = S(T(0));
-  for (int j = 0; j < 37; ++j) {
-    const S tau = T(tab[37 + j]) * col;
-    if (val(tau) < kTauMax) Q = Q + T(tab[j]) * xexp(-tau);
+  if (COMP && comp) {
+    for (int j = 0; j < 37; ++j) {
+      const double kap = chi[0] * tab[74 + j] + chi[1] * tab[111 + j] + chi[2] * tab[148 + j] + chi[3] * tab[185 + j];
+      const S tau = T(kap) * col;
+      if (val(tau) < kTauMax) Q = Q + T(tab[j] * kap) * xexp(-tau);
+    }
+  } else {
+    for (int j = 0; j < 37; ++j) {
+      const S tau = T(tab[37 + j]) * col;
+      if (val(tau) < kTauMax) Q = Q + T(tab[j]) * xexp(-tau);
+    }
   }
   return rho * Q;
 }
 
 // Flux F[c][k] and source Sr[c] at one node of a D-dimensional problem (f = D + 2
 // fields: varrho, sqrt(rho) v, sqrt(rho) T). x: node position; Q: heating rate there.
-template <int D, class S, bool EUV = false>
+// XP: kXpEuv adds the EUVAC heating (heat && P.euv), kXpComp the variable composition
+// (P.comp: m, c_v and the conductivity weight at |x|, and the energy source
+// -(1/c_v) F_Theta . grad c_v = F_Theta . grad ln m of eq. fluxSWNondimensional).
+template <int D, class S, int XP = 0>
 __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], const double* x, double Q,
                                    S (*F)[D], S* Sr, bool heat = true) {
   typedef typename Base<S>::type T;
+  // (the radius is formed here only where the mixture needs it: the other instantiations
+  // keep it out of the registers live across the flux)
+  double rx = 0;
+  if constexpr ((XP & kXpComp) != 0) {
+    for (int k = 0; k < D; ++k) rx += x[k] * x[k];
+    rx = sqrt(rx);
+  }
+  const Mix mx = mixture<XP>(P, rx);
   const S lr = u[0];
   const S s = xexp(T(-0.5) * lr);
   const S sq = T(1) / s;
@@ -175,8 +263,8 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
   for (int i = 0; i < D; ++i) { U[i] = u[1 + i]; v[i] = s * U[i]; }
   const S Th = u[D + 1];
   const S Tm = s * Th;
-  const S mu = xsqrt(Tm * T(P.m)) + T(P.nu_r) * rho;
-  const S kap = T(P.alpha0c) * xpow(Tm, T(P.kexp)) + T(P.alpha_r * P.inv_m) * rho;
+  const S mu = xsqrt(Tm * T(mx.m)) + T(P.nu_r) * rho;
+  const S kap = T(P.alpha0c * mx.kw) * xpow(Tm, T(P.kexp)) + T(P.alpha_r * mx.inv_m) * rho;
   S gl[D], gT[D], gv[D][D];
   for (int k = 0; k < D; ++k) gl[k] = q[0][k];
   for (int i = 0; i < D; ++i)
@@ -188,12 +276,12 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
   for (int i = 0; i < D; ++i)
     for (int k = 0; k < D; ++k) eps[i][k] = gv[i][k] + gv[k][i] - (i == k ? T(2.0 / 3.0) * div : S(T(0)));
   const S mus = T(P.c_visc) * mu * s;                 // mu / (sqrt(rho) sqrt(gamma Gr))
-  const S kas = T(P.c_cond * P.m) * kap * s;          // kappa / (Pr sqrt(rho) c_v) sqrt(gamma/Gr)
+  const S kas = T(P.c_cond * mx.m) * kap * s;         // kappa / (Pr sqrt(rho) c_v) sqrt(gamma/Gr)
   for (int k = 0; k < D; ++k) F[0][k] = lr * v[k];
   for (int i = 0; i < D; ++i)
     for (int k = 0; k < D; ++k) {
       S f = U[i] * v[k] - mus * eps[i][k];
-      if (i == k) f = f + T(P.inv_gm) * Th;
+      if (i == k) f = f + T(mx.inv_gm) * Th;
       F[1 + i][k] = f;
     }
   for (int k = 0; k < D; ++k) F[D + 1][k] = Th * v[k] - kas * gT[k];
@@ -212,7 +300,7 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
   for (int i = 0; i < D; ++i) {
     S eg = eps[i][0] * gl[0];
     for (int k = 1; k < D; ++k) eg = eg + eps[i][k] * gl[k];
-    S a = sq * T(gfac * x[i] + cen[i]) + T(0.5) * div * U[i] - T(0.5 * P.inv_gm) * Th * gl[i] + T(0.5) * mus * eg;
+    S a = sq * T(gfac * x[i] + cen[i]) + T(0.5) * div * U[i] - T(0.5 * mx.inv_gm) * Th * gl[i] + T(0.5) * mus * eg;
     if (D == 3) {
       const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
       // - 2 Fr/sqrt(gamma) (w x U)_i
@@ -226,17 +314,29 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
   for (int i = 0; i < D; ++i)
     for (int k = 0; k < D; ++k)
       if (i + k > 0) ed = ed + eps[i][k] * gv[i][k];
-  Sr[D + 1] = T(Q * P.m) * s + T(1.5 - P.gamma) * Th * div + T(0.5) * kas * Tg + T(P.c_diss * P.m) * mu * s * ed;
-  if constexpr (EUV)
+  Sr[D + 1] = T(Q * mx.m) * s + T(1.5 - P.gamma) * Th * div + T(0.5) * kas * Tg + T(P.c_diss * mx.m) * mu * s * ed;
+  constexpr bool kComp = (XP & kXpComp) != 0;
+  if constexpr ((XP & kXpEuv) != 0) {
     if (heat && P.euv)
-      Sr[D + 1] = Sr[D + 1] + T(P.m) * s *
-                                heating_euvac<D, S>(P.euv_tab, P.euv_hfac, P.r_ref, cos_zenith<D>(P, x), r, rho, Tm);
+      Sr[D + 1] = Sr[D + 1] + T(mx.m) * s *
+                                heating_euvac<D, S, kComp>(P.euv_tab, kComp && P.comp ? mx.inv_m / P.r_ref2 : P.euv_hfac,
+                                                           P.r_ref, cos_zenith<D>(P, x), r, rho, Tm, P.comp != 0,
+                                                           mx.chi);
+  }
+  if constexpr (kComp) {
+    if (P.comp) {
+      S Fx = F[D + 1][0] * T(x[0]);
+      for (int k = 1; k < D; ++k) Fx = Fx + F[D + 1][k] * T(x[k]);
+      Sr[D + 1] = Sr[D + 1] + T(mx.dlnm / r) * Fx;
+    }
+  }
 }
 
-// inviscid part of the flux only (upper boundary)
-template <int D, class S>
-__device__ inline void flux_inviscid(const PhysC& P, const S* u, S (*F)[D]) {
+// inviscid part of the flux only (upper boundary) at radius r
+template <int D, class S, int XP = 0>
+__device__ inline void flux_inviscid(const PhysC& P, const S* u, S (*F)[D], double r) {
   typedef typename Base<S>::type T;
+  const double inv_gm = mixture<XP>(P, r).inv_gm;
   const S lr = u[0];
   const S s = xexp(T(-0.5) * lr);
   S v[D];
@@ -245,23 +345,25 @@ __device__ inline void flux_inviscid(const PhysC& P, const S* u, S (*F)[D]) {
   for (int i = 0; i < D; ++i)
     for (int k = 0; k < D; ++k) {
       S f = u[1 + i] * v[k];
-      if (i == k) f = f + T(P.inv_gm) * u[D + 1];
+      if (i == k) f = f + T(inv_gm) * u[D + 1];
       F[1 + i][k] = f;
     }
   for (int k = 0; k < D; ++k) F[D + 1][k] = u[D + 1] * v[k];
 }
 
-// stabilisation sigma (eq. LDG2) at a trace state: lam + diag(0, mu s c_visc, kappa s m c_cond)
-template <int D, class S>
-__device__ inline void sigma(const PhysC& P, const S* uh, S& sig_m, S& sig_e) {
+// stabilisation sigma (eq. LDG2) at a trace state at radius r: lam + diag(0, mu s c_visc,
+// kappa s m c_cond)
+template <int D, class S, int XP = 0>
+__device__ inline void sigma(const PhysC& P, const S* uh, S& sig_m, S& sig_e, double r) {
   typedef typename Base<S>::type T;
+  const Mix mx = mixture<XP>(P, r);
   const S s = xexp(T(-0.5) * uh[0]);
   const S rho = T(1) / (s * s);
   const S Tm = s * uh[D + 1];
-  const S mu = xsqrt(Tm * T(P.m)) + T(P.nu_r) * rho;
-  const S kap = T(P.alpha0c) * xpow(Tm, T(P.kexp)) + T(P.alpha_r * P.inv_m) * rho;
+  const S mu = xsqrt(Tm * T(mx.m)) + T(P.nu_r) * rho;
+  const S kap = T(P.alpha0c * mx.kw) * xpow(Tm, T(P.kexp)) + T(P.alpha_r * mx.inv_m) * rho;
   sig_m = T(P.lam) + T(P.c_visc) * mu * s;
-  sig_e = T(P.lam) + T(P.c_cond * P.m) * kap * s;
+  sig_e = T(P.lam) + T(P.c_cond * mx.m) * kap * s;
 }
 
 // boundary state u_b for the lower boundary (or the Dirichlet state in bc_mode 1)

@@ -1,4 +1,5 @@
-// EUVAC heating constants (section 2.2, Table A of the appendix on EUV cross sections).
+// EUVAC heating constants (section 2.2, Table A of the appendix on EUV cross sections) and
+// the host-side check of the variable composition (section 2.1.1).
 //
 // The heating rate in the model's units is Q = rho sum_j K_j exp(-kap_j rho H C) (rho, H in
 // nondimensional units; C the Chapman factor evaluated on the device), with per bin j
@@ -6,6 +7,11 @@
 //   I_0^j   = F74113^j max(0.8, 1 + A_j (F10.7bar - 80)) / d^2
 //   K_j     = eps (hc / lambda_j) I_0^j sigma_j q_scale / m
 //   kap_j   = sigma_j col_scale / m
+// for constant mole fractions chi_s and mean mass m. With the variable composition the
+// number densities are rho chi_s(r) / m_s (chi_s mass fractions), so the device forms
+// kap_j = sum_s chi_s phi'_sj with phi'_sj = col_scale phi_s^j / m_s, and K_j = A'_j kap_j with
+// A'_j = eps (hc / lambda_j) I_0^j q_scale / col_scale. The table holds EUVT = 6 x 37 values:
+// [K_j or A'_j, kap_j, phi'_N2, phi'_O2, phi'_O, phi'_He].
 // Table A's photon fluxes are read with the exponent +13 (m^-2 s^-1), the cross sections
 // in units of 1e-22 m^2; a wavelength range stands for its midpoint.
 #include <cmath>
@@ -73,8 +79,9 @@ double euvac_declination(double day) {
   return std::asin(std::sin(-d0) * std::cos(w * (day + 9.0) + 2.0 * e * std::sin(w * (day - 3.0))));
 }
 
-void euvac_constants(const dg_physics_t& in, double* K, double* kap) {
+void euvac_constants(const dg_physics_t& in, double* tab) {
   const double h = 6.62607015e-34, c = 2.99792458e8;
+  const double inv_ms[4] = {kInvMassN2, kInvMassO2, 1.0, kInvMassHe};
   for (int j = 0; j < 37; ++j) {
     const EuvBin& b = kTableA[j];
     double sig = 0;
@@ -82,9 +89,34 @@ void euvac_constants(const dg_physics_t& in, double* K, double* kap) {
     const double lam = 0.5 * (b.lo + b.hi) * 1e-10;
     const double scale = 1.0 + b.a * (in.euv_f107 - 80.0);
     const double I0 = b.f74113 * 1e13 * (scale > 0.8 ? scale : 0.8) / (in.euv_sun_dist * in.euv_sun_dist);
-    K[j] = in.euv_eps * (h * c / lam) * I0 * sig * in.euv_q_scale / in.m;
-    kap[j] = sig * in.euv_col_scale / in.m;
+    if (in.composition) {
+      tab[j] = in.euv_eps * (h * c / lam) * I0 * in.euv_q_scale / in.euv_col_scale;
+      tab[37 + j] = 0.0;
+    } else {
+      tab[j] = in.euv_eps * (h * c / lam) * I0 * sig * in.euv_q_scale / in.m;
+      tab[37 + j] = sig * in.euv_col_scale / in.m;
+    }
+    for (int s = 0; s < 4; ++s) tab[74 + 37 * s + j] = in.euv_col_scale * b.phi[s] * 1e-22 * inv_ms[s];
   }
+}
+
+bool composition_valid(const dg_physics_t& ph, double r_lo, double r_hi) {
+  if (!ph.composition) return true;
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(ph.comp_a[i]) || !std::isfinite(ph.comp_b[i])) return false;
+  const int n = 1024;
+  for (int i = 0; i <= n; ++i) {
+    const double r = r_lo + (r_hi - r_lo) * i / n;
+    double sum = 0;
+    for (int s = 0; s < 3; ++s) {
+      const double chi = ph.comp_a[2 * s] * std::exp(ph.comp_b[2 * s] * r) +
+                         ph.comp_a[2 * s + 1] * std::exp(ph.comp_b[2 * s + 1] * r);
+      if (!(chi >= 0.0 && chi <= 1.0)) return false;
+      sum += chi;
+    }
+    if (!(sum <= 1.0)) return false;
+  }
+  return true;
 }
 
 void col_params(const dg_physics_t& ph, int n_col, std::vector<double>& cpar) {
@@ -102,12 +134,12 @@ void col_params(const dg_physics_t& ph, int n_col, std::vector<double>& cpar) {
 }
 
 void col_euv_tables(const dg_physics_t& ph, int n_col, std::vector<double>& tab) {
-  tab.assign((size_t)74 * n_col, 0.0);
+  tab.assign((size_t)EUVT * n_col, 0.0);
   dg_physics_t q = ph;
   for (int c = 0; c < n_col; ++c) {
     if (ph.col_euv_eps) q.euv_eps = ph.col_euv_eps[c];
     if (ph.col_euv_f107) q.euv_f107 = ph.col_euv_f107[c];
-    euvac_constants(q, &tab[(size_t)74 * c], &tab[(size_t)74 * c + 37]);
+    euvac_constants(q, &tab[(size_t)EUVT * c]);
   }
 }
 

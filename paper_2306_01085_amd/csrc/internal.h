@@ -41,11 +41,15 @@ GllC make_gllc(int p);
 // 1 / heat_H, lam, alpha0c, site unit vector (3; zero: the Sun overhead)
 constexpr int CPAR = 9;
 void col_params(const dg_physics_t& ph, int n_col, std::vector<double>& cpar);
-// per-column EUVAC bin constants [n_col][74] (efficiency and F10.7bar per column)
+// per-column EUVAC bin constants [n_col][EUVT] (efficiency and F10.7bar per column)
 void col_euv_tables(const dg_physics_t& ph, int n_col, std::vector<double>& tab);
-// EUVAC heating constants of the 37 bins and the declination of day N_d (euvac.cpp)
-void euvac_constants(const dg_physics_t& in, double* K, double* kap);
+// EUVAC heating constants of the 37 bins (EUVT values, the layout heating_euvac reads) and
+// the declination of day N_d (euvac.cpp)
+void euvac_constants(const dg_physics_t& in, double* tab);
 double euvac_declination(double day);
+// true unless the composition is on and a fitted mass fraction leaves [0, 1] (or their sum
+// exceeds 1) somewhere in [r_lo, r_hi]
+bool composition_valid(const dg_physics_t& ph, double r_lo, double r_hi);
 // modal filter of degree p on the GLL nodes: F = I - (1 - sigma) P_p(x_a) c_p(i), where
 // c_p(i) = w_i P_p(x_i) / sum_j w_j P_p(x_j)^2 extracts the coefficient of the Legendre
 // polynomial P_p (GLL quadrature is exact for P_k P_p with k < p, so the lower modes
@@ -74,7 +78,7 @@ struct ColDev {
   const double* geo;     // [E][2] bottom radius, thickness
   const int* col;        // [E] column of the element
   const double* cpar;    // [n_col][CPAR] per-column parameters (col_params)
-  const double* euv;     // [n_col][74] per-column EUVAC bin constants, or null (the mesh's table)
+  const double* euv;     // [n_col][EUVT] per-column EUVAC bin constants, or null (the mesh's table)
 };
 
 struct Workspace;   // implicit-step buffers (solver.hip)
@@ -113,7 +117,7 @@ struct dg_mesh_s {
   double* d_fn64 = nullptr;
   float* d_fn32 = nullptr;
   uint16_t* d_bf16op = nullptr;   // dense bf16 reference operators of the BF16 J v (p = 3 shells)
-  double* d_euv = nullptr;        // EUVAC bin constants [K(37), kap(37)] (heating model 1)
+  double* d_euv = nullptr;        // EUVAC bin constants [EUVT] (heating model 1)
   bool krylov_bf16 = false;       // the implicit step in progress takes the BF16 J v
   int line_pc_every = 1;          // rebuild the radial-line preconditioner every this many steps
   int line_pc_prec = 32;          // storage precision of its factors: 64, 32 or 16 (bf16)

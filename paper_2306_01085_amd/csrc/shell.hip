@@ -214,8 +214,8 @@ __device__ inline int nth_bit(int mask, int r) {
 // of the divergence (only the node's own term); every element takes the stabilisation of
 // its own side of the angular faces and sends no angular traces. Radial coupling is
 // exact. Lines (cell, a, b) are then independent.
-// EUV: the instantiation contains the EUVAC heating (used when the mesh's heating model is 1).
-template <int P, int EPB, int OCC, class S, class SU, class TV, class OT, bool RAD = false, bool EUV = false>
+// XP: the extended physics the instantiation contains (kXpEuv, kXpComp; PhysC::xp_mode).
+template <int P, int EPB, int OCC, class S, class SU, class TV, class OT, bool RAD = false, int XP = 0>
 __global__ __launch_bounds__(Shape<P>::TPE * EPB) __attribute__((amdgpu_waves_per_eu(OCC)))
 void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__ u, const TV* __restrict__ v,
                  OT* __restrict__ R, OT* __restrict__ Fn) {
@@ -289,7 +289,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
           S uh[5];
           for (int c = 0; c < 5; ++c) uh[c] = uo[c] + du[c];
           S sm, se;
-          sigma<3, S>(ph, uh, sm, se);
+          sigma<3, S, XP>(ph, uh, sm, se, rc);
           for (int c = 0; c < 5; ++c) {
             const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
             s_z[le][r][c][m] = T(Smag) * sg * du[c];
@@ -372,9 +372,9 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
       S ub[5], Fb[5][3], Sb[5];
       boundary_state<3, S>(ph, uu, ub);
-      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb, false);
+      flux_source<3, S, XP>(ph, ub, q, g.x, 0.0, Fb, Sb, false);
       S sm, se;
-      sigma<3, S>(ph, ub, sm, se);
+      sigma<3, S, XP>(ph, ub, sm, se, g.rc);
       for (int c = 0; c < 5; ++c) {
         const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
         Bc[c] = -(Fb[c][0] * T(Sn[0]) + Fb[c][1] * T(Sn[1]) + Fb[c][2] * T(Sn[2])) - T(Smag) * sg * (uu[c] - ub[c]);
@@ -382,7 +382,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
     }
     const double Q = heating<3>(ph, g.x, t);
     S F[5][3];
-    flux_source<3, S, EUV>(ph, uu, q, g.x, Q, F, Sr);
+    flux_source<3, S, XP>(ph, uu, q, g.x, Q, F, Sr);
     // the metric terms are read again from LDS rather than kept in registers across the flux
     __asm__ __volatile__("" ::: "memory");
     const double (*ang)[N2] = s_ang[le];
@@ -396,7 +396,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         // adiabatic, zero normal stress, open: F_hat.Sn = F_inviscid.Sn + lambda (U.Sn) Sn/|Sn|
         // (the penalty on the normal momentum), so (F - F_hat).Sn = F_viscous.Sn - penalty
         S Fi[5][3];
-        flux_inviscid<3, S>(ph, uu, Fi);
+        flux_inviscid<3, S, XP>(ph, uu, Fi, g.rc);
         const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
         const S Un = (uu[1] * T(Sn[0]) + uu[2] * T(Sn[1]) + uu[3] * T(Sn[2])) * T(ph.lam / Smag);
         for (int c = 0; c < 5; ++c) {
@@ -493,11 +493,11 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   for (int c = 0; c < 5; ++c) R[base + c * N + j] += hl * acc[c];
 }
 
-template <int P, int EPB, int OCC, class S, bool EUV = false, class SU, class TV, class OT>
+template <int P, int EPB, int OCC, class S, int XP = 0, class SU, class TV, class OT>
 static void launch_p1(const ShellDev& M, const PhysC& ph, const GllC& gc, double t, const SU* u, const TV* v, OT* out,
                       OT* fn, hipStream_t s) {
   const int blocks = (M.E + EPB - 1) / EPB;
-  shell_pass1<P, EPB, OCC, S, SU, TV, OT, false, EUV><<<blocks, Shape<P>::TPE * EPB, 0, s>>>(M, ph, gc, t, u, v, out,
+  shell_pass1<P, EPB, OCC, S, SU, TV, OT, false, XP><<<blocks, Shape<P>::TPE * EPB, 0, s>>>(M, ph, gc, t, u, v, out,
                                                                                              fn);
 }
 
@@ -505,12 +505,17 @@ static void launch_p1(const ShellDev& M, const PhysC& ph, const GllC& gc, double
 // FP64 residual and the FP32 J v take the tuned table entry of the mesh, the FP64
 // J v (dual numbers) runs one element per block with a register budget for two waves
 // per SIMD (left free, the allocator reaches 256 + 14 accumulation registers and one wave), and so does every pass of
-// a mesh with the EUVAC heating (the one instantiation that contains it)
+// a mesh with the EUVAC heating or the variable composition (the one instantiation that
+// contains them)
 template <int P, class S, class SU, class TV, class OT>
 static void dispatch_p1(const dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const GllC& gc, double t,
                         const SU* u, const TV* v, OT* out, OT* fn, hipStream_t s) {
-  if (ph.euv) {
-    launch_p1<P, 1, 1, S, true>(M, ph, gc, t, u, v, out, fn, s);
+  if (ph.xp_mode() == (kXpEuv | kXpComp)) {
+    launch_p1<P, 1, 1, S, kXpEuv | kXpComp>(M, ph, gc, t, u, v, out, fn, s);
+    return;
+  }
+  if (ph.xp_mode() == kXpEuv) {
+    launch_p1<P, 1, 1, S, kXpEuv>(M, ph, gc, t, u, v, out, fn, s);
     return;
   }
   if constexpr (std::is_same<S, Dual<double>>::value) {
@@ -573,8 +578,8 @@ dg_status_t shell_jvp_radial(dg_mesh_s* m, double t, const double* u, const doub
   sun_direction(ph, t);
   const int E = M.E;
 #define DG_RAD(P_)                                                                                          \
-  if (ph.euv)                                                                                              \
-    shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true, true><<<E, Shape<P_>::TPE, 0, s>>>(       \
+  if (ph.xp_mode())                                                                                        \
+    shell_pass1<P_, 1, 1, Dual<double>, double, double, double, true, kXpEuv | kXpComp><<<E, Shape<P_>::TPE, 0, s>>>(       \
         M, ph, gc, t, u, v, jv, m->d_fn64);                                                                \
   else                                                                                                     \
     shell_pass1<P_, 1, 2, Dual<double>, double, double, double, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, \
@@ -598,8 +603,8 @@ dg_status_t shell_jvp_radial32(dg_mesh_s* m, double t, const double* u, const fl
   sun_direction(ph, t);
   const int E = M.E;
 #define DG_RAD32(P_)                                                                                        \
-  if (ph.euv)                                                                                              \
-    shell_pass1<P_, 1, 1, Dual<float>, double, float, float, true, true><<<E, Shape<P_>::TPE, 0, s>>>(           \
+  if (ph.xp_mode())                                                                                        \
+    shell_pass1<P_, 1, 1, Dual<float>, double, float, float, true, kXpEuv | kXpComp><<<E, Shape<P_>::TPE, 0, s>>>(           \
         M, ph, gc, t, u, v, jv, m->d_fn32);                                                                \
   else                                                                                                     \
     shell_pass1<P_, 1, 1, Dual<float>, double, float, float, true><<<E, Shape<P_>::TPE, 0, s>>>(M, ph, gc, t, u, v, \
@@ -644,8 +649,9 @@ template <int P> struct BfShape {
   static constexpr int MM_BYTES = 32 * 2 * NP * 2 + 32 * NP * 2 + NP * 30 * 4 + NP * 10 * 4;
 };
 
-template <int P>
-__global__ __launch_bounds__(BfShape<P>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) void shell_pass1_bf16(ShellDev M, PhysC ph, GllC gc, double t,
+// XP: kXpEuv, or kXpEuv | kXpComp for a mesh with the variable composition
+template <int P, int XP>
+__global__ __launch_bounds__(BfShape<P>::THREADS) void shell_pass1_bf16(ShellDev M, PhysC ph, GllC gc, double t,
                                                                        const double* __restrict__ u,
                                                                        const float* __restrict__ v,
                                                                        const uint16_t* __restrict__ ops,
@@ -725,7 +731,7 @@ __global__ __launch_bounds__(BfShape<P>::THREADS) __attribute__((amdgpu_waves_pe
           S uh[5];
           for (int c = 0; c < 5; ++c) uh[c] = uo[c] + du[c];
           S sm, se;
-          sigma<3, S>(ph, uh, sm, se);
+          sigma<3, S, XP & kXpComp>(ph, uh, sm, se, rc);
           for (int c = 0; c < 5; ++c) {
             const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
             s_z[le][r][c][m] = T(Smag) * sg * du[c];
@@ -840,9 +846,9 @@ __global__ __launch_bounds__(BfShape<P>::THREADS) __attribute__((amdgpu_waves_pe
       const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
       S ub[5], Fb[5][3], Sb[5];
       boundary_state<3, S>(ph, uu, ub);
-      flux_source<3, S>(ph, ub, q, g.x, 0.0, Fb, Sb, false);
+      flux_source<3, S, XP & kXpComp>(ph, ub, q, g.x, 0.0, Fb, Sb, false);
       S sm, se;
-      sigma<3, S>(ph, ub, sm, se);
+      sigma<3, S, XP & kXpComp>(ph, ub, sm, se, g.rc);
       for (int c = 0; c < 5; ++c) {
         const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
         Bc[c] = -(Fb[c][0] * T(Sn[0]) + Fb[c][1] * T(Sn[1]) + Fb[c][2] * T(Sn[2])) - T(Smag) * sg * (uu[c] - ub[c]);
@@ -850,7 +856,7 @@ __global__ __launch_bounds__(BfShape<P>::THREADS) __attribute__((amdgpu_waves_pe
     }
     const double Q = heating<3>(ph, g.x, t);
     S F[5][3];
-    flux_source<3, S, true>(ph, uu, q, g.x, Q, F, Sr);
+    flux_source<3, S, XP>(ph, uu, q, g.x, Q, F, Sr);
     __asm__ __volatile__("" ::: "memory");
     const double (*ang)[N2] = s_ang[le];
     if (dir || top) {
@@ -861,7 +867,7 @@ __global__ __launch_bounds__(BfShape<P>::THREADS) __attribute__((amdgpu_waves_pe
           Sr[c] = Sr[c] + (F[c][0] * T(Sn[0]) + F[c][1] * T(Sn[1]) + F[c][2] * T(Sn[2]) + Bc[c]) * T(lfac);
       } else {
         S Fi[5][3];
-        flux_inviscid<3, S>(ph, uu, Fi);
+        flux_inviscid<3, S, XP & kXpComp>(ph, uu, Fi, g.rc);
         const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
         const S Un = (uu[1] * T(Sn[0]) + uu[2] * T(Sn[1]) + uu[3] * T(Sn[2])) * T(ph.lam / Smag);
         for (int c = 0; c < 5; ++c) {
@@ -937,10 +943,16 @@ dg_status_t shell_jvp_bf16(dg_mesh_s* m, double t, const double* u, const float*
   const unsigned blocks = (unsigned)((M.E + BF_EPB - 1) / BF_EPB);
   {
     ProfScope ps(m, 14, s);
-    if (m->p == 3)
-      shell_pass1_bf16<3><<<blocks, BfShape<3>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
+    constexpr int X1 = kXpEuv, X3 = kXpEuv | kXpComp;
+    const bool comp = ph.comp != 0;
+    if (m->p == 3 && comp)
+      shell_pass1_bf16<3, X3><<<blocks, BfShape<3>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
+    else if (m->p == 3)
+      shell_pass1_bf16<3, X1><<<blocks, BfShape<3>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
+    else if (comp)
+      shell_pass1_bf16<4, X3><<<blocks, BfShape<4>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
     else
-      shell_pass1_bf16<4><<<blocks, BfShape<4>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
+      shell_pass1_bf16<4, X1><<<blocks, BfShape<4>::THREADS, 0, s>>>(M, ph, gc, t, u, v, m->d_bf16op, jv, m->d_fn32);
   }
   {
     ProfScope ps(m, 15, s);
@@ -1081,7 +1093,7 @@ __global__ __launch_bounds__(256) void shell_bjac(ShellDev M, PhysC ph, GllC gc,
   const double* Am3[3] = {g.A1, g.A2, g.A3};
   const bool on[6] = {g.a == 0, g.a == n - 1, g.b == 0, g.b == n - 1, g.cz == 0, g.cz == n - 1};
   double sm, se;
-  sigma<3, double>(ph, uu, sm, se);
+  sigma<3, double, kXpComp>(ph, uu, sm, se, g.rc);
   double blk[5][10];
   for (int c = 0; c < 5; ++c) {
     DD ud[5], qd[5][3], Fd[5][3], Sd[5];
@@ -1089,7 +1101,7 @@ __global__ __launch_bounds__(256) void shell_bjac(ShellDev M, PhysC ph, GllC gc,
       ud[r] = DD(uu[r], r == c ? 1.0 : 0.0);
       for (int d = 0; d < 3; ++d) qd[r][d] = DD(q[r][d], 0.0);
     }
-    flux_source<3, DD, true>(ph, ud, qd, g.x, Q, Fd, Sd);
+    flux_source<3, DD, kXpEuv | kXpComp>(ph, ud, qd, g.x, Q, Fd, Sd);
     for (int r = 0; r < 5; ++r) {
       double col = Sd[r].d;
       double gd[3];

@@ -470,6 +470,23 @@ def shell_workload(seed=0, p=3, n_ang=16, n_rad=16, stretch=1.15, name="shell",
                          T_inf=T_inf, phys=phys, pert=pert)
 
 
+def with_composition(w):
+    """the workload with the variable composition of section 2.1.1: the synthetic fits,
+    the rest state in hydrostatic balance with m(r) (the state generators follow the
+    physics set), and lambda_max = max sqrt(T/m) over the rest state"""
+    import dataclasses
+    phys = dict(w.phys)
+    phys.update(composition_physics())
+    mass = mixture_mass(phys)
+    if isinstance(w, ShellWorkload):
+        phys["lam"] = sound_speed_max(w.T_inf, mass) + (0.01 if w.pert is not None else 0.0)
+        return dataclasses.replace(w, phys=phys, name=w.name + "-mixture")
+    col_phys = dict(w.col_phys)
+    col_phys["lam"] = np.array([sound_speed_max(float(T), mass) for T in w.T_inf])
+    phys["lam"] = float(col_phys["lam"][0])
+    return dataclasses.replace(w, phys=phys, col_phys=col_phys, name=w.name + "-mixture")
+
+
 def config_column(seed=0):
     """1D column, 64 uniform elements, p = 2, 200 DIRK(3,3) steps of 10 s"""
     return column_workload(seed=seed, n_elem=64, p=2, name="column-64e-p2")
