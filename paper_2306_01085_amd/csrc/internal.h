@@ -1,9 +1,12 @@
 // Host-side definition of a mesh handle and helpers shared by the library's
 // translation units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/dgthermo.h"
@@ -175,6 +178,29 @@ struct ProfScope {
     }
   }
 };
+// Launch kernel k(args) on s. With the mesh's profiling on, the dispatch itself records the
+// start and stop events (hipExtLaunchKernel), so the interval is the kernel's execution
+// alone, as a kernel trace reports it, without the gap to the previous dispatch that
+// events recorded around the launch include. The arguments are converted to the kernel's
+// parameter types first.
+template <typename... Prm, typename... Arg>
+inline void launch_timed(dg_mesh_s* m, int id, void (*k)(Prm...), dim3 grid, dim3 block, hipStream_t s,
+                         Arg&&... a) {
+  std::tuple<Prm...> args{std::forward<Arg>(a)...};
+  void* ptrs[sizeof...(Prm)];
+  std::apply([&](auto&... x) {
+    int i = 0;
+    ((ptrs[i++] = (void*)&x), ...);
+  }, args);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (m->prof && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    (void)hipExtLaunchKernel((const void*)k, grid, block, ptrs, 0, s, e0, e1, 0);
+    m->prof_events.push_back({id, e0, e1});
+    return;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  (void)hipExtLaunchKernel((const void*)k, grid, block, ptrs, 0, s, nullptr, nullptr, 0);
+}
 // kernels (shell.hip, column.hip)
 dg_status_t shell_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
 dg_status_t shell_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);

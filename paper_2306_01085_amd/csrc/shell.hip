@@ -493,10 +493,16 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   for (int c = 0; c < 5; ++c) R[base + c * N + j] += hl * acc[c];
 }
 
+// (profiled: pm->prof on, the interval goes to slot pid)
 template <int P, int EPB, int OCC, class S, int XP = 0, class SU, class TV, class OT>
 static void launch_p1(const ShellDev& M, const PhysC& ph, const GllC& gc, double t, const SU* u, const TV* v, OT* out,
-                      OT* fn, hipStream_t s) {
+                      OT* fn, hipStream_t s, dg_mesh_s* pm, int pid) {
   const int blocks = (M.E + EPB - 1) / EPB;
+  if (pm->prof) {
+    launch_timed(pm, pid, &shell_pass1<P, EPB, OCC, S, SU, TV, OT, false, XP>, dim3(blocks),
+                 dim3(Shape<P>::TPE * EPB), s, M, ph, gc, t, u, v, out, fn);
+    return;
+  }
   shell_pass1<P, EPB, OCC, S, SU, TV, OT, false, XP><<<blocks, Shape<P>::TPE * EPB, 0, s>>>(M, ph, gc, t, u, v, out,
                                                                                              fn);
 }
@@ -508,29 +514,29 @@ static void launch_p1(const ShellDev& M, const PhysC& ph, const GllC& gc, double
 // a mesh with the EUVAC heating or the variable composition (the one instantiation that
 // contains them)
 template <int P, class S, class SU, class TV, class OT>
-static void dispatch_p1(const dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const GllC& gc, double t,
-                        const SU* u, const TV* v, OT* out, OT* fn, hipStream_t s) {
+static void dispatch_p1(dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const GllC& gc, double t,
+                        const SU* u, const TV* v, OT* out, OT* fn, hipStream_t s, int pid) {
   if (ph.xp_mode() == (kXpEuv | kXpComp)) {
-    launch_p1<P, 1, 1, S, kXpEuv | kXpComp>(M, ph, gc, t, u, v, out, fn, s);
+    launch_p1<P, 1, 1, S, kXpEuv | kXpComp>(M, ph, gc, t, u, v, out, fn, s, m, pid);
     return;
   }
   if (ph.xp_mode() == kXpEuv) {
-    launch_p1<P, 1, 1, S, kXpEuv>(M, ph, gc, t, u, v, out, fn, s);
+    launch_p1<P, 1, 1, S, kXpEuv>(M, ph, gc, t, u, v, out, fn, s, m, pid);
     return;
   }
   if constexpr (std::is_same<S, Dual<double>>::value) {
-    launch_p1<P, 1, 2, S>(M, ph, gc, t, u, v, out, fn, s);
+    launch_p1<P, 1, 2, S>(M, ph, gc, t, u, v, out, fn, s, m, pid);
     return;
   } else {
   constexpr int maxe = 256 / Shape<P>::TPE;
   const int cfg = m->tune_p1;
   switch (cfg) {
-    case 1: launch_p1<P, 1, 1, S>(M, ph, gc, t, u, v, out, fn, s); break;
-    case 2: launch_p1<P, (maxe >= 2 ? 2 : 1), 1, S>(M, ph, gc, t, u, v, out, fn, s); break;
-    case 3: launch_p1<P, 1, 3, S>(M, ph, gc, t, u, v, out, fn, s); break;
-    case 4: launch_p1<P, (maxe >= 2 ? 2 : 1), 3, S>(M, ph, gc, t, u, v, out, fn, s); break;
-    case 5: launch_p1<P, 1, 4, S>(M, ph, gc, t, u, v, out, fn, s); break;
-    default: launch_p1<P, maxe, 1, S>(M, ph, gc, t, u, v, out, fn, s); break;
+    case 1: launch_p1<P, 1, 1, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
+    case 2: launch_p1<P, (maxe >= 2 ? 2 : 1), 1, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
+    case 3: launch_p1<P, 1, 3, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
+    case 4: launch_p1<P, (maxe >= 2 ? 2 : 1), 3, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
+    case 5: launch_p1<P, 1, 4, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
+    default: launch_p1<P, maxe, 1, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
   }
   }
 }
@@ -550,13 +556,14 @@ static dg_status_t launch(dg_mesh_s* m, double t, const SU* u, const TV* v, OT* 
 #define DG_LAUNCH(P_)                                                                                     \
   {                                                                                                        \
     {                                                                                                      \
-      ProfScope ps(m, prof_base, s);                                                                       \
-      dispatch_p1<P_, S>(m, M, ph, gc, t, u, v, out, fn, s);                                               \
+      dispatch_p1<P_, S>(m, M, ph, gc, t, u, v, out, fn, s, prof_base);                                    \
     }                                                                                                      \
     {                                                                                                      \
-      ProfScope ps(m, prof_base + 1, s);                                                                   \
       const int blocks = (E + Shape<P_>::EPB - 1) / Shape<P_>::EPB;                                        \
-      shell_pass2<P_, OT><<<blocks, 256, 0, s>>>(M, gc, fn, out);                                         \
+      if (m->prof)                                                                                         \
+        launch_timed(m, prof_base + 1, &shell_pass2<P_, OT>, dim3(blocks), dim3(256), s, M, gc, fn, out);   \
+      else                                                                                                 \
+        shell_pass2<P_, OT><<<blocks, 256, 0, s>>>(M, gc, fn, out);                                       \
     }                                                                                                      \
   }
   switch (m->p) {

@@ -187,3 +187,24 @@ def test_bad_arguments_raise():
     u = torch.zeros(gm.n_dof + 5, dtype=torch.float64, device="cuda:0")
     with pytest.raises(DgError):
         gm.residual(u)
+
+
+def test_profiled_launches_give_the_same_results():
+    """with the library's per-kernel timing on (the element and trace passes launched with
+    dispatch-recorded events) R and J v are bitwise those of the plain launches, and every
+    timed slot holds one positive interval per launch"""
+    need_gpu()
+    w = synth.shell_workload(9, p=3, n_ang=2, n_rad=2)
+    om, gm = shell_pair(w, 2, 2, 3)
+    u = to_dev(np.moveaxis(w.state_fn()(om.X), 0, 1).copy())
+    v = to_dev(synth.tangent((u.numel(),), 3))
+    plain = [gm.residual(u).cpu().numpy(), gm.jvp(u, v).cpu().numpy(), gm.jvp(u, v.float(), prec="f32").cpu().numpy()]
+    gm.profile(True)
+    timed = [gm.residual(u).cpu().numpy(), gm.jvp(u, v).cpu().numpy(), gm.jvp(u, v.float(), prec="f32").cpu().numpy()]
+    prof = gm.profile_read()
+    gm.profile(False)
+    for a, b in zip(plain, timed):
+        assert np.array_equal(a, b)
+    for k in ("shell_pass1_R", "shell_pass2_R", "shell_pass1_jvp64", "shell_pass2_jvp64", "shell_pass1_jvp32",
+              "shell_pass2_jvp32"):
+        assert prof[k][1] == 1 and prof[k][0] > 0, (k, prof)
