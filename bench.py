@@ -163,7 +163,8 @@ def implicit_steps(w, mesh, u, n_steps, only=None):
     """seconds per DIRK(3,3) step of dt = 60 s at a 1e-8 relative Newton tolerance,
     GMRES(30) right-preconditioned by the radial-line block-Jacobi preconditioner,
     (rebuilt every LINE_PC_EVERY steps, bf16 factors), Eisenstat-Walker GMRES tolerances,
-    plain extrapolated guess: FP64 vs FP32 vs BF16 J v; plus the FP32 run without a
+    plain extrapolated guess: FP64 vs FP32 vs BF16 J v, and the FP64 finite difference of R
+    that section 3.2 describes; plus the FP32 run without a
     preconditioner and the FP32 run with the reduced basis of the 4 latest Newton updates
     on top of the line preconditioner"""
     import torch
@@ -173,6 +174,7 @@ def implicit_steps(w, mesh, u, n_steps, only=None):
            "gmres": "GMRES(30), CGS2, radial-line block-Jacobi preconditioner, Eisenstat-Walker tolerances",
            "steps": n_steps, "filter_rate": FILTER_RATE}
     runs = [(prec, 2, prec, 0) for prec in ("f64", "f32") + (("bf16",) if w.p in (3, 4) else ())]
+    runs.append(("f64_fd", 2, "f64_fd", 0))   # the paper's finite-difference J v (section 3.2)
     runs.append(("f32_rb4", 2, "f32", 4))   # plus the reduced basis of the 4 latest Newton updates
     runs.append(("f32_no_precond", 0, "f32", 0))
     if only:
@@ -419,6 +421,8 @@ def main():
     f_r = lambda: mesh.residual(u, t, out=r)
     f_j64 = lambda: mesh.jvp(u, v, t, "f64", out=jv)
     f_j32 = lambda: mesh.jvp(u, v32, t, "f32", out=jv32)
+    jvfd = torch.empty_like(jv)
+    f_jfd = lambda: mesh.jvp(u, v, t, "f64_fd", out=jvfd)
     jvb = torch.empty_like(v32) if w.p in (3, 4) else None
     f_jb = (lambda: mesh.jvp(u, v32, t, "bf16", out=jvb)) if w.p in (3, 4) else None
     if args.only == "residual":
@@ -437,10 +441,13 @@ def main():
     ms_j64 = timed(f_j64, args.steps)
     ms_j32 = timed(f_j32, args.steps)
     ms_jb = timed(f_jb, args.steps) if f_jb else None
+    f_jfd()
+    ms_jfd = timed(f_jfd, args.steps)
     # reduced-precision J v against the FP64 product (the FP64 product matches the oracle
     # to 1e-12 in the parity tests)
     nrm = torch.linalg.norm(jv).item()
-    jv_err = {"f32": torch.linalg.norm(jv32.double() - jv).item() / nrm}
+    jv_err = {"f32": torch.linalg.norm(jv32.double() - jv).item() / nrm,
+              "f64_fd": torch.linalg.norm(jvfd - jv).item() / nrm}
     if f_jb:
         f_jb()
         jv_err["bf16"] = torch.linalg.norm(jvb.double() - jv).item() / nrm
@@ -505,6 +512,7 @@ def main():
         "jvp_f64_gdofs": ndof / (ms_j64 * 1e-3) / 1e9,
         "jvp_f32_gdofs": ndof / (ms_j32 * 1e-3) / 1e9,
         "jvp_bf16_gdofs": ndof / (ms_jb * 1e-3) / 1e9 if ms_jb else None,
+        "jvp_f64_fd_gdofs": ndof / (ms_jfd * 1e-3) / 1e9,
         "jvp_rel_err_vs_f64": jv_err,
         "kernels_ms": {k: v_[0] / v_[1] for k, v_ in prof.items()},
         "residual_effective_gbs": residual_bytes(w) / (ms_r * 1e-3) / 1e9,
@@ -520,7 +528,7 @@ def main():
     out["euvac"] = euv
     out["composition"] = comp
     out["implicit_step"] = implicit_steps(w, mesh, u, args.implicit_steps)
-    del r, jv, jv32, v, v32
+    del r, jv, jv32, v, v32, jvfd
     log("column batch")
     out["columns"] = column_batch()
     if not args.no_cpu_baseline:

@@ -51,7 +51,8 @@ typedef enum {
   DG_ERR_UNSUPPORTED = 6   /* the requested precision / mode is not available */
 } dg_status_t;
 
-typedef enum { DG_F64 = 0, DG_F32 = 1, DG_BF16 = 2 } dg_prec_t;
+/* DG_F64_FD: FP64, the finite difference of R that section 3.2 describes (a check mode; see dg_jvp) */
+typedef enum { DG_F64 = 0, DG_F32 = 1, DG_BF16 = 2, DG_F64_FD = 3 } dg_prec_t;
 
 typedef enum { DG_MESH_COLUMNS = 0, DG_MESH_SHELL = 1 } dg_mesh_kind_t;
 
@@ -160,6 +161,11 @@ dg_status_t dg_residual(dg_mesh_t mesh, double t, const double* u, double* r, in
  * DG_ERR_UNSUPPORTED): v and jv are float; the tangent's gradient and the divergence
  * of the linearised flux are bf16 MFMA products (operands rounded to bf16, FP32
  * accumulation) of the dense reference derivative operators, the rest as DG_F32.
+ * DG_F64_FD (v, jv double): the paper's matrix-free product, the one-sided difference
+ * jv = (R(u + h v) - R(u)) / h with h = sqrt(eps_64) (1 + |u|_2) / |v|_2 (the paper gives no
+ * step), jv = 0 for v = 0; two R evaluations, its error is O(h) plus rounding of order
+ * eps_64 / h. The norms and h stay on the device. Its first call
+ * allocates two state-sized buffers owned by the mesh (freed at destroy); later calls do not.
  * Enqueue only. */
 dg_status_t dg_jvp(dg_mesh_t mesh, double t, const double* u, const void* v, void* jv, int64_t n_dof,
                    dg_prec_t prec, void* stream);
@@ -173,7 +179,8 @@ typedef struct {
   double newton_rtol;      /* stop when |G(U)| <= newton_rtol |G(u_n)| (1e-8) */
   double gmres_rtol;       /* inexact Newton: relative GMRES tolerance (1e-3) */
   int32_t jvp_prec;        /* dg_prec_t of J v inside GMRES (DG_F32 and DG_BF16 keep FP32 Krylov vectors;
-                              DG_BF16 needs a shell of degree 3 or 4) */
+                              DG_BF16 needs a shell of degree 3 or 4; DG_F64_FD: FP64 vectors, the
+                              finite-difference product of dg_jvp) */
   int32_t precond;         /* shell meshes: 0 none; 1 node 5x5 block Jacobi (q held fixed, rebuilt every
                               Newton iteration); 2 radial-line block Jacobi: I - dt a_ii J_rad with J_rad
                               the linearisation that drops the tangent's coupling between different

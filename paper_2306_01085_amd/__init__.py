@@ -19,8 +19,8 @@ if not os.path.exists(_LIB_PATH):
 _lib = C.CDLL(_LIB_PATH)
 
 DG_OK, DG_ERR_ARG, DG_ERR_ALLOC, DG_ERR_HIP, DG_ERR_NOCONV, DG_ERR_NAN, DG_ERR_UNSUPPORTED = range(7)
-DG_F64, DG_F32, DG_BF16 = 0, 1, 2
-_PREC = {"f64": DG_F64, "f32": DG_F32, "bf16": DG_BF16}
+DG_F64, DG_F32, DG_BF16, DG_F64_FD = 0, 1, 2, 3
+_PREC = {"f64": DG_F64, "f32": DG_F32, "bf16": DG_BF16, "f64_fd": DG_F64_FD}
 
 
 class DgError(RuntimeError):
@@ -264,7 +264,7 @@ class Mesh:
 
     def jvp(self, u, v, t=0.0, prec="f64", out=None, stream=None):
         import torch
-        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}[prec]
+        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32, "f64_fd": torch.float64}[prec]
         if out is None:
             out = torch.empty(self.n_dof, dtype=dt, device=u.device)
         if not (u.numel() == v.numel() == out.numel()):

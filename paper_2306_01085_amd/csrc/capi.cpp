@@ -116,7 +116,8 @@ static void free_mesh(dg_mesh_s* m) {
   void* ptrs[] = {m->d_ang,  m->d_edges,  m->d_cnbr,  m->d_cface,     m->d_cmap,      m->d_off,
                   m->d_prev, m->d_next,   m->d_geo,   m->d_col,       m->d_cpar,      m->d_fn64,
                   m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2], m->d_bstate, m->d_coloff,
-                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op, m->d_euv, m->d_euv_cols};
+                  m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op, m->d_euv, m->d_euv_cols,
+                  m->d_fd};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   free_workspace(m);
@@ -360,6 +361,7 @@ dg_status_t dg_jvp(dg_mesh_t m, double t, const double* u, const void* v, void* 
     return m->kind == DG_MESH_SHELL ? shell_jvp32(m, t, u, (const float*)v, (float*)jv, s)
                                     : col_jvp32(m, t, u, (const float*)v, (float*)jv, s);
   if (prec == DG_BF16 && m->kind == DG_MESH_SHELL) return shell_jvp_bf16(m, t, u, (const float*)v, (float*)jv, s);
+  if (prec == DG_F64_FD) return jvp_fd(m, t, u, (const double*)v, (double*)jv, s);
   set_error("dg_jvp: precision not available");
   return DG_ERR_UNSUPPORTED;
 }
@@ -372,7 +374,8 @@ dg_status_t dg_implicit_step(dg_mesh_t m, double t, double dt, double* u, int64_
   }
   if ((opts->scheme != 33 && opts->scheme != 22) || opts->gmres_m < 1 || opts->gmres_m > 32 ||
       opts->max_newton < 1 || opts->max_restarts < 1 || !(opts->newton_rtol > 0) || !(opts->gmres_rtol > 0) ||
-      (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32 && opts->jvp_prec != DG_BF16) || opts->precond < 0 ||
+      (opts->jvp_prec != DG_F64 && opts->jvp_prec != DG_F32 && opts->jvp_prec != DG_BF16 &&
+       opts->jvp_prec != DG_F64_FD) || opts->precond < 0 ||
       opts->precond > 2 ||
       opts->guess < 0 || opts->guess > 1 || opts->forcing < 0 || opts->forcing > 1 || !(opts->filter_rate >= 0) ||
       !std::isfinite(opts->filter_rate) || opts->n_rb < 0 || opts->n_rb > 8) {

@@ -122,6 +122,8 @@ struct dg_mesh_s {
   uint16_t* d_bf16op = nullptr;   // dense bf16 reference operators of the BF16 J v (p = 3 shells)
   double* d_euv = nullptr;        // EUVAC bin constants [EUVT] (heating model 1)
   bool krylov_bf16 = false;       // the implicit step in progress takes the BF16 J v
+  bool krylov_fd = false;         // the implicit step in progress takes the finite-difference J v
+  double* d_fd = nullptr;         // finite-difference J v: [2][n_dof] states and the norm partials
   int line_pc_every = 1;          // rebuild the radial-line preconditioner every this many steps
   int line_pc_prec = 32;          // storage precision of its factors: 64, 32 or 16 (bf16)
   int tune_lsolve = -1;           // launch configuration of its substitution (0..5, -1 automatic)
@@ -209,6 +211,8 @@ dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hip
 dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
 dg_status_t shell_jvp_bf16(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
+// the finite-difference J v of section 3.2 (solver.hip): two residuals, the step on the device
+dg_status_t jvp_fd(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 std::vector<uint16_t> bf16_operators(int p);
 // radial-line linearisation J_rad v (FP64) and the radial-line block-Jacobi preconditioner
 dg_status_t shell_jvp_radial(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);

@@ -436,7 +436,78 @@ fail:
 static dg_status_t residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s) {
   return m->kind == DG_MESH_SHELL ? shell_residual(m, t, u, r, s) : col_residual(m, t, u, r, s);
 }
+
+// ---------------------------------------------------------------- finite-difference J v
+// Section 3.2 forms J v as a finite difference of R. One-sided, with the usual
+// Jacobian-free Newton-Krylov step (the paper gives none) h = sqrt(eps) (1 + |u|) / |v|
+// (2-norms). sums[0] = |u|^2, sums[1] = |v|^2 are reduced on the device.
+__device__ inline double fd_step(const double* __restrict__ sums) {
+  const double nv = sqrt(sums[1]);
+  if (!(nv > 0.0)) return 0.0;
+  return 1.4901161193847656e-08 * (1.0 + sqrt(sums[0])) / nv;   // 2^-26 = sqrt(eps_64)
+}
+
+// partial sums of a.a and b.b (two accumulators per block)
+__global__ __launch_bounds__(RED_THREADS) void k_sumsq2(int64_t n, const double* __restrict__ a,
+                                                        const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double red[(RED_THREADS / 64) * 2 + 2];
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    acc[0] += a[i] * a[i];
+    acc[1] += b[i] * b[i];
+  }
+  block_sum<2>(acc, red);
+  if (threadIdx.x < 2) part[blockIdx.x * 2 + threadIdx.x] = red[threadIdx.x];
+}
+
+// w = u + h v
+__global__ void k_fd_perturb(int64_t n, const double* __restrict__ u, const double* __restrict__ v,
+                             const double* __restrict__ sums, double* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  w[i] = u[i] + fd_step(sums) * v[i];
+}
+
+// jv = (R(u + h v) - R(u)) / h, held in jv and r0 on entry; 0 when h = 0
+__global__ void k_fd_finish(int64_t n, const double* __restrict__ r0, const double* __restrict__ sums,
+                            double* __restrict__ jv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double h = fd_step(sums);
+  jv[i] = h > 0.0 ? (jv[i] - r0[i]) / h : 0.0;
+}
+
+dg_status_t jvp_fd(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s) {
+  const int64_t n = m->n_dof;
+  // [w (n) | r0 (n) | partials (2 RED_BLOCKS) | sums (2)]
+  if (!m->d_fd) {
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    if (hipMalloc(&m->d_fd, (2 * n + 2 * RED_BLOCKS + 2) * sizeof(double)) != hipSuccess) {
+      m->d_fd = nullptr;
+      set_error("dg_jvp: device allocation of the finite-difference buffers failed");
+      return DG_ERR_ALLOC;
+    }
+  }
+  double* w = m->d_fd;
+  double* r0 = w + n;
+  double* part = r0 + n;
+  double* sums = part + 2 * RED_BLOCKS;
+  const int nb = (int)std::min<int64_t>((n + RED_THREADS - 1) / RED_THREADS, RED_BLOCKS);
+  k_sumsq2<<<nb, RED_THREADS, 0, s>>>(n, u, v, part);
+  k_reduce<<<1, RED_THREADS, 0, s>>>(part, nb, 2, sums);
+  const unsigned g = (unsigned)((n + 255) / 256);
+  k_fd_perturb<<<g, 256, 0, s>>>(n, u, v, sums, w);
+  dg_status_t st = residual(m, t, w, jv, s);
+  if (st != DG_OK) return st;
+  st = residual(m, t, u, r0, s);
+  if (st != DG_OK) return st;
+  k_fd_finish<<<g, 256, 0, s>>>(n, r0, sums, jv);
+  DG_HIP_CHECK(hipGetLastError());
+  return DG_OK;
+}
+
 static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s) {
+  if (m->krylov_fd) return jvp_fd(m, t, u, v, jv, s);
   return m->kind == DG_MESH_SHELL ? shell_jvp64(m, t, u, v, jv, s) : col_jvp64(m, t, u, v, jv, s);
 }
 static dg_status_t jvp(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s) {
@@ -1044,7 +1115,8 @@ dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg
     return DG_ERR_UNSUPPORTED;
   }
   m->krylov_bf16 = (o.jvp_prec == DG_BF16);
-  if (o.jvp_prec != DG_F64) return step_impl<float>(m, t, dt, u, o, st, s);
+  m->krylov_fd = (o.jvp_prec == DG_F64_FD);
+  if (o.jvp_prec == DG_F32 || o.jvp_prec == DG_BF16) return step_impl<float>(m, t, dt, u, o, st, s);
   return step_impl<double>(m, t, dt, u, o, st, s);
 }
 
