@@ -352,14 +352,18 @@ class Network:
                "dg_mlp_forward")
         return out
 
-    def grad(self, x, t, want_grads=False, stream=None):
-        """loss and (optionally) the packed gradient, which the next adam_step uses"""
+    def grad(self, x, t, want_grads=False, want_loss=True, stream=None):
+        """loss and (optionally) the packed gradient, which the next adam_step uses; with
+        want_loss and want_grads False it only enqueues (returns None)"""
         import torch
         loss = C.c_double()
         g = np.zeros(self.n_params, dtype=np.float32) if want_grads else None
-        _check(_lib.dg_mlp_grad(self._h, _ptr(x, torch.float32), _ptr(t, torch.float32), x.shape[0], C.byref(loss),
-                                _f32p(g) if want_grads else None, _stream(stream)), "dg_mlp_grad")
-        return (loss.value, self._unpack(g)) if want_grads else loss.value
+        _check(_lib.dg_mlp_grad(self._h, _ptr(x, torch.float32), _ptr(t, torch.float32), x.shape[0],
+                                C.byref(loss) if want_loss else None, _f32p(g) if want_grads else None,
+                                _stream(stream)), "dg_mlp_grad")
+        if want_grads:
+            return loss.value, self._unpack(g)
+        return loss.value if want_loss else None
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(_lib.dg_mlp_adam_step(self._h, lr, beta1, beta2, eps, _stream(stream)), "dg_mlp_adam_step")

@@ -151,3 +151,39 @@ def test_sweep_columns_match_oracle():
             ref, _ = timeint.implicit_step_dense(om, P, ref, t0 + s * w.dt, w.dt, scheme=22, rtol=1e-13)
         got = out[off[c]:off[c + 1]].reshape(uc.shape)
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref - uc) < 1e-6, c
+
+
+def test_full_batch_sampled_columns_match_oracle():
+    """the 4096-column batch at full size (7.1M DOF), in the autotuned launch configuration
+    and at the Newton tolerance (1e-8) the benchmark times, two filtered DIRK(3,3) steps:
+    no column fails, and the two smallest columns agree with the oracle's dense-Newton
+    stages (1e-12) to 1e-6 of their change"""
+    need_gpu()
+    from paper_2306_01085_amd import Mesh
+    from paper_2306_01085_amd import autotune
+    rate, n_steps = 0.5, 2
+    w = synth.column_batch_workload(0)
+    gm = Mesh.columns(w.nelem, w.p, w.r_bot, w.r_top, w.stretch, w.phys, w.col_phys)
+    r = gm.nodes()
+    off = gm.col_offsets()
+    u0 = np.empty(gm.n_dof)
+    for c in range(gm.n_col):
+        rc = r[off[c] // 3:off[c + 1] // 3].reshape(w.nelem[c], w.p[c] + 1)
+        u0[off[c]:off[c + 1]] = np.moveaxis(w.state(c, rc), 0, 1).ravel()
+    u = to_dev(u0)
+    autotune.tune_columns(gm, u, 0.0, w.dt, steps=1)
+    its, st = gm.columns_integrate(u, 0.0, w.dt, n_steps, newton_rtol=1e-8, filter_rate=rate,
+                                   raise_on_failure=False)
+    assert int((np.asarray(st) != 0).sum()) == 0
+    y = u.cpu().numpy()
+    for c in np.argsort(w.nelem * (w.p + 1))[:2]:
+        om = omesh.columns_mesh([int(w.nelem[c])], int(w.p[c]), w.r_bot, w.r_top, float(w.stretch[c]))
+        P = dict(w.phys)
+        for k in w.col_phys:
+            P[k] = float(w.col_phys[k][c])
+        ref = u0[off[c]:off[c + 1]].reshape(-1, 3, w.p[c] + 1).copy()
+        start = ref.copy()
+        for s in range(n_steps):
+            ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-12, filter_rate=rate)
+        got = y[off[c]:off[c + 1]].reshape(ref.shape)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref - start) < 1e-6, c
