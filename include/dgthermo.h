@@ -255,9 +255,9 @@ dg_status_t dg_mlp_destroy(dg_mlp_t mlp);
 int64_t dg_mlp_param_count(dg_mlp_t mlp);
 /* FP32 master parameters to a host array of dg_mlp_param_count entries (synchronises) */
 dg_status_t dg_mlp_get_params(dg_mlp_t mlp, float* params_host, int64_t len);
-/* y = net(x): x device FP32 [n][n_in], y device FP32 [n][n_out]. Enqueue only. */
+/* y = net(x): x device FP32 [n][n_in] (16-byte aligned), y device FP32 [n][n_out]. Enqueue only. */
 dg_status_t dg_mlp_forward(dg_mlp_t mlp, const float* x, int64_t n, float* y, void* stream);
-/* mean-squared-error loss against t (device FP32 [n][n_out]) and its gradient, kept in
+/* mean-squared-error loss against t (device FP32 [n][n_out]; x as for dg_mlp_forward) and its gradient, kept in
  * the handle for dg_mlp_adam_step; loss_host / grad_host (packed) are optional host
  * outputs (either one synchronises the stream). */
 dg_status_t dg_mlp_grad(dg_mlp_t mlp, const float* x, const float* t, int64_t n, double* loss_host, float* grad_host,

@@ -4,9 +4,9 @@
 // Precision contract: weights, the input and both hidden activations are rounded to
 // bfloat16 (round to nearest even) where they enter a matrix product; biases and all
 // accumulation are FP32. The forward pass runs the three products on bf16 MFMA
-// (v_mfma_f32_32x32x8 bf16, FP32 accumulators): one block of 4 wavefronts takes 32
-// samples, each wavefront a 32x32 output tile per step, the hidden activations staged
-// in LDS as bf16. The backward pass is FP32 (the roundings are the identity there),
+// (v_mfma_f32_32x32x8 bf16, FP32 accumulators): one block of 4 wavefronts takes 64
+// samples, the input streamed through LDS in bf16 chunks, each wavefront two 32x32
+// output tiles per step, the hidden activations staged in LDS as bf16. The backward pass is FP32 (the roundings are the identity there),
 // weight gradients by deterministic split-K reductions.
 #include <cmath>
 #include <cstring>
@@ -29,81 +29,142 @@ struct MlpDev {
   const float* b3;
 };
 
-// layer-1 tile: A rows read from the fp32 input and rounded to bf16 on load
-__device__ inline void mfma_tile_input(v16f& acc, const float* X, int64_t m0, int64_t n, int ldx, const uint16_t* B,
-                                       int b_ld, int K) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 31, kq = (lane >> 5) * 4;
-  const int64_t m = m0 + r;
-  const bool ok = m < n;
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    v4s a, b;
-    for (int v = 0; v < 4; ++v) {
-      a[v] = (short)(ok ? f2bf(X[m * ldx + k0 + kq + v]) : (uint16_t)0);
-      b[v] = (short)B[r * b_ld + k0 + kq + v];
-    }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+// Forward of FW_ROWS = 64 samples per block (256 threads, 4 wavefronts). X: fp32
+// [n][n_in], rounded to bf16 once per block: it streams through LDS in chunks of FW_KC
+// columns (coalesced 16-byte loads, the next chunk's loads in flight while the current
+// one is multiplied), so each input byte is read from memory once. Each wavefront holds
+// two 32x32 accumulator tiles (the block's two row tiles) per output column tile, so two
+// independent MFMA chains alternate. Every product keeps the k order of a single chain
+// over k = 0, 8, 16, ... Optional outputs for the backward pass: Z1, H1, Z2, H2 (fp32
+// [n][H], the H rounded), Y: fp32 [n][n_out].
+constexpr int FW_ROWS = 64, FW_KC = 128, FW_LD = FW_KC + 8, FW_HLD = MLP_H + 8;
+constexpr int FW_NLD = 8;   // 16-byte loads per thread per chunk: FW_ROWS * FW_KC / (4 * 256)
+static_assert(FW_NLD * 4 * 256 == FW_ROWS * FW_KC, "chunk staging");
+static_assert(FW_LD == FW_HLD, "the hidden layers reuse the input buffers");
+
+__device__ inline void fw_load_chunk(const float* __restrict__ X, int64_t m0, int64_t n, int n_in, int k0,
+                                     float4 (&v)[FW_NLD]) {
+  constexpr int C4 = FW_KC / 4;   // 16-byte loads per row
+  const int kc = min(FW_KC, n_in - k0);
+  for (int i = 0; i < FW_NLD; ++i) {
+    const int q = threadIdx.x + 256 * i, row = q / C4, c = (q % C4) * 4;
+    const int64_t m = m0 + row;
+    v[i] = (m < n && c < kc) ? *reinterpret_cast<const float4*>(X + m * n_in + k0 + c) : make_float4(0.f, 0.f, 0.f, 0.f);
   }
 }
 
-// forward of 32 samples per block (256 threads). X: fp32 [n][n_in] (rounded to bf16
-// here). Optional outputs for the backward pass: Z1, H1, Z2, H2 (fp32 [n][H], the H
-// rounded), Y: fp32 [n][n_out].
+__device__ inline void fw_store_chunk(uint16_t* __restrict__ xs, const float4 (&v)[FW_NLD]) {
+  constexpr int C4 = FW_KC / 4;
+  for (int i = 0; i < FW_NLD; ++i) {
+    const int q = threadIdx.x + 256 * i, row = q / C4, c = (q % C4) * 4;
+    const uint32_t lo = (uint32_t)f2bf(v[i].x) | ((uint32_t)f2bf(v[i].y) << 16);
+    const uint32_t hi = (uint32_t)f2bf(v[i].z) | ((uint32_t)f2bf(v[i].w) << 16);
+    *reinterpret_cast<uint2*>(xs + row * FW_LD + c) = make_uint2(lo, hi);
+  }
+}
+
+// two row tiles of one 32-column output tile: acc[t] += A(rows 32 t.., K) B^T, A bf16 in LDS
+// (row stride a_ld), B bf16 in global memory (row = output column, stride b_ld). The
+// fixed-length form is unrolled, so the B fragments of all its k steps are loaded
+// before the first product waits for one.
+template <int KS>
+__device__ inline void fw_tiles_fixed(v16f (&acc)[2], const uint16_t* A, int a_ld, const uint16_t* B, int b_ld) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, kq = (lane >> 5) * 4;
+  v4s b[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) b[s] = *reinterpret_cast<const v4s*>(B + r * b_ld + 8 * s + kq);
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const v4s a0 = *reinterpret_cast<const v4s*>(A + r * a_ld + 8 * s + kq);
+    const v4s a1 = *reinterpret_cast<const v4s*>(A + (32 + r) * a_ld + 8 * s + kq);
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a0, b[s], acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b[s], acc[1], 0, 0, 0);
+  }
+}
+
+__device__ inline void fw_tiles(v16f (&acc)[2], const uint16_t* A, int a_ld, const uint16_t* B, int b_ld, int K) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, kq = (lane >> 5) * 4;
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    const v4s b = *reinterpret_cast<const v4s*>(B + r * b_ld + k0 + kq);
+    const v4s a0 = *reinterpret_cast<const v4s*>(A + r * a_ld + k0 + kq);
+    const v4s a1 = *reinterpret_cast<const v4s*>(A + (32 + r) * a_ld + k0 + kq);
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a0, b, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b, acc[1], 0, 0, 0);
+  }
+}
+
+// bias, ReLU and bf16 rounding of a hidden layer's two tiles (columns 32 w..), into LDS and
+// optionally Z / H in global memory
+__device__ inline void fw_hidden_out(const v16f (&acc)[2], const float* __restrict__ bias, int wave, int64_t m0,
+                                     int64_t n, uint16_t* sh, float* __restrict__ Z, float* __restrict__ Hout) {
+  const int lane = threadIdx.x & 63;
+  const int j = 32 * wave + (lane & 31);
+  for (int t = 0; t < 2; ++t)
+    for (int a = 0; a < 16; ++a) {
+      const int row = 32 * t + mfma_out_row(a);
+      const float z = acc[t][a] + bias[j];
+      const uint16_t hb = f2bf(z > 0.f ? z : 0.f);
+      sh[row * FW_HLD + j] = hb;
+      const int64_t m = m0 + row;
+      if (Z && m < n) {
+        Z[m * MLP_H + j] = z;
+        Hout[m * MLP_H + j] = bf2f(hb);
+      }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev M, int64_t n, const float* __restrict__ X,
                                                      float* __restrict__ Y, float* __restrict__ Z1,
                                                      float* __restrict__ H1, float* __restrict__ Z2,
                                                      float* __restrict__ H2) {
-  __shared__ __align__(16) uint16_t sh[32 * MLP_H];     // hidden layer 1, bf16
-  __shared__ __align__(16) uint16_t sh2[32 * MLP_H];    // hidden layer 2, bf16
+  // two input chunks (bf16) during layer 1; afterwards the same space holds the two
+  // hidden layers (bf16): the last chunk loop ends with a barrier
+  __shared__ __align__(16) uint16_t xs[2][FW_ROWS * FW_LD];
+  uint16_t* sh = xs[0];
+  uint16_t* sh2 = xs[1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t m0 = (int64_t)blockIdx.x * 32;
-  const int col = lane & 31;
-  // ---- layer 1: wave w computes hidden units [32 w, 32 w + 32)
+  const int64_t m0 = (int64_t)blockIdx.x * FW_ROWS;
+  // ---- layer 1: wave w computes hidden units [32 w, 32 w + 32) of the 64 samples
   {
-    v16f acc = {};
-    mfma_tile_input(acc, X, m0, n, M.n_in, M.W1 + (size_t)(32 * wave) * M.n_in, M.n_in, M.n_in);
-    for (int a = 0; a < 16; ++a) {
-      const int row = (a / 4) * 8 + (lane >> 5) * 4 + (a % 4);
-      const int j = 32 * wave + col;
-      const float z = acc[a] + M.b1[j];
-      const uint16_t hb = f2bf(z > 0.f ? z : 0.f);
-      sh[row * MLP_H + j] = hb;
-      const int64_t m = m0 + row;
-      if (Z1 && m < n) {
-        Z1[m * MLP_H + j] = z;
-        H1[m * MLP_H + j] = bf2f(hb);
-      }
+    const int nch = (M.n_in + FW_KC - 1) / FW_KC;
+    const uint16_t* W1w = M.W1 + (size_t)(32 * wave) * M.n_in;
+    float4 pre[FW_NLD];
+    fw_load_chunk(X, m0, n, M.n_in, 0, pre);
+    fw_store_chunk(xs[0], pre);
+    __syncthreads();
+    v16f acc[2] = {};
+    for (int ch = 0; ch < nch; ++ch) {
+      const int k0 = ch * FW_KC, kc = min(FW_KC, M.n_in - k0), buf = ch & 1;
+      if (ch + 1 < nch) fw_load_chunk(X, m0, n, M.n_in, k0 + FW_KC, pre);
+      if (kc == FW_KC)
+        fw_tiles_fixed<FW_KC / 8>(acc, xs[buf], FW_LD, W1w + k0, M.n_in);
+      else
+        fw_tiles(acc, xs[buf], FW_LD, W1w + k0, M.n_in, kc);
+      if (ch + 1 < nch) fw_store_chunk(xs[buf ^ 1], pre);
+      __syncthreads();
     }
+    fw_hidden_out(acc, M.b1, wave, m0, n, sh, Z1, H1);
   }
   __syncthreads();
   // ---- layer 2
   {
-    v16f acc = {};
-    mfma_tile_lds_global(acc, sh, MLP_H, M.W2 + (size_t)(32 * wave) * MLP_H, MLP_H, MLP_H);
-    for (int a = 0; a < 16; ++a) {
-      const int row = (a / 4) * 8 + (lane >> 5) * 4 + (a % 4);
-      const int j = 32 * wave + col;
-      const float z = acc[a] + M.b2[j];
-      const uint16_t hb = f2bf(z > 0.f ? z : 0.f);
-      sh2[row * MLP_H + j] = hb;
-      const int64_t m = m0 + row;
-      if (Z2 && m < n) {
-        Z2[m * MLP_H + j] = z;
-        H2[m * MLP_H + j] = bf2f(hb);
-      }
-    }
+    v16f acc[2] = {};
+    fw_tiles_fixed<MLP_H / 8>(acc, sh, FW_HLD, M.W2 + (size_t)(32 * wave) * MLP_H, MLP_H);
+    fw_hidden_out(acc, M.b2, wave, m0, n, sh2, Z2, H2);
   }
   __syncthreads();
-  // ---- layer 3: n_out / 32 tiles over the 4 waves
+  // ---- layer 3: n_out / 32 column tiles over the 4 waves
   for (int tile = wave; tile < M.n_out / 32; tile += 4) {
-    v16f acc = {};
-    mfma_tile_lds_global(acc, sh2, MLP_H, M.W3 + (size_t)(32 * tile) * MLP_H, MLP_H, MLP_H);
-    for (int a = 0; a < 16; ++a) {
-      const int row = (a / 4) * 8 + (lane >> 5) * 4 + (a % 4);
-      const int j = 32 * tile + col;
-      const int64_t m = m0 + row;
-      if (m < n) Y[m * M.n_out + j] = acc[a] + M.b3[j];
-    }
+    v16f acc[2] = {};
+    fw_tiles_fixed<MLP_H / 8>(acc, sh2, FW_HLD, M.W3 + (size_t)(32 * tile) * MLP_H, MLP_H);
+    const int j = 32 * tile + (lane & 31);
+    for (int t = 0; t < 2; ++t)
+      for (int a = 0; a < 16; ++a) {
+        const int64_t m = m0 + 32 * t + mfma_out_row(a);
+        if (m < n) Y[m * M.n_out + j] = acc[t][a] + M.b3[j];
+      }
   }
 }
 
@@ -270,7 +331,7 @@ static dg_status_t mlp_scratch(dg_mlp_s* m, int64_t n) {
 
 dg_status_t mlp_forward(dg_mlp_s* m, const float* X, int64_t n, float* Y, hipStream_t s, bool keep) {
   if (n <= 0) return DG_OK;
-  const int blocks = (int)((n + 31) / 32);
+  const int blocks = (int)((n + FW_ROWS - 1) / FW_ROWS);
   MlpDev M = m->dev();
   k_mlp_forward<<<blocks, 256, 0, s>>>(M, n, X, Y, keep ? m->Z1 : nullptr, keep ? m->H1 : nullptr,
                                          keep ? m->Z2 : nullptr, keep ? m->H2 : nullptr);
@@ -353,8 +414,8 @@ dg_status_t dg_mlp_get_params(dg_mlp_t m, float* params, int64_t len) {
 }
 
 dg_status_t dg_mlp_forward(dg_mlp_t m, const float* x, int64_t n, float* y, void* stream) {
-  if (!m || !x || !y || n < 0) {
-    set_error("dg_mlp_forward: invalid argument");
+  if (!m || !x || !y || n < 0 || (reinterpret_cast<uintptr_t>(x) & 15)) {
+    set_error("dg_mlp_forward: invalid argument (x must be 16-byte aligned)");
     return DG_ERR_ARG;
   }
   return mlp_forward(m, x, n, y, (hipStream_t)stream, false);
@@ -362,8 +423,8 @@ dg_status_t dg_mlp_forward(dg_mlp_t m, const float* x, int64_t n, float* y, void
 
 dg_status_t dg_mlp_grad(dg_mlp_t m, const float* x, const float* t, int64_t n, double* loss, float* grad_host,
                         void* stream) {
-  if (!m || !x || !t || n < 1) {
-    set_error("dg_mlp_grad: invalid argument");
+  if (!m || !x || !t || n < 1 || (reinterpret_cast<uintptr_t>(x) & 15)) {
+    set_error("dg_mlp_grad: invalid argument (x must be 16-byte aligned)");
     return DG_ERR_ARG;
   }
   hipStream_t s = (hipStream_t)stream;

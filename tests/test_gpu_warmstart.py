@@ -46,6 +46,25 @@ def test_mlp_forward_and_gradients_match_oracle():
         assert _rel(g, gr) < 1e-5
 
 
+@pytest.mark.parametrize("n,n_in,n_out", [(70, 200, 64), (1, 8, 32), (129, 968, 96)])
+def test_mlp_forward_ragged_shapes(n, n_in, n_out):
+    """row counts off the 64-row block, input widths with a partial last 64-column chunk.
+    The bf16 rounding of the hidden activations is decided on FP32 sums on both sides
+    (one activation of the 129 x 968 case lies on a rounding boundary: decided on FP64
+    sums the outputs differ by 1.7e-5)"""
+    need_gpu()
+    from paper_2306_01085_amd import DgError, Network
+    params, x, _ = _problem(3, n=n, n_in=n_in, n_out=n_out)
+    net = Network(n_in, n_out, params)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    yref, _ = omlp.forward(params, x.astype(np.float64), decide=np.float32)
+    assert _rel(y, yref) < 1e-5
+    # an input that is not 16-byte aligned is refused
+    xd = torch.from_numpy(np.concatenate([[0.0], x.ravel()]).astype(np.float32)).cuda()[1:].view(n, n_in)
+    with pytest.raises(DgError):
+        net.forward(xd)
+
+
 def test_mlp_adam_step_matches_oracle():
     need_gpu()
     from paper_2306_01085_amd import Network
