@@ -78,3 +78,23 @@ def test_adam_matches_torch():
         opt.step()
     for a, t in zip(p, tp):
         assert np.allclose(a, t.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_decision_precision_only_moves_boundary_roundings():
+    """pre-activations formed in FP32 instead of FP64 change a hidden activation's bf16
+    rounding only where it lies on a rounding boundary: a few elements in ten thousand,
+    each by exactly one bf16 step"""
+    rng = np.random.default_rng(3)
+    params = mlp.init_params(rng, n_in=968, n_out=96)
+    params[3] = rng.standard_normal(128) * 0.1
+    params[4] = rng.standard_normal(params[4].shape) * 0.05
+    x = rng.standard_normal((129, 968))
+    _, (_, _, h64, _, _) = mlp.forward(params, x)
+    _, (_, _, h32, _, _) = mlp.forward(params, x, decide=np.float32)
+    diff = h64 != h32
+    assert diff.sum() <= 1e-3 * h64.size
+    a, b = h64[diff], h32[diff]
+    step = np.abs(np.maximum(np.abs(a), np.abs(b)))
+    # one bf16 step of the larger value: 2^(exponent - 7)
+    ulp = 2.0 ** (np.floor(np.log2(step)) - 7)
+    assert np.all(np.isclose(np.abs(a - b), ulp, rtol=0, atol=0) | np.isclose(np.abs(a - b), ulp / 2, rtol=0, atol=0))
