@@ -364,8 +364,7 @@ def main():
                     help="evaluate on a held-out trajectory of the workload drawn with this seed")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
