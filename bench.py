@@ -95,8 +95,10 @@ def residual_bytes(w):
 # workload and launch configuration, with the hash of the kernel sources they were taken
 # on (a changed kernel reports null until measured again)
 PASS1_TRAFFIC = {
-    ("shell-p3", 2): {"src": "7a6753241b91e774", "fetch_kib": 55060.1, "write_kib": 151680.0,
-                      "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_counters.txt"},
+    ("shell-p3", 2): {"src": "116a066549f0afe0", "fetch_kib": 55098.1, "write_kib": 151680.0,
+                      "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_cfg2_counters.txt"},
+    ("shell-p3", 3): {"src": "116a066549f0afe0", "fetch_kib": 66323.0, "write_kib": 163821.0,
+                      "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_cfg3_counters.txt"},
 }
 
 
@@ -356,6 +358,8 @@ def main():
                     help="sweep: the parametric study of the 1D model (three cases x 75 columns)")
     ap.add_argument("--sweep-hours", type=float, default=72.0, help="model hours per case (sweep mode)")
     ap.add_argument("--implicit-steps", type=int, default=4)
+    ap.add_argument("--pass1-config", type=int, default=None, choices=range(6),
+                    help="element-pass launch configuration instead of the autotuned one (for counter runs)")
     ap.add_argument("--ws-train-steps", type=int, default=60)
     ap.add_argument("--ws-eval-steps", type=int, default=8)
     ap.add_argument("--ws-epochs", type=int, default=8)
@@ -400,7 +404,11 @@ def main():
     u_np = shell_state(w, X)
     u = torch.from_numpy(u_np.ravel()).to(dev)
     from paper_2306_01085_amd import autotune
-    p1_cfg, _ = autotune.tune_shell_pass1(mesh, u)
+    if args.pass1_config is not None:
+        p1_cfg = args.pass1_config
+        mesh.set_option("shell_pass1_config", p1_cfg)
+    else:
+        p1_cfg, _ = autotune.tune_shell_pass1(mesh, u)
     log("element-pass configuration %d" % p1_cfg)
     v = torch.from_numpy(synth.tangent(u_np.shape, 1).ravel()).to(dev)
     v32 = v.float()

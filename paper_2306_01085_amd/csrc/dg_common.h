@@ -25,12 +25,25 @@ struct Dual {
 template <class S> struct Base { typedef S type; };
 template <class T> struct Base<Dual<T>> { typedef T type; };
 
+// 1/x for the nonzero normal divisors of the model (every one is positive: e^{-varrho/2},
+// T, radii, Jacobians, cos chi on the day side). FP64: the hardware reciprocal estimate
+// refined by two Newton steps, within about an ulp in five instructions where the IEEE
+// division takes about twelve. FP32: the division.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline float recip(float x) { return 1.0f / x; }
+
 template <class T> __device__ inline Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
 template <class T> __device__ inline Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
 template <class T> __device__ inline Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
 template <class T> __device__ inline Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
 template <class T> __device__ inline Dual<T> operator/(Dual<T> a, Dual<T> b) {
-  T inv = T(1) / b.v;
+  T inv = recip(b.v);
   T q = a.v * inv;
   return {q, (a.d - q * b.d) * inv};
 }
@@ -40,9 +53,9 @@ template <class T> __device__ inline Dual<T> operator-(Dual<T> a, T b) { return 
 template <class T> __device__ inline Dual<T> operator-(T b, Dual<T> a) { return {b - a.v, -a.d}; }
 template <class T> __device__ inline Dual<T> operator*(Dual<T> a, T b) { return {a.v * b, a.d * b}; }
 template <class T> __device__ inline Dual<T> operator*(T b, Dual<T> a) { return {a.v * b, a.d * b}; }
-template <class T> __device__ inline Dual<T> operator/(Dual<T> a, T b) { T inv = T(1) / b; return {a.v * inv, a.d * inv}; }
+template <class T> __device__ inline Dual<T> operator/(Dual<T> a, T b) { T inv = recip(b); return {a.v * inv, a.d * inv}; }
 template <class T> __device__ inline Dual<T> operator/(T a, Dual<T> b) {
-  T inv = T(1) / b.v;
+  T inv = recip(b.v);
   T q = a * inv;
   return {q, -q * b.d * inv};
 }
@@ -56,8 +69,12 @@ __device__ inline float xlog(float a) { return logf(a); }
 __device__ inline double xsqrt(double a) { return sqrt(a); }
 __device__ inline float xsqrt(float a) { return sqrtf(a); }
 template <class T> __device__ inline Dual<T> xexp(Dual<T> a) { T e = xexp(a.v); return {e, e * a.d}; }
-template <class T> __device__ inline Dual<T> xlog(Dual<T> a) { return {xlog(a.v), a.d / a.v}; }
-template <class T> __device__ inline Dual<T> xsqrt(Dual<T> a) { T s = xsqrt(a.v); return {s, a.d * (T(0.5) / s)}; }
+template <class T> __device__ inline Dual<T> xlog(Dual<T> a) { return {xlog(a.v), a.d * recip(a.v)}; }
+template <class T> __device__ inline Dual<T> xsqrt(Dual<T> a) { T s = xsqrt(a.v); return {s, a.d * (T(0.5) * recip(s))}; }
+template <class T> __device__ inline Dual<T> recip(Dual<T> a) {
+  const T i = recip(a.v);
+  return {i, -a.d * i * i};
+}
 __device__ inline double xerfcx(double a) { return erfcx(a); }
 __device__ inline float xerfcx(float a) { return erfcxf(a); }
 // d/dy erfcx(y) = 2 y erfcx(y) - 2 / sqrt(pi)
@@ -70,7 +87,7 @@ __device__ inline double xpow(double a, double c) { return exp(c * log(a)); }
 __device__ inline float xpow(float a, float c) { return expf(c * logf(a)); }
 template <class T> __device__ inline Dual<T> xpow(Dual<T> a, T c) {
   T p = xpow(a.v, c);
-  return {p, c * p / a.v * a.d};
+  return {p, c * p * recip(a.v) * a.d};
 }
 
 template <class S> __device__ inline typename Base<S>::type val(S a) { return a; }
@@ -181,7 +198,7 @@ template <int D>
 __device__ inline double cos_zenith(const PhysC& P, const double* x) {
   if constexpr (D == 3) {
     const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    return (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[2] * P.sun_dir[2]) / r;
+    return (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[2] * P.sun_dir[2]) * recip(r);
   } else {
     if (P.site[0] == 0.0 && P.site[1] == 0.0 && P.site[2] == 0.0) return 1.0;
     return P.site[0] * P.sun_dir[0] + P.site[1] * P.sun_dir[1] + P.site[2] * P.sun_dir[2];
@@ -257,7 +274,7 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
   const Mix mx = mixture<XP>(P, rx);
   const S lr = u[0];
   const S s = xexp(T(-0.5) * lr);
-  const S sq = T(1) / s;
+  const S sq = recip(s);
   const S rho = sq * sq;
   S U[D], v[D];
   for (int i = 0; i < D; ++i) { U[i] = u[1 + i]; v[i] = s * U[i]; }
@@ -290,7 +307,7 @@ __device__ inline void flux_source(const PhysC& P, const S* u, const S (*q)[D], 
   double r2 = 0;
   for (int k = 0; k < D; ++k) r2 += x[k] * x[k];
   const double r = sqrt(r2);
-  const double gfac = -P.r_ref2 / (r2 * r) / P.gamma;   // g_k / gamma = gfac x_k
+  const double gfac = -P.r_ref2 * recip(r2 * r * P.gamma);   // g_k / gamma = gfac x_k
   double cen[3] = {0, 0, 0};
   if (D == 3) {
     const double wr = P.om[0] * x[0] + P.om[1] * x[1] + P.om[2] * x[2];
@@ -358,7 +375,7 @@ __device__ inline void sigma(const PhysC& P, const S* uh, S& sig_m, S& sig_e, do
   typedef typename Base<S>::type T;
   const Mix mx = mixture<XP>(P, r);
   const S s = xexp(T(-0.5) * uh[0]);
-  const S rho = T(1) / (s * s);
+  const S rho = recip(s * s);
   const S Tm = s * uh[D + 1];
   const S mu = xsqrt(Tm * T(mx.m)) + T(P.nu_r) * rho;
   const S kap = T(P.alpha0c * mx.kw) * xpow(Tm, T(P.kexp)) + T(P.alpha_r * mx.inv_m) * rho;
@@ -389,13 +406,13 @@ __device__ inline double heating(const PhysC& P, const double* x, double t) {
   const double r = sqrt(r2);
   double cchi = 1.0;
   if constexpr (D == 3)
-    cchi = (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[D - 1] * P.sun_dir[2]) / r;
+    cchi = (x[0] * P.sun_dir[0] + x[1] * P.sun_dir[1] + x[D - 1] * P.sun_dir[2]) * recip(r);
   else
     cchi = cos_zenith<1>(P, x);
   (void)t;
   if (!(cchi > 0.0)) return 0.0;
   const double z = (r - P.heat_rm) * P.heat_inv_H;
-  return P.heat_amp * P.heat_qm * exp(1.0 - z - exp(-z) / cchi);
+  return P.heat_amp * P.heat_qm * exp(1.0 - z - exp(-z) * recip(cchi));
 }
 
 // the same on the device (kernels that advance time themselves)

@@ -130,7 +130,7 @@ __device__ inline void node_gradient(const ShellDev& M, const PhysC& ph, const d
     const double ri = g.rk + 0.5 * (xg[i] + 1.0) * g.hk;
     r2[i] = ri * ri;
   }
-  const double invJ = 1.0 / g.Jac;
+  const double invJ = recip(g.Jac);
   for (int c = 0; c < 5; ++c) {
     S d1[3], d2[3], d3;
     for (int d = 0; d < 3; ++d) { d1[d] = S(T(0)); d2[d] = S(T(0)); }
@@ -313,8 +313,8 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   if (active) {
     g = node_geo<P>(M, gc, s_ang[le], k, j);
     const double rrp = g.rc * g.rp, rc2 = g.rc * g.rc;
-    const double invJ = 1.0 / g.Jac;
-    const double lfac = invJ / w_end;
+    const double invJ = recip(g.Jac);
+    const double lfac = invJ * recip(w_end);
     // metric factors of the three directions at this node
     const double Ja[3][3] = {{rrp * g.A1[0], rrp * g.A1[1], rrp * g.A1[2]},
                              {rrp * g.A2[0], rrp * g.A2[1], rrp * g.A2[2]},
@@ -416,8 +416,8 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
 
   // ---- phase E (node threads): interior-face terms of this side and the traces sent to
   // the neighbours, then the volume divergence one field at a time
-  const double invJ = active ? 1.0 / g.Jac : 0.0;
-  const double lfac = invJ / w_end;
+  const double invJ = active ? recip(g.Jac) : 0.0;
+  const double lfac = invJ * recip(w_end);
   if (active) {
     const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
     for (int f = 0; f < 6; ++f) {
@@ -800,8 +800,8 @@ __global__ __launch_bounds__(BfShape<P>::THREADS) void shell_pass1_bf16(ShellDev
   if (active) {
     g = node_geo<P>(M, gc, s_ang[le], k, j);
     const double rrp = g.rc * g.rp, rc2 = g.rc * g.rc;
-    const double invJ = 1.0 / g.Jac;
-    const double lfac = invJ / w_end;
+    const double invJ = recip(g.Jac);
+    const double lfac = invJ * recip(w_end);
     const double Ja[3][3] = {{rrp * g.A1[0], rrp * g.A1[1], rrp * g.A1[2]},
                              {rrp * g.A2[0], rrp * g.A2[1], rrp * g.A2[2]},
                              {rc2 * g.A3[0], rc2 * g.A3[1], rc2 * g.A3[2]}};
@@ -916,8 +916,8 @@ __global__ __launch_bounds__(BfShape<P>::THREADS) void shell_pass1_bf16(ShellDev
 
   // ---- node threads: interior-face terms, sent traces, output
   if (active) {
-    const double invJ = 1.0 / g.Jac;
-    const double lfac = invJ / w_end;
+    const double invJ = recip(g.Jac);
+    const double lfac = invJ * recip(w_end);
     const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
     for (int f = 0; f < 6; ++f) {
       if (!on[f]) continue;
