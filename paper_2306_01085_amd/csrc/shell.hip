@@ -77,6 +77,29 @@ __device__ inline int face_neighbour(const ShellDev& M, int cell, int k, int f, 
   return c2 * M.n_rad + k;
 }
 
+// the same with the element's angular connectivity staged in LDS: cn[f] = {neighbour
+// cell, its face, the along-edge index map (n entries)} of angular face f
+template <int P>
+__device__ inline int face_neighbour_lds(const ShellDev& M, const int (*cn)[P + 3], int cell, int k, int f, int a,
+                                         int b, int cz, int& jn, int& fn, int& mn) {
+  constexpr int n = P + 1, N2 = n * n;
+  if (f >= 4) return face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
+  const int s = (f < 2) ? b : a;
+  const int c2 = cn[f][0];
+  fn = cn[f][1];
+  const int s2 = cn[f][2 + s];
+  int a2, b2;
+  switch (fn) {
+    case 0: a2 = 0; b2 = s2; break;
+    case 1: a2 = n - 1; b2 = s2; break;
+    case 2: a2 = s2; b2 = 0; break;
+    default: a2 = s2; b2 = n - 1; break;
+  }
+  jn = a2 + n * b2 + N2 * cz;
+  mn = s2 + n * cz;
+  return c2 * M.n_rad + k;
+}
+
 // face-node index of node (a, b, cz) within face f
 template <int P>
 __device__ inline int face_slot(int f, int a, int b, int cz) {
@@ -228,6 +251,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   __shared__ S s_f[EPB][6][5][N2];   // per face slot: u_hat - u; later the flux staging of phase E
   __shared__ S s_z[EPB][5][5][N2];   // Z of the owned faces, in the order of their face index
   __shared__ int s_nb[EPB][6][N2];   // trace slot of the neighbour's matching face node
+  __shared__ int s_cn[EPB][4][P + 3];  // angular connectivity: neighbour cell, its face, index map
   __shared__ double D[n * n];
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
@@ -238,8 +262,13 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   const int k = live ? e % M.n_rad : 0;
   if (threadIdx.x < n * n) D[threadIdx.x] = gc.D[threadIdx.x];
   const double w_end = gc.w[0];
-  if (live)
+  if (live) {
     for (int idx = j; idx < 13 * N2; idx += TPE) s_ang[le][idx / N2][idx % N2] = M.ang[(int64_t)cell * 13 * N2 + idx];
+    if (j < 4 * (n + 2)) {
+      const int f = j / (n + 2), w = j % (n + 2);
+      s_cn[le][f][w] = w == 0 ? M.cnbr[cell * 4 + f] : (w == 1 ? M.cface[cell * 4 + f] : M.cmap[(cell * 4 + f) * n + w - 2]);
+    }
+  }
   S uu[5];
   const int64_t base = (int64_t)e * 5 * N;
   if (active)
@@ -249,15 +278,15 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
     }
   const double rk = live ? M.edges[k] : 0.0;
   const double hk = live ? M.edges[k + 1] - rk : 1.0;
+  __syncthreads();
   // owned interior faces (bit f): the neighbour has the larger element index
   int own = 0;
   if (live) {
     for (int f = 0; f < 4; ++f)
-      if (RAD || M.cnbr[cell * 4 + f] * M.n_rad + k > e) own |= 1 << f;
+      if (RAD || s_cn[le][f][0] * M.n_rad + k > e) own |= 1 << f;
     if (k < M.n_rad - 1) own |= 1 << 5;
   }
   const int n_own = __popc(own);
-  __syncthreads();
 
   // ---- phase B (face-node tasks, owned faces first): numerical trace u_hat - u of every
   // face slot, the neighbour's trace slot, and Z on the owned faces
@@ -271,7 +300,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       S uo[5], du[5];
       for (int c = 0; c < 5; ++c) uo[c] = s_u[le][c][jo];
       int jn, fn, mn;
-      const int en = face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
+      const int en = face_neighbour_lds<P>(M, s_cn[le], cell, k, f, a, b, cz, jn, fn, mn);
       if (en >= 0) {
         for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uo[c]);
         if constexpr (RAD) {
