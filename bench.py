@@ -95,9 +95,9 @@ def residual_bytes(w):
 # workload and launch configuration, with the hash of the kernel sources they were taken
 # on (a changed kernel reports null until measured again)
 PASS1_TRAFFIC = {
-    ("shell-p3", 2): {"src": "116a066549f0afe0", "fetch_kib": 55098.1, "write_kib": 151680.0,
+    ("shell-p3", 2): {"src": "f6477acdb5566b4f", "fetch_kib": 55094.6, "write_kib": 151680.0,
                       "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_cfg2_counters.txt"},
-    ("shell-p3", 3): {"src": "116a066549f0afe0", "fetch_kib": 66323.0, "write_kib": 163821.0,
+    ("shell-p3", 3): {"src": "f6477acdb5566b4f", "fetch_kib": 65023.8, "write_kib": 163388.6,
                       "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_cfg3_counters.txt"},
 }
 
