@@ -123,14 +123,15 @@ def traffic(workload, cfg):
     return fetch + write, {"fetch_bytes": fetch, "write_bytes": write, "profile": t["profile"]}
 
 
-def cpu_baseline(w, budget_s=20.0):
+def cpu_baseline(w, budget_s=15.0):
     """the FP64 oracle's residual on a bounded sample of the same workload: the same
-    element type, degree and physics on a shell of 6 x 4 x 4 x 16 elements"""
+    element type, degree and physics on a shell of 6 x 8 x 8 x 16 elements (a quarter of the
+    benchmark shell), repeated for about budget_s seconds of CPU work (at most 15 runs)"""
     from threadpoolctl import threadpool_limits
 
     from oracle import dg as odg
     from oracle import mesh as omesh
-    n_ang, n_rad = 4, w.n_rad
+    n_ang, n_rad = 8, w.n_rad
     om = omesh.shell_mesh(w.p, n_ang, n_rad, w.r_bot, w.r_top, w.stretch)
     u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
     ndof = u.size
@@ -138,7 +139,7 @@ def cpu_baseline(w, budget_s=20.0):
     with threadpool_limits(limits=1):
         odg.residual(om, w.phys, u, 0.0)            # warm-up
         t_end = time.perf_counter() + budget_s
-        while len(times) < 5 and time.perf_counter() < t_end:
+        while len(times) < 15 and time.perf_counter() < t_end:
             t0 = time.perf_counter()
             odg.residual(om, w.phys, u, 0.0)
             times.append(time.perf_counter() - t0)
