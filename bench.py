@@ -175,6 +175,9 @@ def network_rates(w, steps, warmup, timed):
     from paper_2306_01085_amd import Network
     from paper_2306_01085_amd import warmstart as wsm
     nin, nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
+    if nin % 8 or nout % 32:
+        return {"skipped": "the network's layer widths (%d in, %d out) are not multiples of 8 and 32 at p = %d"
+                           % (nin, nout, w.p)}
     net = Network(nin, nout, wsm.init_params(np.random.default_rng(0), nin, nout))
     rows = w.n_elem
     g = torch.Generator(device="cuda").manual_seed(0)
