@@ -502,6 +502,25 @@ def config_shell_p4(seed=0):
     return shell_workload(seed=seed, p=4, n_ang=32, n_rad=24, stretch=1.15, name="shell-6x32x32x24-p4")
 
 
+def fullsize_workload(name):
+    """the benchmark shells of the full-size parity fixtures: the 7.9M-DOF p = 3 and the
+    92M-DOF p = 4 shells, and the p = 3 shell with the variable composition and EUVAC
+    heating (June solstice, F10.7bar 150) in place of the prescribed profile"""
+    import dataclasses
+    if name == "shell-p3":
+        return config_shell_p3(0)
+    if name == "shell-p4":
+        return config_shell_p4(0)
+    if name == "shell-p3-mixture-euvac":
+        w = with_composition(config_shell_p3(0))
+        phys = dict(w.phys)
+        phys.update(euvac_physics(f107bar=150.0, day=172.0))
+        phys["heating_model"] = 1
+        phys["heat_amp"] = 0.0
+        return dataclasses.replace(w, phys=phys, name=w.name + "-euvac")
+    raise ValueError("unknown full-size workload " + name)
+
+
 def tangent(shape, seed=1):
     """unit-norm Gaussian tangent vector"""
     v = np.random.default_rng(seed).standard_normal(shape)

@@ -1,10 +1,12 @@
 """Write the full-size parity fixtures: the oracle's FP64 R(u) and J(u)v on a whole
 benchmark shell, sampled on a fixed set of elements.
 
-Usage (from the repository root):  python tests/golden/make_fullsize.py shell-p3|shell-p4
+Usage (from the repository root):
+  python tests/golden/make_fullsize.py shell-p3|shell-p4|shell-p3-mixture-euvac
 
 The oracle evaluates eq. (DGformulation) on the complete mesh (the 6x16x16x16 p = 3 shell
-with 7,864,320 DOF, or the 6x32x32x24 p = 4 shell with 92,160,000 DOF); the state is the
+with 7,864,320 DOF, or the 6x32x32x24 p = 4 shell with 92,160,000 DOF; the third fixture is
+the p = 3 shell with the variable composition and EUVAC heating); the state is the
 workload's seeded input at the oracle's own nodes, the tangent the seeded unit-norm
 Gaussian, t = 0.25. Stored per sampled element: R, the per-node term scale
 (|volume| + |lift| + |source|) and J v, all [5, N]. Only oracle/ and the input generators
@@ -30,11 +32,7 @@ TANGENT_SEED = 11
 
 
 def workload(name):
-    if name == "shell-p3":
-        return synth.config_shell_p3(0)
-    if name == "shell-p4":
-        return synth.config_shell_p4(0)
-    raise SystemExit("unknown workload " + name)
+    return synth.fullsize_workload(name)
 
 
 def sample_elements(w, count):
@@ -55,7 +53,7 @@ def sample_elements(w, count):
 
 def main():
     name = sys.argv[1]
-    count = 24 if name == "shell-p3" else 12
+    count = 12 if name == "shell-p4" else 24
     w = workload(name)
     t0 = time.time()
     om = omesh.shell_mesh(w.p, w.n_ang, w.n_rad, w.r_bot, w.r_top, w.stretch)

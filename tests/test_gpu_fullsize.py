@@ -1,5 +1,7 @@
 """Full-size parity of R(u) and J(u)v on the benchmark shells (6x16x16x16 p = 3, 7.9M DOF;
-6x32x32x24 p = 4, 92M DOF) against the oracle's FP64 values on sampled elements.
+6x32x32x24 p = 4, 92M DOF; the p = 3 shell with the variable composition and EUVAC heating,
+which runs the extended-physics instantiation) against the oracle's FP64 values on
+sampled elements.
 
 The expected values are tests/golden/fullsize_<workload>.json, written by
 tests/golden/make_fullsize.py from oracle/ and the input generators only (the oracle
@@ -25,7 +27,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.parametrize("name", ["shell-p3", "shell-p4"])
+@pytest.mark.parametrize("name", ["shell-p3", "shell-p4", "shell-p3-mixture-euvac"])
 def test_fullsize_residual_and_jvp(name):
     need_gpu()
     from paper_2306_01085_amd import Mesh
@@ -34,7 +36,7 @@ def test_fullsize_residual_and_jvp(name):
         pytest.skip("fixture %s not written (python tests/golden/make_fullsize.py %s)" % (path, name))
     with open(path) as f:
         fx = json.load(f)
-    w = synth.config_shell_p3(0) if name == "shell-p3" else synth.config_shell_p4(0)
+    w = synth.fullsize_workload(name)
     assert (w.p, w.n_ang, w.n_rad) == (fx["p"], fx["n_ang"], fx["n_rad"])
     gm = Mesh.shell(p=w.p, n_ang=w.n_ang, n_rad=w.n_rad, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch,
                     phys=w.phys)
@@ -51,7 +53,9 @@ def test_fullsize_residual_and_jvp(name):
     def sampled(x):
         return x.reshape(w.n_elem, 5, N)[torch.as_tensor(els, device=x.device)].double().cpu().numpy()
 
-    for cfg in range(6):
+    # (a mesh with EUVAC or the composition runs its one extended instantiation whatever the
+    # configuration: one pass suffices)
+    for cfg in (range(6) if w.phys.get("heating_model", 0) == 0 and not w.phys.get("composition") else [0]):
         gm.set_option("shell_pass1_config", cfg)
         r = sampled(gm.residual(ut, t=t))
         err = np.max(np.abs(r - R_ref)) / np.max(scale)
