@@ -47,3 +47,33 @@ def test_struct_layout_matches_header(tmp_path):
     sizes = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert sizes == [ctypes.sizeof(pkg.MeshDesc), ctypes.sizeof(pkg.Physics), ctypes.sizeof(pkg.SolverOpts),
                      ctypes.sizeof(pkg.StepStats)]
+
+
+def test_field_offsets_and_enums_match_header(tmp_path):
+    """every field of the ctypes mirrors sits at the C compiler's offset, and the binding's
+    precision codes are the header's"""
+    import shutil
+    import subprocess
+    import paper_2306_01085_amd as pkg
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [("dg_mesh_desc_t", pkg.MeshDesc), ("dg_physics_t", pkg.Physics), ("dg_solver_opts_t", pkg.SolverOpts),
+               ("dg_step_stats_t", pkg.StepStats)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dgthermo.h"', 'int main(void) {']
+    for cname, cls in structs:
+        for fname, _ in cls._fields_:
+            lines.append('  printf("%%zu\\n", offsetof(%s, %s));' % (cname, fname))
+    lines.append('  printf("%d %d %d %d\\n", (int)DG_F64, (int)DG_F32, (int)DG_BF16, (int)DG_F64_FD);')
+    lines.append('  return 0; }')
+    src = tmp_path / "offsets.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "offsets"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    i = 0
+    for cname, cls in structs:
+        for fname, _ in cls._fields_:
+            assert int(out[i]) == getattr(cls, fname).offset, (cname, fname)
+            i += 1
+    assert [int(x) for x in out[i].split()] == [pkg.DG_F64, pkg.DG_F32, pkg.DG_BF16, pkg.DG_F64_FD]
