@@ -65,11 +65,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_mdot(int64_t n, const T* __rest
   if (threadIdx.x < K) part[blockIdx.x * K + threadIdx.x] = red[threadIdx.x];
 }
 
-// out[k] = sum_b part[b*K + k]   (single block)
+// out[k] = sum_b part[b*K + k]; block i takes k = i, i + gridDim.x, ... (launched with one
+// block per k; every k is summed in the same order whatever the grid)
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ part, int nb, int K,
                                                         double* __restrict__ out) {
   __shared__ double red[RED_THREADS / 64];
-  for (int k = 0; k < K; ++k) {
+  for (int k = blockIdx.x; k < K; k += gridDim.x) {
     double s = 0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b * K + k];
     s = wave_sum(s);
@@ -494,7 +495,7 @@ dg_status_t jvp_fd(dg_mesh_s* m, double t, const double* u, const double* v, dou
   double* sums = part + 2 * RED_BLOCKS;
   const int nb = (int)std::min<int64_t>((n + RED_THREADS - 1) / RED_THREADS, RED_BLOCKS);
   k_sumsq2<<<nb, RED_THREADS, 0, s>>>(n, u, v, part);
-  k_reduce<<<1, RED_THREADS, 0, s>>>(part, nb, 2, sums);
+  k_reduce<<<2, RED_THREADS, 0, s>>>(part, nb, 2, sums);
   const unsigned g = (unsigned)((n + 255) / 256);
   k_fd_perturb<<<g, 256, 0, s>>>(n, u, v, sums, w);
   dg_status_t st = residual(m, t, w, jv, s);
@@ -627,7 +628,7 @@ static void rb_coefficients(dg_mesh_s* m, Workspace* ws, const T* v, hipStream_t
   const int k = ws->rb_count;
   double* d = ws->rb_dev + RB_MAX * RB_MAX;
   launch_mdot<T>(k, n, (const T*)ws->rbZ, n, v, ws->part, nb, s);
-  k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
+  k_reduce<<<k, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
   k_rb_coef<<<1, 64, 0, s>>>(k, ws->rb_dev, d, d + RB_MAX);
 }
 
@@ -684,7 +685,7 @@ static dg_status_t rb_push(dg_mesh_s* m, Workspace* ws, int n_rb, double t, doub
   const int k = ws->rb_count;
   double* d = ws->rb_dev + RB_MAX * RB_MAX;
   launch_mdot<T>(k, n, (const T*)ws->rbZ, n, Zd, ws->part, nb, s);
-  k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
+  k_reduce<<<k, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
   DG_HIP_CHECK(hipMemcpyAsync(ws->host_small, d, k * sizeof(double), hipMemcpyDeviceToHost, s));
   DG_HIP_CHECK(hipStreamSynchronize(s));
   for (int j = 0; j < k; ++j) {
@@ -761,9 +762,9 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
       {
         ProfScope ps(m, 9, s);
         launch_mdot<T>(j + 1, n, V, n, w, ws->part, nb, s);
-        k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h1);
+        k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h1);
         launch_orth_mdot<T>(j + 1, n, V, n, h1, w, ws->part, nb, s);
-        k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h2);
+        k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h2);
         k_orth_update<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, j + 1, h2, w, ws->part);
         k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 1, nr);
         k_normalize<T><<<nb, RED_THREADS, 0, s>>>(n, w, nr, V + (size_t)(j + 1) * n);
@@ -976,7 +977,7 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       if (rc != DG_OK) return rc;
       k_stage_op<double><<<nb, RED_THREADS, 0, s>>>(n, ws->X, ca, ws->Rc);
       k_dot2<<<nb, RED_THREADS, 0, s>>>(n, ws->G, ws->Rc, ws->part);
-      k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 2, ws->dev_small);
+      k_reduce<<<2, RED_THREADS, 0, s>>>(ws->part, nb, 2, ws->dev_small);
       DG_HIP_CHECK(hipMemcpyAsync(ws->host_small, ws->dev_small, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
       DG_HIP_CHECK(hipStreamSynchronize(s));
       const double gd = ws->host_small[0], dd = ws->host_small[1];
