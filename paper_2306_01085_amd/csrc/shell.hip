@@ -21,476 +21,10 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "shell_pass1.h"
 #include "mfma_bf16.h"
 
 namespace dg {
-
-template <int P> struct Shape {
-  static constexpr int n = P + 1, N = n * n * n, N2 = n * n;
-  static constexpr int TPE = (P == 2) ? 32 : (P == 3 ? 64 : 128);
-  static constexpr int EPB = 256 / TPE;
-};
-
-// output part of a scalar: the value, or the derivative of a dual
-__device__ inline double outp(double x) { return x; }
-__device__ inline float outp(float x) { return x; }
-template <class T> __device__ inline T outp(Dual<T> x) { return x.d; }
-
-template <class S, class SU, class TV>
-__device__ inline S load_state(const SU* u, const TV* v, int64_t i) {
-  return Io<S>::ld(u, v, i);
-}
-
-// neighbour of a face node: returns the neighbour element (or -1 on a boundary),
-// the neighbour's local node and the neighbour's face index / face-node index
-template <int P>
-__device__ inline int face_neighbour(const ShellDev& M, int cell, int k, int f, int a, int b, int cz,
-                                     int& jn, int& fn, int& mn) {
-  constexpr int n = P + 1, N2 = n * n;
-  if (f >= 4) {
-    if (f == 4) {
-      if (k == 0) return -1;
-      jn = a + n * b + N2 * (n - 1);
-      fn = 5;
-      mn = a + n * b;
-      return cell * M.n_rad + k - 1;
-    }
-    if (k == M.n_rad - 1) return -1;
-    jn = a + n * b;
-    fn = 4;
-    mn = a + n * b;
-    return cell * M.n_rad + k + 1;
-  }
-  const int s = (f < 2) ? b : a;
-  const int c2 = M.cnbr[cell * 4 + f];
-  fn = M.cface[cell * 4 + f];
-  const int s2 = M.cmap[(cell * 4 + f) * n + s];
-  int a2, b2;
-  switch (fn) {
-    case 0: a2 = 0; b2 = s2; break;
-    case 1: a2 = n - 1; b2 = s2; break;
-    case 2: a2 = s2; b2 = 0; break;
-    default: a2 = s2; b2 = n - 1; break;
-  }
-  jn = a2 + n * b2 + N2 * cz;
-  mn = s2 + n * cz;
-  return c2 * M.n_rad + k;
-}
-
-// the same with the element's angular connectivity staged in LDS: cn[f] = {neighbour
-// cell, its face, the along-edge index map (n entries)} of angular face f
-template <int P>
-__device__ inline int face_neighbour_lds(const ShellDev& M, const int (*cn)[P + 3], int cell, int k, int f, int a,
-                                         int b, int cz, int& jn, int& fn, int& mn) {
-  constexpr int n = P + 1, N2 = n * n;
-  if (f >= 4) return face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
-  const int s = (f < 2) ? b : a;
-  const int c2 = cn[f][0];
-  fn = cn[f][1];
-  const int s2 = cn[f][2 + s];
-  int a2, b2;
-  switch (fn) {
-    case 0: a2 = 0; b2 = s2; break;
-    case 1: a2 = n - 1; b2 = s2; break;
-    case 2: a2 = s2; b2 = 0; break;
-    default: a2 = s2; b2 = n - 1; break;
-  }
-  jn = a2 + n * b2 + N2 * cz;
-  mn = s2 + n * cz;
-  return c2 * M.n_rad + k;
-}
-
-// face-node index of node (a, b, cz) within face f
-template <int P>
-__device__ inline int face_slot(int f, int a, int b, int cz) {
-  constexpr int n = P + 1;
-  if (f < 2) return b + n * cz;
-  if (f < 4) return a + n * cz;
-  return a + n * b;
-}
-
-struct NodeGeo {
-  int a, b, cz, ja;
-  double rk, hk, rc, rp, Jac, x[3], A1[3], A2[3], A3[3];
-};
-
-// geometry of node j of an element in radial layer k (angular tables staged in LDS)
-template <int P>
-__device__ inline NodeGeo node_geo(const ShellDev& M, const GllC& gc, const double (*ang)[Shape<P>::N2], int k,
-                                   int j) {
-  constexpr int n = P + 1, N2 = n * n;
-  NodeGeo g;
-  g.a = j % n;
-  g.b = (j / n) % n;
-  g.cz = j / N2;
-  g.ja = g.a + n * g.b;
-  g.rk = M.edges[k];
-  g.hk = M.edges[k + 1] - g.rk;
-  g.rp = 0.5 * g.hk;
-  g.rc = g.rk + 0.5 * (gc.x[g.cz] + 1.0) * g.hk;
-  for (int d = 0; d < 3; ++d) {
-    g.A1[d] = ang[d][g.ja];
-    g.A2[d] = ang[3 + d][g.ja];
-    g.A3[d] = ang[6 + d][g.ja];
-    g.x[d] = g.rc * ang[10 + d][g.ja];
-  }
-  g.Jac = g.rc * g.rc * g.rp * ang[9][g.ja];
-  return g;
-}
-
-// auxiliary gradient q at one node: the conservative strong form of the weak LDG
-// gradient, q = (1/J) sum_a D_a(J a^a u) + sum_faces Sn (u_hat - u)/(w_end J)
-template <int P, class S, class SU, class TV>
-__device__ inline void node_gradient(const ShellDev& M, const PhysC& ph, const double* D, const double* xg, double w_end,
-                                     const double (*ang)[Shape<P>::N2], const S (*su)[Shape<P>::N], const SU* u,
-                                     const TV* v, int cell, int k, const NodeGeo& g, const S* uu, S (*q)[3]) {
-  typedef typename Base<S>::type T;
-  constexpr int n = P + 1, N = n * n * n, N2 = n * n;
-  const int a = g.a, b = g.b, cz = g.cz, ja = g.ja;
-  const double rrp = g.rc * g.rp;
-  double r2[n];
-  for (int i = 0; i < n; ++i) {
-    const double ri = g.rk + 0.5 * (xg[i] + 1.0) * g.hk;
-    r2[i] = ri * ri;
-  }
-  const double invJ = recip(g.Jac);
-  for (int c = 0; c < 5; ++c) {
-    S d1[3], d2[3], d3;
-    for (int d = 0; d < 3; ++d) { d1[d] = S(T(0)); d2[d] = S(T(0)); }
-    d3 = S(T(0));
-    for (int i = 0; i < n; ++i) {
-      const S u1 = su[c][i + n * b + N2 * cz];
-      const S u2 = su[c][a + n * i + N2 * cz];
-      const S u3 = su[c][ja + N2 * i];
-      const double Da = D[a * n + i], Db = D[b * n + i], Dc = D[cz * n + i] * r2[i];
-      for (int d = 0; d < 3; ++d) {
-        d1[d] = d1[d] + u1 * T(Da * ang[d][i + n * b]);
-        d2[d] = d2[d] + u2 * T(Db * ang[3 + d][a + n * i]);
-      }
-      d3 = d3 + u3 * T(Dc);
-    }
-    for (int d = 0; d < 3; ++d) q[c][d] = (T(rrp) * (d1[d] + d2[d]) + T(g.A3[d]) * d3) * T(invJ);
-  }
-  const double lfac = 1.0 / (w_end * g.Jac);
-  for (int f = 0; f < 6; ++f) {
-    const bool on = (f == 0 && a == 0) || (f == 1 && a == n - 1) || (f == 2 && b == 0) || (f == 3 && b == n - 1) ||
-                    (f == 4 && cz == 0) || (f == 5 && cz == n - 1);
-    if (!on) continue;
-    const double side = (f & 1) ? 1.0 : -1.0;
-    double Sn[3];
-    for (int d = 0; d < 3; ++d)
-      Sn[d] = side * (f < 2 ? rrp * g.A1[d] : (f < 4 ? rrp * g.A2[d] : g.rc * g.rc * g.A3[d]));
-    int jn, fn, mn;
-    const int en = face_neighbour<P>(M, cell, k, f, a, b, cz, jn, fn, mn);
-    S du[5];
-    if (en >= 0) {
-      for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uu[c]);
-    } else if (ph.bc_mode == 1 || f == 4) {
-      S ub[5];
-      boundary_state<3, S>(ph, uu, ub);
-      for (int c = 0; c < 5; ++c) du[c] = ub[c] - uu[c];
-    } else {
-      continue;   // upper boundary: u_hat = u
-    }
-    for (int c = 0; c < 5; ++c)
-      for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du[c] * T(Sn[d] * lfac);
-  }
-}
-
-// node (a, b, cz) of slot m of face f (inverse of face_slot)
-template <int P>
-__device__ inline void slot_node(int f, int m, int& a, int& b, int& cz) {
-  constexpr int n = P + 1;
-  if (f < 2) {
-    a = (f == 0) ? 0 : n - 1;
-    b = m % n;
-    cz = m / n;
-  } else if (f < 4) {
-    b = (f == 2) ? 0 : n - 1;
-    a = m % n;
-    cz = m / n;
-  } else {
-    cz = (f == 4) ? 0 : n - 1;
-    a = m % n;
-    b = m / n;
-  }
-}
-
-// The interior-face stabilisation is single valued up to its sign: with
-// u_hat = (u + u^-)/2 the term on this side is -|Sn| sigma(u_hat)(u - u_hat) and on the
-// neighbour's side -|Sn| sigma(u_hat)(u^- - u_hat) = +|Sn| sigma(u_hat)(u - u_hat). Of
-// the two elements of a face, the one with the smaller index (the face's owner)
-// evaluates sigma once and folds the neighbour's share into the trace it sends, so
-// the trace slot of a face node holds F.Sn - 2 Z with Z = |Sn| sigma(u_hat)(u_hat - u)
-// (Z = 0 when the receiving element is the owner).
-
-// the r-th set bit of mask (r counted from 0)
-__device__ inline int nth_bit(int mask, int r) {
-  for (int i = 0; i < r; ++i) mask &= mask - 1;
-  return __ffs(mask) - 1;
-}
-
-// EPB: elements per block; OCC: minimum waves per SIMD the register allocation must allow.
-// RAD (dual numbers only): the radial-line linearisation of the line preconditioner. In
-// the derivative parts the tangent at other angular nodes is taken as zero: across the
-// angular faces (the neighbour's tangent), in the angular line sums of the gradient and
-// of the divergence (only the node's own term); every element takes the stabilisation of
-// its own side of the angular faces and sends no angular traces. Radial coupling is
-// exact. Lines (cell, a, b) are then independent.
-// XP: the extended physics the instantiation contains (kXpEuv, kXpComp; PhysC::xp_mode).
-template <int P, int EPB, int OCC, class S, class SU, class TV, class OT, bool RAD = false, int XP = 0>
-__global__ __launch_bounds__(Shape<P>::TPE * EPB) __attribute__((amdgpu_waves_per_eu(OCC)))
-void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__ u, const TV* __restrict__ v,
-                 OT* __restrict__ R, OT* __restrict__ Fn) {
-  typedef Shape<P> Sh;
-  typedef typename Base<S>::type T;
-  constexpr int n = Sh::n, N = Sh::N, N2 = Sh::N2, TPE = Sh::TPE;
-  static_assert(3 * N <= 6 * 5 * N2, "flux staging must fit in the trace buffer");
-  __shared__ double s_ang[EPB][13][N2];
-  __shared__ S s_u[EPB][5][N];
-  __shared__ S s_f[EPB][6][5][N2];   // per face slot: u_hat - u; later the flux staging of phase E
-  __shared__ S s_z[EPB][5][5][N2];   // Z of the owned faces, in the order of their face index
-  __shared__ int s_nb[EPB][6][N2];   // trace slot of the neighbour's matching face node
-  __shared__ int s_cn[EPB][4][P + 3];  // angular connectivity: neighbour cell, its face, index map
-  __shared__ double D[n * n];
-  const int le = threadIdx.x / TPE;
-  const int j = threadIdx.x % TPE;
-  const int e = blockIdx.x * EPB + le;
-  const bool live = e < M.E;
-  const bool active = live && (j < N);
-  const int cell = live ? e / M.n_rad : 0;
-  const int k = live ? e % M.n_rad : 0;
-  if (threadIdx.x < n * n) D[threadIdx.x] = gc.D[threadIdx.x];
-  const double w_end = gc.w[0];
-  if (live) {
-    for (int idx = j; idx < 13 * N2; idx += TPE) s_ang[le][idx / N2][idx % N2] = M.ang[(int64_t)cell * 13 * N2 + idx];
-    if (j < 4 * (n + 2)) {
-      const int f = j / (n + 2), w = j % (n + 2);
-      s_cn[le][f][w] = w == 0 ? M.cnbr[cell * 4 + f] : (w == 1 ? M.cface[cell * 4 + f] : M.cmap[(cell * 4 + f) * n + w - 2]);
-    }
-  }
-  S uu[5];
-  const int64_t base = (int64_t)e * 5 * N;
-  if (active)
-    for (int c = 0; c < 5; ++c) {
-      uu[c] = load_state<S>(u, v, base + c * N + j);
-      s_u[le][c][j] = uu[c];
-    }
-  const double rk = live ? M.edges[k] : 0.0;
-  const double hk = live ? M.edges[k + 1] - rk : 1.0;
-  __syncthreads();
-  // owned interior faces (bit f): the neighbour has the larger element index
-  int own = 0;
-  if (live) {
-    for (int f = 0; f < 4; ++f)
-      if (RAD || s_cn[le][f][0] * M.n_rad + k > e) own |= 1 << f;
-    if (k < M.n_rad - 1) own |= 1 << 5;
-  }
-  const int n_own = __popc(own);
-
-  // ---- phase B (face-node tasks, owned faces first): numerical trace u_hat - u of every
-  // face slot, the neighbour's trace slot, and Z on the owned faces
-  if (live)
-    for (int tsk = j; tsk < 6 * N2; tsk += TPE) {
-      const int r = tsk / N2, m = tsk % N2;
-      const int f = (r < n_own) ? nth_bit(own, r) : nth_bit(~own & 63, r - n_own);
-      int a, b, cz;
-      slot_node<P>(f, m, a, b, cz);
-      const int jo = a + n * b + N2 * cz;
-      S uo[5], du[5];
-      for (int c = 0; c < 5; ++c) uo[c] = s_u[le][c][jo];
-      int jn, fn, mn;
-      const int en = face_neighbour_lds<P>(M, s_cn[le], cell, k, f, a, b, cz, jn, fn, mn);
-      if (en >= 0) {
-        for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uo[c]);
-        if constexpr (RAD) {
-          if (f < 4)
-            for (int c = 0; c < 5; ++c) du[c].d = T(-0.5) * uo[c].d;
-        }
-        s_nb[le][f][m] = (en * 6 + fn) * 5 * N2 + mn;
-        if (r < n_own) {
-          const int dd = f >> 1;
-          const int ja = a + n * b;
-          const double rc = rk + 0.5 * (gc.x[cz] + 1.0) * hk;
-          const double fac = (dd < 2) ? rc * 0.5 * hk : rc * rc;
-          const double A0 = s_ang[le][3 * dd][ja], A1 = s_ang[le][3 * dd + 1][ja], A2 = s_ang[le][3 * dd + 2][ja];
-          const double Smag = fac * sqrt(A0 * A0 + A1 * A1 + A2 * A2);
-          S uh[5];
-          for (int c = 0; c < 5; ++c) uh[c] = uo[c] + du[c];
-          S sm, se;
-          sigma<3, S, XP>(ph, uh, sm, se, rc);
-          for (int c = 0; c < 5; ++c) {
-            const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
-            s_z[le][r][c][m] = T(Smag) * sg * du[c];
-          }
-        }
-      } else if (ph.bc_mode == 1 || f == 4) {
-        S ub[5];
-        boundary_state<3, S>(ph, uo, ub);
-        for (int c = 0; c < 5; ++c) du[c] = ub[c] - uo[c];
-      } else {
-        for (int c = 0; c < 5; ++c) du[c] = S(T(0));   // upper boundary: u_hat = u
-      }
-      for (int c = 0; c < 5; ++c) s_f[le][f][c][m] = du[c];
-    }
-  __syncthreads();
-
-  // ---- phase C (node threads): gradient, pointwise flux and source, contravariant fluxes
-  NodeGeo g;
-  S Sr[5], G[5][3];
-  const int a = j % n, b = (j / n) % n, cz = j / N2;
-  if (active) {
-    g = node_geo<P>(M, gc, s_ang[le], k, j);
-    const double rrp = g.rc * g.rp, rc2 = g.rc * g.rc;
-    const double invJ = recip(g.Jac);
-    const double lfac = invJ * recip(w_end);
-    // metric factors of the three directions at this node
-    const double Ja[3][3] = {{rrp * g.A1[0], rrp * g.A1[1], rrp * g.A1[2]},
-                             {rrp * g.A2[0], rrp * g.A2[1], rrp * g.A2[2]},
-                             {rc2 * g.A3[0], rc2 * g.A3[1], rc2 * g.A3[2]}};
-    // line coefficients shared by the five fields: D(a,i) J a^1(i,b), D(b,i) J a^2(a,i), D(cz,i) r_i^2
-    double c1[n][3], c2[n][3], c3[n];
-    for (int i = 0; i < n; ++i) {
-      const double ri = rk + 0.5 * (gc.x[i] + 1.0) * hk;
-      c3[i] = D[cz * n + i] * ri * ri;
-      for (int d = 0; d < 3; ++d) {
-        c1[i][d] = D[a * n + i] * rrp * s_ang[le][d][i + n * b];
-        c2[i][d] = D[b * n + i] * rrp * s_ang[le][3 + d][a + n * i];
-      }
-    }
-    S q[5][3];
-    for (int c = 0; c < 5; ++c) {
-      S g1[3], d3 = S(T(0));
-      for (int d = 0; d < 3; ++d) g1[d] = S(T(0));
-      for (int i = 0; i < n; ++i) {
-        const S u1 = s_u[le][c][i + n * b + N2 * cz];
-        const S u2 = s_u[le][c][a + n * i + N2 * cz];
-        const S u3 = s_u[le][c][g.ja + N2 * i];
-        for (int d = 0; d < 3; ++d) g1[d] = g1[d] + u1 * T(c1[i][d]) + u2 * T(c2[i][d]);
-        d3 = d3 + u3 * T(c3[i]);
-      }
-      if constexpr (RAD) {
-        const T vd = s_u[le][c][j].d;
-        for (int d = 0; d < 3; ++d) g1[d].d = vd * T(c1[a][d] + c2[b][d]);
-      }
-      for (int d = 0; d < 3; ++d) q[c][d] = (g1[d] + T(g.A3[d]) * d3) * T(invJ);
-    }
-    // lift of u_hat - u from the faces through this node
-    const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0, cz == n - 1};
-    for (int f = 0; f < 6; ++f) {
-      if (!on[f]) continue;
-      const int m = face_slot<P>(f, a, b, cz);
-      const double sd = ((f & 1) ? 1.0 : -1.0) * lfac;
-      const int dd = f >> 1;
-      for (int c = 0; c < 5; ++c) {
-        const S du = s_f[le][f][c][m];
-        for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du * T(sd * Ja[dd][d]);
-      }
-    }
-    // boundary faces: the terms (F - F_hat).Sn are completed here. On the lower face (and
-    // every boundary face in bc_mode 1), F_hat.Sn = F(u_b, q).Sn + |Sn| sigma(u_b)(u - u_b)
-    // is taken before the node's own flux so that q need not outlive it.
-    const bool bot = (k == 0 && cz == 0);
-    const bool top = (k == M.n_rad - 1 && cz == n - 1);
-    const bool dir = bot || (top && ph.bc_mode == 1);
-    const double bside = bot ? -rc2 : rc2;
-    S Bc[5];
-    if (dir) {
-      double Sn[3];
-      for (int d = 0; d < 3; ++d) Sn[d] = bside * g.A3[d];
-      const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
-      S ub[5], Fb[5][3], Sb[5];
-      boundary_state<3, S>(ph, uu, ub);
-      flux_source<3, S, XP>(ph, ub, q, g.x, 0.0, Fb, Sb, false);
-      S sm, se;
-      sigma<3, S, XP>(ph, ub, sm, se, g.rc);
-      for (int c = 0; c < 5; ++c) {
-        const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
-        Bc[c] = -(Fb[c][0] * T(Sn[0]) + Fb[c][1] * T(Sn[1]) + Fb[c][2] * T(Sn[2])) - T(Smag) * sg * (uu[c] - ub[c]);
-      }
-    }
-    const double Q = heating<3>(ph, g.x, t);
-    S F[5][3];
-    flux_source<3, S, XP>(ph, uu, q, g.x, Q, F, Sr);
-    // the metric terms are read again from LDS rather than kept in registers across the flux
-    __asm__ __volatile__("" ::: "memory");
-    const double (*ang)[N2] = s_ang[le];
-    if (dir || top) {
-      double Sn[3];
-      for (int d = 0; d < 3; ++d) Sn[d] = bside * ang[6 + d][g.ja];
-      if (dir) {
-        for (int c = 0; c < 5; ++c)
-          Sr[c] = Sr[c] + (F[c][0] * T(Sn[0]) + F[c][1] * T(Sn[1]) + F[c][2] * T(Sn[2]) + Bc[c]) * T(lfac);
-      } else {
-        // adiabatic, zero normal stress, open: F_hat.Sn = F_inviscid.Sn + lambda (U.Sn) Sn/|Sn|
-        // (the penalty on the normal momentum), so (F - F_hat).Sn = F_viscous.Sn - penalty
-        S Fi[5][3];
-        flux_inviscid<3, S, XP>(ph, uu, Fi, g.rc);
-        const double Smag = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
-        const S Un = (uu[1] * T(Sn[0]) + uu[2] * T(Sn[1]) + uu[3] * T(Sn[2])) * T(ph.lam / Smag);
-        for (int c = 0; c < 5; ++c) {
-          S fd = (F[c][0] - Fi[c][0]) * T(Sn[0]) + (F[c][1] - Fi[c][1]) * T(Sn[1]) +
-                 (F[c][2] - Fi[c][2]) * T(Sn[2]);
-          if (c >= 1 && c <= 3) fd = fd - Un * T(Sn[c - 1]);
-          Sr[c] = Sr[c] + fd * T(lfac);
-        }
-      }
-    }
-    for (int dd = 0; dd < 3; ++dd) {
-      const double fac = (dd < 2) ? rrp : rc2;
-      const double J0 = fac * ang[3 * dd][g.ja], J1 = fac * ang[3 * dd + 1][g.ja], J2 = fac * ang[3 * dd + 2][g.ja];
-      for (int c = 0; c < 5; ++c) G[c][dd] = F[c][0] * T(J0) + F[c][1] * T(J1) + F[c][2] * T(J2);
-    }
-  }
-
-  // ---- phase E (node threads): interior-face terms of this side and the traces sent to
-  // the neighbours, then the volume divergence one field at a time
-  const double invJ = active ? recip(g.Jac) : 0.0;
-  const double lfac = invJ * recip(w_end);
-  if (active) {
-    const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
-    for (int f = 0; f < 6; ++f) {
-      if (!on[f]) continue;
-      const int m = face_slot<P>(f, a, b, cz);
-      const int dd = f >> 1;
-      const T side = (f & 1) ? T(1) : T(-1);
-      const int nb = s_nb[le][f][m];
-      const bool mine = (own >> f) & 1;
-      const int r = __popc(own & ((1 << f) - 1));
-      for (int c = 0; c < 5; ++c) {
-        const S Fs = side * G[c][dd];
-        const S z = mine ? s_z[le][r][c][m] : S(T(0));
-        Sr[c] = Sr[c] + (T(0.5) * Fs + z) * T(lfac);
-        if (RAD && f < 4)
-          Fn[(int64_t)nb + c * N2] = outp(S(T(0)));
-        else
-          Fn[(int64_t)nb + c * N2] = outp(Fs - T(2) * z);
-      }
-    }
-  }
-  __syncthreads();   // every u_hat - u has been read: the trace buffer becomes the flux staging
-  S (*s_G)[N] = reinterpret_cast<S (*)[N]>(&s_f[le][0][0][0]);
-  for (int c = 0; c < 5; ++c) {
-    if (active)
-      for (int dd = 0; dd < 3; ++dd) s_G[dd][j] = G[c][dd];
-    __syncthreads();
-    if (active) {
-      S dv = S(T(0));
-      for (int i = 0; i < n; ++i) {
-        dv = dv + s_G[0][i + n * b + N2 * cz] * T(D[a * n + i]);
-        dv = dv + s_G[1][a + n * i + N2 * cz] * T(D[b * n + i]);
-        dv = dv + s_G[2][g.ja + N2 * i] * T(D[cz * n + i]);
-      }
-      if constexpr (RAD) {
-        T dr = G[c][0].d * T(D[a * n + a]) + G[c][1].d * T(D[b * n + b]);
-        for (int i = 0; i < n; ++i) dr += s_G[2][g.ja + N2 * i].d * T(D[cz * n + i]);
-        dv.d = dr;
-      }
-      R[base + c * N + j] = outp(Sr[c] - dv * T(invJ));
-    }
-    __syncthreads();
-  }
-}
 
 // pass 2: R += (F^-.(-Sn))/(2 w_end J) on every interior face node, reading the
 // traces that the neighbours' pass 1 wrote into this element's incoming slots
@@ -522,53 +56,6 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   for (int c = 0; c < 5; ++c) R[base + c * N + j] += hl * acc[c];
 }
 
-// (profiled: pm->prof on, the interval goes to slot pid)
-template <int P, int EPB, int OCC, class S, int XP = 0, class SU, class TV, class OT>
-static void launch_p1(const ShellDev& M, const PhysC& ph, const GllC& gc, double t, const SU* u, const TV* v, OT* out,
-                      OT* fn, hipStream_t s, dg_mesh_s* pm, int pid) {
-  const int blocks = (M.E + EPB - 1) / EPB;
-  if (pm->prof) {
-    launch_timed(pm, pid, &shell_pass1<P, EPB, OCC, S, SU, TV, OT, false, XP>, dim3(blocks),
-                 dim3(Shape<P>::TPE * EPB), s, M, ph, gc, t, u, v, out, fn);
-    return;
-  }
-  shell_pass1<P, EPB, OCC, S, SU, TV, OT, false, XP><<<blocks, Shape<P>::TPE * EPB, 0, s>>>(M, ph, gc, t, u, v, out,
-                                                                                             fn);
-}
-
-// pass-1 launch configurations (elements per block, minimum waves per SIMD): the
-// FP64 residual and the FP32 J v take the tuned table entry of the mesh, the FP64
-// J v (dual numbers) runs one element per block with a register budget for two waves
-// per SIMD (left free, the allocator reaches 256 + 14 accumulation registers and one wave), and so does every pass of
-// a mesh with the EUVAC heating or the variable composition (the one instantiation that
-// contains them)
-template <int P, class S, class SU, class TV, class OT>
-static void dispatch_p1(dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const GllC& gc, double t,
-                        const SU* u, const TV* v, OT* out, OT* fn, hipStream_t s, int pid) {
-  if (ph.xp_mode() == (kXpEuv | kXpComp)) {
-    launch_p1<P, 1, 1, S, kXpEuv | kXpComp>(M, ph, gc, t, u, v, out, fn, s, m, pid);
-    return;
-  }
-  if (ph.xp_mode() == kXpEuv) {
-    launch_p1<P, 1, 1, S, kXpEuv>(M, ph, gc, t, u, v, out, fn, s, m, pid);
-    return;
-  }
-  if constexpr (std::is_same<S, Dual<double>>::value) {
-    launch_p1<P, 1, 2, S>(M, ph, gc, t, u, v, out, fn, s, m, pid);
-    return;
-  } else {
-  constexpr int maxe = 256 / Shape<P>::TPE;
-  const int cfg = m->tune_p1;
-  switch (cfg) {
-    case 1: launch_p1<P, 1, 1, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
-    case 2: launch_p1<P, (maxe >= 2 ? 2 : 1), 1, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
-    case 3: launch_p1<P, 1, 3, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
-    case 4: launch_p1<P, (maxe >= 2 ? 2 : 1), 3, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
-    case 5: launch_p1<P, 1, 4, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
-    default: launch_p1<P, maxe, 1, S>(M, ph, gc, t, u, v, out, fn, s, m, pid); break;
-  }
-  }
-}
 
 template <class S, class SU, class TV, class OT>
 static dg_status_t launch(dg_mesh_s* m, double t, const SU* u, const TV* v, OT* out, OT* fn, hipStream_t s,
@@ -585,7 +72,10 @@ static dg_status_t launch(dg_mesh_s* m, double t, const SU* u, const TV* v, OT* 
 #define DG_LAUNCH(P_)                                                                                     \
   {                                                                                                        \
     {                                                                                                      \
-      dispatch_p1<P_, S>(m, M, ph, gc, t, u, v, out, fn, s, prof_base);                                    \
+      if constexpr (std::is_same<S, double>::value)                                                        \
+        shell_pass1_f64(m, M, ph, gc, t, u, out, fn, s, prof_base);                                         \
+      else                                                                                                 \
+        dispatch_p1<P_, S>(m, M, ph, gc, t, u, v, out, fn, s, prof_base);                                  \
     }                                                                                                      \
     {                                                                                                      \
       const int blocks = (E + Shape<P_>::EPB - 1) / Shape<P_>::EPB;                                        \
