@@ -543,33 +543,58 @@ static dg_status_t finish_norm2(Workspace* w, int nb, hipStream_t s, double* out
   return DG_OK;
 }
 
+// blocks of RED_THREADS of kernel f resident on the device at once (at most RED_BLOCKS). The
+// grid of a grid-stride sweep is capped there: with more registers than 64 per lane the full
+// RED_BLOCKS no longer fit in one round, and the blocks of a second round would run on a
+// nearly empty chip. The cap depends only on the kernel, so each kernel's partition of the
+// sum, and with it the summation order, stays fixed.
+static int resident_grid(const void* f) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, RED_THREADS, 0) != hipSuccess || per < 1 || cus < 1)
+    return RED_BLOCKS;
+  return std::min(RED_BLOCKS, per * cus);
+}
+
+// the launches below return the grid they used: the caller's k_reduce sums that many parts
 template <int K, class T>
-static void launch_mdot_k(int64_t n, const T* V, int64_t ldv, const T* w, double* part, int nb, hipStream_t s) {
+static int launch_mdot_k(int64_t n, const T* V, int64_t ldv, const T* w, double* part, int nb, hipStream_t s) {
+  static const int cap = resident_grid(reinterpret_cast<const void*>(&k_mdot<K, T>));
+  nb = std::min(nb, cap);
   k_mdot<K, T><<<nb, RED_THREADS, 0, s>>>(n, V, ldv, w, part);
+  return nb;
+}
+
+template <int K, class T>
+static int launch_orth_mdot_k(int64_t n, const T* V, int64_t ldv, const double* h, T* w, double* part, int nb,
+                              hipStream_t s) {
+  static const int cap = resident_grid(reinterpret_cast<const void*>(&k_orth_mdot<K, T>));
+  nb = std::min(nb, cap);
+  k_orth_mdot<K, T><<<nb, RED_THREADS, 0, s>>>(n, V, ldv, h, w, part);
+  return nb;
 }
 
 template <class T, int K = 1>
-static void launch_orth_mdot(int kk, int64_t n, const T* V, int64_t ldv, const double* h, T* w, double* part, int nb,
-                             hipStream_t s) {
+static int launch_orth_mdot(int kk, int64_t n, const T* V, int64_t ldv, const double* h, T* w, double* part, int nb,
+                            hipStream_t s) {
   if constexpr (K > 33) {
-    (void)kk; (void)n; (void)V; (void)ldv; (void)h; (void)w; (void)part; (void)nb; (void)s;
+    (void)kk; (void)n; (void)V; (void)ldv; (void)h; (void)w; (void)part; (void)s;
+    return nb;
   } else {
-    if (kk == K)
-      k_orth_mdot<K, T><<<nb, RED_THREADS, 0, s>>>(n, V, ldv, h, w, part);
-    else
-      launch_orth_mdot<T, K + 1>(kk, n, V, ldv, h, w, part, nb, s);
+    if (kk == K) return launch_orth_mdot_k<K, T>(n, V, ldv, h, w, part, nb, s);
+    return launch_orth_mdot<T, K + 1>(kk, n, V, ldv, h, w, part, nb, s);
   }
 }
 
 template <class T, int K = 1>
-static void launch_mdot(int kk, int64_t n, const T* V, int64_t ldv, const T* w, double* part, int nb, hipStream_t s) {
+static int launch_mdot(int kk, int64_t n, const T* V, int64_t ldv, const T* w, double* part, int nb, hipStream_t s) {
   if constexpr (K > 33) {
-    (void)kk; (void)n; (void)V; (void)ldv; (void)w; (void)part; (void)nb; (void)s;
+    (void)kk; (void)n; (void)V; (void)ldv; (void)w; (void)part; (void)s;
+    return nb;
   } else {
-    if (kk == K)
-      launch_mdot_k<K, T>(n, V, ldv, w, part, nb, s);
-    else
-      launch_mdot<T, K + 1>(kk, n, V, ldv, w, part, nb, s);
+    if (kk == K) return launch_mdot_k<K, T>(n, V, ldv, w, part, nb, s);
+    return launch_mdot<T, K + 1>(kk, n, V, ldv, w, part, nb, s);
   }
 }
 
@@ -627,8 +652,8 @@ static void rb_coefficients(dg_mesh_s* m, Workspace* ws, const T* v, hipStream_t
   const int nb = grid_for(n);
   const int k = ws->rb_count;
   double* d = ws->rb_dev + RB_MAX * RB_MAX;
-  launch_mdot<T>(k, n, (const T*)ws->rbZ, n, v, ws->part, nb, s);
-  k_reduce<<<k, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
+  const int nbd = launch_mdot<T>(k, n, (const T*)ws->rbZ, n, v, ws->part, nb, s);
+  k_reduce<<<k, RED_THREADS, 0, s>>>(ws->part, nbd, k, d);
   k_rb_coef<<<1, 64, 0, s>>>(k, ws->rb_dev, d, d + RB_MAX);
 }
 
@@ -684,8 +709,8 @@ static dg_status_t rb_push(dg_mesh_s* m, Workspace* ws, int n_rb, double t, doub
   ws->rb_count = std::min(ws->rb_count + 1, n_rb);
   const int k = ws->rb_count;
   double* d = ws->rb_dev + RB_MAX * RB_MAX;
-  launch_mdot<T>(k, n, (const T*)ws->rbZ, n, Zd, ws->part, nb, s);
-  k_reduce<<<k, RED_THREADS, 0, s>>>(ws->part, nb, k, d);
+  const int nbd = launch_mdot<T>(k, n, (const T*)ws->rbZ, n, Zd, ws->part, nb, s);
+  k_reduce<<<k, RED_THREADS, 0, s>>>(ws->part, nbd, k, d);
   DG_HIP_CHECK(hipMemcpyAsync(ws->host_small, d, k * sizeof(double), hipMemcpyDeviceToHost, s));
   DG_HIP_CHECK(hipStreamSynchronize(s));
   for (int j = 0; j < k; ++j) {
@@ -761,10 +786,10 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
       // classical Gram-Schmidt, twice
       {
         ProfScope ps(m, 9, s);
-        launch_mdot<T>(j + 1, n, V, n, w, ws->part, nb, s);
-        k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h1);
-        launch_orth_mdot<T>(j + 1, n, V, n, h1, w, ws->part, nb, s);
-        k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb, j + 1, h2);
+        const int nb1 = launch_mdot<T>(j + 1, n, V, n, w, ws->part, nb, s);
+        k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb1, j + 1, h1);
+        const int nb2 = launch_orth_mdot<T>(j + 1, n, V, n, h1, w, ws->part, nb, s);
+        k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb2, j + 1, h2);
         k_orth_update<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, j + 1, h2, w, ws->part);
         k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 1, nr);
         k_normalize<T><<<nb, RED_THREADS, 0, s>>>(n, w, nr, V + (size_t)(j + 1) * n);
