@@ -74,8 +74,11 @@ def tune_columns(mesh, u, t0, dt, steps=1, candidates=(256, 512, 1024, 2048, 409
     return best, times
 
 
-def tune_shell_pass1(mesh, u, t=0.0, reps=10, configs=range(6), force=False, log=None):
-    """choose 'shell_pass1_config' by the element pass's own event timing"""
+def tune_shell_pass1(mesh, u, t=0.0, reps=10, configs=range(6), force=False, log=None, warm_s=0.3):
+    """choose 'shell_pass1_config' by the element pass's own event timing
+
+    The GPU is first kept busy with residual evaluations for warm_s seconds: timed while its
+    clock still rises, the configurations tried first would read slower than they are."""
     key = "shell:%d:%d:%d" % (mesh.p, mesh.n_elem, mesh.n_dof)
     cache = _load()
     if key in cache and not force:
@@ -83,6 +86,11 @@ def tune_shell_pass1(mesh, u, t=0.0, reps=10, configs=range(6), force=False, log
         return cache[key]["config"], cache[key].get("times", {})
     import torch
     r = torch.empty_like(u)
+    t_end = time.perf_counter() + warm_s
+    while time.perf_counter() < t_end:
+        for _ in range(20):
+            mesh.residual(u, t, out=r)
+        torch.cuda.synchronize()
     times = {}
     for c in configs:
         mesh.set_option("shell_pass1_config", c)

@@ -47,13 +47,21 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   const double Jac = rc * rc * (0.5 * hk) * M.ang[((int64_t)cell * 13 + 9) * N2 + ja];
   const OT hl = OT(0.5 / (gc.w[0] * Jac));
   const int64_t base = (int64_t)e * 5 * N;
-  OT acc[5] = {OT(0), OT(0), OT(0), OT(0), OT(0)};
+  // Every load is issued before any is used: R first, then all 6 x 5 trace slots of this node
+  // position (each element has all six faces' slots allocated; m < N2 on every face), the
+  // faces the node is not on discarded by a select (slots never written may hold any bits).
+  // Gathered under per-face branches, a wavefront instead waited for one face at a time.
+  const OT* Fe = Fin + (int64_t)e * 6 * 5 * N2;
+  OT r[5], acc[5] = {OT(0), OT(0), OT(0), OT(0), OT(0)};
+  for (int c = 0; c < 5; ++c) r[c] = R[base + c * N + j];
   for (int f = 0; f < 6; ++f) {
-    if (!on[f]) continue;
     const int m = face_slot<P>(f, a, b, cz);
-    for (int c = 0; c < 5; ++c) acc[c] += Fin[(((int64_t)e * 6 + f) * 5 + c) * N2 + m];
+    for (int c = 0; c < 5; ++c) {
+      const OT x = Fe[(f * 5 + c) * N2 + m];
+      acc[c] += on[f] ? x : OT(0);
+    }
   }
-  for (int c = 0; c < 5; ++c) R[base + c * N + j] += hl * acc[c];
+  for (int c = 0; c < 5; ++c) R[base + c * N + j] = r[c] + hl * acc[c];
 }
 
 
