@@ -445,8 +445,9 @@ static dg_status_t line_pc_apply_t(dg_mesh_s* m, int prec, const void* P, const 
     set_error("radial-line preconditioner: too many radial layers for the substitution's LDS");
     return DG_ERR_ARG;
   }
-  // automatic choice (measured on the 7.9M-DOF p = 3 shell): cell blocks for double vectors
-  const int cfg = m->tune_lsolve >= 0 ? m->tune_lsolve : (sizeof(T) == 8 ? 4 : 3);
+  // automatic choice (implicit steps on the 7.9M-DOF p = 3 shell at the sustained clock): cell
+  // blocks with a 2-deep ring for double vectors, 4 wavefronts with a 4-deep ring for float
+  const int cfg = m->tune_lsolve >= 0 ? m->tune_lsolve : (sizeof(T) == 8 ? 5 : 3);
   switch (m->p) {
     case 2: line_solve_cfg<15, T>(cfg, L, lines, prec, P, r, z, s); break;
     case 3: line_solve_cfg<20, T>(cfg, L, lines, prec, P, r, z, s); break;
