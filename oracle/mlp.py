@@ -20,24 +20,13 @@ def bf16_round(x):
     return b.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def forward(params, x, round_hidden=True, decide=np.float64):
-    """decide: the precision in which a hidden pre-activation is formed before its
-    bf16 rounding. A value near a rounding boundary can round differently from sums in
-    FP64 and in FP32 (one bf16 step, 2^-8 relative); with np.float32 the oracle takes
-    that decision in the kernel's accumulation precision (the products of bf16 values
-    are exact in FP32, the sums rounded to FP32 in numpy's order)."""
+def forward(params, x, round_hidden=True):
     W1, b1, W2, b2, W3, b3 = [bf16_round(p) if i % 2 == 0 else p for i, p in enumerate(params)]
     rh = bf16_round if round_hidden else (lambda a: a)
     x = bf16_round(x)
-
-    def pre(a, W, b):
-        if decide is np.float64:
-            return a @ W.T + b
-        z = a.astype(np.float32) @ W.T.astype(np.float32) + b.astype(np.float32)
-        return z.astype(np.float64)
-    z1 = pre(x, W1, b1)
+    z1 = x @ W1.T + b1
     h1 = rh(np.maximum(z1, 0.0))
-    z2 = pre(h1, W2, b2)
+    z2 = h1 @ W2.T + b2
     h2 = rh(np.maximum(z2, 0.0))
     y = h2 @ W3.T + b3
     return y, (x, z1, h1, z2, h2)

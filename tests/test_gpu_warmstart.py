@@ -7,6 +7,7 @@ import pytest
 
 import synth
 from gpu_common import need_gpu, shell_pair, to_dev, torch
+from mlp_bound import flip_bound
 from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
@@ -48,17 +49,19 @@ def test_mlp_forward_and_gradients_match_oracle():
 
 @pytest.mark.parametrize("n,n_in,n_out", [(70, 200, 64), (1, 8, 32), (129, 968, 96)])
 def test_mlp_forward_ragged_shapes(n, n_in, n_out):
-    """row counts off the 64-row block, input widths with a partial last 64-column chunk.
-    The bf16 rounding of the hidden activations is decided on FP32 sums on both sides
-    (one activation of the 129 x 968 case lies on a rounding boundary: decided on FP64
-    sums the outputs differ by 1.7e-5)"""
+    """row counts off the 64-row block, input widths with a partial last 64-column chunk,
+    against the FP64 oracle: every output within 1e-5 of the output scale plus the
+    admissible effect of one-step bf16 flips of hidden activations that lie within FP32
+    accumulation error of a rounding boundary (tests/mlp_bound.py; one activation of the
+    129 x 968 case is such a one)"""
     need_gpu()
     from paper_2306_01085_amd import DgError, Network
     params, x, _ = _problem(3, n=n, n_in=n_in, n_out=n_out)
     net = Network(n_in, n_out, params)
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
-    yref, _ = omlp.forward(params, x.astype(np.float64), decide=np.float32)
-    assert _rel(y, yref) < 1e-5
+    yref, _ = omlp.forward(params, x.astype(np.float64))
+    bound, _ = flip_bound(params, x.astype(np.float64))
+    assert np.all(np.abs(y - yref) <= 1e-5 * np.max(np.abs(yref)) + bound)
     # an input that is not 16-byte aligned is refused
     xd = torch.from_numpy(np.concatenate([[0.0], x.ravel()]).astype(np.float32)).cuda()[1:].view(n, n_in)
     with pytest.raises(DgError):
