@@ -164,9 +164,8 @@ dg_status_t dg_residual(dg_mesh_t mesh, double t, const double* u, double* r, in
  * DG_F64_FD (v, jv double): the paper's matrix-free product, the one-sided difference
  * jv = (R(u + h v) - R(u)) / h with h = sqrt(eps_64) (1 + |u|_2) / |v|_2 (the paper gives no
  * step), jv = 0 for v = 0; two R evaluations, its error is O(h) plus rounding of order
- * eps_64 / h. The norms and h stay on the device. Its first call
- * allocates two state-sized buffers owned by the mesh (freed at destroy); later calls do not.
- * Enqueue only. */
+ * eps_64 / h. The norms and h stay on the device, in two state-sized buffers that
+ * dg_mesh_create allocates with the mesh (no call of dg_jvp allocates). Enqueue only. */
 dg_status_t dg_jvp(dg_mesh_t mesh, double t, const double* u, const void* v, void* jv, int64_t n_dof,
                    dg_prec_t prec, void* stream);
 
@@ -266,8 +265,9 @@ dg_status_t dg_mlp_grad(dg_mlp_t mlp, const float* x, const float* t, int64_t n,
 dg_status_t dg_mlp_adam_step(dg_mlp_t mlp, float lr, float beta1, float beta2, float eps, void* stream);
 
 /* x[r][k] = (x[r][k] - mean[k]) / scale[k] for a device FP32 [n][width] array in place
- * (standardisation of recorded training rows); mean / scale: host [width]. Synchronises. */
-dg_status_t dg_affine_rows(float* x, int64_t n, int32_t width, const float* mean_host, const float* scale_host,
+ * (standardisation of recorded training rows); mean / scale: device FP32 [width], read by
+ * the kernel (they must stay valid until it has run). Enqueue only; allocates nothing. */
+dg_status_t dg_affine_rows(float* x, int64_t n, int32_t width, const float* mean, const float* scale,
                            void* stream);
 
 /* Attach a trained network to a shell mesh for opts->guess = 1 (NULL detaches). The

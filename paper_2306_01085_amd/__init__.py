@@ -96,7 +96,7 @@ _lib.dg_mlp_get_params.argtypes = [_vp, _fp, C.c_int64]
 _lib.dg_mlp_forward.argtypes = [_vp, _vp, C.c_int64, _vp, _vp]
 _lib.dg_mlp_grad.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(C.c_double), _fp, _vp]
 _lib.dg_mlp_adam_step.argtypes = [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]
-_lib.dg_affine_rows.argtypes = [_vp, C.c_int64, C.c_int32, _fp, _fp, _vp]
+_lib.dg_affine_rows.argtypes = [_vp, C.c_int64, C.c_int32, _vp, _vp, _vp]
 _lib.dg_warmstart_set.argtypes = [_vp, _vp, _fp, _fp, _fp, _fp]
 _lib.dg_warmstart_record.argtypes = [_vp, _vp, _vp, C.c_int64, C.c_int32]
 _lib.dg_warmstart_recorded.argtypes = [_vp, C.POINTER(C.c_int64)]
@@ -370,11 +370,16 @@ class Network:
 
 
 def affine_rows(x, mean, scale, stream=None):
+    """x <- (x - mean) / scale row-wise, in place on the device; mean and scale (host arrays
+    [width]) are staged on x's device for the call, which waits for the kernel so that the
+    staged copies outlive it"""
     import torch
-    m = np.ascontiguousarray(mean, dtype=np.float32)
-    s = np.ascontiguousarray(scale, dtype=np.float32)
-    _check(_lib.dg_affine_rows(_ptr(x, torch.float32), x.shape[0], x.shape[1], _f32p(m), _f32p(s), _stream(stream)),
-           "dg_affine_rows")
+    m = torch.as_tensor(np.ascontiguousarray(mean, dtype=np.float32)).to(x.device)
+    s = torch.as_tensor(np.ascontiguousarray(scale, dtype=np.float32)).to(x.device)
+    st = _stream(stream)
+    _check(_lib.dg_affine_rows(_ptr(x, torch.float32), x.shape[0], x.shape[1], _ptr(m, torch.float32),
+                               _ptr(s, torch.float32), st), "dg_affine_rows")
+    torch.cuda.synchronize(x.device)
 
 
 def _warmstart_set(self, net, x_mean=None, x_scale=None, y_mean=None, y_scale=None):

@@ -236,8 +236,11 @@ dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys,
   }
   hipError_t e1 = hipMalloc(&m->d_fn64, m->fn_len * sizeof(double));
   hipError_t e2 = hipMalloc(&m->d_fn32, m->fn_len * sizeof(float));
-  if (e1 != hipSuccess || e2 != hipSuccess) {
-    set_error("dg_mesh_create: device allocation of the face traces failed");
+  // the finite-difference J v's two state-sized buffers and norm partials: allocated here so
+  // that no later call allocates
+  hipError_t e4 = hipMalloc(&m->d_fd, fd_buffer_len(m->n_dof) * sizeof(double));
+  if (e1 != hipSuccess || e2 != hipSuccess || e4 != hipSuccess) {
+    set_error("dg_mesh_create: device allocation of the face traces or finite-difference buffers failed");
     free_mesh(m);
     return DG_ERR_ALLOC;
   }

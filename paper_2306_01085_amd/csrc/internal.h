@@ -217,6 +217,8 @@ dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, f
 dg_status_t shell_jvp_bf16(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
 // the finite-difference J v of section 3.2 (solver.hip): two residuals, the step on the device
 dg_status_t jvp_fd(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
+// doubles of the buffer jvp_fd uses (allocated with the mesh)
+int64_t fd_buffer_len(int64_t n_dof);
 std::vector<uint16_t> bf16_operators(int p);
 // radial-line linearisation J_rad v (FP64) and the radial-line block-Jacobi preconditioner
 dg_status_t shell_jvp_radial(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);

@@ -489,14 +489,8 @@ dg_status_t dg_affine_rows(float* x, int64_t n, int32_t width, const float* mean
   }
   if (n == 0) return DG_OK;
   hipStream_t s = (hipStream_t)stream;
-  float* d = nullptr;
-  DG_HIP_CHECK(hipMalloc(&d, 2 * width * sizeof(float)));
-  DG_HIP_CHECK(hipMemcpy(d, mean, width * sizeof(float), hipMemcpyHostToDevice));
-  DG_HIP_CHECK(hipMemcpy(d + width, scale, width * sizeof(float), hipMemcpyHostToDevice));
-  k_affine_rows<<<(unsigned)((n * width + 255) / 256), 256, 0, s>>>(n, width, d, d + width, x);
+  k_affine_rows<<<(unsigned)((n * width + 255) / 256), 256, 0, s>>>(n, width, mean, scale, x);
   DG_HIP_CHECK(hipGetLastError());
-  DG_HIP_CHECK(hipStreamSynchronize(s));
-  DG_HIP_CHECK(hipFree(d));
   return DG_OK;
 }
 

@@ -478,16 +478,14 @@ __global__ void k_fd_finish(int64_t n, const double* __restrict__ r0, const doub
   jv[i] = h > 0.0 ? (jv[i] - r0[i]) / h : 0.0;
 }
 
+// doubles of the mesh-owned finite-difference buffer: [w (n) | r0 (n) | partials (2 RED_BLOCKS) | sums (2)]
+int64_t fd_buffer_len(int64_t n_dof) { return 2 * n_dof + 2 * RED_BLOCKS + 2; }
+
 dg_status_t jvp_fd(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s) {
   const int64_t n = m->n_dof;
-  // [w (n) | r0 (n) | partials (2 RED_BLOCKS) | sums (2)]
   if (!m->d_fd) {
-    DG_HIP_CHECK(hipStreamSynchronize(s));
-    if (hipMalloc(&m->d_fd, (2 * n + 2 * RED_BLOCKS + 2) * sizeof(double)) != hipSuccess) {
-      m->d_fd = nullptr;
-      set_error("dg_jvp: device allocation of the finite-difference buffers failed");
-      return DG_ERR_ALLOC;
-    }
+    set_error("dg_jvp: the mesh has no finite-difference buffers");
+    return DG_ERR_ALLOC;
   }
   double* w = m->d_fd;
   double* r0 = w + n;
