@@ -153,6 +153,21 @@ dg_status_t dg_mesh_col_offsets(dg_mesh_t mesh, int64_t* offsets_host, int64_t n
  * r: device [n_dof] double (output, must not alias u). Enqueue only. */
 dg_status_t dg_residual(dg_mesh_t mesh, double t, const double* u, double* r, int64_t n_dof, void* stream);
 
+/* For callers that cannot allocate device memory during a call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): R(u) exactly as
+ * dg_residual computes it (the same kernels, bitwise the same result), with the face traces
+ * held in a library-owned device array of DG_NOALLOC_SCRATCH_BYTES per GPU instead of the
+ * mesh's trace buffer. Every GPU the library runs on holds that array until the process
+ * ends; its address is looked up when a mesh is created on the GPU. Nothing is allocated
+ * and nothing needs clearing: every trace slot the evaluation reads is written by the same
+ * evaluation. All calls on one GPU share the array, so calls that overlap in time on one
+ * GPU (different streams, or other host threads) race and give wrong results: serialise
+ * them. A mesh whose traces exceed the array (shell: n_elem * 30 * (p+1)^2 * 8 bytes; at
+ * p = 3 at most 26,214 elements) gets DG_ERR_ARG with a message naming both sizes.
+ * Arguments and other errors as dg_residual. Enqueue only. */
+#define DG_NOALLOC_SCRATCH_BYTES (96ll << 20)
+dg_status_t dg_residual_noalloc(dg_mesh_t mesh, double t, const double* u, double* r, int64_t n_dof, void* stream);
+
 /* J(u) v, the exact directional derivative of R at u along v (section 3.2 uses a
  * finite difference of R; dual-number arithmetic gives the same product without the
  * step error). u: device double [n_dof]; v and jv: device arrays [n_dof] of the

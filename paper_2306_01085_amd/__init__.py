@@ -82,6 +82,7 @@ _lib.dg_mesh_info.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C
 _lib.dg_mesh_nodes.argtypes = [_vp, C.POINTER(C.c_double), C.c_int64]
 _lib.dg_mesh_col_offsets.argtypes = [_vp, C.POINTER(C.c_int64), C.c_int64]
 _lib.dg_residual.argtypes = [_vp, C.c_double, _vp, _vp, C.c_int64, _vp]
+_lib.dg_residual_noalloc.argtypes = [_vp, C.c_double, _vp, _vp, C.c_int64, _vp]
 _lib.dg_jvp.argtypes = [_vp, C.c_double, _vp, _vp, _vp, C.c_int64, C.c_int32, _vp]
 _lib.dg_implicit_step.argtypes = [_vp, C.c_double, C.c_double, _vp, C.c_int64, C.POINTER(SolverOpts),
                                   C.POINTER(StepStats), _vp]
@@ -104,7 +105,8 @@ _lib.dg_profile_enable.argtypes = [_vp, C.c_int32]
 _lib.dg_set_option.argtypes = [_vp, C.c_char_p, C.c_int64]
 _lib.dg_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int32]
 for _f in ("dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh_info", "dg_mesh_nodes",
-           "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_profile_enable",
+           "dg_mesh_col_offsets", "dg_residual", "dg_residual_noalloc", "dg_jvp", "dg_implicit_step",
+           "dg_profile_enable",
            "dg_profile_read", "dg_set_option", "dg_columns_integrate", "dg_mlp_create", "dg_mlp_destroy",
            "dg_mlp_get_params", "dg_mlp_forward", "dg_mlp_grad", "dg_mlp_adam_step", "dg_affine_rows",
            "dg_warmstart_set", "dg_warmstart_record", "dg_warmstart_recorded"):
@@ -114,7 +116,8 @@ EXPORTED = ["dg_mesh_create", "dg_mesh_destroy", "dg_mesh_set_physics", "dg_mesh
             "dg_mesh_col_offsets", "dg_residual", "dg_jvp", "dg_implicit_step", "dg_last_error", "dg_version",
             "dg_profile_enable", "dg_profile_read", "dg_set_option", "dg_columns_integrate", "dg_mlp_create",
             "dg_mlp_destroy", "dg_mlp_param_count", "dg_mlp_get_params", "dg_mlp_forward", "dg_mlp_grad",
-            "dg_mlp_adam_step", "dg_affine_rows", "dg_warmstart_set", "dg_warmstart_record", "dg_warmstart_recorded"]
+            "dg_mlp_adam_step", "dg_affine_rows", "dg_warmstart_set", "dg_warmstart_record", "dg_warmstart_recorded",
+            "dg_residual_noalloc"]
 PROFILE_SLOTS = {0: "shell_pass1_R", 1: "shell_pass2_R", 2: "shell_pass1_jvp64", 3: "shell_pass2_jvp64",
                  4: "shell_pass1_jvp32", 5: "shell_pass2_jvp32", 6: "columns_R", 7: "columns_jvp64",
                  8: "columns_jvp32", 9: "gmres_arnoldi", 10: "bjac_build", 11: "bjac_apply", 12: "vector_ops",
@@ -260,6 +263,16 @@ class Mesh:
             raise ValueError("out must have as many elements as u")
         _check(_lib.dg_residual(self._h, float(t), _ptr(u, torch.float64), _ptr(out, torch.float64), u.numel(),
                                 _stream(stream)), "dg_residual")
+        return out
+
+    def residual_noalloc(self, u, out, t=0.0, stream=None):
+        """R(u) into the caller's `out` through dg_residual_noalloc (the library allocates
+        nothing; the face traces use its per-GPU scratch array)"""
+        import torch
+        if out.numel() != u.numel():
+            raise ValueError("out must have as many elements as u")
+        _check(_lib.dg_residual_noalloc(self._h, float(t), _ptr(u, torch.float64), _ptr(out, torch.float64),
+                                        u.numel(), _stream(stream)), "dg_residual_noalloc")
         return out
 
     def jvp(self, u, v, t=0.0, prec="f64", out=None, stream=None):

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -13,6 +14,44 @@ namespace dg {
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
+
+// ---------------------------------------------------------------- allocation-free residual
+// dg_residual_noalloc keeps the face traces of its R(u) evaluation in this file-scope device
+// array instead of the mesh's trace buffer. Every GPU the library runs on holds its own
+// copy for the life of the process; host code never names the array itself (its name is a
+// host-side stand-in there) but the per-device address that hipGetSymbolAddress returns.
+constexpr int64_t kScratchDoubles = DG_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of the scratch array, looked up once per device
+static dg_status_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_error(std::string("scratch: ") + hipGetErrorString(e));
+    return DG_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("scratch: device index out of range");
+    return DG_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("scratch: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+      return DG_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return DG_OK;
+}
 
 dg_status_t build_shell(dg_mesh_s* m, const dg_mesh_desc_t& d);
 dg_status_t build_columns(dg_mesh_s* m, const dg_mesh_desc_t& d, const dg_physics_t& ph);
@@ -259,6 +298,13 @@ dg_status_t dg_mesh_create(const dg_mesh_desc_t* desc, const dg_physics_t* phys,
     free_mesh(m);
     return DG_ERR_HIP;
   }
+  // set-up of the allocation-free residual: the scratch array's address on this device
+  double* scr = nullptr;
+  st = scratch_address(&scr);
+  if (st != DG_OK) {
+    free_mesh(m);
+    return st;
+  }
   *out = m;
   return DG_OK;
 }
@@ -348,6 +394,24 @@ dg_status_t dg_residual(dg_mesh_t m, double t, const double* u, double* r, int64
   }
   hipStream_t s = (hipStream_t)stream;
   return m->kind == DG_MESH_SHELL ? shell_residual(m, t, u, r, s) : col_residual(m, t, u, r, s);
+}
+
+dg_status_t dg_residual_noalloc(dg_mesh_t m, double t, const double* u, double* r, int64_t n_dof, void* stream) {
+  if (!m || !u || !r || n_dof != m->n_dof || u == r) {
+    set_error("dg_residual_noalloc: null pointer, aliasing or n_dof mismatch");
+    return DG_ERR_ARG;
+  }
+  if (m->fn_len > kScratchDoubles) {
+    set_error("dg_residual_noalloc: the mesh's face traces (" + std::to_string(m->fn_len * 8) +
+              " bytes) exceed the scratch array (" + std::to_string((long long)DG_NOALLOC_SCRATCH_BYTES) +
+              " bytes); use dg_residual");
+    return DG_ERR_ARG;
+  }
+  double* scr = nullptr;
+  const dg_status_t st = scratch_address(&scr);
+  if (st != DG_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  return m->kind == DG_MESH_SHELL ? shell_residual_traces(m, t, u, r, scr, s) : col_residual_traces(m, t, u, r, scr, s);
 }
 
 dg_status_t dg_jvp(dg_mesh_t m, double t, const double* u, const void* v, void* jv, int64_t n_dof, dg_prec_t prec,

@@ -314,6 +314,9 @@ dg_status_t col_filter_apply(dg_mesh_s* m, double sigma, double* u, hipStream_t 
 dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s) {
   return launch_cols<double, double, double, double>(m, t, u, (const double*)nullptr, r, m->d_fn64, s, 6);
 }
+dg_status_t col_residual_traces(dg_mesh_s* m, double t, const double* u, double* r, double* fn, hipStream_t s) {
+  return launch_cols<double, double, double, double>(m, t, u, (const double*)nullptr, r, fn, s, 6);
+}
 dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s) {
   return launch_cols<Dual<double>, double, double, double>(m, t, u, v, jv, m->d_fn64, s, 7);
 }

@@ -205,6 +205,8 @@ inline void launch_timed(dg_mesh_s* m, int id, void (*k)(Prm...), dim3 grid, dim
 }
 // kernels (shell.hip, column.hip)
 dg_status_t shell_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
+// the same with the face traces in a caller-chosen device buffer of m->fn_len doubles
+dg_status_t shell_residual_traces(dg_mesh_s* m, double t, const double* u, double* r, double* fn, hipStream_t s);
 // the element pass of the FP64 residual (shell_r64.hip); m->p in {2, 3, 4}; profiled
 // launches record into slot pid
 void shell_pass1_f64(dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const GllC& gc, double t, const double* u,
@@ -212,6 +214,7 @@ void shell_pass1_f64(dg_mesh_s* m, const ShellDev& M, const PhysC& ph, const Gll
 dg_status_t shell_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 dg_status_t shell_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
 dg_status_t col_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s);
+dg_status_t col_residual_traces(dg_mesh_s* m, double t, const double* u, double* r, double* fn, hipStream_t s);
 dg_status_t col_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s);
 dg_status_t col_jvp32(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);
 dg_status_t shell_jvp_bf16(dg_mesh_s* m, double t, const double* u, const float* v, float* jv, hipStream_t s);

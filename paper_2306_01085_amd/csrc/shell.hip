@@ -157,6 +157,9 @@ dg_status_t shell_jvp_radial32(dg_mesh_s* m, double t, const double* u, const fl
 dg_status_t shell_residual(dg_mesh_s* m, double t, const double* u, double* r, hipStream_t s) {
   return launch<double, double, double, double>(m, t, u, (const double*)nullptr, r, m->d_fn64, s, 0);
 }
+dg_status_t shell_residual_traces(dg_mesh_s* m, double t, const double* u, double* r, double* fn, hipStream_t s) {
+  return launch<double, double, double, double>(m, t, u, (const double*)nullptr, r, fn, s, 0);
+}
 dg_status_t shell_jvp64(dg_mesh_s* m, double t, const double* u, const double* v, double* jv, hipStream_t s) {
   return launch<Dual<double>, double, double, double>(m, t, u, v, jv, m->d_fn64, s, 2);
 }
