@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   constexpr int n = Sh::n, N = Sh::N, N2 = Sh::N2, TPE = Sh::TPE, EPB = Sh::EPB;
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block_reversed(blockIdx.x, gridDim.x) * EPB + le;
   if (e >= M.E || j >= N) return;
   const int a = j % n, b = (j / n) % n, cz = j / N2;
   const int cell = e / M.n_rad, k = e % M.n_rad;
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(BfShape<P>::THREADS) void shell_pass1_bf16(ShellDev
   const int wave = threadIdx.x >> 6;
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool live = e < M.E;
   const bool active = live && j < N;
   const int cell = live ? e / M.n_rad : 0;

@@ -208,6 +208,27 @@ __device__ inline void slot_node(int f, int m, int& a, int& b, int& cz) {
 // the trace slot of a face node holds F.Sn - 2 Z with Z = |Sn| sigma(u_hat)(u_hat - u)
 // (Z = 0 when the receiving element is the owner).
 
+// XCD-aware order of the blocks of an element-per-block launch. The dispatcher hands
+// workgroup b to accelerator die (XCD) b mod 8, each with its own L2. Renumbered, die x runs
+// one contiguous range of elements in order, so an element's radial neighbours (e +- 1) and
+// its angular neighbours within a panel row or two (e +- n_rad, e +- n_ang n_rad) are being
+// processed on the same die at about the same time, and their face values are read from
+// that die's L2 instead of from memory. A bijection of [0, G) for every grid size G.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int G) {
+  const int q = G / kXcds, r = G % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return x * q + min(x, r) + i;
+}
+// the same ranges per die, each run from its end: a pass that follows the element pass
+// starts on the elements whose output the die wrote last (the part still in its L2)
+__device__ inline int xcd_block_reversed(int b, int G) {
+  const int q = G / kXcds, r = G % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  const int count = q + (x < r ? 1 : 0);
+  return x * q + min(x, r) + (count - 1 - i);
+}
+
 // the r-th set bit of mask (r counted from 0)
 __device__ inline int nth_bit(int mask, int r) {
   for (int i = 0; i < r; ++i) mask &= mask - 1;
@@ -239,7 +260,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   __shared__ double D[n * n];
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool live = e < M.E;
   const bool active = live && (j < N);
   const int cell = live ? e / M.n_rad : 0;
