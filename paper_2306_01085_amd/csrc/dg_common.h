@@ -62,9 +62,66 @@ template <class T> __device__ inline Dual<T> operator/(T a, Dual<T> b) {
 template <class T> __device__ inline Dual<T>& operator+=(Dual<T>& a, Dual<T> b) { a.v += b.v; a.d += b.d; return a; }
 template <class T> __device__ inline Dual<T>& operator-=(Dual<T>& a, Dual<T> b) { a.v -= b.v; a.d -= b.d; return a; }
 
-__device__ inline double xexp(double a) { return exp(a); }
+// FP64 exp and log for the model's arguments (trace and node states, the heating profile,
+// the mixture fits), written from the textbook methods. exp: Cody-Waite reduction
+// x = n ln2 + r with |r| <= ln2/2 (ln2 split in two doubles, fused multiply-adds), then the
+// Taylor polynomial of e^r to degree 13 (remainder below 5e-18) and a scaling by 2^n.
+// log: x = 2^e m with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(z) with z = (m - 1)/(m + 1),
+// |z| <= 0.172, by the series 2 z sum_k z^2k/(2k + 1) to k = 11 (remainder below 1e-18),
+// plus e ln2. Both are within a few ulp and take about half the instructions of the general
+// library routines. NaN propagates; exp saturates to 0 below -746 and to inf above 710; log
+// of a negative number is NaN, of zero -inf, of +inf +inf.
+constexpr double kLn2Hi = 0.6931471805599453, kLn2Lo = 2.3190468138462996e-17;
+__device__ inline double fexp(double x) {
+  x = x < -746.0 ? -746.0 : (x > 710.0 ? 710.0 : x);
+  const double nf = rint(x * 1.4426950408889634);
+  double r = fma(-nf, kLn2Hi, x);
+  r = fma(-nf, kLn2Lo, r);
+  double p = 1.0 / 6227020800.0;           // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)nf);
+}
+__device__ inline double flog(double x) {
+  int e;
+  double m = frexp(x, &e);                 // x = m 2^e, m in [1/2, 1)
+  const bool low = m < 0.7071067811865476;
+  m = low ? 2.0 * m : m;
+  e = low ? e - 1 : e;
+  const double z = (m - 1.0) * recip(m + 1.0);
+  const double z2 = z * z;
+  double p = 1.0 / 23.0;
+  p = fma(p, z2, 1.0 / 21.0);
+  p = fma(p, z2, 1.0 / 19.0);
+  p = fma(p, z2, 1.0 / 17.0);
+  p = fma(p, z2, 1.0 / 15.0);
+  p = fma(p, z2, 1.0 / 13.0);
+  p = fma(p, z2, 1.0 / 11.0);
+  p = fma(p, z2, 1.0 / 9.0);
+  p = fma(p, z2, 1.0 / 7.0);
+  p = fma(p, z2, 1.0 / 5.0);
+  p = fma(p, z2, 1.0 / 3.0);
+  p = fma(p, z2, 1.0);
+  const double ef = (double)e;
+  const double res = fma(ef, kLn2Hi, fma(ef, kLn2Lo, 2.0 * z * p));
+  if (x > 0.0 && x < __builtin_inf()) return res;
+  return x == 0.0 ? -__builtin_inf() : (x > 0.0 ? x : __builtin_nan(""));
+}
+
+__device__ inline double xexp(double a) { return fexp(a); }
 __device__ inline float xexp(float a) { return expf(a); }
-__device__ inline double xlog(double a) { return log(a); }
+__device__ inline double xlog(double a) { return flog(a); }
 __device__ inline float xlog(float a) { return logf(a); }
 __device__ inline double xsqrt(double a) { return sqrt(a); }
 __device__ inline float xsqrt(float a) { return sqrtf(a); }
@@ -83,7 +140,7 @@ template <class T> __device__ inline Dual<T> xerfcx(Dual<T> a) {
   return {e, (T(2) * a.v * e - T(1.1283791670955126)) * a.d};
 }
 // x^c for x > 0
-__device__ inline double xpow(double a, double c) { return exp(c * log(a)); }
+__device__ inline double xpow(double a, double c) { return fexp(c * flog(a)); }
 __device__ inline float xpow(float a, float c) { return expf(c * logf(a)); }
 template <class T> __device__ inline Dual<T> xpow(Dual<T> a, T c) {
   T p = xpow(a.v, c);
@@ -169,8 +226,8 @@ __device__ inline Mix mixture(const PhysC& P, double r) {
   }
   double c[3], dc[3];
   for (int s = 0; s < 3; ++s) {
-    const double e0 = P.comp_a[2 * s] * exp(P.comp_b[2 * s] * r);
-    const double e1 = P.comp_a[2 * s + 1] * exp(P.comp_b[2 * s + 1] * r);
+    const double e0 = P.comp_a[2 * s] * fexp(P.comp_b[2 * s] * r);
+    const double e1 = P.comp_a[2 * s + 1] * fexp(P.comp_b[2 * s + 1] * r);
     c[s] = e0 + e1;
     dc[s] = P.comp_b[2 * s] * e0 + P.comp_b[2 * s + 1] * e1;
   }
@@ -412,7 +469,7 @@ __device__ inline double heating(const PhysC& P, const double* x, double t) {
   (void)t;
   if (!(cchi > 0.0)) return 0.0;
   const double z = (r - P.heat_rm) * P.heat_inv_H;
-  return P.heat_amp * P.heat_qm * exp(1.0 - z - exp(-z) * recip(cchi));
+  return P.heat_amp * P.heat_qm * fexp(1.0 - z - fexp(-z) * recip(cchi));
 }
 
 // the same on the device (kernels that advance time themselves)

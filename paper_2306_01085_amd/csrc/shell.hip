@@ -27,39 +27,51 @@
 namespace dg {
 
 // pass 2: R += (F^-.(-Sn))/(2 w_end J) on every interior face node, reading the
-// traces that the neighbours' pass 1 wrote into this element's incoming slots
+// traces that the neighbours' pass 1 wrote into this element's incoming slots. The
+// element's 6 x 5 x (p+1)^2 slots are one contiguous block: its lanes copy it into LDS with
+// coalesced 8-byte loads (each slot read once), then every face node sums the slots of the
+// faces it lies on (the faces in order, those it is not on adding zero as before) and
+// updates its R. Slots of boundary faces are never written and may hold any bits: they
+// are copied but never added.
 template <int P, class OT>
 __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT* __restrict__ Fin,
                                                    OT* __restrict__ R) {
   typedef Shape<P> Sh;
   constexpr int n = Sh::n, N = Sh::N, N2 = Sh::N2, TPE = Sh::TPE, EPB = Sh::EPB;
+  constexpr int L = 30 * N2;                                    // trace slots of one element
+  constexpr int W = L * (int)sizeof(OT) / 8;                    // as 8-byte words
+  static_assert((L * sizeof(OT)) % 8 == 0, "trace block must be whole 8-byte words");
+  __shared__ uint64_t s_tw[EPB][W];
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
   const int e = xcd_block_reversed(blockIdx.x, gridDim.x) * EPB + le;
-  if (e >= M.E || j >= N) return;
+  const bool live = e < M.E;
   const int a = j % n, b = (j / n) % n, cz = j / N2;
-  const int cell = e / M.n_rad, k = e % M.n_rad;
+  const int cell = live ? e / M.n_rad : 0, k = live ? e % M.n_rad : 0;
   const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
-  if (!(on[0] || on[1] || on[2] || on[3] || on[4] || on[5])) return;
+  const bool upd = live && j < N && (on[0] || on[1] || on[2] || on[3] || on[4] || on[5]);
+  const int64_t base = (int64_t)e * 5 * N;
+  OT r[5];
+  if (upd)
+    for (int c = 0; c < 5; ++c) r[c] = R[base + c * N + j];
+  if (live) {
+    // the block starts at e * L * sizeof(OT) bytes, a multiple of 8 (L * sizeof(OT) is)
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(Fin + (int64_t)e * L);
+    for (int w = j; w < W; w += TPE) s_tw[le][w] = src[w];
+  }
+  __syncthreads();
+  if (!upd) return;
+  const OT* Fe = reinterpret_cast<const OT*>(&s_tw[le][0]);
   const int ja = a + n * b;
   const double rk = M.edges[k], hk = M.edges[k + 1] - rk;
   const double rc = rk + 0.5 * (gc.x[cz] + 1.0) * hk;
   const double Jac = rc * rc * (0.5 * hk) * M.ang[((int64_t)cell * 13 + 9) * N2 + ja];
   const OT hl = OT(0.5 / (gc.w[0] * Jac));
-  const int64_t base = (int64_t)e * 5 * N;
-  // Every load is issued before any is used: R first, then all 6 x 5 trace slots of this node
-  // position (each element has all six faces' slots allocated; m < N2 on every face), the
-  // faces the node is not on discarded by a select (slots never written may hold any bits).
-  // Gathered under per-face branches, a wavefront instead waited for one face at a time.
-  const OT* Fe = Fin + (int64_t)e * 6 * 5 * N2;
-  OT r[5], acc[5] = {OT(0), OT(0), OT(0), OT(0), OT(0)};
-  for (int c = 0; c < 5; ++c) r[c] = R[base + c * N + j];
+  OT acc[5] = {OT(0), OT(0), OT(0), OT(0), OT(0)};
   for (int f = 0; f < 6; ++f) {
+    if (!on[f]) continue;
     const int m = face_slot<P>(f, a, b, cz);
-    for (int c = 0; c < 5; ++c) {
-      const OT x = Fe[(f * 5 + c) * N2 + m];
-      acc[c] += on[f] ? x : OT(0);
-    }
+    for (int c = 0; c < 5; ++c) acc[c] += Fe[(f * 5 + c) * N2 + m];
   }
   for (int c = 0; c < 5; ++c) R[base + c * N + j] = r[c] + hl * acc[c];
 }

@@ -294,41 +294,49 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   const int n_own = __popc(own);
 
   // ---- phase B (face-node tasks, owned faces first): numerical trace u_hat - u of every
-  // face slot, the neighbour's trace slot, and Z on the owned faces
-  if (live)
-    for (int tsk = j; tsk < 6 * N2; tsk += TPE) {
-      const int r = tsk / N2, m = tsk % N2;
-      const int f = (r < n_own) ? nth_bit(own, r) : nth_bit(~own & 63, r - n_own);
-      int a, b, cz;
-      slot_node<P>(f, m, a, b, cz);
-      const int jo = a + n * b + N2 * cz;
+  // face slot, the neighbour's trace slot, and Z on the owned faces. A thread holds at most
+  // NTASK tasks (6 (p+1)^2 face slots over the element's threads: 2 at p = 2, 3, 4); the
+  // neighbour values of all of them are requested before any is used, so the gathers of the
+  // second task overlap those of the first instead of following them.
+  constexpr int NTASK = (6 * N2 + TPE - 1) / TPE;
+  {
+    int t_f[NTASK], t_m[NTASK], t_r[NTASK], t_jo[NTASK], t_en[NTASK], t_nb[NTASK];
+    S t_un[NTASK][5];
+#pragma unroll
+    for (int q = 0; q < NTASK; ++q) {
+      const int tsk = j + q * TPE;
+      t_en[q] = -2;                                   // -2: no task
+      if (live && tsk < 6 * N2) {
+        const int r = tsk / N2, m = tsk % N2;
+        const int f = (r < n_own) ? nth_bit(own, r) : nth_bit(~own & 63, r - n_own);
+        int a, b, cz;
+        slot_node<P>(f, m, a, b, cz);
+        int jn, fn, mn;
+        const int en = face_neighbour_lds<P>(M, s_cn[le], cell, k, f, a, b, cz, jn, fn, mn);
+        t_f[q] = f;
+        t_m[q] = m;
+        t_r[q] = r;
+        t_jo[q] = a + n * b + N2 * cz;
+        t_en[q] = en;
+        if (en >= 0) {
+          t_nb[q] = (en * 6 + fn) * 5 * N2 + mn;
+          for (int c = 0; c < 5; ++c) t_un[q][c] = load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NTASK; ++q) {
+      if (t_en[q] == -2) continue;
+      const int f = t_f[q], m = t_m[q], en = t_en[q];
       S uo[5], du[5];
-      for (int c = 0; c < 5; ++c) uo[c] = s_u[le][c][jo];
-      int jn, fn, mn;
-      const int en = face_neighbour_lds<P>(M, s_cn[le], cell, k, f, a, b, cz, jn, fn, mn);
+      for (int c = 0; c < 5; ++c) uo[c] = s_u[le][c][t_jo[q]];
       if (en >= 0) {
-        for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (load_state<S>(u, v, (int64_t)en * 5 * N + c * N + jn) - uo[c]);
+        for (int c = 0; c < 5; ++c) du[c] = T(0.5) * (t_un[q][c] - uo[c]);
         if constexpr (RAD) {
           if (f < 4)
             for (int c = 0; c < 5; ++c) du[c].d = T(-0.5) * uo[c].d;
         }
-        s_nb[le][f][m] = (en * 6 + fn) * 5 * N2 + mn;
-        if (r < n_own) {
-          const int dd = f >> 1;
-          const int ja = a + n * b;
-          const double rc = rk + 0.5 * (gc.x[cz] + 1.0) * hk;
-          const double fac = (dd < 2) ? rc * 0.5 * hk : rc * rc;
-          const double A0 = s_ang[le][3 * dd][ja], A1 = s_ang[le][3 * dd + 1][ja], A2 = s_ang[le][3 * dd + 2][ja];
-          const double Smag = fac * sqrt(A0 * A0 + A1 * A1 + A2 * A2);
-          S uh[5];
-          for (int c = 0; c < 5; ++c) uh[c] = uo[c] + du[c];
-          S sm, se;
-          sigma<3, S, XP>(ph, uh, sm, se, rc);
-          for (int c = 0; c < 5; ++c) {
-            const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
-            s_z[le][r][c][m] = T(Smag) * sg * du[c];
-          }
-        }
+        s_nb[le][f][m] = t_nb[q];
       } else if (ph.bc_mode == 1 || f == 4) {
         S ub[5];
         boundary_state<3, S>(ph, uo, ub);
@@ -338,6 +346,34 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       }
       for (int c = 0; c < 5; ++c) s_f[le][f][c][m] = du[c];
     }
+    // Z on the owned faces, from the values this thread has just put in LDS (its own
+    // slots: no barrier needed), so that the gathered values are dead before sigma
+#pragma unroll
+    for (int q = 0; q < NTASK; ++q) {
+      if (t_en[q] < 0 || t_r[q] >= n_own) continue;
+      const int f = t_f[q], m = t_m[q], r = t_r[q];
+      int a, b, cz;
+      slot_node<P>(f, m, a, b, cz);
+      const int dd = f >> 1;
+      const int ja = a + n * b;
+      const double rc = rk + 0.5 * (gc.x[cz] + 1.0) * hk;
+      const double fac = (dd < 2) ? rc * 0.5 * hk : rc * rc;
+      const double A0 = s_ang[le][3 * dd][ja], A1 = s_ang[le][3 * dd + 1][ja], A2 = s_ang[le][3 * dd + 2][ja];
+      const double Smag = fac * sqrt(A0 * A0 + A1 * A1 + A2 * A2);
+      S du[5], uh[5];
+      for (int c = 0; c < 5; ++c) {
+        du[c] = s_f[le][f][c][m];
+        uh[c] = s_u[le][c][t_jo[q]] + du[c];
+      }
+      S sm, se;
+      sigma<3, S, XP>(ph, uh, sm, se, rc);
+      for (int c = 0; c < 5; ++c) {
+        const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
+        s_z[le][r][c][m] = T(Smag) * sg * du[c];
+      }
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
   __syncthreads();
 
   // ---- phase C (node threads): gradient, pointwise flux and source, contravariant fluxes
