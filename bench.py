@@ -79,15 +79,54 @@ FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 
 
-def residual_bytes(w):
-    """algorithmic HBM bytes of one full R(u) (both passes): pass 1 as above; pass 2
-    reads the neighbours' traces and face-node states and updates R on face nodes"""
+def pass2_bytes(w):
+    """algorithmic HBM bytes of the trace pass (pass 2): read the 6 x 5 x (p+1)^2 incoming
+    trace slots of every element, read and write R on its face nodes"""
     n = w.p + 1
     N, N2 = n ** 3, n ** 2
     Nface = N - (n - 2) ** 3
-    E = w.n_elem
-    p2 = E * (6 * 5 * N2 * 8 + 5 * N * 8 + 2 * 5 * Nface * 8)
-    return pass1_bytes(w) + p2
+    return w.n_elem * (6 * 5 * N2 * 8 + 2 * 5 * Nface * 8)
+
+
+def residual_bytes(w):
+    """algorithmic HBM bytes of one full R(u) as this design moves them (both passes)"""
+    return pass1_bytes(w) + pass2_bytes(w)
+
+
+# the survey's reference roofline of R(u): two-pass LDG with a stored gradient moves
+# 8 (3 + 2d) = 72 bytes per DOF in 3D (pass 1 reads u and writes q, pass 2 reads u and q and
+# writes R); the target is half of that roofline
+R_REF_BYTES_PER_DOF = 72.0
+HBM_TARGET_FRAC = 0.5
+FP64_RIDGE = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)     # flop per byte
+
+
+def element_pass_roofline(fl1, b1, p1_ms, tr_bytes, tr_detail, counters):
+    """the element pass against the roof its arithmetic intensity selects: below the FP64
+    ridge (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B) that is HBM, above it the FP64 vector peak.
+    Both fractions are reported, with the VALU issue fraction from the counters where a
+    counter run of this kernel exists"""
+    ai = fl1 / b1
+    gbs = b1 / (p1_ms * 1e-3) / 1e9
+    tflops = fl1 / (p1_ms * 1e-3) / 1e12
+    bound = "hbm" if ai < FP64_RIDGE else "alu"
+    out = {"bound": bound,
+           "achieved": gbs if bound == "hbm" else tflops,
+           "peak": HBM_PEAK_GBS if bound == "hbm" else FP64_PEAK_TFLOPS,
+           "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+           "frac": gbs / HBM_PEAK_GBS if bound == "hbm" else tflops / FP64_PEAK_TFLOPS,
+           "traffic": tr_bytes, "traffic_detail": tr_detail,
+           "kernel": "shell_pass1 (R, f64)",
+           "arithmetic_intensity_flop_per_byte": ai, "fp64_ridge_flop_per_byte": FP64_RIDGE,
+           "algorithmic_bytes_per_launch": b1, "algorithmic_flops_per_launch": fl1,
+           "avg_launch_ms": p1_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac_algorithmic": gbs / HBM_PEAK_GBS,
+           "fp64_tflops_algorithmic": tflops, "fp64_frac_algorithmic": tflops / FP64_PEAK_TFLOPS}
+    if tr_bytes:
+        out["hbm_frac_counters"] = tr_bytes / (p1_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+        out["traffic_over_algorithmic"] = tr_bytes / b1
+    if counters:
+        out.update(counters)
+    return out
 
 
 # HBM bytes per launch of the element pass (FP64 R) from rocprofv3 --pmc FETCH_SIZE and
@@ -129,30 +168,110 @@ def traffic(workload, cfg):
     return fetch + write, {"fetch_bytes": fetch, "write_bytes": write, "profile": t["profile"]}
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """the FP64 oracle's residual on a bounded sample of the same workload: the same
-    element type, degree and physics on a shell of 6 x 8 x 8 x 16 elements (a quarter of the
-    benchmark shell), repeated for about budget_s seconds of CPU work (at most 15 runs)"""
+# VALU issue: a wave64 VALU instruction occupies a SIMD (16 lanes) for 4 cycles; 1024 SIMDs
+CHIP_SIMDS = 1024
+CLOCK_GHZ = 2.4
+
+
+def valu_counters(workload, cfg, p1_ms):
+    """VALU issue fraction of the element pass at the measured launch time, from the
+    SQ_INSTS_VALU count of its counter run (None if the kernel changed since)"""
+    t = PASS1_TRAFFIC.get((workload, cfg))
+    if t is None or "valu_insts" not in t or t["src"] != kernel_source_hash():
+        return {}
+    cycles = p1_ms * 1e-3 * CLOCK_GHZ * 1e9
+    return {"valu_insts_per_launch": t["valu_insts"],
+            "valu_issue_frac": t["valu_insts"] * 4.0 / (CHIP_SIMDS * cycles),
+            "valu_note": "SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x launch time x 2.4 GHz)"}
+
+
+def _cpu_info():
+    """model name and socket count of the host, and the threads this process may use"""
+    model, sockets = None, set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "model name" and model is None:
+                    model = v.strip()
+                elif k == "physical id":
+                    sockets.add(v.strip())
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "sockets": len(sockets) or None, "os_cpu_count": os.cpu_count(), "usable_threads": usable}
+
+
+def _median_time(fn, budget_s, max_runs, warm=True):
+    if warm:
+        fn()
+    times = []
+    t_end = time.perf_counter() + budget_s
+    while len(times) < max_runs and (len(times) < min(2, max_runs) or time.perf_counter() < t_end):
+        t0 = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - t0)
+    return float(np.median(times)), len(times)
+
+
+def cpu_baseline(w, implicit=None, budget_s=4.0):
+    """the FP64 oracle timed on this host's cores, on bounded samples of the workloads:
+    R(u) and the complex-step J(u)v on a shell of 6 x 8 x 8 x 16 elements at the benchmark's
+    degree (a quarter of the benchmark shell) with one BLAS thread and with every usable
+    thread; one dense-Newton implicit DIRK(3,3) step of the 64-element p = 2 column (dt = 10 s)
+    with one thread; and the implicit steps of the shells extrapolated from the R and J v
+    counts of the GPU's FP64 runs times the oracle's per-call time scaled by DOF (labelled
+    as extrapolations: they leave out the preconditioner and the Krylov vector work, a
+    lower bound). `value` is the one-thread R(u) rate."""
     from threadpoolctl import threadpool_limits
 
+    import synth
     from oracle import dg as odg
+    from oracle import jac as ojac
     from oracle import mesh as omesh
+    from oracle import timeint
+    info = _cpu_info()
     n_ang, n_rad = 8, w.n_rad
     om = omesh.shell_mesh(w.p, n_ang, n_rad, w.r_bot, w.r_top, w.stretch)
     u = np.moveaxis(w.state_fn()(om.X), 0, 1).copy()
+    v = synth.tangent(u.shape, 1)
     ndof = u.size
-    times = []
+    res = {}
+    for label, threads in (("1_thread", 1), ("all_threads", info["usable_threads"])):
+        with threadpool_limits(limits=threads):
+            tr, nr = _median_time(lambda: odg.residual(om, w.phys, u, 0.0), budget_s, 15)
+            tj, nj = _median_time(lambda: ojac.jvp_complex(om, w.phys, u, v, 0.0), budget_s, 10)
+        res[label] = {"threads": threads, "residual_s": tr, "residual_gdofs": ndof / tr / 1e9, "residual_runs": nr,
+                      "jvp_s": tj, "jvp_gdofs": ndof / tj / 1e9, "jvp_runs": nj}
+    # one implicit step of the 1D column workload (64 elements, p = 2, 576 DOF), dense Newton
+    wc = synth.config_column(0)
+    cm = omesh.columns_mesh([int(wc.nelem[0])], int(wc.p[0]), wc.r_bot, wc.r_top)
+    Pc = dict(wc.phys)
+    for k in wc.col_phys:
+        Pc[k] = float(wc.col_phys[k][0])
+    uc = np.moveaxis(wc.state(0, cm.X[:, :, 0]), 0, 1).copy()
     with threadpool_limits(limits=1):
-        odg.residual(om, w.phys, u, 0.0)            # warm-up
-        t_end = time.perf_counter() + budget_s
-        while len(times) < 15 and time.perf_counter() < t_end:
-            t0 = time.perf_counter()
-            odg.residual(om, w.phys, u, 0.0)
-            times.append(time.perf_counter() - t0)
-    med = float(np.median(times))
-    return {"value": ndof / med / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": "R(u) of the oracle on a 6x%dx%dx%d p=%d shell (%d DOF), median of %d runs, 1 BLAS thread"
-                      % (n_ang, n_ang, n_rad, w.p, ndof, len(times))}
+        tc, ncr = _median_time(lambda: timeint.implicit_step_dense(cm, Pc, uc, 0.0, wc.dt, scheme=33, rtol=1e-8),
+                               0.0, 1, warm=False)
+    out = {"value": res["1_thread"]["residual_gdofs"], "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+           "sample": "R(u) of the oracle on a 6x%dx%dx%d p=%d shell (%d DOF), median of %d runs, 1 BLAS thread"
+                     % (n_ang, n_ang, n_rad, w.p, ndof, res["1_thread"]["residual_runs"]),
+           "cpu": info, "shell_sample": res,
+           "column_implicit_step": {"workload": "column-64-p2 (576 DOF), dt 10 s, DIRK(3,3), dense Newton 1e-8",
+                                    "s_per_step": tc, "runs": ncr, "threads": 1},
+           "note": "the oracle is a plain NumPy correctness reference, not a tuned CPU solver"}
+    if implicit:
+        per_dof = {k: res["1_thread"][k + "_s"] / ndof for k in ("residual", "jvp")}
+        ext = {}
+        for key, (n_dof, counts) in implicit.items():
+            n_r = counts["newton_per_step"] + 3           # a residual per Newton iteration and per stage end
+            n_j = counts["gmres_per_step"]
+            ext[key] = {"n_dof": n_dof, "residuals_per_step": n_r, "jvps_per_step": n_j,
+                        "s_per_step_extrapolated": n_dof * (n_r * per_dof["residual"] + n_j * per_dof["jvp"]),
+                        "kind": "extrapolation (1 thread, lower bound)"}
+        out["implicit_step_extrapolated"] = ext
+    return out
 
 
 FILTER_RATE = 0.5   # modal filter after every implicit step (per unit nondimensional time)
@@ -259,6 +378,23 @@ def implicit_steps(w, mesh, u, n_steps, only=None):
     return res
 
 
+def implicit_steps_shell(name, n_steps, runs):
+    """the implicit steps on another shell workload (its own mesh and state)"""
+    import torch
+
+    from paper_2306_01085_amd import Mesh
+    w = workload(name)
+    mesh = Mesh.shell(p=w.p, n_ang=w.n_ang, n_rad=w.n_rad, r_bot=w.r_bot, r_top=w.r_top, stretch=w.stretch,
+                      phys=w.phys)
+    u = torch.from_numpy(shell_state(w, mesh.nodes().reshape(w.n_elem, -1, 3)).ravel()).cuda()
+    res = implicit_steps(w, mesh, u, n_steps, only=runs)
+    res["workload"] = w.name
+    res["n_dof"] = w.n_dof
+    del mesh, u
+    torch.cuda.empty_cache()
+    return res
+
+
 def column_batch(n_steps=None):
     """the batched radial-column sweep: 4096 columns advanced n_steps DIRK(3,3) steps of
     10 s in one persistent launch (autotuned grid), columns/s (sampled columns of this
@@ -360,6 +496,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="shell-p3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-p4", action="store_true", help="skip the implicit steps on the 92M-DOF p = 4 shell")
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the reduced warm-start experiment")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of known size (calibrates HBM counters)")
     ap.add_argument("--only", default="all", choices=["all", "residual", "implicit", "columns"],
@@ -371,6 +509,8 @@ def main():
                     help="sweep: the parametric study of the 1D model (three cases x 75 columns)")
     ap.add_argument("--sweep-hours", type=float, default=72.0, help="model hours per case (sweep mode)")
     ap.add_argument("--implicit-steps", type=int, default=16)
+    ap.add_argument("--all-pass1-configs", action="store_true",
+                    help="with --only residual: time every element-pass launch configuration")
     ap.add_argument("--pass1-config", type=int, default=None, choices=range(6),
                     help="element-pass launch configuration instead of the autotuned one (for counter runs)")
     ap.add_argument("--ws-train-steps", type=int, default=60)
@@ -431,8 +571,15 @@ def main():
     jv32 = torch.empty_like(v32)
     t = 0.0
 
-    def timed(fn, steps):
-        torch.cuda.synchronize()
+    def timed(fn, steps, preroll_s=0.3):
+        # keep the GPU busy with the same work for preroll_s first: a timed region of a few
+        # milliseconds right after lighter work catches the clock still rising (R read ~10%
+        # slow over 20 evaluations after 3 warm-ups without it)
+        t_end = time.perf_counter() + preroll_s
+        while time.perf_counter() < t_end:
+            for _ in range(10):
+                fn()
+            torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
@@ -465,12 +612,20 @@ def main():
     jvb = torch.empty_like(v32) if w.p in (3, 4) else None
     f_jb = (lambda: mesh.jvp(u, v32, t, "bf16", out=jvb)) if w.p in (3, 4) else None
     if args.only == "residual":
-        for _ in range(args.warmup):
-            f_r()
-        ms_r = timed(f_r, args.steps)
+        # with --all-pass1-configs every element-pass launch configuration runs in turn (one
+        # counter run then covers them all: their kernels have distinct template names)
+        cfgs = range(6) if args.all_pass1_configs else [p1_cfg]
+        res = {}
+        for cfg in cfgs:
+            mesh.set_option("shell_pass1_config", cfg)
+            for _ in range(args.warmup):
+                f_r()
+            ms_r = timed(f_r, args.steps)
+            res[cfg] = {"residual_ms": ms_r, "gdofs": w.n_dof / ms_r / 1e6}
+            log("configuration %d: %.4f ms" % (cfg, ms_r))
         if args.copy_probe:
             copy_probe(dev)
-        print(json.dumps({"residual_ms": ms_r, "gdofs": w.n_dof / ms_r / 1e6}), flush=True)
+        print(json.dumps(res), flush=True)
         return
     for _ in range(args.warmup):
         f_r(); f_j64(); f_j32()
@@ -533,7 +688,6 @@ def main():
     b1 = pass1_bytes(w)
     fl1 = pass1_flops(w.p) * w.n_elem * (w.p + 1) ** 3
     tr_bytes, tr_detail = traffic(args.workload, p1_cfg)
-    achieved = fl1 / (p1_ms * 1e-3) / 1e12
     out = {
         "metric": "GDOF/s for DG R(u) & JVP; s per implicit step, learned/mixed vs plain @1e-8",
         "value": ndof / (ms_r * 1e-3) / 1e9,
@@ -556,12 +710,18 @@ def main():
         "jvp_rel_err_vs_f64": jv_err,
         "kernels_ms": {k: v_[0] / v_[1] for k, v_ in prof.items()},
         "residual_effective_gbs": residual_bytes(w) / (ms_r * 1e-3) / 1e9,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": tr_bytes, "traffic_detail": tr_detail,
-                     "kernel": "shell_pass1 (R, f64)", "algorithmic_flops_per_launch": fl1,
-                     "avg_launch_ms": p1_ms, "algorithmic_bytes_per_launch": b1,
-                     "hbm_gbs_algorithmic": b1 / (p1_ms * 1e-3) / 1e9,
-                     "hbm_frac_algorithmic": b1 / (p1_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "residual_target": {
+            "reference_bytes_per_dof": R_REF_BYTES_PER_DOF,
+            "hbm_frac_of_reference_roofline": R_REF_BYTES_PER_DOF * ndof / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "target_frac": HBM_TARGET_FRAC,
+            "target_gdofs": HBM_TARGET_FRAC * HBM_PEAK_GBS / R_REF_BYTES_PER_DOF,
+            "met": bool(R_REF_BYTES_PER_DOF * ndof / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBS >= HBM_TARGET_FRAC)},
+        "roofline": element_pass_roofline(fl1, b1, p1_ms, tr_bytes, tr_detail,
+                                          valu_counters(args.workload, p1_cfg, p1_ms)),
+        "trace_pass": {"kernel": "shell_pass2 (R, f64)", "avg_launch_ms": p2_ms,
+                       "algorithmic_bytes_per_launch": pass2_bytes(w),
+                       "hbm_gbs_algorithmic": pass2_bytes(w) / (p2_ms * 1e-3) / 1e9,
+                       "hbm_frac_algorithmic": pass2_bytes(w) / (p2_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "finite": ok,
     }
     log("implicit steps")
@@ -570,11 +730,26 @@ def main():
     out["network"] = network
     out["implicit_step"] = implicit_steps(w, mesh, u, args.implicit_steps)
     del r, jv, jv32, v, v32, jvfd
+    if not args.no_warmstart:
+        log("warm-start network: record, train, plain vs learned")
+        ws = warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epochs=8)
+        ws["scale"] = "reduced (60 recorded steps, 8 evaluation steps); bench.py --mode warmstart " \
+                      "--ws-train-steps 667 --ws-eval-steps 200 --ws-eval-seed 1 is the configured scale"
+        out["warmstart"] = ws
+    del mesh, u
+    torch.cuda.empty_cache()
+    if not args.no_p4:
+        log("implicit steps on the 92M-DOF p = 4 shell")
+        out["implicit_step_p4"] = implicit_steps_shell("shell-p4", 5, ("f64", "f32"))
     log("column batch")
     out["columns"] = column_batch()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(w)
+        counts = {"shell-p3 (7.9M DOF), f64 J v, line preconditioner": (w.n_dof, out["implicit_step"]["f64"])}
+        if "implicit_step_p4" in out and out["implicit_step_p4"]["f64"]["s_per_step"]:
+            counts["shell-p4 (92M DOF), f64 J v, line preconditioner"] = (out["implicit_step_p4"]["n_dof"],
+                                                                       out["implicit_step_p4"]["f64"])
+        out["cpu_baseline"] = cpu_baseline(w, implicit=counts)
     print(json.dumps(out), flush=True)
 
 

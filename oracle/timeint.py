@@ -147,27 +147,46 @@ def gmres(Aop, rhs, x0=None, m=30, rtol=1e-10, max_restarts=50, M=None):
     return x, total
 
 
-def newton_jfnk(mesh, P, Gfun, U0, ti, aii_dt, ref_norm, rtol=1e-12, maxit=40, gmres_rtol=1e-12):
+def newton_jfnk(mesh, P, Gfun, U0, ti, aii_dt, ref_norm, rtol=1e-12, maxit=40, gmres_rtol=1e-12, M=None):
     """Newton with matrix-free GMRES on complex-step products (for meshes too large for
-    the dense Jacobian); same stage equation and stopping rule as newton_dense"""
+    the dense Jacobian); same stage equation and stopping rule as newton_dense. A Newton
+    step whose residual is not finite or has not fallen is halved (up to 12 times): large
+    steps (dt = 60 s from the step's start state) can otherwise leave the physical states
+    (negative temperature). The damping changes the path, not the solution G(U) = 0, and so
+    does the optional right preconditioner M of GMRES (a callable on flat vectors)."""
     from . import jac
     U = U0.copy()
+    G = Gfun(U)
+    nG = np.linalg.norm(G)
     prev = np.inf
     for it in range(maxit):
-        G = Gfun(U)
-        nG = np.linalg.norm(G)
         if nG <= rtol * ref_norm or (nG > 0.5 * prev and nG <= 1e-10 * ref_norm):
             return U, it
         prev = nG
         Aop = lambda v: v - aii_dt * jac.jvp_complex(mesh, P, U, v.reshape(U.shape), ti).ravel()
-        dx, _ = gmres(Aop, -G.ravel(), m=60, rtol=gmres_rtol, max_restarts=200)
-        U = U + dx.reshape(U.shape)
+        dx, _ = gmres(Aop, -G.ravel(), m=60, rtol=gmres_rtol, max_restarts=200, M=M)
+        dx = dx.reshape(U.shape)
+        lam = 1.0
+        for _ in range(13):
+            with np.errstate(invalid="ignore", over="ignore"):
+                Gt = Gfun(U + lam * dx)
+            nt = np.linalg.norm(Gt)
+            if np.isfinite(nt) and (nt < nG or lam == 1.0 and nG <= 1e-10 * ref_norm):
+                break
+            lam *= 0.5
+        else:
+            if nG <= 1e-10 * ref_norm:       # the round-off floor of the residual evaluation
+                return U, it
+            raise RuntimeError("JFNK Newton: no step lowers the residual")
+        U = U + lam * dx
+        G, nG = Gt, nt
     raise RuntimeError("JFNK Newton did not converge")
 
 
-def implicit_step_jfnk(mesh, P, u, t, dt, scheme=33, rtol=1e-12, filter_rate=0.0):
+def implicit_step_jfnk(mesh, P, u, t, dt, scheme=33, rtol=1e-12, filter_rate=0.0, M=None):
     """one DIRK step with every stage solved by matrix-free Newton-GMRES to rtol, then
-    the optional modal filter"""
+    the optional modal filter; M: optional right preconditioner of every GMRES solve (it
+    steers the iterations only)"""
     A, b, c = dirk_tableau(scheme)
     Rs, Us = [], []
     for i in range(len(c)):
@@ -175,7 +194,7 @@ def implicit_step_jfnk(mesh, P, u, t, dt, scheme=33, rtol=1e-12, filter_rate=0.0
         bi = u + dt * sum(A[i, j] * Rs[j] for j in range(i))
         aii = A[i, i]
         G = lambda U: U - dt * aii * dg.residual(mesh, P, U, ti) - bi
-        Ui, _ = newton_jfnk(mesh, P, G, u, ti, dt * aii, np.linalg.norm(G(u)), rtol)
+        Ui, _ = newton_jfnk(mesh, P, G, u, ti, dt * aii, np.linalg.norm(G(u)), rtol, M=M)
         Us.append(Ui)
         Rs.append(dg.residual(mesh, P, Ui, ti))
     un = modal_filter(mesh, Us[-1], np.exp(-filter_rate * dt)) if filter_rate > 0 else Us[-1]
