@@ -157,26 +157,35 @@ def residual(mesh, P, u, t=0.0, q=None):
     return np.moveaxis(R, 0, 1).copy()
 
 
-def residual_parts(mesh, P, u, t=0.0):
-    """(R, term scale): the scale is |volume divergence| + |face lift| + |source| per
-    node, used to express parity tolerances relative to the cancelling terms."""
+def residual_terms(mesh, P, u, t=0.0):
+    """R and its three parts, each [f, E, N]: the volume divergence V, the face
+    contribution Fc (lifted numerical fluxes) and the source S, R = V + Fc + S (works on
+    complex states as well, for the complex step)"""
     ref = mesh.ref
     d = P["d"]
     R = residual(mesh, P, u, t)
-    # volume part alone, face part alone
-    P0 = dict(P)
     q = gradient(mesh, P, u)
     un = np.moveaxis(u, 1, 0)
     qn = np.moveaxis(np.moveaxis(q, 1, 0), 2, 1)
+    del q
     xn = np.moveaxis(mesh.X, 2, 0)
-    S = _arr(ph.source(un, qn, xn, t, P0, np), un[0])
-    F = _arr2(ph.flux(un, qn, P0, np, xn), un[0])
+    S = _arr(ph.source(un, qn, xn, t, P, np), un[0])
+    F = _arr2(ph.flux(un, qn, P, np, xn), un[0])
+    del qn
     V = np.zeros_like(S)
     for a in range(d):
         G = ref.W[None, None, :] * np.einsum("eik,ckei->cei", mesh.Ja[:, :, a, :], F)
         V += G @ ref.Dr[a]
+    del F
     V = V / (ref.W[None, :] * mesh.J)[None]
-    Fc = np.moveaxis(R, 0, 1) - V - S            # face contribution
+    Fc = np.moveaxis(R, 0, 1) - V - S
+    return R, V, Fc, S
+
+
+def residual_parts(mesh, P, u, t=0.0):
+    """(R, term scale): the scale is |volume divergence| + |face lift| + |source| per
+    node, used to express parity tolerances relative to the cancelling terms."""
+    R, V, Fc, S = residual_terms(mesh, P, u, t)
     scale = np.abs(V) + np.abs(Fc) + np.abs(S)
     return R, np.moveaxis(scale, 0, 1).copy()
 
@@ -219,3 +228,77 @@ def conservation_terms(mesh, P, u, t=0.0):
         rhs -= np.einsum("cem,m->c", Fh, wf)
         mag += np.einsum("cem,m->c", np.abs(Fh), wf)
     return lhs, rhs, mag
+
+
+# ------------------------------------------------------------------ over-integration (1D)
+def gauss_tables(ref, nq):
+    """nq-point Gauss-Legendre rule on [-1, 1] and the nodal basis there: V[g, j] = l_j(x_g),
+    Dg[g, j] = l_j'(x_g), and the exact reference mass matrix M[i, j] = int l_i l_j"""
+    from .gll import lagrange_eval
+    xg, wg = np.polynomial.legendre.leggauss(nq)
+    V = lagrange_eval(ref.x1, xg)
+    Dg = V @ ref.D1
+    M = V.T @ (wg[:, None] * V)
+    return xg, wg, V, Dg, M
+
+
+def residual_overint(mesh, P, u, t=0.0, nq=None):
+    """R(u) of eq. (DGformulation) on 1D columns with the volume integrals evaluated by
+    nq-point Gauss quadrature (default p + 2) and the exact mass matrix, instead of the
+    collocated GLL rule: the gradient equation and the state equation are each
+    M (.) = (weak volume terms) + (face terms), the fluxes and sources taken at the Gauss
+    points from the interpolated u and q. The numerical trace and flux of eq. (LDG2) and
+    the boundary treatment are those of `residual`, at the face points (the element's end
+    nodes). Shape [E, f, N] like `residual`."""
+    if P["d"] != 1:
+        raise ValueError("over-integration is implemented for 1D columns")
+    ref = mesh.ref
+    nq = ref.p + 2 if nq is None else nq
+    xg, wg, V, Dg, Mr = gauss_tables(ref, nq)
+    Mi = np.linalg.inv(Mr)
+    E, f, N = u.shape
+    Jel = mesh.J[:, 0]                              # h / 2 (affine elements)
+    uh = traces(mesh, P, u)                         # u_hat on the two faces: [f, E, 1] each
+    # gradient: J M q = -(u, dl/dxi) + <u_hat n, l>, exactly integrated (degree 2p - 1)
+    ug = np.einsum("gj,ecj->ecg", V, u)
+    rq = -np.einsum("g,gi,ecg->eci", wg, Dg, ug)
+    for fi, (a, side, nodes, wf) in enumerate(ref.faces):
+        rq[:, :, nodes[0]] += side * uh[fi][:, :, 0].T
+    q = np.einsum("ij,ecj->eci", Mi, rq) / Jel[:, None, None]
+    # state equation: J M R = (F, dl/dxi) + J (s, l) - <F_hat n, l>
+    qg = np.einsum("gj,ecj->ecg", V, q)
+    xq = mesh.X[:, 0, 0][:, None] + (xg[None, :] + 1.0) * Jel[:, None]     # Gauss point radii [E, nq]
+    un = np.moveaxis(ug, 1, 0)                      # [f, E, nq]
+    qn = np.moveaxis(qg, 1, 0)[:, None]             # [f, 1, E, nq]
+    F = _arr2(ph.flux(un, qn, P, np, [xq]), un[0])[:, 0]     # [f, E, nq]
+    S = _arr(ph.source(un, qn, [xq], t, P, np), un[0])        # [f, E, nq]
+    rr = np.einsum("g,gi,ceg->eci", wg, Dg, F) + Jel[:, None, None] * np.einsum("g,gi,ceg->eci", wg, V, S)
+    unodes = np.moveaxis(u, 1, 0).reshape(f, E * N)
+    qnodes = np.moveaxis(q, 1, 0).reshape(f, E * N)
+    for fi, (a, side, nodes, wf) in enumerate(ref.faces):
+        j = nodes[0]
+        Sn = np.full(E, float(side))                # outward normal of the face (1D)
+        uin = u[:, :, j].T                          # [f, E]
+        qin = q[:, :, j].T[:, None]                 # [f, 1, E]
+        nb = mesh.nbr[:, fi, 0]
+        safe = np.where(nb >= 0, nb, 0)
+        uout, qout = unodes[:, safe], qnodes[:, safe][:, None]
+        Xf = [mesh.X[:, j, 0]]
+        Fin = _arr2(ph.flux(uin, qin, P, np, Xf), uin[0])[:, 0]
+        Fout = _arr2(ph.flux(uout, qout, P, np, Xf), uout[0])[:, 0]
+        uhat = uh[fi][:, :, 0]
+        sig = _arr(ph.sigma(uhat, P, np, Xf), uhat[0])
+        Fh_int = 0.5 * (Fin + Fout) * Sn + sig * (uin - uhat)
+        ub = boundary_value(mesh, P, uin[:, :, None], [Xf[0][:, None]])[:, :, 0]
+        Fb = _arr2(ph.flux(ub, qin, P, np, Xf), ub[0])[:, 0]
+        sigb = _arr(ph.sigma(ub, P, np, Xf), ub[0])
+        Fh_dir = Fb * Sn + sigb * (uin - ub)
+        Fi_top = _arr2(ph.flux_inviscid(uin, P, np, Xf), uin[0])[:, 0]
+        Fh_top = Fi_top * Sn + top_penalty(P, uin, [Sn], np.abs(Sn), 1)
+        tag = mesh.tag[:, fi][None, :]
+        if P.get("bc_mode", 0) == 1:
+            Fh = np.where(tag > 0, Fh_dir, Fh_int)
+        else:
+            Fh = np.where(tag == 1, Fh_dir, np.where(tag == 2, Fh_top, Fh_int))
+        rr[:, :, j] -= Fh.T
+    return np.einsum("ij,ecj->eci", Mi, rr) / Jel[:, None, None]

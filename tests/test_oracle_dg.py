@@ -307,3 +307,17 @@ def test_dense_jacobian_brute_force():
     assert np.max(np.abs(Jc - Jf)) < 1e-6 * np.max(np.abs(Jc))
     v = synth.tangent(u.shape, 3)
     assert np.allclose(Jc @ v.ravel(), jac.jvp_complex(m, P, u, v).ravel(), rtol=0, atol=1e-12 * np.max(np.abs(Jc)))
+
+
+def test_jvp_parts_sum_and_scale():
+    """the complex step of the residual's parts (volume, faces, source) sums to the complex
+    step of R, and the linearised term scale bounds every entry of J v"""
+    w = synth.shell_workload(4, p=2, n_ang=1, n_rad=2)
+    m = M.shell_mesh(2, 1, 2, w.r_bot, w.r_top, w.stretch)
+    u = np.moveaxis(w.state_fn()(m.X), 0, 1).copy()
+    v = synth.tangent(u.shape, 2)
+    jv, scale = jac.jvp_parts(m, w.phys, u, v, 0.3)
+    ref = jac.jvp_complex(m, w.phys, u, v, 0.3)
+    assert np.max(np.abs(jv - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert np.all(scale >= np.abs(jv) * (1 - 1e-12))
+    assert np.max(scale) > 2 * np.max(np.abs(jv))      # the parts do cancel: the scale is not |J v|
