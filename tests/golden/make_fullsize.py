@@ -9,7 +9,8 @@ with 7,864,320 DOF, or the 6x32x32x24 p = 4 shell with 92,160,000 DOF; the third
 the p = 3 shell with the variable composition and EUVAC heating); the state is the
 workload's seeded input at the oracle's own nodes, the tangent the seeded unit-norm
 Gaussian, t = 0.25. Stored per sampled element: R, the per-node term scale
-(|volume| + |lift| + |source|) and J v, all [5, N]. Only oracle/ and the input generators
+(|volume| + |lift| + |source|), J v and its linearised term scale (|d volume| + |d lift| +
+|d source|, from the complex step of each part), all [5, N]. Only oracle/ and the input generators
 are called. It takes minutes (about 3 for shell-p3) and several GB of memory.
 """
 import json
@@ -64,13 +65,14 @@ def main():
     R, scale = R[els].copy(), scale[els].copy()
     print("R %.0f s" % (time.time() - t0), flush=True)
     v = synth.tangent(u.shape, TANGENT_SEED)
-    J = ojac.jvp_complex(om, w.phys, u, v, T_EVAL)[els].copy()
+    J, jscale = ojac.jvp_parts(om, w.phys, u, v, T_EVAL)
+    J, jscale = J[els].copy(), jscale[els].copy()
     print("J v %.0f s" % (time.time() - t0), flush=True)
     out = {
         "what": "oracle FP64 R(u) and J(u)v on the full %s workload (eq. DGformulation), sampled elements" % name,
         "workload": name, "p": w.p, "n_ang": w.n_ang, "n_rad": w.n_rad, "n_dof": int(u.size),
         "t": T_EVAL, "tangent_seed": TANGENT_SEED, "elements": els,
-        "R": R.tolist(), "scale": scale.tolist(), "Jv": J.tolist(),
+        "R": R.tolist(), "scale": scale.tolist(), "Jv": J.tolist(), "jv_scale": jscale.tolist(),
     }
     path = os.path.join(ROOT, "tests", "golden", "fullsize_%s.json" % name)
     with open(path, "w") as f:
