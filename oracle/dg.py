@@ -242,14 +242,15 @@ def gauss_tables(ref, nq):
     return xg, wg, V, Dg, M
 
 
-def residual_overint(mesh, P, u, t=0.0, nq=None):
+def residual_overint(mesh, P, u, t=0.0, nq=None, parts=False):
     """R(u) of eq. (DGformulation) on 1D columns with the volume integrals evaluated by
     nq-point Gauss quadrature (default p + 2) and the exact mass matrix, instead of the
     collocated GLL rule: the gradient equation and the state equation are each
     M (.) = (weak volume terms) + (face terms), the fluxes and sources taken at the Gauss
     points from the interpolated u and q. The numerical trace and flux of eq. (LDG2) and
     the boundary treatment are those of `residual`, at the face points (the element's end
-    nodes). Shape [E, f, N] like `residual`."""
+    nodes). Shape [E, f, N] like `residual`. With parts=True: (R, term scale), the scale
+    being |volume and source part| + |face part| per node, each projected by M^-1."""
     if P["d"] != 1:
         raise ValueError("over-integration is implemented for 1D columns")
     ref = mesh.ref
@@ -275,6 +276,7 @@ def residual_overint(mesh, P, u, t=0.0, nq=None):
     rr = np.einsum("g,gi,ceg->eci", wg, Dg, F) + Jel[:, None, None] * np.einsum("g,gi,ceg->eci", wg, V, S)
     unodes = np.moveaxis(u, 1, 0).reshape(f, E * N)
     qnodes = np.moveaxis(q, 1, 0).reshape(f, E * N)
+    rvol = rr.copy()
     for fi, (a, side, nodes, wf) in enumerate(ref.faces):
         j = nodes[0]
         Sn = np.full(E, float(side))                # outward normal of the face (1D)
@@ -301,4 +303,8 @@ def residual_overint(mesh, P, u, t=0.0, nq=None):
         else:
             Fh = np.where(tag == 1, Fh_dir, np.where(tag == 2, Fh_top, Fh_int))
         rr[:, :, j] -= Fh.T
-    return np.einsum("ij,ecj->eci", Mi, rr) / Jel[:, None, None]
+    R = np.einsum("ij,ecj->eci", Mi, rr) / Jel[:, None, None]
+    if not parts:
+        return R
+    vol = np.einsum("ij,ecj->eci", Mi, rvol) / Jel[:, None, None]
+    return R, np.abs(vol) + np.abs(R - vol)

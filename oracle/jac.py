@@ -12,9 +12,11 @@ import numpy as np
 from . import dg
 
 
-def jvp_complex(mesh, P, u, v, t=0.0, h=1e-30):
+def jvp_complex(mesh, P, u, v, t=0.0, h=1e-30, residual=None):
+    """residual: the residual function (dg.residual, the collocated one, by default)"""
+    residual = dg.residual if residual is None else residual
     uc = u.astype(np.complex128) + 1j * h * v
-    return np.imag(dg.residual(mesh, P, uc, t)) / h
+    return np.imag(residual(mesh, P, uc, t)) / h
 
 
 def jvp_parts(mesh, P, u, v, t=0.0, h=1e-30):
@@ -41,11 +43,11 @@ def jvp_fd(mesh, P, u, v, t=0.0, eps=None, central=False):
     return (dg.residual(mesh, P, u + eps * v, t) - dg.residual(mesh, P, u, t)) / eps
 
 
-def dense_jacobian(mesh, P, u, t=0.0):
+def dense_jacobian(mesh, P, u, t=0.0, residual=None):
     n = u.size
     Jm = np.zeros((n, n))
     for j in range(n):
         e = np.zeros(n)
         e[j] = 1.0
-        Jm[:, j] = jvp_complex(mesh, P, u, e.reshape(u.shape), t).ravel()
+        Jm[:, j] = jvp_complex(mesh, P, u, e.reshape(u.shape), t, residual=residual).ravel()
     return Jm

@@ -76,9 +76,11 @@ def modal_filter(mesh, u, sigma):
     return v.reshape(u.shape)
 
 
-def implicit_step_dense(mesh, P, u, t, dt, scheme=33, rtol=1e-13, guesses=None, filter_rate=0.0):
+def implicit_step_dense(mesh, P, u, t, dt, scheme=33, rtol=1e-13, guesses=None, filter_rate=0.0, residual=None):
     """one DIRK step with every stage solved by dense Newton, then the optional modal
-    filter. Returns (u_new, stages)."""
+    filter. residual: the spatial residual (dg.residual, collocated, by default).
+    Returns (u_new, stages)."""
+    residual = dg.residual if residual is None else residual
     A, b, c = dirk_tableau(scheme)
     s = len(c)
     Rs, Us = [], []
@@ -86,13 +88,13 @@ def implicit_step_dense(mesh, P, u, t, dt, scheme=33, rtol=1e-13, guesses=None, 
         ti = t + c[i] * dt
         bi = u + dt * sum(A[i, j] * Rs[j] for j in range(i))
         aii = A[i, i]
-        G = lambda U: U - dt * aii * dg.residual(mesh, P, U, ti) - bi
-        Jf = lambda U: np.eye(U.size) - dt * aii * jac.dense_jacobian(mesh, P, U, ti)
+        G = lambda U: U - dt * aii * residual(mesh, P, U, ti) - bi
+        Jf = lambda U: np.eye(U.size) - dt * aii * jac.dense_jacobian(mesh, P, U, ti, residual=residual)
         ref = np.linalg.norm(G(u))
         U0 = u if guesses is None else guesses[i]
         Ui, _, _ = newton_dense(G, Jf, U0, ref, rtol)
         Us.append(Ui)
-        Rs.append(dg.residual(mesh, P, Ui, ti))
+        Rs.append(residual(mesh, P, Ui, ti))
     un = modal_filter(mesh, Us[-1], np.exp(-filter_rate * dt)) if filter_rate > 0 else Us[-1]
     return un, Us
 
