@@ -402,30 +402,45 @@ void free_workspace(dg_mesh_s* m) {
   m->ws = nullptr;
 }
 
+// the Krylov part of the workspace (basis, work vectors, reduced-basis window): stored in
+// the J v precision, so re-allocated when the precision or the basis size changes
+static void free_krylov(Workspace* w) {
+  for (void* p : {w->V, w->w, w->z, w->s, w->rbW, w->rbZ, w->rbT})
+    if (p) (void)hipFree(p);
+  w->V = w->w = w->z = w->s = w->rbW = w->rbZ = w->rbT = nullptr;
+  w->rb_cap = w->rb_count = w->rb_head = 0;
+}
+
 static dg_status_t ensure_workspace(dg_mesh_s* m, int mk, bool f32) {
   Workspace* w = m->ws;
   if (w && w->m == mk && w->f32 == f32) return DG_OK;
-  // keep the stage history across a re-allocation of the Krylov part
-  free_workspace(m);
-  w = new Workspace();
-  m->ws = w;
   const int64_t n = m->n_dof;
-  w->n = n;
-  w->m = mk;
-  w->f32 = f32;
   const size_t vb = f32 ? sizeof(float) : sizeof(double);
-  double** dbl[] = {&w->un, &w->U, &w->G, &w->B, &w->X, &w->Rc, &w->Rs[0], &w->Rs[1], &w->Rs[2], &w->hist[0],
-                    &w->hist[1], &w->Up};
-  for (double** p : dbl)
-    if (hipMalloc(p, n * sizeof(double)) != hipSuccess) goto fail;
-  if (m->kind == DG_MESH_SHELL && hipMalloc(&w->Binv, n * 5 * sizeof(double)) != hipSuccess) goto fail;
+  if (w) {
+    // a change of J v precision or basis size: the FP64 stage vectors, the guess history and
+    // the preconditioner stay; only the Krylov part is re-allocated
+    free_krylov(w);
+    w->m = mk;
+    w->f32 = f32;
+  } else {
+    w = new Workspace();
+    m->ws = w;
+    w->n = n;
+    w->m = mk;
+    w->f32 = f32;
+    double** dbl[] = {&w->un, &w->U, &w->G, &w->B, &w->X, &w->Rc, &w->Rs[0], &w->Rs[1], &w->Rs[2], &w->hist[0],
+                      &w->hist[1], &w->Up};
+    for (double** p : dbl)
+      if (hipMalloc(p, n * sizeof(double)) != hipSuccess) goto fail;
+    if (m->kind == DG_MESH_SHELL && hipMalloc(&w->Binv, n * 5 * sizeof(double)) != hipSuccess) goto fail;
+    if (hipMalloc(&w->part, (size_t)RED_BLOCKS * KMAX * sizeof(double)) != hipSuccess) goto fail;
+    if (hipMalloc(&w->dev_small, 4 * KMAX * sizeof(double)) != hipSuccess) goto fail;
+    if (hipHostMalloc(&w->host_small, 4 * KMAX * sizeof(double)) != hipSuccess) goto fail;
+  }
   if (hipMalloc(&w->V, (size_t)(mk + 1) * n * vb) != hipSuccess) goto fail;
   if (hipMalloc(&w->w, n * vb) != hipSuccess || hipMalloc(&w->z, n * vb) != hipSuccess ||
       hipMalloc(&w->s, n * vb) != hipSuccess)
     goto fail;
-  if (hipMalloc(&w->part, (size_t)RED_BLOCKS * KMAX * sizeof(double)) != hipSuccess) goto fail;
-  if (hipMalloc(&w->dev_small, 4 * KMAX * sizeof(double)) != hipSuccess) goto fail;
-  if (hipHostMalloc(&w->host_small, 4 * KMAX * sizeof(double)) != hipSuccess) goto fail;
   return DG_OK;
 fail:
   free_workspace(m);
@@ -977,6 +992,8 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
     }
     DG_HIP_CHECK(hipMemcpyAsync(ws->Up, ws->U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     // learned guess: the network's correction of the plain guess, kept only if it lowers |G|
+    bool have_G = false;
+    double g2_guess = 0;
     if (o.guess == 1 && m->ws_mlp && have_hist) {
       const int N = m->N, nin = 15 * N, nout = 5 * N;
       const int64_t E = m->n_elem;
@@ -1017,17 +1034,24 @@ static dg_status_t step_impl(dg_mesh_s* m, double t, double dt, double* u, const
       if (!(gl2 < gp2)) {
         DG_HIP_CHECK(hipMemcpyAsync(ws->U, ws->Up, n * sizeof(double), hipMemcpyDeviceToDevice, s));
         stats.fallback[i] = 1;
+      } else {
+        have_G = true;     // G and R of the accepted guess are in ws->G and ws->Rc
+        g2_guess = gl2;
       }
     }
     int newton = 0, gm_total = 0, halvings = 0;
     double nG = 0, prev = 0, alpha = 1.0, eta = 0.1;
     for (;;) {
-      rc = residual(m, ti, ws->U, ws->Rc, s);
-      if (rc != DG_OK) return rc;
-      k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->U, ws->Rc, ca, ws->B, ws->G, ws->part);
       double g2;
-      rc = finish_norm2(ws, nb, s, &g2);
-      if (rc != DG_OK) return rc;
+      if (newton == 0 && have_G) {
+        g2 = g2_guess;
+      } else {
+        rc = residual(m, ti, ws->U, ws->Rc, s);
+        if (rc != DG_OK) return rc;
+        k_stage_residual<<<nb, RED_THREADS, 0, s>>>(n, ws->U, ws->Rc, ca, ws->B, ws->G, ws->part);
+        rc = finish_norm2(ws, nb, s, &g2);
+        if (rc != DG_OK) return rc;
+      }
       nG = std::sqrt(g2);
       if (newton == 0) stats.res0[i] = nG;
       // backtracking: a Newton update that leaves a non-finite or larger residual is halved
@@ -1140,8 +1164,16 @@ dg_status_t implicit_step(dg_mesh_s* m, double t, double dt, double* u, const dg
   }
   m->krylov_bf16 = (o.jvp_prec == DG_BF16);
   m->krylov_fd = (o.jvp_prec == DG_F64_FD);
-  if (o.jvp_prec == DG_F32 || o.jvp_prec == DG_BF16) return step_impl<float>(m, t, dt, u, o, st, s);
-  return step_impl<double>(m, t, dt, u, o, st, s);
+  const dg_status_t rc = (o.jvp_prec == DG_F32 || o.jvp_prec == DG_BF16) ? step_impl<float>(m, t, dt, u, o, st, s)
+                                                                         : step_impl<double>(m, t, dt, u, o, st, s);
+  if (rc != DG_OK && m->ws) {
+    // a failed step leaves u unchanged: the next one starts a new guess history and
+    // reduced-basis window (nothing from the failed attempt is reused)
+    m->ws->hist_n = 0;
+    m->ws->rb_count = m->ws->rb_head = 0;
+    m->ws->t_end = NAN;
+  }
+  return rc;
 }
 
 }  // namespace dg
