@@ -338,6 +338,17 @@ dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_hos
  *   preconditioner's factors (double, float, bfloat16) read by its substitution, whatever
  *   the J v precision; the substitution computes in the precision of the Krylov vectors.
  *   Like line_pc_every it changes iteration counts, not the converged step.
+ *   "columns_jac_every" >= 1 (default 32): dg_columns_integrate factors each column's chord
+ *   Jacobian I - dt a_ii J (shared by the SDIRK stages) at the start of every this many
+ *   steps instead of every step, and sooner after a step whose stages needed more than 3
+ *   iterations or within a stage whose iteration reduced |G| less than twofold. It changes
+ *   iteration counts, not what each stage converges to (within newton_rtol).
+ *   "column_quadrature" 0 (default) or 1, column meshes only: 0 evaluates eq. (DGformulation)
+ *   with the collocated GLL rule (diagonal mass); 1 integrates the volume terms of both LDG
+ *   equations with p + 2 Gauss points and the exact mass matrix (over-integration; the traces,
+ *   numerical fluxes and boundary treatment unchanged). It changes R, J v, dg_implicit_step and
+ *   dg_columns_integrate of the mesh; the linearised operator of the collocated residual has
+ *   growing intra-element modes that the over-integrated one does not have.
  * Returns DG_ERR_ARG for an unknown name or value. */
 dg_status_t dg_set_option(dg_mesh_t mesh, const char* name, int64_t value);
 

@@ -156,7 +156,7 @@ static void free_mesh(dg_mesh_s* m) {
                   m->d_prev, m->d_next,   m->d_geo,   m->d_col,       m->d_cpar,      m->d_fn64,
                   m->d_fn32, m->d_plist[0], m->d_plist[1], m->d_plist[2], m->d_bstate, m->d_coloff,
                   m->d_cols_ws, m->ws_norm, m->ws_X, m->ws_Y, m->d_bf16op, m->d_euv, m->d_euv_cols,
-                  m->d_fd};
+                  m->d_fd, m->d_quad};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   free_workspace(m);
@@ -229,6 +229,14 @@ dg_status_t dg_set_option(dg_mesh_t m, const char* name, int64_t value) {
   }
   if (std::strcmp(name, "line_solve_config") == 0 && value >= -1 && value <= 5) {
     m->tune_lsolve = (int)value;
+    return DG_OK;
+  }
+  if (std::strcmp(name, "column_quadrature") == 0 && (value == 0 || value == 1) && m->kind == DG_MESH_COLUMNS) {
+    m->col_quad = (int)value;
+    return DG_OK;
+  }
+  if (std::strcmp(name, "columns_jac_every") == 0 && value >= 1 && value <= 1000000) {
+    m->cols_jac_every = (int)value;
     return DG_OK;
   }
   if (std::strcmp(name, "line_pc_precision") == 0 && (value == 64 || value == 32 || value == 16)) {

@@ -165,14 +165,165 @@ __device__ __forceinline__ void col_elem_pass1(const ColElem& ce, const PhysC& P
     for (int i = 0; i < n; ++i) R[off + c * n + i] = outc(Rl[c][i]);
 }
 
-template <int P, class S, int XP, class SU, class TV, class OT>
-__device__ __forceinline__ void col_elem_pass2(const ColElem& ce, const PhysC& Pc, const GllC& gc, const SU* __restrict__ u,
-                                      const TV* __restrict__ v, const OT* __restrict__ Fn, OT* __restrict__ R) {
+// The over-integrated variant of pass 1 (mesh option "column_quadrature" 1): the weak form of
+// eq. (DGformulation) with the volume integrals taken by nq = p + 2 Gauss points and the exact
+// mass matrix,
+//   J M q = M D u + e_end (u_hat - u) n                      (u is polynomial: exact)
+//   J M R = sum_g w_g [F(u_g, q_g) l'(x_g) + J s(u_g, q_g) l(x_g)] - e_end F_hat.n
+// so every face term reaches all nodes through the columns of M^-1. The traces sent to the
+// neighbours (F.n of this side at the end nodes) and the boundary fluxes are those of the
+// collocated pass.
+template <int P, class S, int XP = 0, class SU, class TV, class OT>
+__device__ __forceinline__ void col_elem_pass1_oi(const ColElem& ce, const PhysC& Pc, const GllC& gc, const QuadC& qc,
+                                                  double t, const SU* __restrict__ u, const TV* __restrict__ v,
+                                                  OT* __restrict__ R, OT* __restrict__ Fn) {
+  typedef typename Base<S>::type T;
+  constexpr int n = P + 1, nq = P + 2;
+  const double* D = gc.D;
+  const int64_t off = ce.off;
+  const double r0 = ce.r0, h = ce.h;
+  const double Jac = 0.5 * h, invJ = 1.0 / Jac;
+  const bool hp = ce.off_prev >= 0, hn = ce.off_next >= 0;
+  const int64_t e = ce.fslot;
+  S uu[3][n];
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < n; ++i) uu[c][i] = Io<S>::ld(u, v, off + c * n + i);
+  S dlo[3], dhi[3];
+  {
+    S u0[3], ub[3];
+    for (int c = 0; c < 3; ++c) u0[c] = uu[c][0];
+    if (hp) {
+      for (int c = 0; c < 3; ++c) dlo[c] = T(0.5) * (Io<S>::ld(u, v, ce.off_prev + c * n + (n - 1)) - u0[c]);
+    } else {
+      boundary_state<1, S>(Pc, u0, ub);
+      for (int c = 0; c < 3; ++c) dlo[c] = ub[c] - u0[c];
+    }
+    for (int c = 0; c < 3; ++c) u0[c] = uu[c][n - 1];
+    if (hn) {
+      for (int c = 0; c < 3; ++c) dhi[c] = T(0.5) * (Io<S>::ld(u, v, ce.off_next + c * n) - u0[c]);
+    } else if (Pc.bc_mode == 1) {
+      boundary_state<1, S>(Pc, u0, ub);
+      for (int c = 0; c < 3; ++c) dhi[c] = ub[c] - u0[c];
+    } else {
+      for (int c = 0; c < 3; ++c) dhi[c] = S(T(0));
+    }
+  }
+  // gradient at the nodes: D u / J plus the lifts of both faces through M^-1
+  S qq[3][n];
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < n; ++i) {
+      S g = S(T(0));
+      for (int l = 0; l < n; ++l) g = g + uu[c][l] * T(D[i * n + l]);
+      g = g + dhi[c] * T(qc.Mi[i * n + (n - 1)]) - dlo[c] * T(qc.Mi[i * n]);
+      qq[c][i] = g * T(invJ);
+    }
+  // volume and source integrals at the Gauss points
+  S rr[3][n];
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < n; ++i) rr[c][i] = S(T(0));
+  // the Gauss loop stays rolled: fully unrolled, the dual-number (FP64 J v) instantiation at
+  // p = 3 returned non-finite values on gfx950 while the same source built for the host and the
+  // p = 2 and p = 4 instantiations were exact; rolled it matches the oracle's complex step
+#pragma unroll 1
+  for (int gq = 0; gq < nq; ++gq) {
+    S ug[3], qg[3][1], Fg[3][1], Sg[3];
+    for (int c = 0; c < 3; ++c) {
+      S a = S(T(0)), b = S(T(0));
+      for (int j = 0; j < n; ++j) {
+        a = a + uu[c][j] * T(qc.V[gq * n + j]);
+        b = b + qq[c][j] * T(qc.V[gq * n + j]);
+      }
+      ug[c] = a;
+      qg[c][0] = b;
+    }
+    const double x = r0 + 0.5 * (qc.x[gq] + 1.0) * h;
+    const double Q = heating<1>(Pc, &x, t);
+    flux_source<1, S, XP>(Pc, ug, qg, &x, Q, Fg, Sg);
+    for (int c = 0; c < 3; ++c)
+      for (int i = 0; i < n; ++i)
+        rr[c][i] = rr[c][i] + Fg[c][0] * T(qc.w[gq] * qc.Dg[gq * n + i]) + Sg[c] * T(qc.w[gq] * Jac * qc.V[gq * n + i]);
+  }
+  // face terms: -F_hat.n at the end node of each face (projected below)
+  S flo[3], fhi[3];
+  {
+    S u0[3], q0[3][1], F0[3][1];
+    for (int c = 0; c < 3; ++c) {
+      u0[c] = uu[c][0];
+      q0[c][0] = qq[c][0];
+    }
+    const double x = r0;
+    if (hp) {
+      // own half of the central flux; the trace F.n (n = -1) goes to the neighbour
+      S S0[3];
+      flux_source<1, S, XP & kXpComp>(Pc, u0, q0, &x, 0.0, F0, S0, false);
+      for (int c = 0; c < 3; ++c) {
+        const S fsn = -F0[c][0];
+        flo[c] = -T(0.5) * fsn;
+        Fn[(e * 2 + 0) * 3 + c] = outc(fsn);
+      }
+    } else {
+      S ub[3], Sb[3], sm, se;
+      boundary_state<1, S>(Pc, u0, ub);
+      flux_source<1, S, XP & kXpComp>(Pc, ub, q0, &x, 0.0, F0, Sb, false);
+      sigma<1, S, XP & kXpComp>(Pc, ub, sm, se, x);
+      for (int c = 0; c < 3; ++c) {
+        const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
+        flo[c] = F0[c][0] - sg * (u0[c] - ub[c]);        // -F_hat.n, n = -1
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      u0[c] = uu[c][n - 1];
+      q0[c][0] = qq[c][n - 1];
+    }
+    const double x1 = r0 + h;
+    if (hn) {
+      S S0[3];
+      flux_source<1, S, XP & kXpComp>(Pc, u0, q0, &x1, 0.0, F0, S0, false);
+      for (int c = 0; c < 3; ++c) {
+        const S fsn = F0[c][0];
+        fhi[c] = -T(0.5) * fsn;
+        Fn[(e * 2 + 1) * 3 + c] = outc(fsn);
+      }
+    } else if (Pc.bc_mode == 1) {
+      S ub[3], Sb[3], sm, se;
+      boundary_state<1, S>(Pc, u0, ub);
+      flux_source<1, S, XP & kXpComp>(Pc, ub, q0, &x1, 0.0, F0, Sb, false);
+      sigma<1, S, XP & kXpComp>(Pc, ub, sm, se, x1);
+      for (int c = 0; c < 3; ++c) {
+        const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
+        fhi[c] = -(F0[c][0] + sg * (u0[c] - ub[c]));
+      }
+    } else {
+      // adiabatic, zero normal stress, open, with the penalty lambda U on the momentum
+      flux_inviscid<1, S, XP & kXpComp>(Pc, u0, F0, x1);
+      for (int c = 0; c < 3; ++c) fhi[c] = -F0[c][0];
+      fhi[1] = fhi[1] - T(Pc.lam) * u0[1];
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    rr[c][0] = rr[c][0] + flo[c];
+    rr[c][n - 1] = rr[c][n - 1] + fhi[c];
+  }
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < n; ++i) {
+      S r = S(T(0));
+      for (int j = 0; j < n; ++j) r = r + rr[c][j] * T(qc.Mi[i * n + j]);
+      R[off + c * n + i] = outc(r * T(invJ));
+    }
+}
+
+// OI: the face term reaches every node through the column of M^-1 of its end node (the
+// over-integrated residual); otherwise the end node alone, with the collocated 1/(w_end J)
+template <int P, class S, int XP, bool OI = false, class SU, class TV, class OT>
+__device__ __forceinline__ void col_elem_pass2(const ColElem& ce, const PhysC& Pc, const GllC& gc, const QuadC& qc,
+                                               const SU* __restrict__ u, const TV* __restrict__ v,
+                                               const OT* __restrict__ Fn, OT* __restrict__ R) {
   typedef typename Base<S>::type T;
   constexpr int n = P + 1;
   const double w_end = gc.w[0];
   const int64_t off = ce.off;
   const double lfac = 1.0 / (w_end * 0.5 * ce.h);
+  const double invJ = 1.0 / (0.5 * ce.h);
   for (int side = 0; side < 2; ++side) {
     const int64_t o2 = side ? ce.off_next : ce.off_prev;
     if (o2 < 0) continue;
@@ -189,7 +340,12 @@ __device__ __forceinline__ void col_elem_pass2(const ColElem& ce, const PhysC& P
     for (int c = 0; c < 3; ++c) {
       const S sg = (c == 0) ? S(T(Pc.lam)) : (c == 2 ? se : sm);
       const OT fnb = Fn[(nb * 2 + (1 - side)) * 3 + c];
-      R[off + c * n + i] += OT(lfac) * (OT(0.5) * fnb - outc(sg * (ui[c] - uh[c])));
+      const OT term = OT(0.5) * fnb - outc(sg * (ui[c] - uh[c]));
+      if constexpr (OI) {
+        for (int r = 0; r < n; ++r) R[off + c * n + r] += OT(qc.Mi[r * n + i] * invJ) * term;
+      } else {
+        R[off + c * n + i] += OT(lfac) * term;
+      }
     }
   }
 }
@@ -208,24 +364,27 @@ __device__ inline ColElem col_elem_of(const ColDev& C, int e) {
   return ce;
 }
 
-template <int P, class S, class SU, class TV, class OT, int XP = 0>
+template <int P, class S, class SU, class TV, class OT, int XP = 0, bool OI = false>
 __global__ __launch_bounds__(128) void col_pass1(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
-                                                 double t, const SU* __restrict__ u, const TV* __restrict__ v,
-                                                 OT* __restrict__ R, OT* __restrict__ Fn) {
+                                                 QuadC qc, double t, const SU* __restrict__ u,
+                                                 const TV* __restrict__ v, OT* __restrict__ R, OT* __restrict__ Fn) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ne) return;
   const int e = elist[idx];
-  col_elem_pass1<P, S, XP>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, t, u, v, R, Fn);
+  if constexpr (OI)
+    col_elem_pass1_oi<P, S, XP>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, qc, t, u, v, R, Fn);
+  else
+    col_elem_pass1<P, S, XP>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, t, u, v, R, Fn);
 }
 
-template <int P, class S, class SU, class TV, class OT, int XP = 0>
+template <int P, class S, class SU, class TV, class OT, int XP = 0, bool OI = false>
 __global__ __launch_bounds__(128) void col_pass2(ColDev C, const int* __restrict__ elist, int ne, PhysC ph, GllC gc,
-                                                 const SU* __restrict__ u, const TV* __restrict__ v,
+                                                 QuadC qc, const SU* __restrict__ u, const TV* __restrict__ v,
                                                  const OT* __restrict__ Fn, OT* __restrict__ R) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ne) return;
   const int e = elist[idx];
-  col_elem_pass2<P, S, XP>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, u, v, Fn, R);
+  col_elem_pass2<P, S, XP, OI>(col_elem_of(C, e), column_phys(C, ph, C.col[e]), gc, qc, u, v, Fn, R);
 }
 
 template <class S, class SU, class TV, class OT>
@@ -234,6 +393,8 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
   ColDev C = m->cols();
   ProfScope ps(m, prof_base, s);
   const GllC gc[3] = {make_gllc(2), make_gllc(3), make_gllc(4)};
+  const QuadC qc[3] = {make_quadc(2), make_quadc(3), make_quadc(4)};
+  const bool oi = m->col_quad == 1;
   PhysC ph = m->phys;
   sun_direction(ph, t);
   for (int pi = 0; pi < 3; ++pi) {
@@ -241,17 +402,24 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
     if (!ne) continue;
     const int blocks = (ne + 127) / 128;
     const int* el = m->d_plist[pi];
-#define DG_COL_P1(P_, G_)                                                                                  \
-  if (ph.xp_mode() == (kXpEuv | kXpComp))                                                                 \
-    col_pass1<P_, S, SU, TV, OT, kXpEuv | kXpComp><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn); \
+#define DG_COL_P1(P_, G_, Q_)                                                                              \
+  if (oi) {                                                                                               \
+    if (ph.xp_mode() == (kXpEuv | kXpComp))                                                               \
+      col_pass1<P_, S, SU, TV, OT, kXpEuv | kXpComp, true><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, t, u, v, out, fn); \
+    else if (ph.xp_mode() == kXpEuv)                                                                      \
+      col_pass1<P_, S, SU, TV, OT, kXpEuv, true><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, t, u, v, out, fn); \
+    else                                                                                                  \
+      col_pass1<P_, S, SU, TV, OT, 0, true><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, t, u, v, out, fn); \
+  } else if (ph.xp_mode() == (kXpEuv | kXpComp))                                                          \
+    col_pass1<P_, S, SU, TV, OT, kXpEuv | kXpComp><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, t, u, v, out, fn); \
   else if (ph.xp_mode() == kXpEuv)                                                                        \
-    col_pass1<P_, S, SU, TV, OT, kXpEuv><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn);      \
+    col_pass1<P_, S, SU, TV, OT, kXpEuv><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, t, u, v, out, fn);  \
   else                                                                                                    \
-    col_pass1<P_, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, t, u, v, out, fn);
+    col_pass1<P_, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, t, u, v, out, fn);
     switch (pi + 2) {
-      case 2: DG_COL_P1(2, gc[0]); break;
-      case 3: DG_COL_P1(3, gc[1]); break;
-      default: DG_COL_P1(4, gc[2]); break;
+      case 2: DG_COL_P1(2, gc[0], qc[0]); break;
+      case 3: DG_COL_P1(3, gc[1], qc[1]); break;
+      default: DG_COL_P1(4, gc[2], qc[2]); break;
     }
 #undef DG_COL_P1
   }
@@ -260,15 +428,20 @@ static dg_status_t launch_cols(dg_mesh_s* m, double t, const SU* u, const TV* v,
     if (!ne) continue;
     const int blocks = (ne + 127) / 128;
     const int* el = m->d_plist[pi];
-#define DG_COL_P2(P_, G_)                                                                                  \
-  if (ph.comp)                                                                                            \
-    col_pass2<P_, S, SU, TV, OT, kXpComp><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, u, v, fn, out);           \
+#define DG_COL_P2(P_, G_, Q_)                                                                              \
+  if (oi) {                                                                                               \
+    if (ph.comp)                                                                                          \
+      col_pass2<P_, S, SU, TV, OT, kXpComp, true><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, u, v, fn, out); \
+    else                                                                                                  \
+      col_pass2<P_, S, SU, TV, OT, 0, true><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, u, v, fn, out);   \
+  } else if (ph.comp)                                                                                     \
+    col_pass2<P_, S, SU, TV, OT, kXpComp><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, u, v, fn, out);       \
   else                                                                                                    \
-    col_pass2<P_, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, u, v, fn, out);
+    col_pass2<P_, S, SU, TV, OT><<<blocks, 128, 0, s>>>(C, el, ne, ph, G_, Q_, u, v, fn, out);
     switch (pi + 2) {
-      case 2: DG_COL_P2(2, gc[0]); break;
-      case 3: DG_COL_P2(3, gc[1]); break;
-      default: DG_COL_P2(4, gc[2]); break;
+      case 2: DG_COL_P2(2, gc[0], qc[0]); break;
+      case 3: DG_COL_P2(3, gc[1], qc[1]); break;
+      default: DG_COL_P2(4, gc[2], qc[2]); break;
     }
 #undef DG_COL_P2
   }
@@ -367,6 +540,8 @@ struct ColBatch {
   int* jac_builds;
   int filter;          // 1: modal filter after every step
   FiltC filt[3];       // for p = 2, 3, 4
+  int jac_every;       // the chord Jacobian is rebuilt at the start of every jac_every-th step
+  const QuadC* quad;   // Gauss tables of degrees 2, 3, 4 (over-integrated residual)
 };
 
 __device__ inline double wave_allsum(double x) {
@@ -374,11 +549,12 @@ __device__ inline double wave_allsum(double x) {
   return x;
 }
 
-template <int P, class S, class TV, class OT, int XP>
+template <int P, class S, class TV, class OT, int XP, bool OI>
 __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                               const double* u, const TV* v, OT* out, OT* fn) {
   constexpr int b = 3 * (P + 1);
   const int lane = threadIdx.x;
+  const QuadC& qc = B.quad[P - 2];
   for (int el = lane; el < E; el += 64) {
     ColElem ce;
     ce.off = (int64_t)el * b;
@@ -389,7 +565,10 @@ __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, 
     ce.fslot = el;
     ce.fslot_prev = el - 1;
     ce.fslot_next = el + 1;
-    col_elem_pass1<P, S, XP>(ce, Pc, gc, t, u, v, out, fn);
+    if constexpr (OI)
+      col_elem_pass1_oi<P, S, XP>(ce, Pc, gc, qc, t, u, v, out, fn);
+    else
+      col_elem_pass1<P, S, XP>(ce, Pc, gc, t, u, v, out, fn);
   }
   __syncthreads();
   for (int el = lane; el < E; el += 64) {
@@ -402,7 +581,7 @@ __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, 
     ce.fslot = el;
     ce.fslot_prev = el - 1;
     ce.fslot_next = el + 1;
-    col_elem_pass2<P, S, XP>(ce, Pc, gc, u, v, fn, out);
+    col_elem_pass2<P, S, XP, OI>(ce, Pc, gc, qc, u, v, fn, out);
   }
   __syncthreads();
 }
@@ -464,7 +643,13 @@ __device__ __forceinline__ void colw_invert(double* blk, double (*M)[2 * b], dou
   __syncthreads();
 }
 
-template <int P, int XP>
+// Probing: elements of one colour are perturbed together. The collocated residual of an
+// element depends on its own and its two neighbours' states (3 colours separate them); the
+// over-integrated one also on the states two elements away (its neighbours' gradients take
+// their far faces' traces through M^-1), so 5 colours keep every response apart and the
+// couplings two elements away, outside the stored block-tridiagonal part, are dropped: the
+// chord iteration then runs on an approximate Jacobian (its converged stages are unchanged).
+template <int P, int XP, bool OI>
 __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                                       double ca, const double* U, double* V, double* Jv, double* fnT, double* Lo,
                                       double* Di, double* Up) {
@@ -476,16 +661,17 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
   __shared__ double fac[b];
   __shared__ double tmp[bb];
   __shared__ int piv_s;
-  for (int kap = 0; kap < 3; ++kap)
+  constexpr int NCOL = OI ? 5 : 3;
+  for (int kap = 0; kap < NCOL; ++kap)
     for (int l = 0; l < b; ++l) {
-      for (int i = lane; i < nd; i += 64) V[i] = (((i / b) % 3 == kap) && (i % b == l)) ? 1.0 : 0.0;
+      for (int i = lane; i < nd; i += 64) V[i] = (((i / b) % NCOL == kap) && (i % b == l)) ? 1.0 : 0.0;
       __syncthreads();
-      colw_residual<P, Dual<double>, double, double, XP>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
+      colw_residual<P, Dual<double>, double, double, XP, OI>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
       for (int idx = lane; idx < E * b; idx += 64) {
         const int ep = idx / b, r = idx % b;
         for (int d = -1; d <= 1; ++d) {
           const int e = ep + d;
-          if (e < 0 || e >= E || e % 3 != kap) continue;
+          if (e < 0 || e >= E || e % NCOL != kap) continue;
           double* blk = (d == -1) ? Lo : (d == 0 ? Di : Up);
           blk[(int64_t)ep * bb + r * b + l] = (d == 0 && r == l ? 1.0 : 0.0) - ca * Jv[ep * b + r];
         }
@@ -563,7 +749,7 @@ __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double
   }
 }
 
-template <int P, int XP>
+template <int P, int XP, bool OI>
 __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC& ph, const GllC& gc) {
   constexpr int n = P + 1;
   constexpr int b = 3 * n;
@@ -596,12 +782,24 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   __syncthreads();
   const double ca = B.dt * B.A[0][0];
   int newton_total = 0, builds = 0, status = 0;
+  // Chord Newton: the factored stage operator I - dt a_ii J is shared by every SDIRK stage
+  // (a_ii is the same) and, with jac_every > 1, by several steps. It is rebuilt at the start
+  // of every jac_every-th step, after a step in which a stage needed more than 3 iterations,
+  // and within a stage when an iteration reduces |G| less than twofold or 12 iterations have
+  // passed since the last build. The iteration path changes, not the converged stages.
+  int since_build = 0;
+  bool stale = true;
   for (int step = 0; step < B.n_steps && status == 0; ++step) {
     const double t = B.t0 + step * B.dt;
     // chord Jacobian at the start of the step (a sited column follows the Sun's direction)
-    if (sited) sun_direction_dev(Pc, t + B.c[0] * B.dt);
-    colw_build_and_factor<P, XP>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
-    ++builds;
+    if (stale || step % B.jac_every == 0) {
+      if (sited) sun_direction_dev(Pc, t + B.c[0] * B.dt);
+      colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
+      ++builds;
+      since_build = 0;
+      stale = false;
+    }
+    int max_stage_its = 0;
     for (int i = lane; i < nd; i += 64) U[i] = un[i];
     __syncthreads();
     for (int s = 0; s < B.n_stages && status == 0; ++s) {
@@ -613,11 +811,13 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
         Bv[i] = bv;
       }
       __syncthreads();
-      colw_residual<P, double, double, double, XP>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
+      colw_residual<P, double, double, double, XP, OI>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
       const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, G));
-      int it = 0, since_build = 0;
+      int it = 0;
+      double prev = 0.0;
+      if (B.jac_every == 1) since_build = 0;   // (a fresh Jacobian every step: counted per stage)
       for (;;) {
-        colw_residual<P, double, double, double, XP>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
+        colw_residual<P, double, double, double, XP, OI>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
         const double nG = sqrt(colw_stage_residual(nd, U, Rc, ca, Bv, G));
         if (!isfinite(nG)) {
           status = 5;
@@ -628,8 +828,8 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
           status = 4;
           break;
         }
-        if (since_build >= 6) {
-          colw_build_and_factor<P, XP>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
+        if (since_build >= 12 || (it > 0 && B.jac_every > 1 && nG > 0.5 * prev) || (B.jac_every == 1 && since_build >= 6)) {
+          colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
           ++builds;
           since_build = 0;
         }
@@ -638,13 +838,16 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
         colw_solve<P>(E, Lo, Di, Up, X);
         for (int i = lane; i < nd; i += 64) U[i] += X[i];
         __syncthreads();
+        prev = nG;
         ++it;
         ++since_build;
       }
       newton_total += it;
+      max_stage_its = max(max_stage_its, it);
       for (int i = lane; i < nd; i += 64) Rs[s * md + i] = Rc[i];
       __syncthreads();
     }
+    if (max_stage_its > 3) stale = true;
     if (status == 0) {
       for (int i = lane; i < nd; i += 64) un[i] = U[i];
       __syncthreads();
@@ -677,7 +880,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
 
 // two waves per SIMD: 256 registers and some scratch spills beat 512 registers at one wave
 // (5% on the 4096-column batch)
-template <int XP>
+template <int XP, bool OI>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_columns_persistent(ColBatch B, PhysC ph, GllC g2, GllC g3, GllC g4) {
   __shared__ int s_k;
   for (;;) {
@@ -688,9 +891,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (k >= B.n_col) break;
     const int col = B.order[k];
     switch (B.col_p[col]) {
-      case 2: colw_run<2, XP>(B, col, ph, g2); break;
-      case 3: colw_run<3, XP>(B, col, ph, g3); break;
-      default: colw_run<4, XP>(B, col, ph, g4); break;
+      case 2: colw_run<2, XP, OI>(B, col, ph, g2); break;
+      case 3: colw_run<3, XP, OI>(B, col, ph, g3); break;
+      default: colw_run<4, XP, OI>(B, col, ph, g4); break;
     }
   }
 }
@@ -762,6 +965,8 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   for (int pi = 0; pi < 3; ++pi) B.filt[pi] = make_filter(pi + 2, std::exp(-o.filter_rate * dt));
   B.ws = m->d_cols_ws;
   B.ws_stride = stride;
+  B.jac_every = m->cols_jac_every;
+  B.quad = m->d_quad;
   B.max_dof = (int)md;
   // DIRK tableau
   {
@@ -793,12 +998,20 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   sun_direction(ph, t0);
   {
     ProfScope ps(m, 13, s);
-    if (ph.xp_mode() == (kXpEuv | kXpComp))
-      k_columns_persistent<kXpEuv | kXpComp><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+    const GllC g2 = make_gllc(2), g3 = make_gllc(3), g4 = make_gllc(4);
+    if (m->col_quad == 1) {
+      if (ph.xp_mode() == (kXpEuv | kXpComp))
+        k_columns_persistent<kXpEuv | kXpComp, true><<<slots, 64, 0, s>>>(B, ph, g2, g3, g4);
+      else if (ph.xp_mode() == kXpEuv)
+        k_columns_persistent<kXpEuv, true><<<slots, 64, 0, s>>>(B, ph, g2, g3, g4);
+      else
+        k_columns_persistent<0, true><<<slots, 64, 0, s>>>(B, ph, g2, g3, g4);
+    } else if (ph.xp_mode() == (kXpEuv | kXpComp))
+      k_columns_persistent<kXpEuv | kXpComp, false><<<slots, 64, 0, s>>>(B, ph, g2, g3, g4);
     else if (ph.xp_mode() == kXpEuv)
-      k_columns_persistent<kXpEuv><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+      k_columns_persistent<kXpEuv, false><<<slots, 64, 0, s>>>(B, ph, g2, g3, g4);
     else
-      k_columns_persistent<0><<<slots, 64, 0, s>>>(B, ph, make_gllc(2), make_gllc(3), make_gllc(4));
+      k_columns_persistent<0, false><<<slots, 64, 0, s>>>(B, ph, g2, g3, g4);
   }
   DG_HIP_CHECK(hipGetLastError());
   DG_HIP_CHECK(hipStreamSynchronize(s));

@@ -40,6 +40,17 @@ struct GllC {
 };
 GllC make_gllc(int p);
 
+// Gauss quadrature of the over-integrated 1D residual: nq = p + 2 Gauss-Legendre points x, w
+// on [-1, 1], the nodal (GLL) basis there, V[g][j] = l_j(x_g), its derivative Dg[g][j] =
+// l_j'(x_g), and the inverse Mi of the exact reference mass matrix sum_g w_g l_i l_j
+struct QuadC {
+  int nq;
+  double x[6], w[6];
+  double V[30], Dg[30];   // [g * n + j]
+  double Mi[25];          // [i * n + j]
+};
+QuadC make_quadc(int p);
+
 // per-column parameters of a column mesh, CPAR per column: heat_amp, heat_qm, heat_rm,
 // 1 / heat_H, lam, alpha0c, site unit vector (3; zero: the Sun overhead)
 constexpr int CPAR = 9;
@@ -132,10 +143,13 @@ struct dg_mesh_s {
   // batched-column solver state (dg_columns_integrate)
   int* d_bstate = nullptr;               // [8][n_col] ints: E, p, first element, order, stats, counter
   int64_t* d_coloff = nullptr;
+  dg::QuadC* d_quad = nullptr;    // columns: Gauss tables of degrees 2, 3, 4 (over-integration)
+  int col_quad = 0;               // columns: 0 GLL collocation, 1 over-integrated (option "column_quadrature")
   double* d_cols_ws = nullptr;
   int64_t cols_ws_len = 0;
   int col_max_dof = 0;
   int tune_cols_grid = 2048;             // persistent wavefronts (dg_set_option "columns_grid")
+  int cols_jac_every = 32;               // chord Jacobian of the column batch rebuilt every this many steps
   int tune_p1 = 2;
   // learned warm start (dg_warmstart_set / dg_warmstart_record)
   struct dg_mlp_s* ws_mlp = nullptr;

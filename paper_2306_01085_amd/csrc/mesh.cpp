@@ -21,6 +21,7 @@
 #include <stdexcept>
 #include <tuple>
 #include <unordered_map>
+#include <utility>
 
 #include "internal.h"
 
@@ -97,6 +98,70 @@ GllC make_gllc(int p) {
     c.x[i] = g.x[i];
     c.w[i] = g.w[i];
   }
+  return c;
+}
+
+QuadC make_quadc(int p) {
+  Gll g = make_gll(p);
+  const int n = g.n, nq = p + 2;
+  QuadC c{};
+  c.nq = nq;
+  // Gauss-Legendre points: roots of P_nq by Newton from Chebyshev guesses; w = 2 / ((1 - x^2) P'^2)
+  for (int i = 0; i < nq; ++i) {
+    double x = -std::cos(M_PI * (i + 0.75) / (nq + 0.5)), dP = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double P0 = 1.0, P1 = x;
+      for (int k = 1; k < nq; ++k) {
+        const double P2 = ((2 * k + 1) * x * P1 - k * P0) / (k + 1);
+        P0 = P1;
+        P1 = P2;
+      }
+      dP = nq * (x * P1 - P0) / (x * x - 1.0);
+      const double dx = P1 / dP;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    c.x[i] = x;
+    c.w[i] = 2.0 / ((1.0 - x * x) * dP * dP);
+  }
+  // Lagrange basis of the GLL nodes at the Gauss points, and its derivative
+  for (int gq = 0; gq < nq; ++gq)
+    for (int j = 0; j < n; ++j) {
+      double l = 1.0;
+      for (int k = 0; k < n; ++k)
+        if (k != j) l *= (c.x[gq] - g.x[k]) / (g.x[j] - g.x[k]);
+      c.V[gq * n + j] = l;
+    }
+  for (int gq = 0; gq < nq; ++gq)
+    for (int j = 0; j < n; ++j) {
+      double s = 0;
+      for (int k = 0; k < n; ++k) s += c.V[gq * n + k] * g.D[k * n + j];
+      c.Dg[gq * n + j] = s;   // l_j' is a degree-p polynomial: interpolate its nodal values
+    }
+  // exact reference mass matrix and its inverse (Gauss-Jordan with partial pivoting)
+  double A[5][10] = {};
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0;
+      for (int gq = 0; gq < nq; ++gq) s += c.w[gq] * c.V[gq * n + i] * c.V[gq * n + j];
+      A[i][j] = s;
+      A[i][n + j] = (i == j) ? 1.0 : 0.0;
+    }
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(A[r][k]) > std::fabs(A[piv][k])) piv = r;
+    for (int col = 0; col < 2 * n; ++col) std::swap(A[k][col], A[piv][col]);
+    const double inv = 1.0 / A[k][k];
+    for (int col = 0; col < 2 * n; ++col) A[k][col] *= inv;
+    for (int r = 0; r < n; ++r)
+      if (r != k) {
+        const double f = A[r][k];
+        for (int col = 0; col < 2 * n; ++col) A[r][col] -= f * A[k][col];
+      }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) c.Mi[i * n + j] = A[i][n + j];
   return c;
 }
 
@@ -410,6 +475,10 @@ dg_status_t build_columns(dg_mesh_s* m, const dg_mesh_desc_t& d, const dg_physic
     }
   }
   m->fn_len = E * 2 * 3;
+  // Gauss tables of the over-integrated residual (degrees 2, 3, 4), read by the column batch
+  const QuadC qt[3] = {make_quadc(2), make_quadc(3), make_quadc(4)};
+  DG_HIP_CHECK(hipMalloc(&m->d_quad, sizeof(qt)));
+  DG_HIP_CHECK(hipMemcpy(m->d_quad, qt, sizeof(qt), hipMemcpyHostToDevice));
   return DG_OK;
 }
 
