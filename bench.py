@@ -133,11 +133,20 @@ def element_pass_roofline(fl1, b1, p1_ms, tr_bytes, tr_detail, counters):
 # WRITE_SIZE runs of `bench.py --only residual --copy-probe`, scaled as above, keyed by
 # workload and launch configuration, with the hash of the kernel sources they were taken
 # on (a changed kernel reports null until measured again)
+PASS1_PROFILE = "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_all-configs_counters.txt"
 PASS1_TRAFFIC = {
-    ("shell-p3", 2): {"src": "47ae2126dce6e4aa", "fetch_kib": 55082.9, "write_kib": 151680.0,
-                      "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_cfg2_counters.txt"},
-    ("shell-p3", 3): {"src": "47ae2126dce6e4aa", "fetch_kib": 63056.7, "write_kib": 151680.0,
-                      "profile": "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_cfg3_counters.txt"},
+    ("shell-p3", 0): {"src": "b084db721f47f190", "fetch_kib": 52088.7, "write_kib": 151680.0, "valu_insts": 4.29869e+07,
+                      "profile": PASS1_PROFILE},
+    ("shell-p3", 1): {"src": "b084db721f47f190", "fetch_kib": 48124.9, "write_kib": 151680.0, "valu_insts": 4.25368e+07,
+                      "profile": PASS1_PROFILE},
+    ("shell-p3", 2): {"src": "b084db721f47f190", "fetch_kib": 51358.3, "write_kib": 151680.0, "valu_insts": 4.30176e+07,
+                      "profile": PASS1_PROFILE},
+    ("shell-p3", 3): {"src": "b084db721f47f190", "fetch_kib": 79085.2, "write_kib": 200832.0, "valu_insts": 4.21267e+07,
+                      "profile": PASS1_PROFILE},
+    ("shell-p3", 4): {"src": "b084db721f47f190", "fetch_kib": 58364.7, "write_kib": 163968.0, "valu_insts": 4.25584e+07,
+                      "profile": PASS1_PROFILE},
+    ("shell-p3", 5): {"src": "b084db721f47f190", "fetch_kib": 198292.0, "write_kib": 318528.0, "valu_insts": 4.2331e+07,
+                      "profile": PASS1_PROFILE},
 }
 
 
@@ -497,12 +506,15 @@ def main():
     ap.add_argument("--workload", default="shell-p3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-p4", action="store_true", help="skip the implicit steps on the 92M-DOF p = 4 shell")
+    ap.add_argument("--preroll", type=float, default=0.3,
+                    help="seconds of the same work before each timed loop (0 for counter runs)")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the reduced warm-start experiment")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of known size (calibrates HBM counters)")
-    ap.add_argument("--only", default="all", choices=["all", "residual", "implicit", "columns"],
+    ap.add_argument("--only", default="all", choices=["all", "residual", "implicit", "columns", "mfma"],
                     help="residual: only the R(u) timing; implicit: only the implicit steps; columns: only "
-                         "the column batch (for counter runs)")
+                         "the column batch; mfma: only the two matrix-core kernels, the BF16 J v and the "
+                         "network's inference (for counter runs)")
     ap.add_argument("--implicit-runs", default="f64,f32,bf16,f32_rb4,f32_no_precond",
                     help="which implicit-step runs (with --only implicit)")
     ap.add_argument("--mode", default="default", choices=["default", "warmstart", "sweep"],
@@ -571,7 +583,8 @@ def main():
     jv32 = torch.empty_like(v32)
     t = 0.0
 
-    def timed(fn, steps, preroll_s=0.3):
+    def timed(fn, steps, preroll_s=None):
+        preroll_s = args.preroll if preroll_s is None else preroll_s
         # keep the GPU busy with the same work for preroll_s first: a timed region of a few
         # milliseconds right after lighter work catches the clock still rising (R read ~10%
         # slow over 20 evaluations after 3 warm-ups without it)
@@ -611,6 +624,12 @@ def main():
     f_jfd = lambda: mesh.jvp(u, v, t, "f64_fd", out=jvfd)
     jvb = torch.empty_like(v32) if w.p in (3, 4) else None
     f_jb = (lambda: mesh.jvp(u, v32, t, "bf16", out=jvb)) if w.p in (3, 4) else None
+    if args.only == "mfma":
+        jvb = torch.empty_like(v32)
+        ms_b = timed(lambda: mesh.jvp(u, v32, t, "bf16", out=jvb), args.steps)
+        net = network_rates(w, args.steps, args.warmup, timed)
+        print(json.dumps({"jvp_bf16_ms": ms_b, "jvp_bf16_gdofs": w.n_dof / ms_b / 1e6, "network": net}), flush=True)
+        return
     if args.only == "residual":
         # with --all-pass1-configs every element-pass launch configuration runs in turn (one
         # counter run then covers them all: their kernels have distinct template names)
