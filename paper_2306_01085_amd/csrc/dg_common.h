@@ -25,6 +25,17 @@ struct Dual {
 template <class S> struct Base { typedef S type; };
 template <class T> struct Base<Dual<T>> { typedef T type; };
 
+// Workgroup barrier that orders LDS only. __syncthreads also fences global memory at
+// workgroup scope, which makes every wave wait for all of its outstanding global stores
+// (and loads) before the barrier; where a barrier only hands LDS data between the lanes of a
+// block, this one waits for the LDS operations alone. Global stores issued before it stay in
+// flight across it.
+__device__ __attribute__((always_inline)) inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // 1/x for the nonzero normal divisors of the model (every one is positive: e^{-varrho/2},
 // T, radii, Jacobians, cos chi on the day side). FP64: the hardware reciprocal estimate
 // refined by two Newton steps, within about an ulp in five instructions where the IEEE

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
     const uint64_t* src = reinterpret_cast<const uint64_t*>(Fin + (int64_t)e * L);
     for (int w = j; w < W; w += TPE) s_tw[le][w] = src[w];
   }
-  __syncthreads();
+  lds_barrier();
   if (!upd) return;
   const OT* Fe = reinterpret_cast<const OT*>(&s_tw[le][0]);
   const int ja = a + n * b;

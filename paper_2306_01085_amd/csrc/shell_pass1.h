@@ -252,9 +252,16 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   constexpr int n = Sh::n, N = Sh::N, N2 = Sh::N2, TPE = Sh::TPE;
   static_assert(3 * N <= 6 * 5 * N2, "flux staging must fit in the trace buffer");
   __shared__ double s_ang[EPB][13][N2];
-  __shared__ S s_u[EPB][5][N];
-  __shared__ S s_f[EPB][6][5][N2];   // per face slot: u_hat - u; later the flux staging of phase E
-  __shared__ S s_z[EPB][5][5][N2];   // Z of the owned faces, in the order of their face index
+  // node (a, b, cz) of a field at a + n b + NS cz: the planes padded by PL so that the line
+  // reads of the gradient and divergence (16 distinct addresses per wavefront at p = 3) fall
+  // in different LDS banks for the a- and b-lines (without it, four planes share each bank)
+  constexpr int PL = (P == 3 && sizeof(S) == 8) ? 2 : 0;
+  constexpr int NS = N2 + PL, NP = NS * n;
+  __shared__ S s_u[EPB][5][NP];
+  // per face slot: u_hat - u (faces 0..5), then Z of the owned faces in the order of their face
+  // index (rows 6..10); phase E stages several fields' contravariant fluxes over the whole
+  __shared__ S s_fz[EPB][11][5][N2];
+  constexpr int kFzStride = 11 * 5 * N2;
   __shared__ int s_nb[EPB][6][N2];   // trace slot of the neighbour's matching face node
   __shared__ int s_cn[EPB][4][P + 3];  // angular connectivity: neighbour cell, its face, index map
   __shared__ double D[n * n];
@@ -279,11 +286,11 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   if (active)
     for (int c = 0; c < 5; ++c) {
       uu[c] = load_state<S>(u, v, base + c * N + j);
-      s_u[le][c][j] = uu[c];
+      s_u[le][c][j + PL * (j / N2)] = uu[c];
     }
   const double rk = live ? M.edges[k] : 0.0;
   const double hk = live ? M.edges[k + 1] - rk : 1.0;
-  __syncthreads();
+  lds_barrier();
   // owned interior faces (bit f): the neighbour has the larger element index
   int own = 0;
   if (live) {
@@ -316,7 +323,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         t_f[q] = f;
         t_m[q] = m;
         t_r[q] = r;
-        t_jo[q] = a + n * b + N2 * cz;
+        t_jo[q] = a + n * b + NS * cz;
         t_en[q] = en;
         if (en >= 0) {
           t_nb[q] = (en * 6 + fn) * 5 * N2 + mn;
@@ -344,7 +351,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       } else {
         for (int c = 0; c < 5; ++c) du[c] = S(T(0));   // upper boundary: u_hat = u
       }
-      for (int c = 0; c < 5; ++c) s_f[le][f][c][m] = du[c];
+      for (int c = 0; c < 5; ++c) s_fz[le][f][c][m] = du[c];
     }
     // Z on the owned faces, from the values this thread has just put in LDS (its own
     // slots: no barrier needed), so that the gathered values are dead before sigma
@@ -362,19 +369,19 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       const double Smag = fac * sqrt(A0 * A0 + A1 * A1 + A2 * A2);
       S du[5], uh[5];
       for (int c = 0; c < 5; ++c) {
-        du[c] = s_f[le][f][c][m];
+        du[c] = s_fz[le][f][c][m];
         uh[c] = s_u[le][c][t_jo[q]] + du[c];
       }
       S sm, se;
       sigma<3, S, XP>(ph, uh, sm, se, rc);
       for (int c = 0; c < 5; ++c) {
         const S sg = (c == 0) ? S(T(ph.lam)) : (c == 4 ? se : sm);
-        s_z[le][r][c][m] = T(Smag) * sg * du[c];
+        s_fz[le][6 + r][c][m] = T(Smag) * sg * du[c];
       }
     }
   }
   __builtin_amdgcn_sched_barrier(0);
-  __syncthreads();
+  lds_barrier();
 
   // ---- phase C (node threads): gradient, pointwise flux and source, contravariant fluxes
   NodeGeo g;
@@ -404,14 +411,14 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       S g1[3], d3 = S(T(0));
       for (int d = 0; d < 3; ++d) g1[d] = S(T(0));
       for (int i = 0; i < n; ++i) {
-        const S u1 = s_u[le][c][i + n * b + N2 * cz];
-        const S u2 = s_u[le][c][a + n * i + N2 * cz];
-        const S u3 = s_u[le][c][g.ja + N2 * i];
+        const S u1 = s_u[le][c][i + n * b + NS * cz];
+        const S u2 = s_u[le][c][a + n * i + NS * cz];
+        const S u3 = s_u[le][c][g.ja + NS * i];
         for (int d = 0; d < 3; ++d) g1[d] = g1[d] + u1 * T(c1[i][d]) + u2 * T(c2[i][d]);
         d3 = d3 + u3 * T(c3[i]);
       }
       if constexpr (RAD) {
-        const T vd = s_u[le][c][j].d;
+        const T vd = s_u[le][c][j + PL * cz].d;
         for (int d = 0; d < 3; ++d) g1[d].d = vd * T(c1[a][d] + c2[b][d]);
       }
       for (int d = 0; d < 3; ++d) q[c][d] = (g1[d] + T(g.A3[d]) * d3) * T(invJ);
@@ -424,7 +431,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       const double sd = ((f & 1) ? 1.0 : -1.0) * lfac;
       const int dd = f >> 1;
       for (int c = 0; c < 5; ++c) {
-        const S du = s_f[le][f][c][m];
+        const S du = s_fz[le][f][c][m];
         for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du * T(sd * Ja[dd][d]);
       }
     }
@@ -500,7 +507,7 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       const int r = __popc(own & ((1 << f) - 1));
       for (int c = 0; c < 5; ++c) {
         const S Fs = side * G[c][dd];
-        const S z = mine ? s_z[le][r][c][m] : S(T(0));
+        const S z = mine ? s_fz[le][6 + r][c][m] : S(T(0));
         Sr[c] = Sr[c] + (T(0.5) * Fs + z) * T(lfac);
         if (RAD && f < 4)
           Fn[(int64_t)nb + c * N2] = outp(S(T(0)));
@@ -509,27 +516,33 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       }
     }
   }
-  __syncthreads();   // every u_hat - u has been read: the trace buffer becomes the flux staging
-  S (*s_G)[N] = reinterpret_cast<S (*)[N]>(&s_f[le][0][0][0]);
-  for (int c = 0; c < 5; ++c) {
+  lds_barrier();   // every u_hat - u has been read: the trace buffer becomes the flux staging
+  // the divergence, FPR fields per LDS round (as many as the face-slot and Z rows hold)
+  constexpr int FPR = (kFzStride / (3 * NP)) < 5 ? (kFzStride / (3 * NP)) : 5;
+  static_assert(FPR >= 1, "flux staging must fit in the face-slot rows");
+  S (*s_G)[3][NP] = reinterpret_cast<S (*)[3][NP]>(&s_fz[le][0][0][0]);
+  for (int c0 = 0; c0 < 5; c0 += FPR) {
     if (active)
-      for (int dd = 0; dd < 3; ++dd) s_G[dd][j] = G[c][dd];
-    __syncthreads();
-    if (active) {
-      S dv = S(T(0));
-      for (int i = 0; i < n; ++i) {
-        dv = dv + s_G[0][i + n * b + N2 * cz] * T(D[a * n + i]);
-        dv = dv + s_G[1][a + n * i + N2 * cz] * T(D[b * n + i]);
-        dv = dv + s_G[2][g.ja + N2 * i] * T(D[cz * n + i]);
+      for (int cc = 0; cc < FPR && c0 + cc < 5; ++cc)
+        for (int dd = 0; dd < 3; ++dd) s_G[cc][dd][j + PL * cz] = G[c0 + cc][dd];
+    lds_barrier();
+    if (active)
+      for (int cc = 0; cc < FPR && c0 + cc < 5; ++cc) {
+        const int c = c0 + cc;
+        S dv = S(T(0));
+        for (int i = 0; i < n; ++i) {
+          dv = dv + s_G[cc][0][i + n * b + NS * cz] * T(D[a * n + i]);
+          dv = dv + s_G[cc][1][a + n * i + NS * cz] * T(D[b * n + i]);
+          dv = dv + s_G[cc][2][g.ja + NS * i] * T(D[cz * n + i]);
+        }
+        if constexpr (RAD) {
+          T dr = G[c][0].d * T(D[a * n + a]) + G[c][1].d * T(D[b * n + b]);
+          for (int i = 0; i < n; ++i) dr += s_G[cc][2][g.ja + NS * i].d * T(D[cz * n + i]);
+          dv.d = dr;
+        }
+        R[base + c * N + j] = outp(Sr[c] - dv * T(invJ));
       }
-      if constexpr (RAD) {
-        T dr = G[c][0].d * T(D[a * n + a]) + G[c][1].d * T(D[b * n + b]);
-        for (int i = 0; i < n; ++i) dr += s_G[2][g.ja + N2 * i].d * T(D[cz * n + i]);
-        dv.d = dr;
-      }
-      R[base + c * N + j] = outp(Sr[c] - dv * T(invJ));
-    }
-    __syncthreads();
+    if (c0 + FPR < 5) lds_barrier();
   }
 }
 
