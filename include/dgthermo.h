@@ -340,9 +340,10 @@ dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_hos
  *   Like line_pc_every it changes iteration counts, not the converged step.
  *   "columns_jac_every" >= 1 (default 32): dg_columns_integrate factors each column's chord
  *   Jacobian I - dt a_ii J (shared by the SDIRK stages) at the start of every this many
- *   steps instead of every step, and sooner after a step whose stages needed more than 3
- *   iterations or within a stage whose iteration reduced |G| less than twofold. It changes
- *   iteration counts, not what each stage converges to (within newton_rtol).
+ *   steps instead of every step, and sooner after a step whose stages needed more than
+ *   "columns_jac_stale_its" (default 5) iterations or within a stage whose iteration left |G|
+ *   above "columns_jac_slow_pct" percent (1..100, default 75) of its previous value. All three
+ *   change iteration counts, not what each stage converges to (within newton_rtol).
  *   "column_quadrature" 0 (default) or 1, column meshes only: 0 evaluates eq. (DGformulation)
  *   with the collocated GLL rule (diagonal mass); 1 integrates the volume terms of both LDG
  *   equations with p + 2 Gauss points and the exact mass matrix (over-integration; the traces,

@@ -239,6 +239,14 @@ dg_status_t dg_set_option(dg_mesh_t m, const char* name, int64_t value) {
     m->cols_jac_every = (int)value;
     return DG_OK;
   }
+  if (std::strcmp(name, "columns_jac_slow_pct") == 0 && value >= 1 && value <= 100) {
+    m->cols_jac_slow_pct = (int)value;
+    return DG_OK;
+  }
+  if (std::strcmp(name, "columns_jac_stale_its") == 0 && value >= 1 && value <= 1000) {
+    m->cols_jac_stale = (int)value;
+    return DG_OK;
+  }
   if (std::strcmp(name, "line_pc_precision") == 0 && (value == 64 || value == 32 || value == 16)) {
     m->line_pc_prec = (int)value;
     return DG_OK;

@@ -541,11 +541,32 @@ struct ColBatch {
   int filter;          // 1: modal filter after every step
   FiltC filt[3];       // for p = 2, 3, 4
   int jac_every;       // the chord Jacobian is rebuilt at the start of every jac_every-th step
+  double jac_slow;     // ... within a stage when an iteration reduces |G| by less than this factor
+  int jac_stale;       // ... at the next step when a stage needed more than this many iterations
   const QuadC* quad;   // Gauss tables of degrees 2, 3, 4 (over-integrated residual)
 };
 
+// The lane index for the batched-column functions, opaque to the optimiser. Everything a
+// function derives from it (element offsets, shuffle addresses) is then formed where it is
+// used; derived from threadIdx.x directly, those values are hoisted to the kernel's entry,
+// live across the residual passes and spilled (the persistent kernel runs at its register
+// limit), and every reload from scratch inside a chain of small steps waits for all
+// outstanding memory operations.
+__device__ __forceinline__ int wlane() {
+  int l = threadIdx.x;
+  __asm__ __volatile__("" : "+v"(l));
+  return l;
+}
+// x from lane (lane ^ off) of the wavefront
+__device__ __forceinline__ double wshfl_xor(double x, int lane, int off) {
+  const int idx = (lane ^ off) << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(idx, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(idx, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
 __device__ inline double wave_allsum(double x) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  const int lane = wlane();
+  for (int off = 32; off > 0; off >>= 1) x += wshfl_xor(x, lane, off);
   return x;
 }
 
@@ -553,7 +574,7 @@ template <int P, class S, class TV, class OT, int XP, bool OI>
 __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                               const double* u, const TV* v, OT* out, OT* fn) {
   constexpr int b = 3 * (P + 1);
-  const int lane = threadIdx.x;
+  const int lane = wlane();
   const QuadC& qc = B.quad[P - 2];
   for (int el = lane; el < E; el += 64) {
     ColElem ce;
@@ -590,7 +611,7 @@ __device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, 
 __device__ inline double colw_stage_residual(int nd, const double* U, const double* R, double ca, const double* Bv,
                                              double* G) {
   double acc = 0;
-  for (int i = threadIdx.x; i < nd; i += 64) {
+  for (int i = wlane(); i < nd; i += 64) {
     const double g = U[i] - ca * R[i] - Bv[i];
     G[i] = g;
     acc += g * g;
@@ -602,7 +623,7 @@ __device__ inline double colw_stage_residual(int nd, const double* U, const doub
 // in-place inverse of a b x b block (row-major) by Gauss-Jordan with partial pivoting
 template <int b>
 __device__ __forceinline__ void colw_invert(double* blk, double (*M)[2 * b], double* fac, int* piv_s) {
-  const int lane = threadIdx.x;
+  const int lane = wlane();
   for (int idx = lane; idx < b * 2 * b; idx += 64) {
     const int r = idx / (2 * b), c = idx % (2 * b);
     M[r][c] = c < b ? blk[r * b + c] : (c - b == r ? 1.0 : 0.0);
@@ -655,7 +676,7 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
                                       double* Di, double* Up) {
   constexpr int b = 3 * (P + 1);
   constexpr int bb = b * b;
-  const int lane = threadIdx.x;
+  const int lane = wlane();
   const int nd = E * b;
   __shared__ double M[b][2 * b];
   __shared__ double fac[b];
@@ -710,50 +731,95 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
   }
 }
 
-// solve (I - ca J) X = rhs with the factored blocks; rhs in X on entry
+// solve (I - ca J) X = rhs with the factored blocks; rhs in X on entry.
+// The substitution is a chain over the elements, so the chain itself stays in LDS: row r of
+// a block belongs to the four lanes 4r..4r+3 (columns q, q + 4, ... of lane q; their partial
+// products are summed across the four lanes), each element's solution goes to LDS for the
+// next element and to X for the backward sweep, and the block rows and right-hand side of the
+// next element are loaded while the current one is worked on. Only LDS ordering is needed
+// between the steps (one wavefront); global memory is fenced at the end.
 template <int P>
 __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double* Di, const double* Up, double* X) {
   constexpr int b = 3 * (P + 1);
   constexpr int bb = b * b;
-  const int lane = threadIdx.x;
-  __shared__ double y[b];
+  constexpr int NQ = (b + 3) / 4;   // columns per lane
+  const int lane = wlane();
+  const int r = lane >> 2, q = lane & 3;
+  const bool row = r < b;
+  __shared__ double s_x[b], s_v[b];
+  auto seg = [&](const double* blk, double (&o)[NQ]) {
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      const int k = q + 4 * t;
+      o[t] = (row && k < b) ? blk[r * b + k] : 0.0;
+    }
+  };
+  auto dot4 = [&](const double (&a)[NQ], const double* x) {
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      const int k = q + 4 * t;
+      if (k < b) acc += a[t] * x[k];
+    }
+    acc += wshfl_xor(acc, lane, 1);
+    acc += wshfl_xor(acc, lane, 2);
+    return acc;
+  };
+  // forward: x_e = D_e (rhs_e - L_e x_{e-1})
+  double Lc[NQ], Dc[NQ], Ln[NQ], Dn[NQ];
+  seg(Di, Dc);
+  double rc = row ? X[r] : 0.0, rn = 0.0;
+  for (int t = 0; t < NQ; ++t) Lc[t] = 0.0;
   for (int e = 0; e < E; ++e) {
-    double* xe = X + e * b;
-    if (e > 0 && lane < b) {
-      const double* L = Lo + (int64_t)e * bb;
-      const double* xp = X + (e - 1) * b;
-      double s = 0;
-      for (int k = 0; k < b; ++k) s += L[lane * b + k] * xp[k];
-      xe[lane] -= s;
+    if (e + 1 < E) {
+      seg(Lo + (int64_t)(e + 1) * bb, Ln);
+      seg(Di + (int64_t)(e + 1) * bb, Dn);
+      rn = row ? X[(e + 1) * b + r] : 0.0;
     }
-    __syncthreads();
-    if (lane < b) {
-      const double* D = Di + (int64_t)e * bb;
-      double s = 0;
-      for (int k = 0; k < b; ++k) s += D[lane * b + k] * xe[k];
-      y[lane] = s;
+    double v = rc;
+    if (e > 0) v -= dot4(Lc, s_x);
+    if (row && q == 0) s_v[r] = v;
+    lds_barrier();
+    const double y = dot4(Dc, s_v);
+    if (row) X[e * b + r] = y;   // (every lane of the row: each reads back its own store)
+    if (row && q == 0) s_x[r] = y;
+    lds_barrier();
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      Lc[t] = Ln[t];
+      Dc[t] = Dn[t];
     }
-    __syncthreads();
-    if (lane < b) xe[lane] = y[lane];
-    __syncthreads();
+    rc = rn;
+  }
+  // backward: x_e -= W_e x_{e+1}, the latest x in s_x
+  double Wc[NQ], Wn[NQ];
+  double xc = 0.0, xn = 0.0;
+  if (E >= 2) {
+    seg(Up + (int64_t)(E - 2) * bb, Wc);
+    xc = row ? X[(E - 2) * b + r] : 0.0;
   }
   for (int e = E - 2; e >= 0; --e) {
-    if (lane < b) {
-      const double* W = Up + (int64_t)e * bb;
-      const double* xn = X + (e + 1) * b;
-      double s = 0;
-      for (int k = 0; k < b; ++k) s += W[lane * b + k] * xn[k];
-      X[e * b + lane] -= s;
+    if (e >= 1) {
+      seg(Up + (int64_t)(e - 1) * bb, Wn);
+      xn = row ? X[(e - 1) * b + r] : 0.0;
     }
-    __syncthreads();
+    const double x = xc - dot4(Wc, s_x);
+    lds_barrier();   // every lane has read s_x
+    if (row) X[e * b + r] = x;
+    if (row && q == 0) s_x[r] = x;
+    lds_barrier();
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) Wc[t] = Wn[t];
+    xc = xn;
   }
+  __syncthreads();   // X is read by other lanes next
 }
 
 template <int P, int XP, bool OI>
 __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC& ph, const GllC& gc) {
   constexpr int n = P + 1;
   constexpr int b = 3 * n;
-  const int lane = threadIdx.x;
+  const int lane = wlane();
   const int E = B.col_E[col];
   const int e0 = B.col_e0[col];
   const int nd = E * b;
@@ -784,10 +850,10 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   int newton_total = 0, builds = 0, status = 0;
   // Chord Newton: the factored stage operator I - dt a_ii J is shared by every SDIRK stage
   // (a_ii is the same) and, with jac_every > 1, by several steps. It is rebuilt at the start
-  // of every jac_every-th step, after a step in which a stage needed more than 3 iterations,
-  // and within a stage when an iteration reduces |G| less than twofold or 12 iterations have
-  // passed since the last build. The iteration path changes, not the converged stages.
-  int since_build = 0;
+  // of every jac_every-th step, after a step in which a stage needed more than jac_stale
+  // iterations, and within a stage when an iteration leaves |G| above jac_slow times its
+  // previous value or 12 of the stage's iterations (6 with jac_every 1) have passed since the
+  // last build. The iteration path changes, not the converged stages.
   bool stale = true;
   for (int step = 0; step < B.n_steps && status == 0; ++step) {
     const double t = B.t0 + step * B.dt;
@@ -796,7 +862,6 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
       if (sited) sun_direction_dev(Pc, t + B.c[0] * B.dt);
       colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
       ++builds;
-      since_build = 0;
       stale = false;
     }
     int max_stage_its = 0;
@@ -815,7 +880,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
       const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, G));
       int it = 0;
       double prev = 0.0;
-      if (B.jac_every == 1) since_build = 0;   // (a fresh Jacobian every step: counted per stage)
+      int last_build = 0;   // iteration of this stage at which the Jacobian was last rebuilt
       for (;;) {
         colw_residual<P, double, double, double, XP, OI>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
         const double nG = sqrt(colw_stage_residual(nd, U, Rc, ca, Bv, G));
@@ -828,10 +893,11 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
           status = 4;
           break;
         }
-        if (since_build >= 12 || (it > 0 && B.jac_every > 1 && nG > 0.5 * prev) || (B.jac_every == 1 && since_build >= 6)) {
+        const bool slow = it > 0 && B.jac_every > 1 && nG > B.jac_slow * prev;
+        if (slow || it - last_build >= (B.jac_every == 1 ? 6 : 12)) {
           colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
           ++builds;
-          since_build = 0;
+          last_build = it;
         }
         for (int i = lane; i < nd; i += 64) X[i] = -G[i];
         __syncthreads();
@@ -840,14 +906,13 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
         __syncthreads();
         prev = nG;
         ++it;
-        ++since_build;
       }
       newton_total += it;
       max_stage_its = max(max_stage_its, it);
       for (int i = lane; i < nd; i += 64) Rs[s * md + i] = Rc[i];
       __syncthreads();
     }
-    if (max_stage_its > 3) stale = true;
+    if (max_stage_its > B.jac_stale) stale = true;
     if (status == 0) {
       for (int i = lane; i < nd; i += 64) un[i] = U[i];
       __syncthreads();
@@ -966,6 +1031,8 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   B.ws = m->d_cols_ws;
   B.ws_stride = stride;
   B.jac_every = m->cols_jac_every;
+  B.jac_slow = 0.01 * m->cols_jac_slow_pct;
+  B.jac_stale = m->cols_jac_stale;
   B.quad = m->d_quad;
   B.max_dof = (int)md;
   // DIRK tableau

@@ -149,7 +149,9 @@ struct dg_mesh_s {
   int64_t cols_ws_len = 0;
   int col_max_dof = 0;
   int tune_cols_grid = 2048;             // persistent wavefronts (dg_set_option "columns_grid")
-  int cols_jac_every = 32;               // chord Jacobian of the column batch rebuilt every this many steps
+  int cols_jac_every = 32;               // chord Jacobian of the column batch rebuilt every this many steps,
+  int cols_jac_slow_pct = 75;            // within a stage when an iteration leaves |G| above this percentage
+  int cols_jac_stale = 5;                // and after a step with a stage of more than this many iterations
   int tune_p1 = 2;
   // learned warm start (dg_warmstart_set / dg_warmstart_record)
   struct dg_mlp_s* ws_mlp = nullptr;
