@@ -406,8 +406,11 @@ def implicit_steps_shell(name, n_steps, runs):
 
 def column_batch(n_steps=None):
     """the batched radial-column sweep: 4096 columns advanced n_steps DIRK(3,3) steps of
-    10 s in one persistent launch (autotuned grid), columns/s (sampled columns of this
-    batch are checked against the oracle in the GPU tests)"""
+    10 s in one persistent launch (autotuned grid), columns/s, in two discretisations: the
+    over-integrated residual without a filter (the paper's weak form) and the collocated one
+    with the modal filter. Also one step of the whole batch from the same start, kept for
+    sampled columns (the smallest column of each degree) that the CPU-baseline leg compares
+    with the oracle. Returns (report, samples)."""
     import torch
 
     import synth
@@ -423,16 +426,70 @@ def column_batch(n_steps=None):
         rc = r[off[c] // 3:off[c + 1] // 3].reshape(w.nelem[c], w.p[c] + 1)
         u0[off[c]:off[c + 1]] = np.moveaxis(w.state(c, rc), 0, 1).ravel()
     u = torch.from_numpy(u0).cuda()
-    grid, _ = autotune.tune_columns(gm, u, 0.0, w.dt, steps=1)
-    x = u.clone()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its, st = gm.columns_integrate(x, 0.0, w.dt, n_steps, filter_rate=FILTER_RATE, raise_on_failure=False)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    out = {"n_col": gm.n_col, "n_dof": gm.n_dof, "steps": n_steps, "filter_rate": FILTER_RATE, "seconds": el,
-           "columns_per_s": gm.n_col / el,
-           "grid": grid, "newton_per_step_mean": float(its.mean() / n_steps), "failed": int((st != 0).sum())}
+    pick = [int(np.flatnonzero(w.p == p)[np.argmin(w.nelem[w.p == p])]) for p in (2, 3, 4)]
+    report, samples = {}, {"workload": w, "u0": u0, "offsets": off, "columns": pick, "runs": {}}
+    for name, quad, rate in (("over_integrated", 1, 0.0), ("collocated_filtered", 0, FILTER_RATE)):
+        gm.set_option("column_quadrature", quad)
+        # trials of 32 steps: every call starts with a Jacobian build for every column, which
+        # shorter trials overweight (they favour small grids, whose builds thrash the caches less)
+        grid, _ = autotune.tune_columns(gm, u, 0.0, w.dt, steps=32, tag="q%d" % quad, log=log)
+        x = u.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, st = gm.columns_integrate(x, 0.0, w.dt, n_steps, filter_rate=rate, raise_on_failure=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = np.asarray(st)
+        report[name] = {"quadrature": "p + 2 Gauss points, exact mass matrix" if quad else "GLL collocation",
+                        "filter_rate": rate, "seconds": el, "columns_per_s": gm.n_col / el, "grid": grid,
+                        "newton_per_step_mean": float(np.asarray(its).mean() / n_steps),
+                        "failed": int((st != 0).sum()),
+                        "failed_columns": [{"column": int(c), "elements": int(w.nelem[c]), "p": int(w.p[c]),
+                                            "T_inf_K": float(w.T_inf[c]), "status": int(st[c])}
+                                           for c in np.flatnonzero(st)[:8]]}
+        x = u.clone()
+        gm.columns_integrate(x, 0.0, w.dt, 1, filter_rate=rate, raise_on_failure=False)
+        y = x.cpu().numpy()
+        samples["runs"][name] = {"quad": quad, "rate": rate,
+                                 "states": {c: y[off[c]:off[c + 1]].copy() for c in pick}}
+    out = {"n_col": gm.n_col, "n_dof": gm.n_dof, "steps": n_steps, "newton_rtol": 1e-8}
+    out.update(report)
+    # the headline rate: the paper's discretisation (no filter)
+    out["columns_per_s"] = report["over_integrated"]["columns_per_s"]
+    out["failed"] = report["over_integrated"]["failed"]
+    return out, samples
+
+
+def column_sample_error(samples):
+    """(CPU-baseline leg) the oracle's dense-Newton DIRK(3,3) step of the sampled batch
+    columns in each discretisation, timed, and the GPU batch's step against it: relative
+    error |u_gpu - u_oracle| / |u_oracle - u_0| per column"""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dg as odg
+    from oracle import mesh as omesh
+    from oracle import timeint
+    w = samples["workload"]
+    off = samples["offsets"]
+    out = {}
+    for name, run in samples["runs"].items():
+        rows = []
+        for c in samples["columns"]:
+            om = omesh.columns_mesh([int(w.nelem[c])], int(w.p[c]), w.r_bot, w.r_top, float(w.stretch[c]))
+            P = dict(w.phys)
+            for k in w.col_phys:
+                P[k] = float(w.col_phys[k][c])
+            start = samples["u0"][off[c]:off[c + 1]].reshape(-1, 3, w.p[c] + 1).copy()
+            t0 = time.perf_counter()
+            with threadpool_limits(limits=1):
+                ref, _ = timeint.implicit_step_dense(om, P, start, 0.0, w.dt, rtol=1e-9, filter_rate=run["rate"],
+                                                     residual=odg.residual_overint if run["quad"] else None)
+            tc = time.perf_counter() - t0
+            got = run["states"][c].reshape(ref.shape)
+            rows.append({"column": int(c), "elements": int(w.nelem[c]), "p": int(w.p[c]), "dof": int(got.size),
+                         "rel_err_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref - start)),
+                         "oracle_s_per_step": tc})
+        out[name] = rows
     return out
 
 
@@ -557,7 +614,7 @@ def main():
         return
 
     if args.only == "columns":
-        print(json.dumps(column_batch()), flush=True)
+        print(json.dumps(column_batch()[0]), flush=True)
         return
 
     dev = torch.device("cuda:0")
@@ -761,7 +818,7 @@ def main():
         log("implicit steps on the 92M-DOF p = 4 shell")
         out["implicit_step_p4"] = implicit_steps_shell("shell-p4", 5, ("f64", "f32"))
     log("column batch")
-    out["columns"] = column_batch()
+    out["columns"], col_samples = column_batch()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         counts = {"shell-p3 (7.9M DOF), f64 J v, line preconditioner": (w.n_dof, out["implicit_step"]["f64"])}
@@ -769,6 +826,15 @@ def main():
             counts["shell-p4 (92M DOF), f64 J v, line preconditioner"] = (out["implicit_step_p4"]["n_dof"],
                                                                        out["implicit_step_p4"]["f64"])
         out["cpu_baseline"] = cpu_baseline(w, implicit=counts)
+        # sampled columns of the batch: one oracle step each (timed with the baseline) and the
+        # GPU batch's step against it
+        cse = column_sample_error(col_samples)
+        out["cpu_baseline"]["column_batch_sample"] = {
+            "workload": "the smallest column of each degree in the 4096-column batch, one DIRK(3,3) step of "
+                        "10 s, dense Newton 1e-9, 1 thread", "columns": cse}
+        for name, rows in cse.items():
+            out["columns"][name]["sampled_rel_err_vs_oracle"] = {str(r["column"]): r["rel_err_vs_oracle"]
+                                                                 for r in rows}
     print(json.dumps(out), flush=True)
 
 

@@ -44,16 +44,23 @@ def columns_key(mesh):
     return "columns:%d:%d:%d:%d" % (len(ne), *hist)
 
 
-def tune_columns(mesh, u, t0, dt, steps=1, candidates=(256, 512, 1024, 2048, 4096), force=False, log=None):
-    """choose 'columns_grid' for this batch; returns (best grid, {grid: seconds})"""
+def tune_columns(mesh, u, t0, dt, steps=8, candidates=(256, 512, 1024, 2048, 4096), force=False, log=None, tag=""):
+    """choose 'columns_grid' for this batch; returns (best grid, {grid: seconds}). tag: a
+    label of the mesh's other settings (the quadrature) added to the cache key"""
     import torch
-    key = columns_key(mesh)
+    key = columns_key(mesh) + tag
     cache = _load()
     if key in cache and not force:
         mesh.set_option("columns_grid", cache[key]["grid"])
         return cache[key]["grid"], cache[key].get("times", {})
     times = {}
     scratch = torch.empty_like(u)
+    # an untimed call at the largest grid first: the workspace (per persistent wavefront) is
+    # allocated there once, so no timed trial pays for growing it
+    mesh.set_option("columns_grid", int(min(max(candidates), mesh.n_col)))
+    scratch.copy_(u)
+    mesh.columns_integrate(scratch, t0, dt, steps, raise_on_failure=False)
+    torch.cuda.synchronize()
     for g in candidates:
         g = int(min(g, mesh.n_col)) if g > mesh.n_col else int(g)
         if str(g) in times:

@@ -665,15 +665,22 @@ __device__ __forceinline__ void colw_invert(double* blk, double (*M)[2 * b], dou
 }
 
 // Probing: elements of one colour are perturbed together. The collocated residual of an
-// element depends on its own and its two neighbours' states (3 colours separate them); the
-// over-integrated one also on the states two elements away (its neighbours' gradients take
-// their far faces' traces through M^-1), so 5 colours keep every response apart and the
-// couplings two elements away, outside the stored block-tridiagonal part, are dropped: the
-// chord iteration then runs on an approximate Jacobian (its converged stages are unchanged).
+// element depends on its own and its two neighbours' states (3 colours separate them; the
+// Jacobian is block tridiagonal); the over-integrated one also on the states two elements
+// away (its neighbours' gradients take their far faces' traces through M^-1), so 5 colours
+// keep every response apart and the Jacobian is block pentadiagonal (Lo2, Up2 hold the blocks
+// two elements away).
+// Block LU, A = L (I + W), without pivoting between blocks (partial pivoting inside each
+// diagonal block's inverse): per element e, in order,
+//   L2_e = A_{e,e-2},  L1_e = A_{e,e-1} - L2_e W1_{e-2},
+//   S_e = A_ee - L1_e W1_{e-1} - L2_e W2_{e-2},
+//   W1_e = S_e^-1 (A_{e,e+1} - L1_e W2_{e-1}),  W2_e = S_e^-1 A_{e,e+2};
+// in place: Lo = L1, Di = S^-1, Up = W1, Lo2 = L2, Up2 = W2. Without the far blocks
+// (collocated) the same recurrence is the block-tridiagonal LU.
 template <int P, int XP, bool OI>
 __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                                       double ca, const double* U, double* V, double* Jv, double* fnT, double* Lo,
-                                      double* Di, double* Up) {
+                                      double* Di, double* Up, double* Lo2, double* Up2) {
   constexpr int b = 3 * (P + 1);
   constexpr int bb = b * b;
   const int lane = wlane();
@@ -683,6 +690,7 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
   __shared__ double tmp[bb];
   __shared__ int piv_s;
   constexpr int NCOL = OI ? 5 : 3;
+  constexpr int BW = OI ? 2 : 1;   // block bandwidth
   for (int kap = 0; kap < NCOL; ++kap)
     for (int l = 0; l < b; ++l) {
       for (int i = lane; i < nd; i += 64) V[i] = (((i / b) % NCOL == kap) && (i % b == l)) ? 1.0 : 0.0;
@@ -690,63 +698,84 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
       colw_residual<P, Dual<double>, double, double, XP, OI>(B, E, e0, Pc, gc, t, U, V, Jv, fnT);
       for (int idx = lane; idx < E * b; idx += 64) {
         const int ep = idx / b, r = idx % b;
-        for (int d = -1; d <= 1; ++d) {
+        for (int d = -BW; d <= BW; ++d) {
           const int e = ep + d;
           if (e < 0 || e >= E || e % NCOL != kap) continue;
-          double* blk = (d == -1) ? Lo : (d == 0 ? Di : Up);
+          double* blk = (d == -2) ? Lo2 : (d == -1) ? Lo : (d == 0) ? Di : (d == 1) ? Up : Up2;
           blk[(int64_t)ep * bb + r * b + l] = (d == 0 && r == l ? 1.0 : 0.0) - ca * Jv[ep * b + r];
         }
       }
       __syncthreads();
     }
-  // block LU: Di <- inverse of the Schur complements, Up <- W = Dinv * Up
+  // Dst -= A Bm (all b x b, row-major)
+  auto mm_sub = [&](double* Dst, const double* A, const double* Bm) {
+    for (int idx = lane; idx < bb; idx += 64) {
+      const int r = idx / b, c = idx % b;
+      double s = 0;
+      for (int k = 0; k < b; ++k) s += A[r * b + k] * Bm[k * b + c];
+      tmp[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = lane; idx < bb; idx += 64) Dst[idx] -= tmp[idx];
+    __syncthreads();
+  };
+  // Dst = A Dst
+  auto mm_left = [&](const double* A, double* Dst) {
+    for (int idx = lane; idx < bb; idx += 64) {
+      const int r = idx / b, c = idx % b;
+      double s = 0;
+      for (int k = 0; k < b; ++k) s += A[r * b + k] * Dst[k * b + c];
+      tmp[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = lane; idx < bb; idx += 64) Dst[idx] = tmp[idx];
+    __syncthreads();
+  };
   for (int e = 0; e < E; ++e) {
     double* D = Di + (int64_t)e * bb;
-    if (e > 0) {
-      const double* L = Lo + (int64_t)e * bb;
-      const double* W = Up + (int64_t)(e - 1) * bb;
-      for (int idx = lane; idx < bb; idx += 64) {
-        const int r = idx / b, c = idx % b;
-        double s = 0;
-        for (int k = 0; k < b; ++k) s += L[r * b + k] * W[k * b + c];
-        tmp[idx] = s;
-      }
-      __syncthreads();
-      for (int idx = lane; idx < bb; idx += 64) D[idx] -= tmp[idx];
-      __syncthreads();
+    double* L1 = Lo + (int64_t)e * bb;
+    if constexpr (OI) {
+      if (e >= 2) mm_sub(L1, Lo2 + (int64_t)e * bb, Up + (int64_t)(e - 2) * bb);
+    }
+    if (e > 0) mm_sub(D, L1, Up + (int64_t)(e - 1) * bb);
+    if constexpr (OI) {
+      if (e >= 2) mm_sub(D, Lo2 + (int64_t)e * bb, Up2 + (int64_t)(e - 2) * bb);
     }
     colw_invert<b>(D, M, fac, &piv_s);
     if (e < E - 1) {
-      double* Uu = Up + (int64_t)e * bb;
-      for (int idx = lane; idx < bb; idx += 64) {
-        const int r = idx / b, c = idx % b;
-        double s = 0;
-        for (int k = 0; k < b; ++k) s += D[r * b + k] * Uu[k * b + c];
-        tmp[idx] = s;
+      double* W1 = Up + (int64_t)e * bb;
+      if constexpr (OI) {
+        if (e >= 1) mm_sub(W1, L1, Up2 + (int64_t)(e - 1) * bb);
       }
-      __syncthreads();
-      for (int idx = lane; idx < bb; idx += 64) Uu[idx] = tmp[idx];
-      __syncthreads();
+      mm_left(D, W1);
+    }
+    if constexpr (OI) {
+      if (e < E - 2) mm_left(D, Up2 + (int64_t)e * bb);
     }
   }
 }
 
-// solve (I - ca J) X = rhs with the factored blocks; rhs in X on entry.
+// solve (I - ca J) X = rhs with the factored blocks; rhs in X on entry. BW2: block bandwidth
+// two (the over-integrated residual; Lo2, Up2 used), otherwise one:
+//   forward  y_e = S_e^-1 (r_e - L1_e y_{e-1} - L2_e y_{e-2}),
+//   backward x_e = y_e - W1_e x_{e+1} - W2_e x_{e+2}.
 // The substitution is a chain over the elements, so the chain itself stays in LDS: row r of
 // a block belongs to the four lanes 4r..4r+3 (columns q, q + 4, ... of lane q; their partial
-// products are summed across the four lanes), each element's solution goes to LDS for the
-// next element and to X for the backward sweep, and the block rows and right-hand side of the
-// next element are loaded while the current one is worked on. Only LDS ordering is needed
-// between the steps (one wavefront); global memory is fenced at the end.
-template <int P>
-__device__ __forceinline__ void colw_solve(int E, const double* Lo, const double* Di, const double* Up, double* X) {
+// products are summed across the four lanes), the latest two solutions are in LDS for the
+// next elements, each also goes to X for the backward sweep, and the block rows and
+// right-hand side of the next element are loaded while the current one is worked on. Only
+// LDS ordering is needed between the steps (one wavefront); global memory is fenced at the
+// end.
+template <int P, bool BW2>
+__device__ __forceinline__ void colw_solve(int E, const double* Lo, const double* Di, const double* Up,
+                                           const double* Lo2, const double* Up2, double* X) {
   constexpr int b = 3 * (P + 1);
   constexpr int bb = b * b;
   constexpr int NQ = (b + 3) / 4;   // columns per lane
   const int lane = wlane();
   const int r = lane >> 2, q = lane & 3;
   const bool row = r < b;
-  __shared__ double s_x[b], s_v[b];
+  __shared__ double s_x[b], s_x2[b], s_v[b];
   auto seg = [&](const double* blk, double (&o)[NQ]) {
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
@@ -765,34 +794,52 @@ __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double
     acc += wshfl_xor(acc, lane, 2);
     return acc;
   };
-  // forward: x_e = D_e (rhs_e - L_e x_{e-1})
-  double Lc[NQ], Dc[NQ], Ln[NQ], Dn[NQ];
+  auto zero = [&](double (&o)[NQ]) {
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) o[t] = 0.0;
+  };
+  // forward
+  double Lc[NQ], Dc[NQ], L2c[NQ], Ln[NQ], Dn[NQ], L2n[NQ];
   seg(Di, Dc);
+  zero(Lc);
+  zero(L2c);
+  zero(L2n);
   double rc = row ? X[r] : 0.0, rn = 0.0;
-  for (int t = 0; t < NQ; ++t) Lc[t] = 0.0;
   for (int e = 0; e < E; ++e) {
     if (e + 1 < E) {
       seg(Lo + (int64_t)(e + 1) * bb, Ln);
       seg(Di + (int64_t)(e + 1) * bb, Dn);
+      if constexpr (BW2) {
+        if (e + 1 >= 2) seg(Lo2 + (int64_t)(e + 1) * bb, L2n);
+      }
       rn = row ? X[(e + 1) * b + r] : 0.0;
     }
     double v = rc;
     if (e > 0) v -= dot4(Lc, s_x);
+    if constexpr (BW2) {
+      if (e > 1) v -= dot4(L2c, s_x2);
+    }
     if (row && q == 0) s_v[r] = v;
     lds_barrier();
     const double y = dot4(Dc, s_v);
     if (row) X[e * b + r] = y;   // (every lane of the row: each reads back its own store)
-    if (row && q == 0) s_x[r] = y;
+    if (row && q == 0) {
+      if constexpr (BW2) s_x2[r] = s_x[r];
+      s_x[r] = y;
+    }
     lds_barrier();
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
       Lc[t] = Ln[t];
       Dc[t] = Dn[t];
+      L2c[t] = L2n[t];
     }
     rc = rn;
   }
-  // backward: x_e -= W_e x_{e+1}, the latest x in s_x
-  double Wc[NQ], Wn[NQ];
+  // backward; s_x holds x_{E-1} = y_{E-1}
+  double Wc[NQ], Wn[NQ], W2c[NQ], W2n[NQ];
+  zero(W2c);
+  zero(W2n);
   double xc = 0.0, xn = 0.0;
   if (E >= 2) {
     seg(Up + (int64_t)(E - 2) * bb, Wc);
@@ -801,15 +848,25 @@ __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double
   for (int e = E - 2; e >= 0; --e) {
     if (e >= 1) {
       seg(Up + (int64_t)(e - 1) * bb, Wn);
+      if constexpr (BW2) seg(Up2 + (int64_t)(e - 1) * bb, W2n);
       xn = row ? X[(e - 1) * b + r] : 0.0;
     }
-    const double x = xc - dot4(Wc, s_x);
-    lds_barrier();   // every lane has read s_x
+    double x = xc - dot4(Wc, s_x);
+    if constexpr (BW2) {
+      if (e + 2 < E) x -= dot4(W2c, s_x2);
+    }
+    lds_barrier();   // every lane has read s_x, s_x2
     if (row) X[e * b + r] = x;
-    if (row && q == 0) s_x[r] = x;
+    if (row && q == 0) {
+      if constexpr (BW2) s_x2[r] = s_x[r];
+      s_x[r] = x;
+    }
     lds_barrier();
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) Wc[t] = Wn[t];
+    for (int t = 0; t < NQ; ++t) {
+      Wc[t] = Wn[t];
+      W2c[t] = W2n[t];
+    }
     xc = xn;
   }
   __syncthreads();   // X is read by other lanes next
@@ -843,6 +900,8 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   const int64_t blk_len = (int64_t)(md / b + 1) * b * b;
   double* Di = Lo + blk_len;
   double* Up = Di + blk_len;
+  double* Lo2 = OI ? Up + blk_len : nullptr;   // block bandwidth two (over-integrated)
+  double* Up2 = OI ? Lo2 + blk_len : nullptr;
   double* ug = B.u + B.col_off[col];
   for (int i = lane; i < nd; i += 64) un[i] = ug[i];
   __syncthreads();
@@ -860,7 +919,8 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
     // chord Jacobian at the start of the step (a sited column follows the Sun's direction)
     if (stale || step % B.jac_every == 0) {
       if (sited) sun_direction_dev(Pc, t + B.c[0] * B.dt);
-      colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up);
+      colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, t + B.c[0] * B.dt, ca, un, V, Jv, fnT, Lo, Di, Up, Lo2,
+                                       Up2);
       ++builds;
       stale = false;
     }
@@ -895,13 +955,13 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
         }
         const bool slow = it > 0 && B.jac_every > 1 && nG > B.jac_slow * prev;
         if (slow || it - last_build >= (B.jac_every == 1 ? 6 : 12)) {
-          colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up);
+          colw_build_and_factor<P, XP, OI>(B, E, e0, Pc, gc, ti, ca, U, V, Jv, fnT, Lo, Di, Up, Lo2, Up2);
           ++builds;
           last_build = it;
         }
         for (int i = lane; i < nd; i += 64) X[i] = -G[i];
         __syncthreads();
-        colw_solve<P>(E, Lo, Di, Up, X);
+        colw_solve<P, OI>(E, Lo, Di, Up, Lo2, Up2, X);
         for (int i = lane; i < nd; i += 64) U[i] += X[i];
         __syncthreads();
         prev = nG;
@@ -999,7 +1059,7 @@ dg_status_t columns_integrate(dg_mesh_s* m, double t0, double dt, int n_steps, d
   const int slots = std::max(1, std::min(nc, m->tune_cols_grid));
   const int64_t md = m->col_max_dof;
   const int64_t blk = (md / 9 + 1) * 15 * 15;   // generous: b >= 9 so md/b <= md/9 elements
-  const int64_t stride = 14 * md + 3 * blk + 64;
+  const int64_t stride = 14 * md + (m->col_quad ? 5 : 3) * blk + 64;   // 5 blocks per element over-integrated
   if (m->cols_ws_len < stride * slots) {
     if (m->d_cols_ws) (void)hipFree(m->d_cols_ws);
     m->d_cols_ws = nullptr;
