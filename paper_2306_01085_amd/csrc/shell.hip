@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   constexpr int L = 30 * N2;                                    // trace slots of one element
   constexpr int W = L * (int)sizeof(OT) / 8;                    // as 8-byte words
   static_assert((L * sizeof(OT)) % 8 == 0, "trace block must be whole 8-byte words");
-  __shared__ uint64_t s_tw[EPB][W];
+  constexpr bool kWide = (W % 2) == 0;                          // the block is whole 16-byte words
+  __shared__ __align__(16) uint64_t s_tw[EPB][W];
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
   const int e = xcd_block_reversed(blockIdx.x, gridDim.x) * EPB + le;
@@ -56,15 +57,24 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
     for (int c = 0; c < 5; ++c) r[c] = R[base + c * N + j];
   if (live) {
     // the block starts at e * L * sizeof(OT) bytes, a multiple of 8 (L * sizeof(OT) is)
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(Fin + (int64_t)e * L);
-    for (int w = j; w < W; w += TPE) s_tw[le][w] = src[w];
+    // (16-byte words where the block is made of them: it then starts on a 16-byte boundary)
+    if constexpr (kWide) {
+      const uint4* src = reinterpret_cast<const uint4*>(Fin + (int64_t)e * L);
+      uint4* dst = reinterpret_cast<uint4*>(&s_tw[le][0]);
+      for (int w = j; w < W / 2; w += TPE) dst[w] = src[w];
+    } else {
+      const uint64_t* src = reinterpret_cast<const uint64_t*>(Fin + (int64_t)e * L);
+      for (int w = j; w < W; w += TPE) s_tw[le][w] = src[w];
+    }
   }
   lds_barrier();
   if (!upd) return;
   const OT* Fe = reinterpret_cast<const OT*>(&s_tw[le][0]);
   const int ja = a + n * b;
   const double rk = M.edges[k], hk = M.edges[k + 1] - rk;
-  const double rc = rk + 0.5 * (gc.x[cz] + 1.0) * hk;
+  double xz = gc.x[0];   // the node's GLL point, selected (not indexed: no memory access)
+  for (int q = 1; q < n; ++q) xz = (cz == q) ? gc.x[q] : xz;
+  const double rc = rk + 0.5 * (xz + 1.0) * hk;
   const double Jac = rc * rc * (0.5 * hk) * M.ang[((int64_t)cell * 13 + 9) * N2 + ja];
   const OT hl = OT(0.5 / (gc.w[0] * Jac));
   OT acc[5] = {OT(0), OT(0), OT(0), OT(0), OT(0)};
