@@ -577,6 +577,8 @@ def main():
     ap.add_argument("--mode", default="default", choices=["default", "warmstart", "sweep"],
                     help="sweep: the parametric study of the 1D model (three cases x 75 columns)")
     ap.add_argument("--sweep-hours", type=float, default=72.0, help="model hours per case (sweep mode)")
+    ap.add_argument("--sweep-quadrature", type=int, default=1, choices=(0, 1),
+                    help="sweep mode: 1 over-integrated residual without a filter, 0 collocated with the filter")
     ap.add_argument("--implicit-steps", type=int, default=16)
     ap.add_argument("--all-pass1-configs", action="store_true",
                     help="with --only residual: time every element-pass launch configuration")
@@ -604,7 +606,8 @@ def main():
                "higher_is_better": True, "cases": []}
         for case in (1, 2, 3):
             w = synth.sweep_case(case)
-            res = sweep.run_case(w, hours=args.sweep_hours, log=log)
+            res = sweep.run_case(w, hours=args.sweep_hours, quadrature=args.sweep_quadrature,
+                                 filter_rate=0.0 if args.sweep_quadrature else FILTER_RATE, log=log)
             res["rho400_spread"] = sweep.summarise(w, res)
             del res["logrho_400km"]
             res.update({"f107bar": w.extra["fbar"], "day": w.extra["day"], "elements": int(w.nelem[0]), "p": 2})

@@ -23,13 +23,17 @@ def initial_state(w, gm):
     return np.concatenate(parts), r, off
 
 
-def run_case(w, hours=72.0, chunk_hours=6.0, filter_rate=0.5, log=None):
+def run_case(w, hours=72.0, chunk_hours=6.0, quadrature=1, filter_rate=0.0, log=None):
     """advance every column of the case `hours` of model time; returns timing, failures
-    and the log-density at the node nearest 400 km of each column at the end"""
+    and the log-density at the node nearest 400 km of each column at the end.
+    quadrature 1 (default): the over-integrated residual, the weak form of eq. (DGformulation)
+    with p + 2 Gauss points, no filter needed; 0: GLL collocation, which needs the modal
+    filter (filter_rate) against its growing intra-element mode"""
     import torch
 
     from . import Mesh
     gm = Mesh.columns(w.nelem, w.p, w.r_bot, w.r_top, w.stretch, w.phys, w.col_phys)
+    gm.set_option("column_quadrature", quadrature)
     u0, r, off = initial_state(w, gm)
     u = torch.from_numpy(u0).cuda()
     step_s = 30.0
@@ -62,6 +66,7 @@ def run_case(w, hours=72.0, chunk_hours=6.0, filter_rate=0.5, log=None):
         e, a = divmod(j, int(w.p[c]) + 1)
         z400.append(float(uf[off[c] + e * 3 * (int(w.p[c]) + 1) + a]))
     return {"case": w.name, "columns": gm.n_col, "dof": gm.n_dof, "steps": n_total, "model_hours": hours,
+            "quadrature": "p + 2 Gauss points" if quadrature else "GLL collocation", "filter_rate": filter_rate,
             "seconds": seconds, "column_steps_per_s": gm.n_col * n_total / seconds,
             "newton_per_column_step": newton / (gm.n_col * n_total), "failed": int(failed.sum()),
             "logrho_400km": z400}
