@@ -135,17 +135,17 @@ def element_pass_roofline(fl1, b1, p1_ms, tr_bytes, tr_detail, counters):
 # on (a changed kernel reports null until measured again)
 PASS1_PROFILE = "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_all-configs_counters.txt"
 PASS1_TRAFFIC = {
-    ("shell-p3", 0): {"src": "5d3c885aa94bd595", "fetch_kib": 52042.3, "write_kib": 151680.0, "valu_insts": 4.3085e+07,
+    ("shell-p3", 0): {"src": "07374365e5664407", "fetch_kib": 52042.3, "write_kib": 151680.0, "valu_insts": 4.3085e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 1): {"src": "5d3c885aa94bd595", "fetch_kib": 48189.3, "write_kib": 151680.0, "valu_insts": 4.2586e+07,
+    ("shell-p3", 1): {"src": "07374365e5664407", "fetch_kib": 48189.3, "write_kib": 151680.0, "valu_insts": 4.2586e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 2): {"src": "5d3c885aa94bd595", "fetch_kib": 51384.5, "write_kib": 151680.0, "valu_insts": 4.3091e+07,
+    ("shell-p3", 2): {"src": "07374365e5664407", "fetch_kib": 51384.5, "write_kib": 151680.0, "valu_insts": 4.3091e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 3): {"src": "5d3c885aa94bd595", "fetch_kib": 71786.6, "write_kib": 188544.0, "valu_insts": 4.2225e+07,
+    ("shell-p3", 3): {"src": "07374365e5664407", "fetch_kib": 71786.6, "write_kib": 188544.0, "valu_insts": 4.2225e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 4): {"src": "5d3c885aa94bd595", "fetch_kib": 58635.3, "write_kib": 163967.9, "valu_insts": 4.2632e+07,
+    ("shell-p3", 4): {"src": "07374365e5664407", "fetch_kib": 58635.3, "write_kib": 163967.9, "valu_insts": 4.2632e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 5): {"src": "5d3c885aa94bd595", "fetch_kib": 197420.9, "write_kib": 318528.0, "valu_insts": 4.2351e+07,
+    ("shell-p3", 5): {"src": "07374365e5664407", "fetch_kib": 197420.9, "write_kib": 318528.0, "valu_insts": 4.2351e+07,
                       "profile": PASS1_PROFILE},
 }
 
