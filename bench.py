@@ -433,6 +433,7 @@ def column_batch(n_steps=None):
         # trials of 32 steps: every call starts with a Jacobian build for every column, which
         # shorter trials overweight (they favour small grids, whose builds thrash the caches less)
         grid, _ = autotune.tune_columns(gm, u, 0.0, w.dt, steps=32, tag="q%d" % quad, log=log)
+        policy, _ = autotune.tune_columns_policy(gm, u, 0.0, w.dt, steps=32, tag="q%d" % quad, log=log)
         x = u.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -442,6 +443,7 @@ def column_batch(n_steps=None):
         st = np.asarray(st)
         report[name] = {"quadrature": "p + 2 Gauss points, exact mass matrix" if quad else "GLL collocation",
                         "filter_rate": rate, "seconds": el, "columns_per_s": gm.n_col / el, "grid": grid,
+                        "chord_rebuild": {"slow_pct": policy[0], "stale_its": policy[1], "every_steps": 32},
                         "newton_per_step_mean": float(np.asarray(its).mean() / n_steps),
                         "failed": int((st != 0).sum()),
                         "failed_columns": [{"column": int(c), "elements": int(w.nelem[c]), "p": int(w.p[c]),

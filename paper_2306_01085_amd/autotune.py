@@ -2,7 +2,8 @@
 
 tune_columns: picks the number of persistent wavefronts of dg_columns_integrate
 for a column batch by timing short trial integrations (on a scratch copy of the
-state) for each candidate; tune_shell_pass1: picks the element-pass configuration
+state) for each candidate; tune_columns_policy: then its chord-Jacobian rebuild
+thresholds the same way; tune_shell_pass1: picks the element-pass configuration
 of the shell residual. Results are cached in a JSON file keyed by the workload's
 shape (DG_TUNE_CACHE, default ~/.cache/dgthermo_tuning.json) and re-applied
 without timing on later calls.
@@ -77,6 +78,46 @@ def tune_columns(mesh, u, t0, dt, steps=8, candidates=(256, 512, 1024, 2048, 409
     best = int(min(times, key=times.get))
     mesh.set_option("columns_grid", best)
     cache[key] = {"grid": best, "times": times}
+    _store(cache)
+    return best, times
+
+
+def tune_columns_policy(mesh, u, t0, dt, steps=32, candidates=((75, 5), (50, 3), (90, 6), (99, 12)), force=False,
+                        log=None, tag=""):
+    """choose the chord-Jacobian rebuild thresholds of the column batch ('columns_jac_slow_pct',
+    'columns_jac_stale_its': rebuild within a stage when an iteration leaves |G| above that
+    percentage of its previous value, and after a step with a stage of more iterations than
+    that) by timing trials of `steps` steps at the mesh's current grid; they change iteration
+    counts, not what each stage converges to. Returns ((slow_pct, stale_its), {label: seconds})"""
+    import torch
+    key = columns_key(mesh) + tag + ":policy"
+    cache = _load()
+    if key in cache and not force:
+        best = tuple(cache[key]["policy"])
+        mesh.set_option("columns_jac_slow_pct", best[0])
+        mesh.set_option("columns_jac_stale_its", best[1])
+        return best, cache[key].get("times", {})
+    times = {}
+    scratch = torch.empty_like(u)
+    for slow, stale in candidates:
+        mesh.set_option("columns_jac_slow_pct", slow)
+        mesh.set_option("columns_jac_stale_its", stale)
+        scratch.copy_(u)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = mesh.columns_integrate(scratch, t0, dt, steps, raise_on_failure=False)
+        torch.cuda.synchronize()
+        label = "%d/%d" % (slow, stale)
+        # a policy that leaves more columns failed than the others is not a candidate
+        times[label] = (time.perf_counter() - t, int((np.asarray(st) != 0).sum()))
+        if log:
+            log("columns chord policy %s: %.3f s, %d failed" % (label, *times[label]))
+    fewest = min(f for _, f in times.values())
+    label = min((k for k, v in times.items() if v[1] == fewest), key=lambda k: times[k][0])
+    best = tuple(int(x) for x in label.split("/"))
+    mesh.set_option("columns_jac_slow_pct", best[0])
+    mesh.set_option("columns_jac_stale_its", best[1])
+    cache[key] = {"policy": list(best), "times": times}
     _store(cache)
     return best, times
 
