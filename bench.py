@@ -550,6 +550,20 @@ def warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epoc
                                                           for a, b in zip(s1["res0"], s2["res0"]) if b > 0]))},
             "state_rel_diff": float(torch.linalg.norm(up - ul).item() / torch.linalg.norm(up - u).item()),
         }
+        # what a guess must reach to save a Newton iteration: the plain guess starts at
+        # rho = |G(U_p)| / |G(u_n)| and Newton takes k iterations to 1e-8, so one iteration is worth
+        # a factor of about (1e-8 / rho)^(1/k) of the starting residual (geometric mean)
+        rho_p = [a / b for s in sp for a, b in zip(s["res0"], s["ref"]) if b > 0]
+        rho_l = [a / b for s in sl for a, b in zip(s["res0"], s["ref"]) if b > 0]
+        k_p = out[prec]["plain"]["newton"] / 3.0
+        gm_p = float(np.exp(np.mean(np.log(rho_p)))) if rho_p else None
+        out[prec]["guess_residual"] = {
+            "plain_res0_over_ref_geomean": gm_p,
+            "learned_res0_over_ref_geomean": float(np.exp(np.mean(np.log(rho_l)))) if rho_l else None,
+            "newton_per_stage_plain": k_p,
+            "factor_one_iteration_is_worth": float((1e-8 / gm_p) ** (1.0 / k_p)) if gm_p else None,
+            "note": "a guess saves a Newton iteration only if it lowers the starting stage residual by about "
+                    "this factor relative to the plain guess; the learned guess lowers it by res0_over_plain"}
     out["value"] = out["f32"]["learned"]["s_per_step"]
     out["vs_plain_f64"] = out["f64"]["plain"]["s_per_step"] / out["value"]
     return out
