@@ -112,16 +112,21 @@ __global__ __launch_bounds__(RED_THREADS) void k_orth_mdot(int64_t n, const T* _
   if (threadIdx.x < K) part[blockIdx.x * K + threadIdx.x] = red[threadIdx.x];
 }
 
-// w -= sum_k h[k] V_k ; part = partial sums of w^2 (for the norm)
-template <class T>
-__global__ __launch_bounds__(RED_THREADS) void k_orth_update(int64_t n, const T* __restrict__ V, int64_t ldv, int K,
+// w -= sum_k h[k] V_k ; part = partial sums of w^2 (for the norm). K is a template argument
+// like the dot-product sweeps': with K known the loads of the K basis vectors are issued
+// together (with K read at run time each load was waited for before the next, the sweep ran
+// at a quarter of the HBM rate); the subtraction order is the same.
+template <int K, class T>
+__global__ __launch_bounds__(RED_THREADS) void k_orth_update(int64_t n, const T* __restrict__ V, int64_t ldv,
                                                              const double* __restrict__ h, T* __restrict__ w,
                                                              double* __restrict__ part) {
   __shared__ double red[(RED_THREADS / 64) + 1];
+  double hk[K];
+  for (int k = 0; k < K; ++k) hk[k] = h[k];
   double acc[1] = {0.0};
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double x = (double)w[i];
-    for (int k = 0; k < K; ++k) x -= h[k] * (double)V[k * ldv + i];
+    for (int k = 0; k < K; ++k) x -= hk[k] * (double)V[k * ldv + i];
     const T xt = (T)x;
     w[i] = xt;
     acc[0] += (double)xt * (double)xt;
@@ -197,14 +202,40 @@ __global__ void k_stage_op(int64_t n, const T* __restrict__ z, double c, T* __re
     jz[i] = (T)((double)z[i] - c * (double)jz[i]);
 }
 
-// s = sum_k y[k] V_k (T), with y on the device
-template <class T>
-__global__ void k_combine(int64_t n, const T* __restrict__ V, int64_t ldv, int K, const double* __restrict__ y,
+// s = sum_k y[k] V_k (T), with y on the device (K a template argument, as in k_orth_update)
+template <int K, class T>
+__global__ void k_combine(int64_t n, const T* __restrict__ V, int64_t ldv, const double* __restrict__ y,
                           T* __restrict__ s) {
+  double yk[K];
+  for (int k = 0; k < K; ++k) yk[k] = y[k];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double a = 0;
-    for (int k = 0; k < K; ++k) a += y[k] * (double)V[k * ldv + i];
+    for (int k = 0; k < K; ++k) a += yk[k] * (double)V[k * ldv + i];
     s[i] = (T)a;
+  }
+}
+
+template <class T>
+__global__ void k_zero(int64_t n, T* __restrict__ s) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s[i] = T(0);
+}
+
+template <class T, int K = 1>
+static void launch_combine(int kk, int nb, hipStream_t st, int64_t n, const T* V, int64_t ldv, const double* y,
+                           T* s) {
+  if (K == 1 && kk < 1) {   // (an empty basis: s = 0)
+    k_zero<T><<<nb, RED_THREADS, 0, st>>>(n, s);
+    return;
+  }
+  if constexpr (K > 33) {
+    (void)kk; (void)nb; (void)st; (void)n; (void)V; (void)ldv; (void)y; (void)s;
+  } else {
+    if (kk == K) {
+      k_combine<K, T><<<nb, RED_THREADS, 0, st>>>(n, V, ldv, y, s);
+      return;
+    }
+    launch_combine<T, K + 1>(kk, nb, st, n, V, ldv, y, s);
   }
 }
 
@@ -588,6 +619,27 @@ static int launch_orth_mdot_k(int64_t n, const T* V, int64_t ldv, const double* 
   return nb;
 }
 
+template <int K, class T>
+static int launch_orth_update_k(int64_t n, const T* V, int64_t ldv, const double* h, T* w, double* part, int nb,
+                                hipStream_t s) {
+  static const int cap = resident_grid(reinterpret_cast<const void*>(&k_orth_update<K, T>));
+  nb = std::min(nb, cap);
+  k_orth_update<K, T><<<nb, RED_THREADS, 0, s>>>(n, V, ldv, h, w, part);
+  return nb;
+}
+
+template <class T, int K = 1>
+static int launch_orth_update(int kk, int64_t n, const T* V, int64_t ldv, const double* h, T* w, double* part, int nb,
+                              hipStream_t s) {
+  if constexpr (K > 33) {
+    (void)kk; (void)n; (void)V; (void)ldv; (void)h; (void)w; (void)part; (void)s;
+    return nb;
+  } else {
+    if (kk == K) return launch_orth_update_k<K, T>(n, V, ldv, h, w, part, nb, s);
+    return launch_orth_update<T, K + 1>(kk, n, V, ldv, h, w, part, nb, s);
+  }
+}
+
 template <class T, int K = 1>
 static int launch_orth_mdot(int kk, int64_t n, const T* V, int64_t ldv, const double* h, T* w, double* part, int nb,
                             hipStream_t s) {
@@ -803,8 +855,8 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
         k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb1, j + 1, h1);
         const int nb2 = launch_orth_mdot<T>(j + 1, n, V, n, h1, w, ws->part, nb, s);
         k_reduce<<<j + 1, RED_THREADS, 0, s>>>(ws->part, nb2, j + 1, h2);
-        k_orth_update<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, j + 1, h2, w, ws->part);
-        k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb, 1, nr);
+        const int nb3 = launch_orth_update<T>(j + 1, n, V, n, h2, w, ws->part, nb, s);
+        k_reduce<<<1, RED_THREADS, 0, s>>>(ws->part, nb3, 1, nr);
         k_normalize<T><<<nb, RED_THREADS, 0, s>>>(n, w, nr, V + (size_t)(j + 1) * n);
       }
       DG_HIP_CHECK(hipMemcpyAsync(host, ws->dev_small, (2 * KMAX + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -844,7 +896,7 @@ static dg_status_t gmres(dg_mesh_s* m, Workspace* ws, double t, double c, const 
     }
     for (int i = 0; i < kused; ++i) host[3 * KMAX + i] = y[i];
     DG_HIP_CHECK(hipMemcpyAsync(yv, host + 3 * KMAX, kused * sizeof(double), hipMemcpyHostToDevice, s));
-    k_combine<T><<<nb, RED_THREADS, 0, s>>>(n, V, n, kused, yv, sv);
+    launch_combine<T>(kused, nb, s, n, V, n, yv, sv);
     dg_status_t st = precond_rb(m, ws, pc, sv, z, w, s);
     if (st != DG_OK) return st;
     k_add_to<T><<<nb, RED_THREADS, 0, s>>>(n, z, X);
