@@ -281,13 +281,9 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
       s_cn[le][f][w] = w == 0 ? M.cnbr[cell * 4 + f] : (w == 1 ? M.cface[cell * 4 + f] : M.cmap[(cell * 4 + f) * n + w - 2]);
     }
   }
-  S uu[5];
   const int64_t base = (int64_t)e * 5 * N;
   if (active)
-    for (int c = 0; c < 5; ++c) {
-      uu[c] = load_state<S>(u, v, base + c * N + j);
-      s_u[le][c][j + PL * (j / N2)] = uu[c];
-    }
+    for (int c = 0; c < 5; ++c) s_u[le][c][j + PL * (j / N2)] = load_state<S>(u, v, base + c * N + j);
   const double rk = live ? M.edges[k] : 0.0;
   const double hk = live ? M.edges[k + 1] - rk : 1.0;
   lds_barrier();
@@ -438,6 +434,10 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
     // boundary faces: the terms (F - F_hat).Sn are completed here. On the lower face (and
     // every boundary face in bc_mode 1), F_hat.Sn = F(u_b, q).Sn + |Sn| sigma(u_b)(u - u_b)
     // is taken before the node's own flux so that q need not outlive it.
+    // the node's own state, read back from LDS here rather than held in registers through
+    // the face tasks and the gradient
+    S uu[5];
+    for (int c = 0; c < 5; ++c) uu[c] = s_u[le][c][j + PL * cz];
     const bool bot = (k == 0 && cz == 0);
     const bool top = (k == M.n_rad - 1 && cz == n - 1);
     const bool dir = bot || (top && ph.bc_mode == 1);
