@@ -42,40 +42,61 @@ __global__ __launch_bounds__(256) void shell_pass2(ShellDev M, GllC gc, const OT
   constexpr int W = L * (int)sizeof(OT) / 8;                    // as 8-byte words
   static_assert((L * sizeof(OT)) % 8 == 0, "trace block must be whole 8-byte words");
   constexpr bool kWide = (W % 2) == 0;                          // the block is whole 16-byte words
-  __shared__ __align__(16) uint64_t s_tw[EPB][W];
+  // (each element's block padded to whole rounds of TPE copies: every lane stores each round)
+  constexpr int WP = kWide ? 2 * TPE * ((W / 2 + TPE - 1) / TPE) : TPE * ((W + TPE - 1) / TPE);
+  __shared__ __align__(16) uint64_t s_tw[EPB][WP];
   const int le = threadIdx.x / TPE;
   const int j = threadIdx.x % TPE;
   const int e = xcd_block_reversed(blockIdx.x, gridDim.x) * EPB + le;
   const bool live = e < M.E;
   const int a = j % n, b = (j / n) % n, cz = j / N2;
-  const int cell = live ? e / M.n_rad : 0, k = live ? e % M.n_rad : 0;
+  const int k = live ? e % M.n_rad : 0;
   const bool on[6] = {a == 0, a == n - 1, b == 0, b == n - 1, cz == 0 && k > 0, cz == n - 1 && k < M.n_rad - 1};
   const bool upd = live && j < N && (on[0] || on[1] || on[2] || on[3] || on[4] || on[5]);
-  const int64_t base = (int64_t)e * 5 * N;
+  // Every load of the pass is issued in one branch-free stretch, before any is used, so that a
+  // wavefront waits for memory once: the lanes without work (past the last element, past the
+  // element's nodes, interior nodes) read in-range addresses of element min(e, E - 1) and node
+  // min(j, N - 1) and store nothing.
+  const int ec = live ? e : M.E - 1;
+  const int jc = j < N ? j : N - 1;
+  const int64_t base = (int64_t)ec * 5 * N;
   OT r[5];
-  if (upd)
-    for (int c = 0; c < 5; ++c) r[c] = R[base + c * N + j];
-  if (live) {
-    // the block starts at e * L * sizeof(OT) bytes, a multiple of 8 (L * sizeof(OT) is)
-    // (16-byte words where the block is made of them: it then starts on a 16-byte boundary)
-    if constexpr (kWide) {
-      const uint4* src = reinterpret_cast<const uint4*>(Fin + (int64_t)e * L);
-      uint4* dst = reinterpret_cast<uint4*>(&s_tw[le][0]);
-      for (int w = j; w < W / 2; w += TPE) dst[w] = src[w];
-    } else {
-      const uint64_t* src = reinterpret_cast<const uint64_t*>(Fin + (int64_t)e * L);
-      for (int w = j; w < W; w += TPE) s_tw[le][w] = src[w];
-    }
+  for (int c = 0; c < 5; ++c) r[c] = R[base + c * N + jc];
+  const int ja = (jc % n) + n * ((jc / n) % n);
+  const int kc = ec % M.n_rad;
+  const double jang = M.ang[((int64_t)(ec / M.n_rad) * 13 + 9) * N2 + ja];
+  const double e0 = M.edges[kc], e1 = M.edges[kc + 1];
+  double xz = gc.x[0];   // the node's GLL point
+  for (int q = 1; q < n; ++q) xz = (cz == q) ? gc.x[q] : xz;
+  // the element's incoming trace block (it starts at e * L * sizeof(OT) bytes, a multiple of 8,
+  // of 16 where the block is made of 16-byte words), copied to LDS
+  if constexpr (kWide) {
+    constexpr int NW = W / 2, NI = (NW + TPE - 1) / TPE;
+    const uint4* src = reinterpret_cast<const uint4*>(Fin + (int64_t)ec * L);
+    uint4* dst = reinterpret_cast<uint4*>(&s_tw[le][0]);
+    uint4 tw[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) tw[i] = src[min(j + i * TPE, NW - 1)];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) dst[j + i * TPE] = tw[i];
+  } else {
+    constexpr int NI = (W + TPE - 1) / TPE;
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(Fin + (int64_t)ec * L);
+    uint64_t tw[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) tw[i] = src[min(j + i * TPE, W - 1)];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) s_tw[le][j + i * TPE] = tw[i];
   }
+  // (the compiler turns the GLL point's selection into a load from the argument block and
+  // would sink it past the barrier, into the updating lanes' branch: its value is required here)
+  __asm__ __volatile__("" : "+v"(xz));
   lds_barrier();
   if (!upd) return;
   const OT* Fe = reinterpret_cast<const OT*>(&s_tw[le][0]);
-  const int ja = a + n * b;
-  const double rk = M.edges[k], hk = M.edges[k + 1] - rk;
-  double xz = gc.x[0];   // the node's GLL point, selected (not indexed: no memory access)
-  for (int q = 1; q < n; ++q) xz = (cz == q) ? gc.x[q] : xz;
-  const double rc = rk + 0.5 * (xz + 1.0) * hk;
-  const double Jac = rc * rc * (0.5 * hk) * M.ang[((int64_t)cell * 13 + 9) * N2 + ja];
+  const double hk = e1 - e0;
+  const double rc = e0 + 0.5 * (xz + 1.0) * hk;
+  const double Jac = rc * rc * (0.5 * hk) * jang;
   const OT hl = OT(0.5 / (gc.w[0] * Jac));
   OT acc[5] = {OT(0), OT(0), OT(0), OT(0), OT(0)};
   for (int f = 0; f < 6; ++f) {

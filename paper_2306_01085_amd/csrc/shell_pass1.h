@@ -25,6 +25,14 @@ __device__ inline S load_state(const SU* u, const TV* v, int64_t i) {
   return Io<S>::ld(u, v, i);
 }
 
+// a loaded value required at this point: the load is neither sunk past it (into the branch
+// that stores the value) nor reordered after the loads issued later (an empty instruction
+// that reads and writes the register)
+__device__ inline void pin(double& x) { __asm__ __volatile__("" : "+v"(x)); }
+__device__ inline void pin(float& x) { __asm__ __volatile__("" : "+v"(x)); }
+__device__ inline void pin(int& x) { __asm__ __volatile__("" : "+v"(x)); }
+template <class T> __device__ inline void pin(Dual<T>& x) { pin(x.v); pin(x.d); }
+
 // neighbour of a face node: returns the neighbour element (or -1 on a boundary),
 // the neighbour's local node and the neighbour's face index / face-node index
 template <int P>
@@ -272,20 +280,51 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   const bool active = live && (j < N);
   const int cell = live ? e / M.n_rad : 0;
   const int k = live ? e % M.n_rad : 0;
-  if (threadIdx.x < n * n) D[threadIdx.x] = gc.D[threadIdx.x];
   const double w_end = gc.w[0];
-  if (live) {
-    for (int idx = j; idx < 13 * N2; idx += TPE) s_ang[le][idx / N2][idx % N2] = M.ang[(int64_t)cell * 13 * N2 + idx];
-    if (j < 4 * (n + 2)) {
-      const int f = j / (n + 2), w = j % (n + 2);
-      s_cn[le][f][w] = w == 0 ? M.cnbr[cell * 4 + f] : (w == 1 ? M.cface[cell * 4 + f] : M.cmap[(cell * 4 + f) * n + w - 2]);
-    }
-  }
   const int64_t base = (int64_t)e * 5 * N;
+  // ---- phase A: the element's own data (the operator D, the angular metric terms, the
+  // connectivity, the state, the layer's radii) to LDS. Every load is issued before the first
+  // is stored, so that a wavefront waits for memory once (a copy loop would wait once per
+  // round); lanes without a value to store read in-range addresses (element min(e, E - 1),
+  // node min(j, N - 1)).
+  constexpr int NA = (13 * N2 + TPE - 1) / TPE;
+  constexpr int NC = 4 * (n + 2);
+  static_assert(NC <= TPE, "one connectivity word per thread");
+  const int ec = live ? e : M.E - 1;
+  const int cc = ec / M.n_rad, kc = ec % M.n_rad;
+  double ta[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) ta[i] = M.ang[(int64_t)cc * 13 * N2 + min(j + i * TPE, 13 * N2 - 1)];
+  const int jw = min(j, NC - 1), cf = jw / (n + 2), cw = jw % (n + 2);
+  const int* cp = cw == 0 ? M.cnbr + cc * 4 + cf : (cw == 1 ? M.cface + cc * 4 + cf : M.cmap + (cc * 4 + cf) * n + cw - 2);
+  int tcn = *cp;
+  S tu[5];
+  const int64_t bc = (int64_t)ec * 5 * N + min(j, N - 1);
+  for (int c = 0; c < 5; ++c) tu[c] = load_state<S>(u, v, bc + c * N);
+  double e0 = M.edges[kc], e1 = M.edges[kc + 1];
+  double tD = gc.D[min((int)threadIdx.x, n * n - 1)];
+  // (D first: it is read from the argument block, a load the compiler would otherwise issue
+  // only after the others had been waited for)
+  pin(tD);
+#pragma unroll
+  for (int i = 0; i < NA; ++i) pin(ta[i]);
+  pin(tcn);
+  for (int c = 0; c < 5; ++c) pin(tu[c]);
+  pin(e0);
+  pin(e1);
+  if (threadIdx.x < n * n) D[threadIdx.x] = tD;
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int idx = j + i * TPE;
+      if (idx < 13 * N2) s_ang[le][idx / N2][idx % N2] = ta[i];
+    }
+    if (j < NC) s_cn[le][cf][cw] = tcn;
+  }
   if (active)
-    for (int c = 0; c < 5; ++c) s_u[le][c][j + PL * (j / N2)] = load_state<S>(u, v, base + c * N + j);
-  const double rk = live ? M.edges[k] : 0.0;
-  const double hk = live ? M.edges[k + 1] - rk : 1.0;
+    for (int c = 0; c < 5; ++c) s_u[le][c][j + PL * (j / N2)] = tu[c];
+  const double rk = live ? e0 : 0.0;
+  const double hk = live ? e1 - e0 : 1.0;
   lds_barrier();
   // owned interior faces (bit f): the neighbour has the larger element index
   int own = 0;
