@@ -226,6 +226,11 @@ __device__ inline void line_row(F (&dst)[RS], const F* __restrict__ src) {
   }
 }
 
+// a loaded value required at this point (the load can be neither sunk into the branch that
+// stores it nor issued after the loads that follow it in the source)
+__device__ inline void line_pin(double& x) { __asm__ __volatile__("" : "+v"(x)); }
+__device__ inline void line_pin(float& x) { __asm__ __volatile__("" : "+v"(x)); }
+
 // ordering of LDS accesses among the lanes of one wavefront (LDS operations of a
 // wavefront complete in issue order; this only keeps the compiler from moving them)
 __device__ inline void line_wave_sync() {
@@ -254,14 +259,31 @@ __global__ __launch_bounds__(64 * WPB) void k_line_solve(LineDev L, int64_t n_li
   const bool act = ls < LPW && slot < LPB && line < n_lines;
   const int nr = L.n_rad;
   const int nb = nr * b;
-  // gather: unknown (k, c * n + cz) of line slot q <- r[e = cell n_rad + k][c][ab + N2 cz]
-  for (int idx = threadIdx.x; idx < LPB * nb; idx += 64 * WPB) {
-    const int q = idx / nb, w = idx % nb;
-    const int64_t ln = line0 + q;
-    if (ln >= n_lines) continue;
-    const int k = w / b, rr = w % b, c = rr / L.n, cz = rr % L.n;
-    const int64_t e = (ln / L.N2) * nr + k;
-    x[idx] = rin[(e * 5 + c) * L.N + (ln % L.N2) + L.N2 * cz];
+  // gather: unknown w = (k, c n + cz) of line slot q <- r[e = cell n_rad + k][c][ab + N2 cz],
+  // taken in the order idx = w LPB + q (consecutive lanes read consecutive lines: the same
+  // node of consecutive (a, b) columns, adjacent in memory), GK loads per thread issued before
+  // any is stored (a load-store loop waits for memory once per round); lanes past the end read
+  // the last in-range entry and store nothing
+  constexpr int n = b / 5, N2 = n * n, N = N2 * n, GK = 8, NT = 64 * WPB;
+  const int tot = LPB * nb;
+  auto rin_index = [&](int idx) -> int64_t {
+    const int q = idx % LPB, w = idx / LPB;
+    const int64_t ln = min(line0 + q, n_lines - 1);
+    const int k = w / b, rr = w % b, c = rr / n, cz = rr % n;
+    const int64_t e = (ln / N2) * nr + k;
+    return (e * 5 + c) * N + (ln % N2) + N2 * cz;
+  };
+  for (int i0 = threadIdx.x; i0 < tot; i0 += GK * NT) {
+    T g[GK];
+#pragma unroll
+    for (int u = 0; u < GK; ++u) g[u] = rin[rin_index(min(i0 + u * NT, tot - 1))];
+#pragma unroll
+    for (int u = 0; u < GK; ++u) line_pin(g[u]);
+#pragma unroll
+    for (int u = 0; u < GK; ++u) {
+      const int idx = i0 + u * NT;
+      if (idx < tot) x[(idx % LPB) * nb + idx / LPB] = g[u];
+    }
   }
   __syncthreads();
   T* xl = x + (act ? slot : 0) * nb;
@@ -308,14 +330,9 @@ __global__ __launch_bounds__(64 * WPB) void k_line_solve(LineDev L, int64_t n_li
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < LPB * nb; idx += 64 * WPB) {
-    const int q = idx / nb, w = idx % nb;
-    const int64_t ln = line0 + q;
-    if (ln >= n_lines) continue;
-    const int k = w / b, rr = w % b, c = rr / L.n, cz = rr % L.n;
-    const int64_t e = (ln / L.N2) * nr + k;
-    z[(e * 5 + c) * L.N + (ln % L.N2) + L.N2 * cz] = x[idx];
-  }
+  // scatter, in the gather's order
+  for (int idx = threadIdx.x; idx < tot; idx += NT)
+    if (line0 + idx % LPB < n_lines) z[rin_index(idx)] = x[(idx % LPB) * nb + idx / LPB];
 }
 
 static LineDev line_dev(dg_mesh_s* m, double* Lo, double* Di, double* Up) {
