@@ -27,10 +27,12 @@ __device__ inline S load_state(const SU* u, const TV* v, int64_t i) {
 
 // a loaded value required at this point: the load is neither sunk past it (into the branch
 // that stores the value) nor reordered after the loads issued later (an empty instruction
-// that reads and writes the register)
-__device__ inline void pin(double& x) { __asm__ __volatile__("" : "+v"(x)); }
-__device__ inline void pin(float& x) { __asm__ __volatile__("" : "+v"(x)); }
-__device__ inline void pin(int& x) { __asm__ __volatile__("" : "+v"(x)); }
+// that reads and writes the register). Not volatile: a volatile one counts as a possible
+// memory write, after which uniform loads of global data (the EUVAC table, physics
+// constants) could no longer be scalar loads.
+__device__ inline void pin(double& x) { __asm__("" : "+v"(x)); }
+__device__ inline void pin(float& x) { __asm__("" : "+v"(x)); }
+__device__ inline void pin(int& x) { __asm__("" : "+v"(x)); }
 template <class T> __device__ inline void pin(Dual<T>& x) { pin(x.v); pin(x.d); }
 
 // neighbour of a face node: returns the neighbour element (or -1 on a boundary),
