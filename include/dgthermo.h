@@ -328,7 +328,7 @@ dg_status_t dg_profile_read(dg_mesh_t mesh, double* ms_host, int64_t* counts_hos
  *   "line_solve_config" -1..5: launch configuration of the radial-line preconditioner's
  *   substitution (0/2: one wavefront per block, 1/3: four, 4/5: the (p + 1)^2 lines of
  *   one angular cell per block; 0/1/5: loads one matrix ahead, 2/3/4: three ahead;
- *   default -1: 4 for FP64 Krylov vectors, 3 for FP32). No effect on results.
+ *   default -1: 5 for FP64 Krylov vectors, 3 for FP32). No effect on results.
  *   "line_pc_every" >= 1 (default 1): dg_implicit_step with precond 2 rebuilds the
  *   radial-line preconditioner from the current state only every this many steps (and
  *   whenever dt a_ii or the J v precision changes or a step does not start where the

@@ -171,9 +171,6 @@ __global__ __launch_bounds__(64) void k_line_factor(LineDev L) {
 // lane reads its whole row with 16- or 8-byte loads.
 __host__ __device__ constexpr int line_rs(int b) { return (b + 3) & ~3; }
 
-__device__ inline double line_cv(double v) { return v; }
-__device__ inline float line_cv(float v) { return v; }
-__device__ inline float line_cv(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 template <class F> __device__ inline F line_st(double v);
 template <> __device__ inline double line_st<double>(double v) { return v; }
@@ -204,26 +201,49 @@ __global__ void k_line_pack(LineDev L, int64_t n_lines, F* __restrict__ P) {
   }
 }
 
-// dst <- the row at src (RS entries of F, RS * sizeof(F) a multiple of 8 and src aligned to it)
+// A row of a packed matrix held as the 32-bit words it was loaded as (RS entries of F,
+// RS * sizeof(F) a multiple of 8, src aligned to it): BF16 rows stay two entries per register
+// until used, so that a ring of rows takes half the registers.
 template <int RS, class F>
-__device__ inline void line_row(F (&dst)[RS], const F* __restrict__ src) {
+struct LineRow {
+  static constexpr int W = RS * (int)sizeof(F) / 4;
+  uint32_t w[W];
+};
+template <int RS, class F>
+__device__ inline void line_row(LineRow<RS, F>& dst, const F* __restrict__ src) {
   constexpr int bytes = RS * (int)sizeof(F);
   if constexpr (bytes % 16 == 0) {
     const uint4* s4 = reinterpret_cast<const uint4*>(src);
 #pragma unroll
     for (int i = 0; i < bytes / 16; ++i) {
-      const uint4 w = s4[i];
-      __builtin_memcpy(reinterpret_cast<char*>(dst) + 16 * i, &w, 16);
+      const uint4 v = s4[i];
+      dst.w[4 * i] = v.x;
+      dst.w[4 * i + 1] = v.y;
+      dst.w[4 * i + 2] = v.z;
+      dst.w[4 * i + 3] = v.w;
     }
   } else {
     static_assert(bytes % 8 == 0, "row size");
     const uint2* s2 = reinterpret_cast<const uint2*>(src);
 #pragma unroll
     for (int i = 0; i < bytes / 8; ++i) {
-      const uint2 w = s2[i];
-      __builtin_memcpy(reinterpret_cast<char*>(dst) + 8 * i, &w, 8);
+      const uint2 v = s2[i];
+      dst.w[2 * i] = v.x;
+      dst.w[2 * i + 1] = v.y;
     }
   }
+}
+// entry q of a row, widened (bf16 -> float exactly, float and double as they are)
+template <int RS>
+__device__ inline float line_at(const LineRow<RS, unsigned short>& r, int q) {
+  const uint32_t w = r.w[q >> 1];
+  return __uint_as_float((q & 1) ? (w & 0xffff0000u) : (w << 16));
+}
+template <int RS>
+__device__ inline float line_at(const LineRow<RS, float>& r, int q) { return __uint_as_float(r.w[q]); }
+template <int RS>
+__device__ inline double line_at(const LineRow<RS, double>& r, int q) {
+  return __hiloint2double((int)r.w[2 * q + 1], (int)r.w[2 * q]);
 }
 
 // a loaded value required at this point (the load can be neither sunk into the branch that
@@ -299,12 +319,12 @@ __global__ __launch_bounds__(64 * WPB) void k_line_solve(LineDev L, int64_t n_li
     if (j < 2 * nr - 1) return Pl + ((int64_t)((j + 1) / 2) * 3 + ((j & 1) ? 0 : 1)) * MS;
     return Pl + ((int64_t)(nr - 2 - (j - (2 * nr - 1))) * 3 + 2) * MS;
   };
-  auto step = [&](int j, const F (&R)[RS]) {
+  auto step = [&](int j, const LineRow<RS, F>& R) {
     if (j < 2 * nr - 1 && !(j & 1)) {
       T* xk = xl + (j / 2) * b;
       T sum = 0;
 #pragma unroll
-      for (int q = 0; q < b; ++q) sum += (T)line_cv(R[q]) * xk[q];
+      for (int q = 0; q < b; ++q) sum += (T)line_at(R, q) * xk[q];
       line_wave_sync();
       if (act) xk[r] = sum;
     } else {
@@ -312,14 +332,14 @@ __global__ __launch_bounds__(64 * WPB) void k_line_solve(LineDev L, int64_t n_li
       const T* xo = xl + (j < 2 * nr - 1 ? k - 1 : k + 1) * b;
       T sum = 0;
 #pragma unroll
-      for (int q = 0; q < b; ++q) sum += (T)line_cv(R[q]) * xo[q];
+      for (int q = 0; q < b; ++q) sum += (T)line_at(R, q) * xo[q];
       if (act) xl[k * b + r] -= sum;
     }
     line_wave_sync();
   };
   // loads are issued on every lane and every pass (idle lanes read line 0) so that the
   // wait for one row never covers the younger ones
-  F R[D][RS];
+  LineRow<RS, F> R[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) line_row<RS>(R[d], row_of(d));
   for (int j = 0; j < nm; j += D) {
@@ -431,7 +451,8 @@ static void line_solve_launch(const LineDev& L, int64_t lines, int prec, const v
 // 0: 1 wavefront per block, 2-deep ring; 1: 4 wavefronts, 2-deep; 2: 1 wavefront, 4-deep;
 // 3: 4 wavefronts, 4-deep; 4 / 5: the (p + 1)^2 lines of one angular cell per block (its
 // vector entries are whole cache lines), 4-deep / 2-deep (at p = 4, whose cell would take
-// 13 wavefronts, the same as 3 / 1)
+// 13 wavefronts, the same as 3 / 1). Eight-deep rings measured the same as four-deep ones
+// (within 1% at p = 3 and p = 4): the substitution streams its factors near the HBM rate.
 template <int b, class T>
 static void line_solve_cfg(int cfg, const LineDev& L, int64_t lines, int prec, const void* P, const T* r, T* z,
                            hipStream_t s) {
