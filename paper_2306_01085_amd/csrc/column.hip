@@ -762,25 +762,39 @@ __device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, 
 // The substitution is a chain over the elements, so the chain itself stays in LDS: row r of
 // a block belongs to the four lanes 4r..4r+3 (columns q, q + 4, ... of lane q; their partial
 // products are summed across the four lanes), the latest two solutions are in LDS for the
-// next elements, each also goes to X for the backward sweep, and the block rows and
-// right-hand side of the next element are loaded while the current one is worked on. Only
-// LDS ordering is needed between the steps (one wavefront); global memory is fenced at the
-// end.
+// next elements, each also goes to X for the backward sweep. The block rows and right-hand
+// sides of the next PF elements are in flight while one is worked on: a ring of PF register
+// slots, refilled right after use, the loads issued unconditionally (clamped to the last
+// element) so that the wait for one slot never covers the younger ones. Only LDS ordering is
+// needed between the steps (one wavefront); global memory is fenced at the end. Not inlined:
+// the ring gets registers of its own instead of sharing the kernel's spilled budget (the
+// pointers are then marked global again, or their loads would be flat ones, which every wait
+// for an LDS result would also wait for).
+typedef const double __attribute__((address_space(1))) gcdouble;
+typedef double __attribute__((address_space(1))) gdouble;
 template <int P, bool BW2>
-__device__ __forceinline__ void colw_solve(int E, const double* Lo, const double* Di, const double* Up,
-                                           const double* Lo2, const double* Up2, double* X) {
+__device__ __attribute__((noinline)) void colw_solve(int E, const double* Lo_, const double* Di_, const double* Up_,
+                                                     const double* Lo2_, const double* Up2_, double* X_) {
+  gcdouble* Lo = (gcdouble*)Lo_;
+  gcdouble* Di = (gcdouble*)Di_;
+  gcdouble* Up = (gcdouble*)Up_;
+  gcdouble* Lo2 = (gcdouble*)Lo2_;
+  gcdouble* Up2 = (gcdouble*)Up2_;
+  gdouble* X = (gdouble*)X_;
   constexpr int b = 3 * (P + 1);
   constexpr int bb = b * b;
   constexpr int NQ = (b + 3) / 4;   // columns per lane
+  constexpr int PF = (P == 4 && BW2) ? 3 : 4;   // elements in flight (the largest blocks: 3, to stay in registers)
   const int lane = wlane();
   const int r = lane >> 2, q = lane & 3;
   const bool row = r < b;
+  const int rr = row ? r : 0;       // (lanes past the block's rows load row 0 and use none of it)
   __shared__ double s_x[b], s_x2[b], s_v[b];
-  auto seg = [&](const double* blk, double (&o)[NQ]) {
+  auto seg = [&](gcdouble* blk, double (&o)[NQ]) {
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
       const int k = q + 4 * t;
-      o[t] = (row && k < b) ? blk[r * b + k] : 0.0;
+      o[t] = blk[rr * b + (k < b ? k : b - 1)];
     }
   };
   auto dot4 = [&](const double (&a)[NQ], const double* x) {
@@ -788,86 +802,80 @@ __device__ __forceinline__ void colw_solve(int E, const double* Lo, const double
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
       const int k = q + 4 * t;
-      if (k < b) acc += a[t] * x[k];
+      if (row && k < b) acc += a[t] * x[k];
     }
     acc += wshfl_xor(acc, lane, 1);
     acc += wshfl_xor(acc, lane, 2);
     return acc;
   };
-  auto zero = [&](double (&o)[NQ]) {
+  // forward: slot d holds element e0 + d's L1, S^-1, L2 rows and right-hand side
+  {
+    double Lr[PF][NQ], Dr[PF][NQ], L2r[PF][NQ], rv[PF];
+    auto fetch = [&](int e, int d) {
+      e = e < E ? e : E - 1;
+      seg(Lo + (int64_t)e * bb, Lr[d]);
+      seg(Di + (int64_t)e * bb, Dr[d]);
+      if constexpr (BW2) seg(Lo2 + (int64_t)e * bb, L2r[d]);
+      rv[d] = X[e * b + rr];
+    };
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) o[t] = 0.0;
-  };
-  // forward
-  double Lc[NQ], Dc[NQ], L2c[NQ], Ln[NQ], Dn[NQ], L2n[NQ];
-  seg(Di, Dc);
-  zero(Lc);
-  zero(L2c);
-  zero(L2n);
-  double rc = row ? X[r] : 0.0, rn = 0.0;
-  for (int e = 0; e < E; ++e) {
-    if (e + 1 < E) {
-      seg(Lo + (int64_t)(e + 1) * bb, Ln);
-      seg(Di + (int64_t)(e + 1) * bb, Dn);
-      if constexpr (BW2) {
-        if (e + 1 >= 2) seg(Lo2 + (int64_t)(e + 1) * bb, L2n);
+    for (int d = 0; d < PF; ++d) fetch(d, d);
+    for (int e0 = 0; e0 < E; e0 += PF) {
+#pragma unroll
+      for (int d = 0; d < PF; ++d) {
+        const int e = e0 + d;
+        if (e < E) {
+          double v = rv[d];
+          if (e > 0) v -= dot4(Lr[d], s_x);
+          if constexpr (BW2) {
+            if (e > 1) v -= dot4(L2r[d], s_x2);
+          }
+          if (row && q == 0) s_v[r] = v;
+          lds_barrier();
+          const double y = dot4(Dr[d], s_v);
+          if (row) X[e * b + r] = y;   // (every lane of the row: each reads back its own store)
+          if (row && q == 0) {
+            if constexpr (BW2) s_x2[r] = s_x[r];
+            s_x[r] = y;
+          }
+          lds_barrier();
+        }
+        fetch(e + PF, d);
       }
-      rn = row ? X[(e + 1) * b + r] : 0.0;
     }
-    double v = rc;
-    if (e > 0) v -= dot4(Lc, s_x);
-    if constexpr (BW2) {
-      if (e > 1) v -= dot4(L2c, s_x2);
-    }
-    if (row && q == 0) s_v[r] = v;
-    lds_barrier();
-    const double y = dot4(Dc, s_v);
-    if (row) X[e * b + r] = y;   // (every lane of the row: each reads back its own store)
-    if (row && q == 0) {
-      if constexpr (BW2) s_x2[r] = s_x[r];
-      s_x[r] = y;
-    }
-    lds_barrier();
-#pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-      Lc[t] = Ln[t];
-      Dc[t] = Dn[t];
-      L2c[t] = L2n[t];
-    }
-    rc = rn;
   }
-  // backward; s_x holds x_{E-1} = y_{E-1}
-  double Wc[NQ], Wn[NQ], W2c[NQ], W2n[NQ];
-  zero(W2c);
-  zero(W2n);
-  double xc = 0.0, xn = 0.0;
-  if (E >= 2) {
-    seg(Up + (int64_t)(E - 2) * bb, Wc);
-    xc = row ? X[(E - 2) * b + r] : 0.0;
-  }
-  for (int e = E - 2; e >= 0; --e) {
-    if (e >= 1) {
-      seg(Up + (int64_t)(e - 1) * bb, Wn);
-      if constexpr (BW2) seg(Up2 + (int64_t)(e - 1) * bb, W2n);
-      xn = row ? X[(e - 1) * b + r] : 0.0;
-    }
-    double x = xc - dot4(Wc, s_x);
-    if constexpr (BW2) {
-      if (e + 2 < E) x -= dot4(W2c, s_x2);
-    }
-    lds_barrier();   // every lane has read s_x, s_x2
-    if (row) X[e * b + r] = x;
-    if (row && q == 0) {
-      if constexpr (BW2) s_x2[r] = s_x[r];
-      s_x[r] = x;
-    }
-    lds_barrier();
+  // backward; s_x holds x_{E-1} = y_{E-1}; slot d holds element E - 2 - (i0 + d)'s W1, W2
+  // rows and forward solution
+  {
+    double Wr[PF][NQ], W2r[PF][NQ], xv[PF];
+    auto fetch = [&](int e, int d) {
+      e = e > 0 ? e : 0;
+      seg(Up + (int64_t)e * bb, Wr[d]);
+      if constexpr (BW2) seg(Up2 + (int64_t)e * bb, W2r[d]);
+      xv[d] = X[e * b + rr];
+    };
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-      Wc[t] = Wn[t];
-      W2c[t] = W2n[t];
+    for (int d = 0; d < PF; ++d) fetch(E - 2 - d, d);
+    for (int i0 = 0; i0 < E - 1; i0 += PF) {
+#pragma unroll
+      for (int d = 0; d < PF; ++d) {
+        const int e = E - 2 - (i0 + d);
+        if (e >= 0) {
+          double x = xv[d] - dot4(Wr[d], s_x);
+          if constexpr (BW2) {
+            if (e + 2 < E) x -= dot4(W2r[d], s_x2);
+          }
+          lds_barrier();   // every lane has read s_x, s_x2
+          if (row) X[e * b + r] = x;
+          if (row && q == 0) {
+            if constexpr (BW2) s_x2[r] = s_x[r];
+            s_x[r] = x;
+          }
+          lds_barrier();
+        }
+        fetch(e - PF, d);
+      }
     }
-    xc = xn;
   }
   __syncthreads();   // X is read by other lanes next
 }
