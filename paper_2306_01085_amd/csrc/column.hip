@@ -570,8 +570,10 @@ __device__ inline double wave_allsum(double x) {
   return x;
 }
 
+// (not inlined, as the Jacobian build below and the substitution: each gets a register
+// allocation of its own; inlined, the kernel's one allocation spilled across all of them)
 template <int P, class S, class TV, class OT, int XP, bool OI>
-__device__ __forceinline__ void colw_residual(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
+__device__ __attribute__((noinline)) void colw_residual(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                               const double* u, const TV* v, OT* out, OT* fn) {
   constexpr int b = 3 * (P + 1);
   const int lane = wlane();
@@ -678,7 +680,7 @@ __device__ __forceinline__ void colw_invert(double* blk, double (*M)[2 * b], dou
 // in place: Lo = L1, Di = S^-1, Up = W1, Lo2 = L2, Up2 = W2. Without the far blocks
 // (collocated) the same recurrence is the block-tridiagonal LU.
 template <int P, int XP, bool OI>
-__device__ __forceinline__ void colw_build_and_factor(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
+__device__ __attribute__((noinline)) void colw_build_and_factor(const ColBatch& B, int E, int e0, const PhysC& Pc, const GllC& gc, double t,
                                       double ca, const double* U, double* V, double* Jv, double* fnT, double* Lo,
                                       double* Di, double* Up, double* Lo2, double* Up2) {
   constexpr int b = 3 * (P + 1);
