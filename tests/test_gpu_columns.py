@@ -7,6 +7,7 @@ import pytest
 
 import synth
 from gpu_common import need_gpu, to_dev
+from oracle import dg as odg
 from oracle import mesh as omesh
 from oracle import timeint
 
@@ -51,6 +52,33 @@ def test_batched_columns_match_oracle(scheme):
             ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, scheme=scheme, rtol=1e-13)
         got = out[off[c]:off[c + 1]].reshape(u.shape)
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref - u) < 1e-6, c
+
+
+@pytest.mark.parametrize("quad", [0, 1])
+def test_short_columns_through_the_substitution_ring(quad):
+    """columns of 2 to 6 elements at p = 4: shorter than, as long as and longer than the block
+    substitution's ring of elements in flight (four deep; three for the over-integrated p = 4
+    blocks), so the clamped prefetch at both ends of both sweeps is exercised; two steps of
+    each discretisation against the oracle's dense-Newton steps"""
+    need_gpu()
+    nelem = [3, 5, 4, 6, 2]
+    p = [4] * 5
+    w, gm, cols = _batch(29, nelem, p)
+    gm.set_option("column_quadrature", quad)
+    u0 = np.concatenate([c[2].ravel() for c in cols])
+    ut = to_dev(u0)
+    n_steps = 2
+    its, st = gm.columns_integrate(ut, 0.0, w.dt, n_steps, newton_rtol=1e-11)
+    assert np.all(st == 0) and np.all(its > 0)
+    out = ut.cpu().numpy()
+    off = gm.col_offsets()
+    res = odg.residual_overint if quad else odg.residual
+    for c, (om, P, u) in enumerate(cols):
+        ref = u.copy()
+        for s in range(n_steps):
+            ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-13, residual=res)
+        got = out[off[c]:off[c + 1]].reshape(u.shape)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref - u) < 1e-6, (quad, c)
 
 
 def test_batched_column_large_matches_jfnk_oracle():
