@@ -4,9 +4,9 @@ tune_columns: picks the number of persistent wavefronts of dg_columns_integrate
 for a column batch by timing short trial integrations (on a scratch copy of the
 state) for each candidate; tune_columns_policy: then its chord-Jacobian rebuild
 thresholds the same way; tune_shell_pass1: picks the element-pass configuration
-of the shell residual. Results are cached in a JSON file keyed by the workload's
-shape (DG_TUNE_CACHE, default ~/.cache/dgthermo_tuning.json) and re-applied
-without timing on later calls.
+of the shell residual by the time of whole residual evaluations. Results are
+cached in a JSON file keyed by the workload's shape (DG_TUNE_CACHE, default
+~/.cache/dgthermo_tuning.json) and re-applied without timing on later calls.
 """
 from __future__ import annotations
 
@@ -122,14 +122,16 @@ def tune_columns_policy(mesh, u, t0, dt, steps=32, candidates=((75, 5), (50, 3),
     return best, times
 
 
-def tune_shell_pass1(mesh, u, t=0.0, reps=10, configs=range(6), force=False, log=None, warm_s=0.3):
-    """choose 'shell_pass1_config' by the element pass's own event timing
+def tune_shell_pass1(mesh, u, t=0.0, reps=40, configs=range(6), force=False, log=None, warm_s=0.3):
+    """choose 'shell_pass1_config' by the time of whole residual evaluations (element pass and
+    trace pass: a configuration whose element pass is a little faster can leave the trace pass
+    slower), timed with events around `reps` back-to-back evaluations per configuration
 
     The GPU is first kept busy with residual evaluations for warm_s seconds: timed while its
     clock still rises, the configurations tried first would read slower than they are."""
     key = "shell:%d:%d:%d" % (mesh.p, mesh.n_elem, mesh.n_dof)
     cache = _load()
-    if key in cache and not force:
+    if key in cache and not force and cache[key].get("by") == "residual":
         mesh.set_option("shell_pass1_config", cache[key]["config"])
         return cache[key]["config"], cache[key].get("times", {})
     import torch
@@ -142,17 +144,20 @@ def tune_shell_pass1(mesh, u, t=0.0, reps=10, configs=range(6), force=False, log
     times = {}
     for c in configs:
         mesh.set_option("shell_pass1_config", c)
-        mesh.residual(u, t, out=r)
-        mesh.profile(True)
+        for _ in range(3):
+            mesh.residual(u, t, out=r)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
         for _ in range(reps):
             mesh.residual(u, t, out=r)
-        pr = mesh.profile_read()
-        mesh.profile(False)
-        times[str(c)] = pr["shell_pass1_R"][0] / reps
+        b.record()
+        torch.cuda.synchronize()
+        times[str(c)] = a.elapsed_time(b) / reps
         if log:
-            log("shell_pass1_config %d: %.1f us" % (c, 1e3 * times[str(c)]))
+            log("shell_pass1_config %d: %.1f us per residual" % (c, 1e3 * times[str(c)]))
     best = int(min(times, key=times.get))
     mesh.set_option("shell_pass1_config", best)
-    cache[key] = {"config": best, "times": times}
+    cache[key] = {"config": best, "times": times, "by": "residual"}
     _store(cache)
     return best, times
