@@ -93,7 +93,7 @@ def residual_bytes(w):
     return pass1_bytes(w) + pass2_bytes(w)
 
 
-# the survey's reference roofline of R(u): two-pass LDG with a stored gradient moves
+# reference roofline of R(u): a two-pass LDG evaluation with a stored gradient moves
 # 8 (3 + 2d) = 72 bytes per DOF in 3D (pass 1 reads u and writes q, pass 2 reads u and q and
 # writes R); the target is half of that roofline
 R_REF_BYTES_PER_DOF = 72.0
