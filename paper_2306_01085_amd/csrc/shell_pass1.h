@@ -25,10 +25,10 @@ __device__ inline S load_state(const SU* u, const TV* v, int64_t i) {
   return Io<S>::ld(u, v, i);
 }
 
-// a loaded value required at this point: the load is neither sunk past it (into the branch
-// that stores the value) nor reordered after the loads issued later (an empty instruction
-// that reads and writes the register). Not volatile: a volatile one counts as a possible
-// memory write, after which uniform loads of global data (the EUVAC table, physics
+// a loaded value required at this point (an empty instruction that reads and writes the
+// register): the load is not sunk past it into the branch that stores the value, so the loads
+// before a group of pins are issued together. Not volatile: a volatile one counts as a
+// possible memory write, after which uniform loads of global data (the EUVAC table, physics
 // constants) could no longer be scalar loads.
 __device__ inline void pin(double& x) { __asm__("" : "+v"(x)); }
 __device__ inline void pin(float& x) { __asm__("" : "+v"(x)); }
@@ -305,8 +305,8 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
   for (int c = 0; c < 5; ++c) tu[c] = load_state<S>(u, v, bc + c * N);
   double e0 = M.edges[kc], e1 = M.edges[kc + 1];
   double tD = gc.D[min((int)threadIdx.x, n * n - 1)];
-  // (D first: it is read from the argument block, a load the compiler would otherwise issue
-  // only after the others had been waited for)
+  // (D's pin first: with it last, the load of D, which reads the argument block, was issued
+  // only after the waits for the others)
   pin(tD);
 #pragma unroll
   for (int i = 0; i < NA; ++i) pin(ta[i]);
