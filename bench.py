@@ -834,7 +834,13 @@ def main():
     out["network"] = network
     out["implicit_step"] = implicit_steps(w, mesh, u, args.implicit_steps)
     del r, jv, jv32, v, v32, jvfd
-    if not args.no_warmstart:
+    # the per-element network's BF16 tiles need 15 (p+1)^3 inputs a multiple of 8 and
+    # 5 (p+1)^3 outputs a multiple of 32: p = 3 (960, 320); not p = 2 (405, 135) or p = 4 (1875, 625)
+    ws_nin, ws_nout = 15 * (w.p + 1) ** 3, 5 * (w.p + 1) ** 3
+    if not args.no_warmstart and (ws_nin % 8 or ws_nout % 32):
+        out["warmstart"] = {"skipped": "per-element network of %d inputs and %d outputs at p = %d: the BF16 tiles "
+                                       "need inputs a multiple of 8 and outputs a multiple of 32" % (ws_nin, ws_nout, w.p)}
+    elif not args.no_warmstart:
         log("warm-start network: record, train, plain vs learned")
         ws = warmstart_experiment(w, mesh, u, train_steps=60, eval_steps=8, every=4, epochs=8)
         ws["scale"] = "reduced (60 recorded steps, 8 evaluation steps); bench.py --mode warmstart " \
