@@ -135,17 +135,17 @@ def element_pass_roofline(fl1, b1, p1_ms, tr_bytes, tr_detail, counters):
 # on (a changed kernel reports null until measured again)
 PASS1_PROFILE = "profiles/shell_pass1_shell_pass2_R_shell-p3-7.9M_all-configs_counters.txt"
 PASS1_TRAFFIC = {
-    ("shell-p3", 0): {"src": "42bab98d77f84ee2", "fetch_kib": 50360.8, "write_kib": 151680.0, "valu_insts": 4.4062e+07,
+    ("shell-p3", 0): {"src": "ac03b2dda95fd231", "fetch_kib": 50360.8, "write_kib": 151680.0, "valu_insts": 4.4062e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 1): {"src": "42bab98d77f84ee2", "fetch_kib": 49949.3, "write_kib": 151680.0, "valu_insts": 4.3471e+07,
+    ("shell-p3", 1): {"src": "ac03b2dda95fd231", "fetch_kib": 49949.3, "write_kib": 151680.0, "valu_insts": 4.3471e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 2): {"src": "42bab98d77f84ee2", "fetch_kib": 50356.4, "write_kib": 151680.0, "valu_insts": 4.4062e+07,
+    ("shell-p3", 2): {"src": "ac03b2dda95fd231", "fetch_kib": 50356.4, "write_kib": 151680.0, "valu_insts": 4.4062e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 3): {"src": "42bab98d77f84ee2", "fetch_kib": 49854.1, "write_kib": 151680.0, "valu_insts": 4.3183e+07,
+    ("shell-p3", 3): {"src": "ac03b2dda95fd231", "fetch_kib": 49854.1, "write_kib": 151680.0, "valu_insts": 4.3183e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 4): {"src": "42bab98d77f84ee2", "fetch_kib": 49824.7, "write_kib": 151680.0, "valu_insts": 4.3677e+07,
+    ("shell-p3", 4): {"src": "ac03b2dda95fd231", "fetch_kib": 49824.7, "write_kib": 151680.0, "valu_insts": 4.3677e+07,
                       "profile": PASS1_PROFILE},
-    ("shell-p3", 5): {"src": "42bab98d77f84ee2", "fetch_kib": 175558.5, "write_kib": 309593.5, "valu_insts": 4.3331e+07,
+    ("shell-p3", 5): {"src": "ac03b2dda95fd231", "fetch_kib": 175558.5, "write_kib": 309593.5, "valu_insts": 4.3331e+07,
                       "profile": PASS1_PROFILE},
 }
 

@@ -472,13 +472,13 @@ void shell_pass1(ShellDev M, PhysC ph, GllC gc, double t, const SU* __restrict__
         for (int d = 0; d < 3; ++d) q[c][d] = q[c][d] + du * T(sd * Ja[dd][d]);
       }
     }
-    // boundary faces: the terms (F - F_hat).Sn are completed here. On the lower face (and
-    // every boundary face in bc_mode 1), F_hat.Sn = F(u_b, q).Sn + |Sn| sigma(u_b)(u - u_b)
-    // is taken before the node's own flux so that q need not outlive it.
     // the node's own state, read back from LDS here rather than held in registers through
     // the face tasks and the gradient
     S uu[5];
     for (int c = 0; c < 5; ++c) uu[c] = s_u[le][c][j + PL * cz];
+    // boundary faces: the terms (F - F_hat).Sn are completed here. On the lower face (and
+    // every boundary face in bc_mode 1), F_hat.Sn = F(u_b, q).Sn + |Sn| sigma(u_b)(u - u_b)
+    // is taken before the node's own flux so that q need not outlive it.
     const bool bot = (k == 0 && cz == 0);
     const bool top = (k == M.n_rad - 1 && cz == n - 1);
     const bool dir = bot || (top && ph.bc_mode == 1);
