@@ -202,8 +202,8 @@ __global__ void k_line_pack(LineDev L, int64_t n_lines, F* __restrict__ P) {
 }
 
 // A row of a packed matrix held as the 32-bit words it was loaded as (RS entries of F,
-// RS * sizeof(F) a multiple of 8, src aligned to it): BF16 rows stay two entries per register
-// until used, so that a ring of rows takes half the registers.
+// RS * sizeof(F) a multiple of 8, src aligned to it); entries are widened where they are used
+// (line_at). BF16 rows take two entries per register, as the compiler already kept them.
 template <int RS, class F>
 struct LineRow {
   static constexpr int W = RS * (int)sizeof(F) / 4;
@@ -246,8 +246,9 @@ __device__ inline double line_at(const LineRow<RS, double>& r, int q) {
   return __hiloint2double((int)r.w[2 * q + 1], (int)r.w[2 * q]);
 }
 
-// a loaded value required at this point (the load can be neither sunk into the branch that
-// stores it nor issued after the loads that follow it in the source)
+// a loaded value required at this point (an empty instruction that reads and writes the
+// register): the load is not sunk past it into the branch that stores the value, so the loads
+// before a group of pins are issued together
 __device__ inline void line_pin(double& x) { __asm__ __volatile__("" : "+v"(x)); }
 __device__ inline void line_pin(float& x) { __asm__ __volatile__("" : "+v"(x)); }
 
