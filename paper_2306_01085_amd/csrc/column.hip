@@ -609,14 +609,49 @@ __device__ __attribute__((noinline)) void colw_residual(const ColBatch& B, int E
   __syncthreads();
 }
 
-// G = U - ca R - Bv; returns |G|^2 (all lanes)
+// The whole-column vector steps below take kVec entries per lane at a time and form all of
+// them (every load issued) before storing any, so the loads' latencies overlap; one entry at a
+// time, each store waits on its own loads and a 3840-entry column costs 60 such round trips
+// per step. Indices past nd are clamped to nd - 1 and their values dropped.
+constexpr int kVec = 4;
+
+// Y[i] = f(i) for i < nd. Y may be an array that f reads at index i: every entry a lane
+// stores is one it alone reads, before the store (a clamped read of entry nd - 1 by another
+// lane is dropped).
+template <class F>
+__device__ __forceinline__ void colw_map(int nd, double* Y, F f) {
+  for (int i0 = wlane(); i0 < nd; i0 += 64 * kVec) {
+    double v[kVec];
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) v[k] = f(min(i0 + 64 * k, nd - 1));
+    // keeps the loads ahead of the stores' branches (otherwise each is sunk into its own)
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) __asm__("" : "+v"(v[k]));
+#pragma unroll
+    for (int k = 0; k < kVec; ++k)
+      if (i0 + 64 * k < nd) Y[i0 + 64 * k] = v[k];
+  }
+}
+
+// G = U - ca R - Bv; returns |G|^2 (all lanes; each lane sums its entries in index order)
 __device__ inline double colw_stage_residual(int nd, const double* U, const double* R, double ca, const double* Bv,
                                              double* G) {
   double acc = 0;
-  for (int i = wlane(); i < nd; i += 64) {
-    const double g = U[i] - ca * R[i] - Bv[i];
-    G[i] = g;
-    acc += g * g;
+  for (int i0 = wlane(); i0 < nd; i0 += 64 * kVec) {
+    double g[kVec];
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) {
+      const int i = min(i0 + 64 * k, nd - 1);
+      g[k] = U[i] - ca * R[i] - Bv[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) __asm__("" : "+v"(g[k]));
+#pragma unroll
+    for (int k = 0; k < kVec; ++k)
+      if (i0 + 64 * k < nd) {
+        G[i0 + 64 * k] = g[k];
+        acc += g[k] * g[k];
+      }
   }
   __syncthreads();
   return wave_allsum(acc);
@@ -913,7 +948,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   double* Lo2 = OI ? Up + blk_len : nullptr;   // block bandwidth two (over-integrated)
   double* Up2 = OI ? Lo2 + blk_len : nullptr;
   double* ug = B.u + B.col_off[col];
-  for (int i = lane; i < nd; i += 64) un[i] = ug[i];
+  colw_map(nd, un, [&](int i) { return ug[i]; });
   __syncthreads();
   const double ca = B.dt * B.A[0][0];
   int newton_total = 0, builds = 0, status = 0;
@@ -935,16 +970,16 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
       stale = false;
     }
     int max_stage_its = 0;
-    for (int i = lane; i < nd; i += 64) U[i] = un[i];
+    colw_map(nd, U, [&](int i) { return un[i]; });
     __syncthreads();
     for (int s = 0; s < B.n_stages && status == 0; ++s) {
       const double ti = t + B.c[s] * B.dt;
       if (sited) sun_direction_dev(Pc, ti);
-      for (int i = lane; i < nd; i += 64) {
+      colw_map(nd, Bv, [&](int i) {
         double bv = un[i];
         for (int j = 0; j < s; ++j) bv += B.dt * B.A[s][j] * Rs[j * md + i];
-        Bv[i] = bv;
-      }
+        return bv;
+      });
       __syncthreads();
       colw_residual<P, double, double, double, XP, OI>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
       const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, G));
@@ -969,22 +1004,22 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
           ++builds;
           last_build = it;
         }
-        for (int i = lane; i < nd; i += 64) X[i] = -G[i];
+        colw_map(nd, X, [&](int i) { return -G[i]; });
         __syncthreads();
         colw_solve<P, OI>(E, Lo, Di, Up, Lo2, Up2, X);
-        for (int i = lane; i < nd; i += 64) U[i] += X[i];
+        colw_map(nd, U, [&](int i) { return U[i] + X[i]; });
         __syncthreads();
         prev = nG;
         ++it;
       }
       newton_total += it;
       max_stage_its = max(max_stage_its, it);
-      for (int i = lane; i < nd; i += 64) Rs[s * md + i] = Rc[i];
+      colw_map(nd, Rs + s * md, [&](int i) { return Rc[i]; });
       __syncthreads();
     }
     if (max_stage_its > B.jac_stale) stale = true;
     if (status == 0) {
-      for (int i = lane; i < nd; i += 64) un[i] = U[i];
+      colw_map(nd, un, [&](int i) { return U[i]; });
       __syncthreads();
       if (B.filter) {
         const double* F = B.filt[P - 2].F;
@@ -1002,7 +1037,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
     }
   }
   if (status == 0)
-    for (int i = lane; i < nd; i += 64) ug[i] = un[i];
+    colw_map(nd, ug, [&](int i) { return un[i]; });
   if (lane == 0) {
     B.newton_total[col] = newton_total;
     B.status[col] = status;
