@@ -633,9 +633,10 @@ __device__ __forceinline__ void colw_map(int nd, double* Y, F f) {
   }
 }
 
-// G = U - ca R - Bv; returns |G|^2 (all lanes; each lane sums its entries in index order)
+// G = U - ca R - Bv, stored negated (-G is the right-hand side of the Newton correction);
+// returns |G|^2 (all lanes; each lane sums its entries in index order)
 __device__ inline double colw_stage_residual(int nd, const double* U, const double* R, double ca, const double* Bv,
-                                             double* G) {
+                                             double* mG) {
   double acc = 0;
   for (int i0 = wlane(); i0 < nd; i0 += 64 * kVec) {
     double g[kVec];
@@ -649,7 +650,7 @@ __device__ inline double colw_stage_residual(int nd, const double* U, const doub
 #pragma unroll
     for (int k = 0; k < kVec; ++k)
       if (i0 + 64 * k < nd) {
-        G[i0 + 64 * k] = g[k];
+        mG[i0 + 64 * k] = -g[k];
         acc += g[k] * g[k];
       }
   }
@@ -931,8 +932,7 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
   double* w = B.ws + (int64_t)blockIdx.x * B.ws_stride;
   const int64_t md = B.max_dof;
   double* U = w;
-  double* G = U + md;
-  double* Bv = G + md;
+  double* Bv = U + 2 * md;        // (the slot at U + md is spare)
   double* un = Bv + md;
   double* X = un + md;
   double* Rc = X + md;
@@ -982,13 +982,13 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
       });
       __syncthreads();
       colw_residual<P, double, double, double, XP, OI>(B, E, e0, Pc, gc, ti, un, (const double*)nullptr, Rc, fn);
-      const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, G));
+      const double ref = sqrt(colw_stage_residual(nd, un, Rc, ca, Bv, X));
       int it = 0;
       double prev = 0.0;
       int last_build = 0;   // iteration of this stage at which the Jacobian was last rebuilt
       for (;;) {
         colw_residual<P, double, double, double, XP, OI>(B, E, e0, Pc, gc, ti, U, (const double*)nullptr, Rc, fn);
-        const double nG = sqrt(colw_stage_residual(nd, U, Rc, ca, Bv, G));
+        const double nG = sqrt(colw_stage_residual(nd, U, Rc, ca, Bv, X));
         if (!isfinite(nG)) {
           status = 5;
           break;
@@ -1004,8 +1004,6 @@ __device__ __forceinline__ void colw_run(const ColBatch& B, int col, const PhysC
           ++builds;
           last_build = it;
         }
-        colw_map(nd, X, [&](int i) { return -G[i]; });
-        __syncthreads();
         colw_solve<P, OI>(E, Lo, Di, Up, Lo2, Up2, X);
         colw_map(nd, U, [&](int i) { return U[i] + X[i]; });
         __syncthreads();
