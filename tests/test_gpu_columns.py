@@ -253,3 +253,21 @@ def test_full_batch_overint_without_filter_matches_oracle():
             ref, _ = timeint.implicit_step_dense(om, P, ref, s * w.dt, w.dt, rtol=1e-9, residual=odg.residual_overint)
         got = y[off[c]:off[c + 1]].reshape(ref.shape)
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref - start) < 1e-5, (c, p)
+
+
+def test_sweep_cases_concurrently_match_one_after_another():
+    """the three cases of the parametric study advanced concurrently (a stream and a host
+    thread per case) end in exactly the states, Newton counts and failures of the cases run
+    one after another: each column's chain is the same whatever else shares the chip"""
+    need_gpu()
+    from paper_2306_01085_amd import sweep
+    ws = [synth.sweep_case(case) for case in (1, 2, 3)]
+    kw = dict(hours=0.5, chunk_hours=0.25, quadrature=1, filter_rate=0.0)
+    serial = [sweep.run_case(w, **kw) for w in ws]
+    conc, wall = sweep.run_cases(ws, **kw)
+    assert wall > 0.0
+    for a, b in zip(serial, conc):
+        assert a["case"] == b["case"] and a["steps"] == b["steps"] == 60
+        assert a["failed"] == b["failed"] == 0
+        assert a["newton_per_column_step"] == b["newton_per_column_step"]
+        np.testing.assert_array_equal(np.asarray(a["logrho_400km"]), np.asarray(b["logrho_400km"]))
